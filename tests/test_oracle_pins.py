@@ -1,0 +1,302 @@
+"""Pins of the oracle against the paper's printed values, closed forms,
+invariants and brute force -- never against itself.
+
+Each test names what fixes the expected value.  ``test_oracle_mutations``
+plants plausible mistakes in the oracle and shows that these pins catch them.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import gibbs, grad, pathsum, sim, stats
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+SQ2 = np.sqrt(2.0)
+
+
+def load_gold(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return json.load(f)
+
+
+# ---------------------------------------------------------------- closed forms
+
+def test_gate_unitarity_and_kraus_completeness():
+    for a in (0.0, 0.3, 2.1, -4.0):
+        for U in (sim.mat_h(), sim.mat_rx(a), sim.mat_rz(a), sim.mat_x(), sim.mat_y(), sim.mat_z()):
+            assert np.allclose(U.conj().T @ U, np.eye(2), atol=1e-15)
+    for kind in ("DEP", "AD", "PD"):
+        for p in (0.0, 0.01, 0.36, 1.0):
+            s = sum(E.conj().T @ E for E in sim.kraus(kind, p))
+            assert np.allclose(s, np.eye(2), atol=1e-15)
+
+
+def test_hadamard_eq_q0m1():
+    # Sec. 2.1, eq. q0m1: H|0> = (|0> + |1>)/sqrt(2)
+    c = W.Circuit(n=1, ops=[("H", 0)], n_angles=0, noise=[])
+    assert np.allclose(sim.statevector(c, []), [1 / SQ2, 1 / SQ2], atol=1e-16)
+
+
+@pytest.mark.parametrize("a", [0.0, 0.4, 1.7, 3.3, 5.9])
+def test_rotation_closed_forms(a):
+    cx = W.Circuit(n=1, ops=[("RX", 0, 0, 1.0)], n_angles=1, noise=[])
+    assert np.allclose(sim.statevector(cx, [a]), [np.cos(a / 2), -1j * np.sin(a / 2)], atol=1e-15)
+    # RZ after H: relative phase e^{ia} between |1> and |0>
+    cz = W.Circuit(n=1, ops=[("H", 0), ("RZ", 0, 0, 1.0)], n_angles=1, noise=[])
+    psi = sim.statevector(cz, [a])
+    assert np.allclose(psi, [np.exp(-0.5j * a) / SQ2, np.exp(0.5j * a) / SQ2], atol=1e-15)
+
+
+def test_bit_order_and_cnot_truth_table():
+    # X-like preparation on q0 only -> basis index 1 (LSB = q0)
+    c = W.Circuit(n=3, ops=[("RX", 0, 0, 1.0)], n_angles=1, noise=[])
+    psi = sim.statevector(c, [np.pi])
+    assert np.isclose(abs(psi[1]), 1.0) and np.isclose(np.sum(abs(psi) ** 2), 1.0)
+    # Table cat_cnot: control q0, target q1, all four inputs
+    for x0 in (0, 1):
+        for x1 in (0, 1):
+            ops = []
+            if x0:
+                ops.append(("RX", 0, 0, 1.0))
+            if x1:
+                ops.append(("RX", 1, 0, 1.0))
+            ops.append(("CNOT", 0, 1))
+            psi = sim.statevector(W.Circuit(n=2, ops=ops, n_angles=1, noise=[]), [np.pi])
+            out = x0 + 2 * (x1 ^ x0)
+            assert np.isclose(abs(psi[out]), 1.0)
+
+
+@pytest.mark.parametrize("n", [2, 3, 5, 8])
+def test_bell_and_ghz(n):
+    ops = [("H", 0)] + [("CNOT", q, q + 1) for q in range(n - 1)]
+    psi = sim.statevector(W.Circuit(n=n, ops=ops, n_angles=0, noise=[]), [])
+    expect = np.zeros(1 << n, dtype=complex)
+    expect[0] = expect[-1] = 1 / SQ2
+    assert np.allclose(psi, expect, atol=1e-15)
+
+
+# ------------------------------------------------------------ worked example
+
+def test_noisy_bell_worked_example():
+    g = load_gold("noisy_bell.json")
+    c = W.noisy_bell(g["gamma"])
+    # rho after H, eq. density_matrix
+    rh = sim.density_matrix(W.Circuit(n=1, ops=[("H", 0)], n_angles=0, noise=[]), [])
+    assert np.allclose(rh, g["rho_after_h"], atol=1e-15)
+    # rho after phase damping on the single qubit (Sec. 2.2.2)
+    rp = sim.density_matrix(W.Circuit(n=1, ops=[("H", 0), ("PD", 0, 0)], n_angles=0,
+                                      noise=[g["gamma"]]), [])
+    assert np.allclose(rp, g["rho_after_pd"], atol=1e-15)
+    # Table inference: branch amplitudes; |.| exact, sign per documented reading
+    for rv in (0, 1):
+        psi = sim.branch_state(c, [], [rv]) * SQ2
+        ref = np.array(g["branch_amplitudes_times_sqrt2"][f"rv{rv}"])
+        assert np.allclose(np.abs(psi), np.abs(ref), atol=1e-15)
+        assert np.allclose(psi.imag, 0, atol=1e-15)
+        bd = np.outer(psi, psi.conj()) / 2
+        assert np.allclose(bd, g["branch_density_matrices"][f"rv{rv}"], atol=1e-15)
+    # the oracle's reading: +sqrt(gamma) (Kraus form), the table's -0.6 differs by sign only
+    a = sim.amplitude(c, [], 3, [1])
+    assert np.isclose(a, -g["root_value_rv1_q0_1_q1_1"], atol=1e-15)
+    # eq. final: the two components sum to the final density matrix
+    assert np.allclose(sim.density_matrix(c, []), g["rho_final"], atol=1e-15)
+    assert np.allclose(sim.probabilities_from_branches(c, []), np.diag(g["rho_final"]), atol=1e-15)
+    # Table cat_phase_damping magnitudes are the Kraus entries
+    E0, E1 = sim.kraus("PD", g["gamma"])
+    assert np.isclose(E0[1, 1], g["pd_cat"]["q_in_1"][0]) and np.isclose(abs(E1[1, 1]), 0.6)
+
+
+# ---------------------------------------------------------------- invariants
+
+def _small_noisy(seed=3, dep=0.05, ad=None, n=4, p=1, ring=True):
+    edges = W.ring_graph(n) if ring else W.random_regular_graph(n, 3, seed)
+    return W.qaoa_maxcut(n, edges, p, dep=dep, ad=ad)
+
+
+def test_dm_equals_sum_of_branch_outer_products():
+    c = W.Circuit(n=2, ops=[("H", 0), ("DEP", 0, 0), ("CNOT", 0, 1), ("AD", 1, 1),
+                            ("RX", 1, 0, 2.0), ("DEP", 1, 0)], n_angles=1, noise=[0.2, 0.3])
+    th = [0.77]
+    rho = sim.density_matrix(c, th)
+    acc = np.zeros_like(rho)
+    total = 0.0
+    for k in sim.all_kraus_assignments(c):
+        psi = sim.branch_state(c, th, k)
+        acc += np.outer(psi, psi.conj())
+        total += np.sum(np.abs(psi) ** 2)
+    assert np.allclose(acc, rho, atol=1e-14)
+    assert np.isclose(total, 1.0, atol=1e-14)      # Kraus completeness -> unit trace
+    assert np.isclose(np.trace(rho).real, 1.0, atol=1e-14)
+
+
+def test_unit_trace_qaoa_noisy():
+    c = _small_noisy(dep=0.02, ad=0.01, n=4)
+    for th in W.uniform_angles(3, 2, 11):
+        assert np.isclose(np.trace(sim.density_matrix(c, th)).real, 1.0, atol=1e-13)
+
+
+def test_gamma_zero_gives_uniform_even_with_depolarizing():
+    c = W.qaoa_maxcut(6, W.random_regular_graph(6, 3, 1), 1, dep=0.03)
+    for b in (0.3, 1.1, 2.9):
+        p = sim.probabilities(c, [0.0, b])
+        assert np.allclose(p, 1 / 64, atol=1e-14)
+
+
+def test_bitflip_symmetry_and_ad_breaks_it():
+    edges = W.random_regular_graph(6, 3, 2)
+    th = [0.9, 0.4]
+    idx = np.arange(64)
+    for c in (W.qaoa_maxcut(6, edges, 1), W.qaoa_maxcut(6, edges, 1, dep=0.02)):
+        p = sim.probabilities(c, th)
+        assert np.allclose(p, p[idx ^ 63], atol=1e-14)
+    p = sim.probabilities(W.qaoa_maxcut(6, edges, 1, dep=0.02, ad=0.05), th)
+    assert np.max(np.abs(p - p[idx ^ 63])) > 1e-4
+
+
+def test_zero_noise_equivalence():
+    edges = W.ring_graph(4)
+    ideal = W.qaoa_maxcut(4, edges, 1)
+    noisy = W.qaoa_maxcut(4, edges, 1, dep=0.0, ad=0.0)
+    th = [1.2, 0.3]
+    psi0 = sim.statevector(ideal, th)
+    assert np.allclose(sim.branch_state(noisy, th), psi0, atol=1e-15)
+    rng = np.random.default_rng(0)
+    C = len(noisy.channels())
+    for _ in range(5):
+        k = rng.integers(0, 2, size=C)
+        if k.sum() == 0:
+            continue
+        assert np.allclose(sim.branch_state(noisy, th, k), 0, atol=1e-15)
+
+
+# ---------------------------------------------------------------- path sums
+
+@pytest.mark.parametrize("n,seed", [(4, None), (6, 1), (8, 2), (10, 3), (12, 4)])
+def test_pathsum_matches_statevector(n, seed):
+    edges = W.ring_graph(n) if seed is None else W.random_regular_graph(n, 3, seed)
+    c = W.qaoa_maxcut(n, edges, 1)
+    ths = W.uniform_angles(3, 2, 99)
+    rng = np.random.default_rng(n)
+    for x in rng.integers(0, 1 << n, size=3):
+        hist = pathsum.path_histogram(n, edges, int(x))
+        assert int(hist.sum()) == 1 << n
+        f = pathsum.amplitudes_from_histogram(hist, n, len(edges), ths[:, 0], ths[:, 1])
+        for t, th in enumerate(ths):
+            assert abs(f[t] - sim.statevector(c, th)[x]) < 1e-14
+
+
+def test_pathsum_closed_forms_large_n():
+    n = 24
+    edges = W.random_regular_graph(n, 3, 5)
+    x = 0xABCDE1
+    hist = pathsum.path_histogram(n, edges, x)
+    # beta = 0: |f|^2 = 2^-n for every x; gamma = 0: f = 2^{-n/2} e^{-i n beta}
+    f = pathsum.amplitudes_from_histogram(hist, n, len(edges), [0.7, 0.0], [0.0, 0.45])
+    assert np.isclose(abs(f[0]) ** 2, 2.0 ** -n, rtol=1e-12)
+    assert abs(f[1] - 2.0 ** (-n / 2) * np.exp(-1j * n * 0.45)) < 1e-15
+
+
+# ---------------------------------------------------------------- gradients
+
+def test_product_rule_matches_finite_difference():
+    c = _small_noisy(dep=0.03, ad=0.02, n=4, p=2)
+    th = np.array([0.3, 1.1, 2.2, 0.6])
+    rng = np.random.default_rng(1)
+    k = np.zeros(len(c.channels()), dtype=int)
+    k[rng.integers(0, len(k), size=3)] = 1
+    g = grad.amplitude_grad(c, th, k)
+    fd = grad.central_difference(lambda t: sim.branch_state(c, t, k), th, h=1e-6)
+    assert np.allclose(g, fd, atol=1e-8)
+
+
+def _tiny_angle_circuit():
+    ops = [("H", 0), ("H", 1), ("CNOT", 0, 1), ("DEP", 1, 0), ("RZ", 1, 0, 2.0), ("AD", 0, 1),
+           ("CNOT", 0, 1), ("RX", 0, 1, 2.0), ("RX", 1, 1, 2.0), ("DEP", 0, 0),
+           ("RZ", 0, 2, 2.0), ("RX", 1, 3, 2.0)]
+    return W.Circuit(n=2, ops=ops, n_angles=4, noise=[0.07, 0.2], edges=[(0, 1)])
+
+
+def test_param_shift_matches_fd():
+    c = _small_noisy(dep=0.02, ad=0.01, n=3, p=2, ring=True)
+    th = np.array([0.8, 0.25, 1.9, 2.7])
+    ps = grad.expected_cost_param_shift(c, th)
+    fd = grad.central_difference(lambda t: sim.expected_cost(c, t), th, h=1e-5)
+    assert np.allclose(ps, fd, atol=1e-8)
+
+
+def test_param_shift_matches_product_rule_through_branches():
+    c = _tiny_angle_circuit()
+    th = np.array([0.8, 0.25, 1.9, 2.7])
+    ps = grad.expected_cost_param_shift(c, th)
+    # d<C>/dtheta = sum_k sum_x C(x) 2 Re(conj f df) (product rule per branch)
+    C = sim.cost_vector(c)
+    acc = np.zeros(4)
+    for k in sim.all_kraus_assignments(c):
+        f = sim.branch_state(c, th, k)
+        df = grad.amplitude_grad(c, th, k)
+        acc += 2 * np.real(np.conj(f)[None, :] * df) @ C
+    assert np.allclose(acc, ps, atol=1e-12)
+    assert np.max(np.abs(ps)) > 1e-3
+
+
+# ---------------------------------------------------------------- Gibbs / RNG
+
+def test_splitmix64_reference_values():
+    # SplitMix64 seeded with state 0 (Steele, Lea, Flood 2014): the first two
+    # outputs of the published generator.
+    assert gibbs.mix64(0) == 0xE220A8397B1DCDAF
+    assert gibbs.mix64(gibbs.GOLDEN) == 0x6E789E6AA1B965F4
+    u = [gibbs.uniform(7, c, s, v) for c in range(4) for s in range(4) for v in range(4)]
+    assert all(0.0 <= x < 1.0 for x in u) and len(set(u)) == len(u)
+
+
+def test_choose_rule():
+    assert gibbs.choose([0.0, 0.0], 0.3) is None
+    assert gibbs.choose([1.0, 1.0], 0.0) == 0
+    assert gibbs.choose([1.0, 1.0], 0.5) == 1          # strict '<': 1.0 < 1.0 false
+    assert gibbs.choose([0.0, 2.0, 0.0], 0.999999) == 1
+    assert gibbs.choose([1.0, 0.0, 3.0], 0.26) == 2
+
+
+def test_exact_kernel_is_stationary():
+    c = W.noisy_bell(0.36)
+    states, d0 = gibbs.exact_sweep_distribution(c, [], 0)
+    pi = np.array([abs(gibbs.BranchCache(c, []).amp(s)) ** 2 for s in states.tolist()])
+    # run the exact kernel from pi itself: must stay at pi
+    _, d1 = gibbs.exact_sweep_distribution(c, [], 1)
+    _, d50 = gibbs.exact_sweep_distribution(c, [], 50)
+    assert np.isclose(pi.sum(), 1.0)
+    # the noisy Bell chain converges to |f|^2 within 50 sweeps
+    assert np.allclose(d50, pi, atol=1e-10)
+    assert np.isclose(d1.sum(), 1.0)
+
+
+def test_reference_chain_matches_exact_sweep_distribution():
+    edges = W.ring_graph(3)
+    c = W.qaoa_maxcut(3, edges, 1)
+    th = [0.6, 0.35]
+    t = 2
+    states, dist = gibbs.exact_sweep_distribution(c, th, t)
+    counts = np.zeros(len(states))
+    index = {tuple(s): i for i, s in enumerate(states.tolist())}
+    for ch in range(3000):
+        samp, _ = gibbs.run_chain(c, th, seed=5, chain=ch, burn_in=t - 1, thin=1, n_samples=1)
+        counts[index[tuple(samp[0])]] += 1
+    _, _, pval = stats.chi2_pooled(counts, dist)
+    assert pval > 1e-3
+
+
+def test_chi2_detects_bias_and_accepts_truth():
+    rng = np.random.default_rng(0)
+    p = rng.dirichlet(np.ones(20))
+    good = np.bincount(rng.choice(20, size=20000, p=p), minlength=20)
+    assert stats.chi2_pooled(good, p)[2] > 1e-3
+    q = p.copy()
+    q[0] *= 1.3
+    q /= q.sum()
+    bad = np.bincount(rng.choice(20, size=20000, p=q), minlength=20)
+    assert stats.chi2_pooled(bad, p)[2] < 1e-3
+    assert stats.kl_divergence(good, p) < stats.kl_divergence(bad, p)
