@@ -1,0 +1,223 @@
+"""Python binding of the AC library: torch tensors in, C ABI calls out.
+
+Every step of the evaluation runs in the HIP kernels of ``libqkc.so``; this
+module only checks shapes, dtypes and devices, allocates outputs and
+workspaces with torch, and passes raw device pointers plus the current HIP
+stream.  There is no CPU fallback: without the library (or a GPU) the calls
+raise.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from .blob import to_blob
+from .compiler import CompiledAC, compile_circuit
+
+_CDTYPE = {"c64": (L.AC_C64, torch.complex64), "c128": (L.AC_C128, torch.complex128)}
+
+
+def _as_words(x):
+    """Evidence words as an int64 tensor holding the uint64 bit patterns."""
+    if isinstance(x, np.ndarray):
+        return torch.from_numpy(np.ascontiguousarray(x).astype(np.uint64, copy=False).view(np.int64))
+    if isinstance(x, torch.Tensor) and x.dtype == getattr(torch, "uint64", None):
+        return x.view(torch.int64)
+    return x
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class ACGraph:
+    """A compiled arithmetic circuit resident on one GPU."""
+
+    def __init__(self, source, device: int = 0):
+        if isinstance(source, (bytes, bytearray)):
+            blob = bytes(source)
+            self.compiled = None
+        else:
+            compiled = source if isinstance(source, CompiledAC) else compile_circuit(source)
+            blob = to_blob(compiled)
+            self.compiled = compiled
+        self.blob = blob
+        self.device = int(device)
+        self._h = ctypes.c_void_p()
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        L.check(L.lib().ac_load(buf, len(blob), self.device, ctypes.byref(self._h)))
+        inf = L.ACInfo()
+        L.check(L.lib().ac_info(self._h, ctypes.byref(inf)))
+        self.info = inf.as_dict()
+        self._ws = {}
+
+    # ------------------------------------------------------------------ util
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            L.lib().ac_free(self._h)
+            self._h = ctypes.c_void_p()
+        self._ws = {}
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def torch_device(self):
+        return torch.device("cuda", self.device)
+
+    def workspace_size(self, dtype: str, batch: int, op: int) -> int:
+        return int(L.lib().ac_workspace_size(self._h, _CDTYPE[dtype][0], int(batch), int(op)))
+
+    def workspace(self, dtype: str, batch: int, op: int) -> torch.Tensor:
+        need = self.workspace_size(dtype, batch, op)
+        key = (dtype, op)
+        ws = self._ws.get(key)
+        if ws is None or ws.numel() < need:
+            ws = torch.empty(max(need, 256), dtype=torch.uint8, device=self.torch_device)
+            self._ws[key] = ws
+        return ws
+
+    def _stream(self):
+        return ctypes.c_void_p(torch.cuda.current_stream(self.torch_device).cuda_stream)
+
+    def _dev(self, t, dtype, name, shape=None):
+        if not isinstance(t, torch.Tensor):
+            t = torch.as_tensor(t)
+        t = t.to(device=self.torch_device, dtype=dtype).contiguous()
+        if shape is not None and tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name}: expected shape {tuple(shape)}, got {tuple(t.shape)}")
+        return t
+
+    def _inputs(self, theta, evidence, param_of, noise):
+        K = self.info["n_angles"]
+        theta = self._dev(theta, torch.float64, "theta")
+        if theta.dim() == 1:
+            theta = theta.reshape(1, -1)
+        if theta.shape[1] != K:
+            raise ValueError(f"theta must have {K} columns, got {theta.shape[1]}")
+        P = theta.shape[0]
+        evidence = _as_words(evidence)
+        evidence = self._dev(evidence, torch.int64, "evidence")
+        if evidence.dim() == 1:
+            evidence = evidence.reshape(1, -1)
+        if evidence.shape[1] != self.info["n_words"]:
+            raise ValueError(f"evidence must have {self.info['n_words']} words per row")
+        B = evidence.shape[0]
+        if param_of is None:
+            if P != 1:
+                raise ValueError("param_of is required when theta has more than one row")
+            param_of = torch.zeros(B, dtype=torch.int32, device=self.torch_device)
+        param_of = self._dev(param_of, torch.int32, "param_of", (B,))
+        if B > 0 and (int(param_of.min()) < 0 or int(param_of.max()) >= P):
+            raise ValueError("param_of entries must lie in [0, P)")
+        if noise is not None:
+            noise = self._dev(noise, torch.float64, "noise", (self.info["n_noise"],))
+            if noise.numel() and (float(noise.min()) < 0.0 or float(noise.max()) > 1.0):
+                raise ValueError("noise strengths must lie in [0, 1]")
+        return theta, evidence, param_of, noise, P, B
+
+    # ------------------------------------------------------------- queries
+    def eval(self, theta, evidence, param_of=None, noise=None, dtype: str = "c64", prob: bool = True):
+        """Amplitudes f(evidence[b]; theta[param_of[b]]) and optionally |f|^2 (FP64)."""
+        code, cdt = _CDTYPE[dtype]
+        theta, evidence, param_of, noise, P, B = self._inputs(theta, evidence, param_of, noise)
+        amp = torch.empty(B, dtype=cdt, device=self.torch_device)
+        pr = torch.empty(B, dtype=torch.float64, device=self.torch_device) if prob else None
+        ws = self.workspace(dtype, B, L.AC_OP_EVAL)
+        L.check(L.lib().ac_eval_batch(self._h, code, _ptr(theta), P, _ptr(noise), _ptr(param_of),
+                                      _ptr(evidence), B, _ptr(amp), _ptr(pr), _ptr(ws), ws.numel(),
+                                      self._stream()))
+        return amp, pr
+
+    def grad(self, theta, evidence, param_of=None, mode: str = "cotangent", cotangent=None,
+             weight=None, noise=None, dtype: str = "c64", want_amp=False, want_dfdtheta=False,
+             want_dind=False):
+        """Gradient in theta of a loss of the amplitudes (see ac_grad_batch)."""
+        code, cdt = _CDTYPE[dtype]
+        theta, evidence, param_of, noise, P, B = self._inputs(theta, evidence, param_of, noise)
+        m = {"cotangent": L.AC_GRAD_COTANGENT, "prob": L.AC_GRAD_PROB, "logprob": L.AC_GRAD_LOGPROB}[mode]
+        cot = self._dev(cotangent, cdt, "cotangent", (B,)) if m == L.AC_GRAD_COTANGENT else None
+        w = self._dev(weight, torch.float64, "weight", (B,)) if m != L.AC_GRAD_COTANGENT else None
+        K = self.info["n_angles"]
+        dev = self.torch_device
+        grad = torch.empty((P, K), dtype=torch.float64, device=dev)
+        amp = torch.empty(B, dtype=cdt, device=dev) if want_amp else None
+        dft = torch.empty((B, K), dtype=cdt, device=dev) if want_dfdtheta else None
+        dind = torch.empty((B, self.info["n_indicator_leaves"]), dtype=cdt, device=dev) if want_dind else None
+        ws = self.workspace(dtype, B, L.AC_OP_GRAD)
+        L.check(L.lib().ac_grad_batch(self._h, code, _ptr(theta), P, _ptr(noise), _ptr(param_of),
+                                      _ptr(evidence), B, m, _ptr(cot), _ptr(w), _ptr(grad), _ptr(amp),
+                                      _ptr(dft), _ptr(dind), _ptr(ws), ws.numel(), self._stream()))
+        return dict(grad=grad, amp=amp, dfdtheta=dft, dind=dind)
+
+    def sample(self, theta, chains_per_param: int, samples_per_chain: int = 1, burn_in: int = 20,
+               thin: int = 1, seed: int = 1, cost_edges: Optional[Sequence] = None, noise=None,
+               dtype: str = "c64", want_states=False, want_cost=False, want_rounds=False):
+        """Gibbs samples of the output bits (see ac_sample)."""
+        code, _ = _CDTYPE[dtype]
+        K = self.info["n_angles"]
+        theta = self._dev(theta, torch.float64, "theta")
+        if theta.dim() == 1:
+            theta = theta.reshape(1, -1)
+        if theta.shape[1] != K:
+            raise ValueError(f"theta must have {K} columns")
+        P = theta.shape[0]
+        if noise is not None:
+            noise = self._dev(noise, torch.float64, "noise", (self.info["n_noise"],))
+        dev = self.torch_device
+        S = chains_per_param * samples_per_chain
+        nwq = (self.info["n_qubits"] + 63) // 64
+        i64 = torch.int64
+        samples = torch.empty((P, S, nwq), dtype=i64, device=dev)
+        states = torch.empty((P, S, self.info["n_words"]), dtype=i64, device=dev) if want_states else None
+        edges_t = None
+        if cost_edges is not None and len(cost_edges):
+            edges_t = self._dev(torch.as_tensor(cost_edges, dtype=torch.int32).reshape(-1, 2), torch.int32, "edges")
+            if int(edges_t.min()) < 0 or int(edges_t.max()) >= self.info["n_qubits"]:
+                raise ValueError("cost edges must name qubits")
+        cost = torch.empty((P, S), dtype=torch.float64, device=dev) if want_cost else None
+        if want_cost and edges_t is None:
+            raise ValueError("want_cost needs cost_edges")
+        rounds = torch.empty(P * chains_per_param, dtype=i64, device=dev) if want_rounds else None
+        cfg = L.SampleCfg(int(chains_per_param), int(samples_per_chain), int(burn_in), int(thin),
+                          int(seed) & ((1 << 64) - 1), 0 if edges_t is None else int(edges_t.shape[0]), 0,
+                          None if edges_t is None else edges_t.data_ptr())
+        ws = self.workspace(dtype, P * chains_per_param, L.AC_OP_SAMPLE)
+        L.check(L.lib().ac_sample(self._h, code, _ptr(theta), P, _ptr(noise), ctypes.byref(cfg),
+                                  _ptr(samples), _ptr(states), _ptr(cost), _ptr(rounds), _ptr(ws),
+                                  ws.numel(), self._stream()))
+        return dict(samples=samples, states=states, cost=cost, rounds=rounds)
+
+
+class ACAmplitude(torch.autograd.Function):
+    """f = AC(evidence; theta[param_of]) with a hand-written adjoint backward."""
+
+    @staticmethod
+    def forward(ctx, theta, graph: ACGraph, evidence, param_of, dtype, noise):
+        amp, _ = graph.eval(theta.detach(), evidence, param_of, noise, dtype, prob=False)
+        ctx.graph, ctx.dtype = graph, dtype
+        ctx.save_for_backward(theta.detach(), evidence, param_of)
+        ctx.noise = noise
+        return amp
+
+    @staticmethod
+    def backward(ctx, grad_amp):
+        theta, evidence, param_of = ctx.saved_tensors
+        out = ctx.graph.grad(theta, evidence, param_of, mode="cotangent",
+                             cotangent=grad_amp.contiguous(), noise=ctx.noise, dtype=ctx.dtype)
+        g = out["grad"].to(theta.dtype).reshape(theta.shape)
+        return g, None, None, None, None, None
+
+
+def amplitudes(graph: ACGraph, theta: torch.Tensor, evidence, param_of=None, dtype="c64", noise=None):
+    """Differentiable amplitudes (theta may require grad)."""
+    if param_of is None:
+        param_of = torch.zeros(evidence.shape[0], dtype=torch.int32, device=graph.torch_device)
+    return ACAmplitude.apply(theta, graph, evidence, param_of, dtype, noise)

@@ -1,0 +1,67 @@
+"""Serialise a compiled AC into the versioned binary blob that ``ac_load``
+parses (layout documented in include/qkc.h).
+
+Slots are reordered so that the angle-dependent ones come first; the
+library evaluates those per batch element and the others once per call.
+"""
+from __future__ import annotations
+
+import struct
+
+import numpy as np
+
+from .compiler import (CompiledAC, TAG_SHIFT, TAG_SLOT, ANGLE_BASES)
+
+MAGIC = b"QKCAC\x00\x00\x01"
+VERSION = 1
+HEADER_FMT = "<8sIIIIIIIIIIIIII"     # magic + 14 u32
+SLOT_FMT = "<BBHiddd"                # base, coef, pad, index, scale, re, im
+
+
+def _align8(buf: bytearray):
+    while len(buf) % 8:
+        buf.append(0)
+
+
+def to_blob(ac: CompiledAC) -> bytes:
+    # angle slots first
+    order = sorted(range(len(ac.slots)), key=lambda s: (0 if ac.slots[s].base in ANGLE_BASES else 1, s))
+    remap = np.zeros(len(ac.slots), dtype=np.uint32)
+    for new, old in enumerate(order):
+        remap[old] = new
+    slots = [ac.slots[o] for o in order]
+    n_angle_slots = sum(1 for s in slots if s.base in ANGLE_BASES)
+    col = ac.col.astype(np.uint32).copy()
+    is_slot = (col >> TAG_SHIFT) == TAG_SLOT
+    col[is_slot] = (np.uint32(TAG_SLOT) << np.uint32(TAG_SHIFT)) | remap[col[is_slot] & np.uint32((1 << TAG_SHIFT) - 1)]
+
+    n_vars = len(ac.var_dom)
+    hdr = struct.pack(HEADER_FMT, MAGIC, VERSION, 0, ac.n_qubits, n_vars, ac.n_words,
+                      ac.n_angles, ac.n_noise, len(slots), n_angle_slots, ac.n_internal,
+                      ac.n_edges, ac.n_levels, ac.root, 0)
+    buf = bytearray(hdr)
+    _align8(buf)
+    buf += np.asarray(ac.var_dom, dtype=np.uint8).tobytes()
+    buf += np.asarray(ac.var_kind, dtype=np.uint8).tobytes()
+    _align8(buf)
+    buf += np.asarray(ac.var_offset, dtype=np.uint32).tobytes()
+    _align8(buf)
+    buf += np.asarray(ac.noise_default, dtype=np.float64).tobytes()
+    for s in slots:
+        buf += struct.pack(SLOT_FMT, s.base, s.coef, 0, s.index, s.scale, s.re, s.im)
+    buf += ac.op.astype(np.uint8).tobytes()
+    _align8(buf)
+    buf += ac.row_ptr.astype(np.uint32).tobytes()
+    _align8(buf)
+    buf += col.tobytes()
+    _align8(buf)
+    buf += ac.level_ptr.astype(np.uint32).tobytes()
+    _align8(buf)
+    return bytes(buf)
+
+
+def blob_summary(blob: bytes) -> dict:
+    f = struct.unpack_from(HEADER_FMT, blob, 0)
+    keys = ["magic", "version", "flags", "n_qubits", "n_vars", "n_words", "n_angles", "n_noise",
+            "n_slots", "n_angle_slots", "n_int", "n_edges", "n_levels", "root", "reserved"]
+    return dict(zip(keys, f))

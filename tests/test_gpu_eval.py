@@ -1,0 +1,206 @@
+"""GPU parity of the upward pass (ac_eval_batch) against the oracle.
+
+Tolerances: complex128 |d amp| <= 1e-12; complex64 outcome probabilities
+within 1e-5 relative (see gpu_common.prob_ok).  Inputs are seeded (workloads);
+expected values come from the oracle's simulators or its path sum.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import pathsum, sim
+from tests.gpu_common import graph, note, oracle_amplitudes, prob_ok, require_gpu
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def test_noisy_bell_every_branch_c128():
+    note("noisy bell c128")
+    circ = W.noisy_bell(0.36)
+    g = graph(circ)
+    vals = np.array([[a, b, c] for c in (0, 1) for b in (0, 1) for a in (0, 1)])
+    ev = W.pack_evidence(circ, vals)
+    amp, prob = g.eval(np.zeros((1, 0)), ev, dtype="c128")
+    ref = oracle_amplitudes(circ, [], vals)
+    assert np.max(np.abs(amp.cpu().numpy() - ref)) <= 1e-12
+    # Table inference magnitudes: 1/sqrt2, 0.8/sqrt2, 0.6/sqrt2
+    got = {tuple(v): a for v, a in zip(vals.tolist(), amp.cpu().numpy())}
+    assert abs(abs(got[(1, 1, 1)]) - 0.6 / np.sqrt(2)) < 1e-15
+    assert np.allclose(prob.cpu().numpy(), np.abs(ref) ** 2, atol=1e-15)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_config1_all_amplitudes(dtype):
+    note(f"config 1 {dtype}")
+    cfg = W.config(1)
+    circ = cfg["circuit"]
+    g = graph(circ)
+    amp, prob = g.eval(cfg["theta"], cfg["evidence"], cfg["param_of"], dtype=dtype)
+    amp = amp.cpu().numpy().astype(np.complex128)
+    prob = prob.cpu().numpy()
+    ref = np.stack([sim.statevector(circ, th) for th in cfg["theta"]]).reshape(-1)
+    if dtype == "c128":
+        assert np.max(np.abs(amp - ref)) <= 1e-12
+    else:
+        for p in range(cfg["theta"].shape[0]):
+            ok, worst = prob_ok(prob[p * 16:(p + 1) * 16], np.abs(ref[p * 16:(p + 1) * 16]) ** 2)
+            assert ok, (p, worst)
+
+
+@pytest.mark.parametrize("B", [1, 63, 64, 65, 130, 1000])
+def test_ragged_batches_c128(B):
+    note(f"ragged B={B}")
+    cfg = W.config(1)
+    circ = cfg["circuit"]
+    g = graph(circ)
+    rng = np.random.default_rng(B)
+    P = 5
+    theta = W.uniform_angles(P, 2, 100 + B)
+    xs = rng.integers(0, 16, size=B)
+    param_of = rng.integers(0, P, size=B).astype(np.int32)        # unsorted on purpose
+    ev = W.pack_evidence(circ, np.stack([W.x_bits(x, 4) for x in xs]))
+    amp, _ = g.eval(theta, ev, param_of, dtype="c128")
+    sv = [sim.statevector(circ, th) for th in theta]
+    ref = np.array([sv[p][x] for p, x in zip(param_of, xs)])
+    assert np.max(np.abs(amp.cpu().numpy() - ref)) <= 1e-12
+
+
+def test_empty_batch_and_bad_arguments():
+    from paper_2103_17226_amd import _lib as L
+    cfg = W.config(1)
+    g = graph(cfg["circuit"])
+    amp, prob = g.eval(cfg["theta"][:2], np.zeros((0, 1), dtype=np.uint64),
+                       np.zeros(0, dtype=np.int32), dtype="c64")
+    assert amp.numel() == 0
+    with pytest.raises(ValueError):
+        g.eval(cfg["theta"][:2], cfg["evidence"][:4], np.array([0, 1, 2, 0], dtype=np.int32))
+    with pytest.raises(L.ACError) as e:
+        ws = torch.empty(16, dtype=torch.uint8, device="cuda")
+        ev = torch.zeros((4, 1), dtype=torch.int64, device="cuda")
+        po = torch.zeros(4, dtype=torch.int32, device="cuda")
+        th = torch.zeros((1, 2), dtype=torch.float64, device="cuda")
+        out = torch.empty(4, dtype=torch.complex64, device="cuda")
+        L.check(L.lib().ac_eval_batch(g._h, 0, th.data_ptr(), 1, None, po.data_ptr(), ev.data_ptr(), 4,
+                                      out.data_ptr(), None, ws.data_ptr(), 16, None))
+    assert e.value.status == L.AC_ERR_INVALID_ARG
+
+
+def test_config2_amplitudes_seeded_subset():
+    note("config 2 subset")
+    cfg = W.config(2, small=True)
+    circ = cfg["circuit"]
+    g = graph(circ)
+    rng = np.random.default_rng(W.sub_seed("evidence", 2))
+    P, M = 4, 96
+    theta = cfg["theta"][:P]
+    xb = rng.integers(0, 2, size=(P * M, circ.n))
+    kk = W.sample_channel_prior(circ, P * M, rng)
+    kk[::7] = rng.integers(0, 4, size=kk[::7].shape)       # plenty of non-identity branches
+    vals = np.concatenate([xb, kk], axis=1)
+    ev = W.pack_evidence(circ, vals)
+    param_of = np.repeat(np.arange(P, dtype=np.int32), M)
+    ref = np.concatenate([oracle_amplitudes(circ, theta[p], vals[p * M:(p + 1) * M]) for p in range(P)])
+    a128, _ = g.eval(theta, ev, param_of, dtype="c128")
+    assert np.max(np.abs(a128.cpu().numpy() - ref)) <= 1e-12
+    _, p64 = g.eval(theta, ev, param_of, dtype="c64")
+    p64 = p64.cpu().numpy()
+    for p in range(P):
+        ok, worst = prob_ok(p64[p * M:(p + 1) * M], np.abs(ref[p * M:(p + 1) * M]) ** 2)
+        note(f"  param {p}: worst rel err {worst:.2e}")
+        assert ok
+
+
+def test_config3_amplitudes_seeded_subset():
+    note("config 3 subset")
+    cfg = W.config(3, small=True)
+    circ = cfg["circuit"]
+    g = graph(circ)
+    B = cfg["evidence"].shape[0]
+    a128, _ = g.eval(cfg["theta"], cfg["evidence"], cfg["param_of"], dtype="c128")
+    _, p64 = g.eval(cfg["theta"], cfg["evidence"], cfg["param_of"], dtype="c64")
+    a128 = a128.cpu().numpy()
+    p64 = p64.cpu().numpy()
+    vals = W.unpack_evidence(circ, cfg["evidence"])
+    rng = np.random.default_rng(7)
+    pick = np.sort(rng.choice(B, size=12, replace=False))
+    ref = np.array([oracle_amplitudes(circ, cfg["theta"][cfg["param_of"][b]], vals[b:b + 1])[0] for b in pick])
+    assert np.max(np.abs(a128[pick] - ref)) <= 1e-12
+    # complex64 vs complex128 on the whole batch (per-result error report)
+    p128 = np.abs(a128) ** 2
+    ok, worst = prob_ok(p64, p128)
+    note(f"  c64 vs c128 worst rel err {worst:.2e}")
+    assert ok
+
+
+def test_config4_amplitudes_path_sum_n20():
+    note("qaoa p=1 n=20 vs path sum")
+    n = 20
+    edges = W.random_regular_graph(n, 3, 404)
+    circ = W.qaoa_maxcut(n, edges, 1)
+    g = graph(circ)
+    rng = np.random.default_rng(4)
+    theta = W.uniform_angles(6, 2, 41)
+    xs = rng.integers(0, 1 << n, size=6)
+    ev = W.pack_evidence(circ, np.stack([W.x_bits(int(x), n) for x in xs]))
+    po = np.arange(6, dtype=np.int32)
+    a128, _ = g.eval(theta, ev, po, dtype="c128")
+    ref = np.array([pathsum.qaoa_p1_amplitude(n, edges, int(x), [t[0]], [t[1]])[0] for x, t in zip(xs, theta)])
+    assert np.max(np.abs(a128.cpu().numpy() - ref)) <= 1e-12
+
+
+def test_config4_amplitudes_golden_n32():
+    path = os.path.join(GOLD, "qaoa_n32_p1_pathsum.json")
+    gold = json.load(open(path))
+    note("qaoa p=1 n=32 vs stored path sums")
+    cfg = W.config(4, small=True)
+    circ = cfg["circuit"]
+    assert [list(e) for e in circ.edges] == gold["edges"]
+    g = graph(circ)
+    theta = np.array(gold["theta"])
+    xs = [int(x) for x in gold["x"]]
+    ev = W.pack_evidence(circ, np.stack([W.x_bits(x, 32) for x in xs]))
+    po = np.array(gold["param"], dtype=np.int32)
+    ref = np.array(gold["amp_re"]) + 1j * np.array(gold["amp_im"])
+    a128, _ = g.eval(theta, ev, po, dtype="c128")
+    assert np.max(np.abs(a128.cpu().numpy() - ref)) <= 1e-12
+    _, p64 = g.eval(theta, ev, po, dtype="c64")
+    ok, worst = prob_ok(p64.cpu().numpy(), np.abs(ref) ** 2)
+    note(f"  c64 worst rel err {worst:.2e}")
+    assert ok
+
+
+def test_noise_override_matches_oracle():
+    note("noise vector override")
+    circ = W.qaoa_maxcut(3, W.ring_graph(3), 1, dep=0.05, ad=0.02)
+    g = graph(circ)
+    rng = np.random.default_rng(12)
+    vals = np.concatenate([rng.integers(0, 2, size=(40, 3)),
+                           rng.integers(0, 2, size=(40, len(circ.channels())))], axis=1)
+    ev = W.pack_evidence(circ, vals)
+    th = np.array([[0.4, 1.9]])
+    noise = np.array([0.2, 0.1])
+    amp, _ = g.eval(th, ev, dtype="c128", noise=noise)
+    ref = np.array([sim.amplitude(circ, th[0], W.x_index(v[:3]), v[3:], noise=noise) for v in vals])
+    assert np.max(np.abs(amp.cpu().numpy() - ref)) <= 1e-12
+
+
+def test_eval_is_deterministic():
+    cfg = W.config(2, small=True)
+    g = graph(cfg["circuit"])
+    rng = np.random.default_rng(1)
+    vals = np.concatenate([rng.integers(0, 2, size=(500, 8)), np.zeros((500, 76), dtype=int)], axis=1)
+    ev = W.pack_evidence(cfg["circuit"], vals)
+    po = rng.integers(0, 16, size=500).astype(np.int32)
+    a1, _ = g.eval(cfg["theta"], ev, po)
+    a2, _ = g.eval(cfg["theta"], ev, po)
+    assert torch.equal(a1, a2)

@@ -1,0 +1,182 @@
+"""GPU parity of the downward pass and gradients (ac_grad_batch).
+
+Expected derivatives come from the oracle's product rule (exact), the
+parameter-shift rule on the density matrix, and finite differences.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import grad as ograd
+from oracle import sim
+from tests.gpu_common import graph, note, oracle_amplitudes, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _tiny():
+    ops = [("H", 0), ("H", 1), ("CNOT", 0, 1), ("DEP", 1, 0), ("RZ", 1, 0, 2.0), ("AD", 0, 1),
+           ("CNOT", 0, 1), ("RX", 0, 1, 2.0), ("PD", 1, 2), ("RX", 1, 1, 2.0), ("DEP", 0, 0),
+           ("RZ", 0, 2, 2.0), ("RX", 1, 3, 2.0)]
+    return W.Circuit(n=2, ops=ops, n_angles=4, noise=[0.07, 0.2, 0.3], edges=[(0, 1)])
+
+
+def _all_states(circ):
+    import itertools
+    return np.array(list(itertools.product(*[range(d) for d in circ.var_domains()])))
+
+
+def test_dfdtheta_matches_product_rule_c128():
+    note("dfdtheta vs product rule")
+    circ = _tiny()
+    g = graph(circ)
+    vals = _all_states(circ)
+    vals = vals[:, list(range(circ.n)) + list(range(circ.n, vals.shape[1]))]
+    theta = np.array([[0.3, 1.1, 2.2, 0.6], [2.9, 0.2, 1.4, 5.0]])
+    B = len(vals)
+    ev = np.concatenate([W.pack_evidence(circ, vals)] * 2)
+    po = np.repeat(np.arange(2, dtype=np.int32), B)
+    cot = np.ones(2 * B, dtype=np.complex128)
+    out = g.grad(theta, ev, po, mode="cotangent", cotangent=cot, dtype="c128", want_amp=True,
+                 want_dfdtheta=True, want_dind=True)
+    dft = out["dfdtheta"].cpu().numpy()
+    amp = out["amp"].cpu().numpy()
+    for p in range(2):
+        for i, v in enumerate(vals):
+            b = p * B + i
+            k = v[circ.n:]
+            x = W.x_index(v[:circ.n])
+            ref = ograd.amplitude_grad(circ, theta[p], k)[:, x]
+            assert np.max(np.abs(dft[b] - ref)) <= 1e-12
+            assert abs(amp[b] - sim.amplitude(circ, theta[p], x, k)) <= 1e-12
+
+
+def test_indicator_derivatives_are_neighbour_amplitudes_c128():
+    # multilinearity: df/dlambda_{v=u} at s equals f(s with v set to u)
+    note("dind vs neighbour amplitudes")
+    cfg = W.config(2, small=True)
+    circ = cfg["circuit"]
+    g = graph(circ)
+    rng = np.random.default_rng(3)
+    vals = np.concatenate([rng.integers(0, 2, size=(6, circ.n)),
+                           W.sample_channel_prior(circ, 6, rng)], axis=1)
+    vals[0, circ.n + 3] = 2
+    theta = cfg["theta"][:1]
+    ev = W.pack_evidence(circ, vals)
+    out = g.grad(theta, ev, mode="cotangent", cotangent=np.ones(6, complex), dtype="c128", want_dind=True)
+    dind = out["dind"].cpu().numpy()
+    doms = circ.var_domains()
+    base = np.concatenate([[0], np.cumsum(doms)])
+    cache = {}
+    for b in range(6):
+        for v in list(range(circ.n)) + [circ.n, circ.n + 3, circ.n + 40, len(doms) - 1]:
+            for u in range(doms[v]):
+                s = vals[b].copy()
+                s[v] = u
+                ref = oracle_amplitudes(circ, theta[0], s[None, :], cache)[0]
+                assert abs(dind[b, base[v] + u] - ref) <= 1e-12
+
+
+def test_grad_modes_and_unsorted_reduction_c128():
+    note("grad modes")
+    circ = _tiny()
+    g = graph(circ)
+    rng = np.random.default_rng(8)
+    P, B = 3, 300
+    theta = W.uniform_angles(P, 4, 77)
+    states = _all_states(circ)
+    vals = states[rng.integers(0, len(states), size=B)]
+    ev = W.pack_evidence(circ, vals)
+    po = rng.integers(0, P, size=B).astype(np.int32)
+    w = rng.uniform(0.1, 2.0, size=B)
+    cot = rng.normal(size=B) + 1j * rng.normal(size=B)
+    f = np.zeros(B, complex)
+    df = np.zeros((B, 4), complex)
+    for b in range(B):
+        k = vals[b, circ.n:]
+        x = W.x_index(vals[b, :circ.n])
+        f[b] = sim.amplitude(circ, theta[po[b]], x, k)
+        df[b] = ograd.amplitude_grad(circ, theta[po[b]], k)[:, x]
+    for mode in ("cotangent", "prob", "logprob"):
+        if mode == "cotangent":
+            gb = cot
+        elif mode == "prob":
+            gb = 2 * w * f
+        else:
+            m2 = np.abs(f) ** 2
+            gb = np.where(m2 > 0, 2 * w * f / np.where(m2 > 0, m2, 1), 0)
+        contrib = np.real(gb[:, None] * np.conj(df))
+        ref = np.zeros((P, 4))
+        for b in range(B):
+            ref[po[b]] += contrib[b]
+        out = g.grad(theta, ev, po, mode=mode, cotangent=cot, weight=w, dtype="c128")
+        assert np.allclose(out["grad"].cpu().numpy(), ref, atol=1e-11, rtol=1e-11), mode
+        out2 = g.grad(theta, ev, po, mode=mode, cotangent=cot, weight=w, dtype="c128")
+        assert torch.equal(out["grad"], out2["grad"])          # fixed-order reduction
+
+
+def test_expected_cost_gradient_matches_parameter_shift():
+    # d<C>/dtheta = sum over (x, k) of C(x) d|f|^2/dtheta: PROB mode over every state
+    note("<C> gradient vs parameter shift")
+    circ = _tiny()
+    g = graph(circ)
+    states = _all_states(circ)
+    ev = W.pack_evidence(circ, states)
+    C = W.maxcut_cost(circ.edges, states[:, :circ.n]).astype(float)
+    theta = np.array([[0.8, 0.25, 1.9, 2.7]])
+    out = g.grad(theta, ev, mode="prob", weight=C, dtype="c128")
+    ps = ograd.expected_cost_param_shift(circ, theta[0])
+    assert np.allclose(out["grad"].cpu().numpy()[0], ps, atol=1e-12)
+    out64 = g.grad(theta, ev, mode="prob", weight=C, dtype="c64")
+    assert np.allclose(out64["grad"].cpu().numpy()[0], ps, rtol=1e-5, atol=1e-6)
+
+
+def test_config3_weighted_loss_gradient_vs_finite_difference():
+    # L(theta) = sum_s C(x_s) |f_theta(s)|^2 over seeded (x, k); central FD of
+    # the oracle's complex128 amplitudes
+    note("config 3 gradient vs FD")
+    cfg = W.config(3, small=True)
+    circ = cfg["circuit"]
+    g = graph(circ)
+    M = 64
+    ev = cfg["evidence"][:2 * M]
+    po = cfg["param_of"][:2 * M]
+    theta = cfg["theta"][:2]
+    vals = W.unpack_evidence(circ, ev)
+    C = W.maxcut_cost(circ.edges, vals[:, :circ.n]).astype(float)
+    pick = np.arange(0, 2 * M, 9)
+    out = g.grad(theta, ev[pick], po[pick], mode="prob", weight=C[pick], dtype="c128")
+    out64 = g.grad(theta, ev[pick], po[pick], mode="prob", weight=C[pick], dtype="c64")
+    for p in range(2):
+        sel = pick[po[pick] == p]
+
+        def loss(t):
+            a = oracle_amplitudes(circ, t, vals[sel])
+            return float(np.sum(C[sel] * np.abs(a) ** 2))
+        fd = ograd.central_difference(loss, theta[p], h=1e-6)
+        got = out["grad"].cpu().numpy()[p]
+        scale = max(1e-12, np.max(np.abs(fd)))
+        assert np.max(np.abs(got - fd)) <= 1e-6 * scale + 1e-14, (got, fd)
+        got64 = out64["grad"].cpu().numpy()[p]
+        assert np.max(np.abs(got64 - got)) <= 1e-4 * scale + 1e-12
+
+
+def test_autograd_gradcheck_c128():
+    note("torch gradcheck")
+    from paper_2103_17226_amd.api import amplitudes
+    circ = _tiny()
+    g = graph(circ)
+    states = _all_states(circ)[:24]
+    ev = torch.as_tensor(W.pack_evidence(circ, states).view(np.int64), device="cuda")
+    po = torch.zeros(len(states), dtype=torch.int32, device="cuda")
+    theta = torch.tensor([[0.3, 1.1, 2.2, 0.6]], dtype=torch.float64, device="cuda", requires_grad=True)
+
+    def fn(t):
+        return amplitudes(g, t, ev, po, dtype="c128")
+    assert torch.autograd.gradcheck(fn, (theta,), eps=1e-6, atol=1e-8)
