@@ -95,7 +95,7 @@ class ACGraph:
             raise ValueError(f"{name}: expected shape {tuple(shape)}, got {tuple(t.shape)}")
         return t
 
-    def _inputs(self, theta, evidence, param_of, noise):
+    def _inputs(self, theta, evidence, param_of, noise, validate=True):
         K = self.info["n_angles"]
         theta = self._dev(theta, torch.float64, "theta")
         if theta.dim() == 1:
@@ -115,19 +115,22 @@ class ACGraph:
                 raise ValueError("param_of is required when theta has more than one row")
             param_of = torch.zeros(B, dtype=torch.int32, device=self.torch_device)
         param_of = self._dev(param_of, torch.int32, "param_of", (B,))
-        if B > 0 and (int(param_of.min()) < 0 or int(param_of.max()) >= P):
+        if validate and B > 0 and (int(param_of.min()) < 0 or int(param_of.max()) >= P):
             raise ValueError("param_of entries must lie in [0, P)")
         if noise is not None:
             noise = self._dev(noise, torch.float64, "noise", (self.info["n_noise"],))
-            if noise.numel() and (float(noise.min()) < 0.0 or float(noise.max()) > 1.0):
+            if validate and noise.numel() and (float(noise.min()) < 0.0 or float(noise.max()) > 1.0):
                 raise ValueError("noise strengths must lie in [0, 1]")
         return theta, evidence, param_of, noise, P, B
 
     # ------------------------------------------------------------- queries
-    def eval(self, theta, evidence, param_of=None, noise=None, dtype: str = "c64", prob: bool = True):
-        """Amplitudes f(evidence[b]; theta[param_of[b]]) and optionally |f|^2 (FP64)."""
+    def eval(self, theta, evidence, param_of=None, noise=None, dtype: str = "c64", prob: bool = True,
+             validate: bool = True):
+        """Amplitudes f(evidence[b]; theta[param_of[b]]) and optionally |f|^2 (FP64).
+        validate=False skips the host-side range checks of param_of and noise
+        (they synchronise with the device); only for inputs known to be valid."""
         code, cdt = _CDTYPE[dtype]
-        theta, evidence, param_of, noise, P, B = self._inputs(theta, evidence, param_of, noise)
+        theta, evidence, param_of, noise, P, B = self._inputs(theta, evidence, param_of, noise, validate)
         amp = torch.empty(B, dtype=cdt, device=self.torch_device)
         pr = torch.empty(B, dtype=torch.float64, device=self.torch_device) if prob else None
         ws = self.workspace(dtype, B, L.AC_OP_EVAL)
@@ -138,10 +141,10 @@ class ACGraph:
 
     def grad(self, theta, evidence, param_of=None, mode: str = "cotangent", cotangent=None,
              weight=None, noise=None, dtype: str = "c64", want_amp=False, want_dfdtheta=False,
-             want_dind=False):
+             want_dind=False, validate: bool = True):
         """Gradient in theta of a loss of the amplitudes (see ac_grad_batch)."""
         code, cdt = _CDTYPE[dtype]
-        theta, evidence, param_of, noise, P, B = self._inputs(theta, evidence, param_of, noise)
+        theta, evidence, param_of, noise, P, B = self._inputs(theta, evidence, param_of, noise, validate)
         m = {"cotangent": L.AC_GRAD_COTANGENT, "prob": L.AC_GRAD_PROB, "logprob": L.AC_GRAD_LOGPROB}[mode]
         cot = self._dev(cotangent, cdt, "cotangent", (B,)) if m == L.AC_GRAD_COTANGENT else None
         w = self._dev(weight, torch.float64, "weight", (B,)) if m != L.AC_GRAD_COTANGENT else None
@@ -159,7 +162,8 @@ class ACGraph:
 
     def sample(self, theta, chains_per_param: int, samples_per_chain: int = 1, burn_in: int = 20,
                thin: int = 1, seed: int = 1, cost_edges: Optional[Sequence] = None, noise=None,
-               dtype: str = "c64", want_states=False, want_cost=False, want_rounds=False):
+               dtype: str = "c64", want_states=False, want_cost=False, want_rounds=False,
+               validate: bool = True):
         """Gibbs samples of the output bits (see ac_sample)."""
         code, _ = _CDTYPE[dtype]
         K = self.info["n_angles"]
@@ -180,7 +184,7 @@ class ACGraph:
         edges_t = None
         if cost_edges is not None and len(cost_edges):
             edges_t = self._dev(torch.as_tensor(cost_edges, dtype=torch.int32).reshape(-1, 2), torch.int32, "edges")
-            if int(edges_t.min()) < 0 or int(edges_t.max()) >= self.info["n_qubits"]:
+            if validate and (int(edges_t.min()) < 0 or int(edges_t.max()) >= self.info["n_qubits"]):
                 raise ValueError("cost edges must name qubits")
         cost = torch.empty((P, S), dtype=torch.float64, device=dev) if want_cost else None
         if want_cost and edges_t is None:

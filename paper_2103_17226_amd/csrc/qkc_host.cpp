@@ -372,7 +372,7 @@ namespace {
 
 constexpr size_t WS_CAP = static_cast<size_t>(48) << 30;   // cap on per-call tile buffers
 constexpr size_t LDS_LIMIT = 64 * 1024;                     // dynamic LDS per workgroup
-constexpr int WG_PER_CU = 2;
+constexpr int WG_PER_CU = 4;
 
 struct Layout {
     size_t wfix_off = 0, contrib_off = 0, tiles_off = 0, total = 0;

@@ -135,24 +135,35 @@ struct Tile {
         return slot(r & REF_MASK);
     }
 
+    // Sum nodes accumulate in FP64 (for the complex64 path too: wide sums
+    // would otherwise lose ~k * 2^-24 relative accuracy); products run in T.
     __device__ __forceinline__ cplx<T> eval_node(uint32_t i) const {
         const uint32_t e0 = g.row_ptr[i], e1 = g.row_ptr[i + 1];
-        const bool is_sum = g.op[i] == 0;
-        cplx<T> acc = is_sum ? cplx<T>{T(0), T(0)} : cplx<T>{T(1), T(0)};
+        if (g.op[i] == 0) {
+            double sr = 0.0, si = 0.0;
+            for (uint32_t e = e0; e < e1; ++e) {
+                const uint32_t r = g.col[e];
+                const uint32_t tag = r >> 30;
+                if (tag == TAG_IND) {
+                    sr += ind_hit(r) ? 1.0 : 0.0;
+                    continue;
+                }
+                const cplx<T> v = (tag == TAG_NODE) ? val[(r & REF_MASK) * WAVE + lane] : slot(r & REF_MASK);
+                sr += static_cast<double>(v.re);
+                si += static_cast<double>(v.im);
+            }
+            return {static_cast<T>(sr), static_cast<T>(si)};
+        }
+        cplx<T> acc{T(1), T(0)};
         for (uint32_t e = e0; e < e1; ++e) {
             const uint32_t r = g.col[e];
             const uint32_t tag = r >> 30;
             if (tag == TAG_IND) {
-                bool hit = ind_hit(r);
-                if (is_sum) {
-                    acc.re += hit ? T(1) : T(0);
-                } else if (!hit) {
-                    acc = {T(0), T(0)};
-                }
+                if (!ind_hit(r)) acc = {T(0), T(0)};
                 continue;
             }
-            cplx<T> v = (tag == TAG_NODE) ? val[(r & REF_MASK) * WAVE + lane] : slot(r & REF_MASK);
-            acc = is_sum ? cadd(acc, v) : cmul(acc, v);
+            const cplx<T> v = (tag == TAG_NODE) ? val[(r & REF_MASK) * WAVE + lane] : slot(r & REF_MASK);
+            acc = cmul(acc, v);
         }
         return acc;
     }
@@ -191,18 +202,20 @@ struct Tile {
         for (int l = g.L - 1; l >= 0; --l) {
             const uint32_t n0 = g.level_ptr[l], n1 = g.level_ptr[l + 1];
             for (uint32_t c = n0 + wave; c < n1; c += nwaves) {
-                cplx<T> a{T(0), T(0)};
+                double ar = 0.0, ai = 0.0;
                 if (c == static_cast<uint32_t>(g.root)) {
-                    a = {T(1), T(0)};
+                    ar = 1.0;
                 } else {
                     const uint32_t q0 = g.par_ptr[c], q1 = g.par_ptr[c + 1];
                     for (uint32_t q = q0; q < q1; ++q) {
                         const uint32_t e = g.par_edge[q];
                         const uint32_t p = g.edge_parent[e];
-                        a = cadd(a, cmul(adj[p * WAVE + lane], sibling_product(p, e)));
+                        const cplx<T> t = cmul(adj[p * WAVE + lane], sibling_product(p, e));
+                        ar += static_cast<double>(t.re);
+                        ai += static_cast<double>(t.im);
                     }
                 }
-                adj[c * WAVE + lane] = a;
+                adj[c * WAVE + lane] = {static_cast<T>(ar), static_cast<T>(ai)};
             }
             __syncthreads();
         }
@@ -210,14 +223,16 @@ struct Tile {
 
     // d root / d leaf (leaf index: indicators first, then slots)
     __device__ __forceinline__ cplx<T> leaf_adjoint(const cplx<T> *adj, uint32_t li) const {
-        cplx<T> a{T(0), T(0)};
+        double ar = 0.0, ai = 0.0;
         const uint32_t q0 = g.leaf_ptr[li], q1 = g.leaf_ptr[li + 1];
         for (uint32_t q = q0; q < q1; ++q) {
             const uint32_t e = g.leaf_edge[q];
             const uint32_t p = g.edge_parent[e];
-            a = cadd(a, cmul(adj[p * WAVE + lane], sibling_product(p, e)));
+            const cplx<T> t = cmul(adj[p * WAVE + lane], sibling_product(p, e));
+            ar += static_cast<double>(t.re);
+            ai += static_cast<double>(t.im);
         }
-        return a;
+        return {static_cast<T>(ar), static_cast<T>(ai)};
     }
 };
 
