@@ -98,6 +98,8 @@ typedef struct {
     int32_t root;              /* internal index of the root                     */
     int32_t device;
     int64_t n_prod_flops;      /* real flops of one upward pass (complex ops)  */
+    int32_t n_selectors;       /* selector leaves                               */
+    int32_t reserved;
 } ac_info_t;
 
 /*
@@ -105,26 +107,34 @@ typedef struct {
  * and copy it to `device`.  The caller keeps ownership of `blob` and may free
  * it on return; the library owns the device copy until ac_free.
  *
- * Blob layout (little endian; every array starts on an 8-byte boundary):
- *   header   8-byte magic "QKCAC\0\0\1", then 14 uint32: version(=1), flags,
+ * Blob layout (little endian; every array starts on an 8-byte boundary
+ * unless marked "packed", which follows the previous array directly):
+ *   header   8-byte magic "QKCAC\0\0\1", then 14 uint32: version(=2), flags,
  *            n_qubits, n_vars, n_words, n_angles, n_noise, n_slots,
- *            n_angle_slots, n_internal, n_edges, n_levels, root, reserved
- *   uint8    var_dom[n_vars]; uint8 var_kind[n_vars] (0 output, 1 depolarizing,
- *            2 amplitude damping, 3 phase damping)
+ *            n_angle_slots, n_internal, n_edges, n_levels, root, n_selectors
+ *   uint8    var_dom[n_vars]; uint8 var_kind[n_vars] (packed; 0 output,
+ *            1 depolarizing, 2 amplitude damping, 3 phase damping)
  *   uint32   var_offset[n_vars]         bit offset of each evidence field
  *   float64  noise_default[n_noise]
- *   slot     [n_slots] of 32 bytes {u8 base, u8 coef, u16 0, i32 index,
+ *   slot     [n_slots] of 32 bytes (packed) {u8 base, u8 coef, u16 0, i32 index,
  *            f64 scale, f64 re, f64 im}; value = coef * base where
  *            coef in {1, -1, i, -i} and base is one of: const (re + i im),
  *            cos(scale*theta[index]/2), sin(..), exp(-i scale theta[index]/2),
  *            exp(+i ..), sqrt(1 - noise[index]), sqrt(noise[index]/3),
  *            sqrt(noise[index]).  The first n_angle_slots depend on theta.
- *   uint8    op[n_internal]             0 = sum, 1 = product
+ *   selector [n_selectors] of 5 uint32 (packed) {variable v, slot[4]}: the leaf
+ *            sum_u lambda_{v=u} * W[slot[u]] (slot 0xFFFFFFFF: zero), i.e. the
+ *            weight of v's current value; v is a noise event with at most 4
+ *            values and the slots do not depend on theta.  It is the
+ *            compiled form of a channel's Kraus entry (Sec. 3.1: the event's
+ *            table holds the Kraus amplitudes).
+ *   uint8    op[n_internal] (packed)    0 = sum, 1 = product
  *   uint32   row_ptr[n_internal + 1]    CSR over child references
  *   uint32   col[n_edges]               child reference: bits 31..30 tag,
  *            tag 0 = internal node index (bits 29..0),
  *            tag 1 = indicator, variable in bits 23..0, value in bits 29..24,
- *            tag 2 = weight slot index (bits 29..0)
+ *            tag 2 = weight slot index (bits 29..0),
+ *            tag 3 = selector index (bits 29..0)
  *   uint32   level_ptr[n_levels + 1]    nodes are sorted by level; level l
  *            holds [level_ptr[l-1], level_ptr[l]) and every internal child
  *            of a node lies on a lower level.

@@ -31,7 +31,8 @@ class ACInfo(ctypes.Structure):
                 ("n_edges", ctypes.c_int64), ("n_levels", ctypes.c_int32),
                 ("max_level_width", ctypes.c_int32), ("n_indicator_leaves", ctypes.c_int32),
                 ("root", ctypes.c_int32), ("device", ctypes.c_int32),
-                ("n_prod_flops", ctypes.c_int64)]
+                ("n_prod_flops", ctypes.c_int64), ("n_selectors", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -10,10 +10,10 @@ import struct
 
 import numpy as np
 
-from .compiler import (CompiledAC, TAG_SHIFT, TAG_SLOT, ANGLE_BASES)
+from .compiler import ANGLE_BASES, NO_SLOT, TAG_SHIFT, TAG_SLOT, CompiledAC
 
 MAGIC = b"QKCAC\x00\x00\x01"
-VERSION = 1
+VERSION = 2
 HEADER_FMT = "<8sIIIIIIIIIIIIII"     # magic + 14 u32
 SLOT_FMT = "<BBHiddd"                # base, coef, pad, index, scale, re, im
 
@@ -38,7 +38,7 @@ def to_blob(ac: CompiledAC) -> bytes:
     n_vars = len(ac.var_dom)
     hdr = struct.pack(HEADER_FMT, MAGIC, VERSION, 0, ac.n_qubits, n_vars, ac.n_words,
                       ac.n_angles, ac.n_noise, len(slots), n_angle_slots, ac.n_internal,
-                      ac.n_edges, ac.n_levels, ac.root, 0)
+                      ac.n_edges, ac.n_levels, ac.root, len(ac.selectors))
     buf = bytearray(hdr)
     _align8(buf)
     buf += np.asarray(ac.var_dom, dtype=np.uint8).tobytes()
@@ -49,6 +49,10 @@ def to_blob(ac: CompiledAC) -> bytes:
     buf += np.asarray(ac.noise_default, dtype=np.float64).tobytes()
     for s in slots:
         buf += struct.pack(SLOT_FMT, s.base, s.coef, 0, s.index, s.scale, s.re, s.im)
+    for v, sl in ac.selectors:
+        ent = [0xFFFFFFFF if x == NO_SLOT else int(remap[x]) for x in sl]
+        ent += [0xFFFFFFFF] * (4 - len(ent))
+        buf += struct.pack("<5I", v, *ent)
     buf += ac.op.astype(np.uint8).tobytes()
     _align8(buf)
     buf += ac.row_ptr.astype(np.uint32).tobytes()
@@ -63,5 +67,5 @@ def to_blob(ac: CompiledAC) -> bytes:
 def blob_summary(blob: bytes) -> dict:
     f = struct.unpack_from(HEADER_FMT, blob, 0)
     keys = ["magic", "version", "flags", "n_qubits", "n_vars", "n_words", "n_angles", "n_noise",
-            "n_slots", "n_angle_slots", "n_int", "n_edges", "n_levels", "root", "reserved"]
+            "n_slots", "n_angle_slots", "n_int", "n_edges", "n_levels", "root", "n_selectors"]
     return dict(zip(keys, f))

@@ -276,7 +276,8 @@ def to_cnf(bn: BayesNet) -> CNF:
 # ---------------------------------------------------------------------------
 
 OP_SUM, OP_PROD = 0, 1
-LEAF_IND, LEAF_SLOT = 2, 3
+LEAF_IND, LEAF_SLOT, LEAF_SEL = 2, 3, 4
+NO_SLOT = -1
 
 
 class ACBuilder:
@@ -300,16 +301,24 @@ class ACBuilder:
             self.memo[key] = nid
         return nid
 
-    def slot(self, s: Slot) -> int:
+    def slot_id(self, s: Slot) -> int:
         sid = self.slot_ids.get(s)
         if sid is None:
             sid = len(self.slots)
             self.slots.append(s)
             self.slot_ids[s] = sid
-        return self._get(LEAF_SLOT, (sid,))
+        return sid
+
+    def slot(self, s: Slot) -> int:
+        return self._get(LEAF_SLOT, (self.slot_id(s),))
 
     def indicator(self, var: int, val: int) -> int:
         return self._get(LEAF_IND, (var, val))
+
+    def selector(self, var: int, slots: Tuple[int, ...]) -> int:
+        """Leaf sum_u lambda_{var=u} * W[slots[u]] (NO_SLOT: zero entry).
+        For one-hot evidence it selects the weight of the variable's value."""
+        return self._get(LEAF_SEL, (var, tuple(slots)))
 
     def const_value(self, nid) -> Optional[complex]:
         if self.kind[nid] == LEAF_SLOT:
@@ -493,6 +502,7 @@ class CompiledAC:
     n_noise: int
     noise_default: List[float]
     slots: List[Slot]
+    selectors: List[Tuple[int, Tuple[int, ...]]]   # (variable, slot per value or NO_SLOT)
     op: np.ndarray                # uint8 [N_int]
     row_ptr: np.ndarray           # int32 [N_int + 1]
     col: np.ndarray               # uint32 [E] tagged child refs
@@ -517,6 +527,7 @@ class CompiledAC:
 TAG_NODE = 0
 TAG_IND = 1
 TAG_SLOT = 2
+TAG_SEL = 3
 TAG_SHIFT = 30
 IND_VAL_SHIFT = 24          # indicator ref: var in bits 0..23, value in bits 24..29
 
@@ -533,6 +544,10 @@ def ref_slot(s):
     return (TAG_SLOT << TAG_SHIFT) | s
 
 
+def ref_sel(q):
+    return (TAG_SEL << TAG_SHIFT) | q
+
+
 def _var_layout(doms):
     offs, pos = [], 0
     for d in doms:
@@ -544,8 +559,12 @@ def _var_layout(doms):
     return offs, max(1, (pos + 63) // 64)
 
 
-def compile_circuit(circ, flatten: bool = True) -> CompiledAC:
-    """Compile a circuit (op-list form) into a flat level-ordered AC."""
+def compile_circuit(circ, flatten: bool = True, selectors: bool = True) -> CompiledAC:
+    """Compile a circuit (op-list form) into a flat level-ordered AC.
+
+    selectors=True folds each channel's event indicators and Kraus entries
+    into selector leaves (one per matrix entry); False keeps them as sums of
+    indicator x weight products.  Both give the same polynomial."""
     bn = circuit_to_bn(circ)
     ac = ACBuilder()
 
@@ -593,6 +612,26 @@ def compile_circuit(circ, flatten: bool = True) -> CompiledAC:
         else:
             diagonal = False                                         # CNOT target flips
         pv = [var_of[p] for p in parents]
+        if nd.kind == "channel" and selectors:
+            # Kraus selection: the event's indicators and the Kraus entries
+            # E_k[j][i] fold into one selector leaf per (i, j) entry
+            ev_var = ev_index[parents[1]]
+            d = bn.nodes[parents[1]].dom
+            per_entry: Dict[Tuple[int, int], List[int]] = {}
+            for (a, k, b), e in nd.cat.items():
+                lst = per_entry.setdefault((a, b), [NO_SLOT] * d)
+                lst[k] = ac.slot_id(_const(1.0) if e is ONE else e)
+            if diagonal:
+                v = var_of[qin]
+                tab = {(a,): ac.selector(ev_var, tuple(lst)) for (a, b), lst in per_entry.items()}
+                fv = (v,)
+            else:
+                v = new_var(2)
+                tab = {(a, b): ac.selector(ev_var, tuple(lst)) for (a, b), lst in per_entry.items()}
+                fv = (pv[0], v)
+            var_of[i] = v
+            factors.append(Factor(fv, tab))
+            continue
         if diagonal:
             v = var_of[qin]
             var_of[i] = v
@@ -660,15 +699,15 @@ def compile_circuit(circ, flatten: bool = True) -> CompiledAC:
                              if op[0] in CHANNEL_KINDS]
     offs, W = _var_layout(var_dom)
     out = _flatten_and_level(ac, root, flatten)
-    op_arr, row_ptr, col, level_ptr, root_idx, slot_list = out
+    op_arr, row_ptr, col, level_ptr, root_idx, slot_list, sel_list = out
     res = CompiledAC(n_qubits=bn.n, var_dom=var_dom, var_kind=var_kind, var_offset=offs,
                      n_words=W, n_angles=circ.n_angles, n_noise=len(circ.noise),
-                     noise_default=list(circ.noise), slots=slot_list, op=op_arr,
-                     row_ptr=row_ptr, col=col, level_ptr=level_ptr, root=root_idx)
+                     noise_default=list(circ.noise), slots=slot_list, selectors=sel_list,
+                     op=op_arr, row_ptr=row_ptr, col=col, level_ptr=level_ptr, root=root_idx)
     res.stats = dict(bn_nodes=bn_node_count(bn), bn_events=len(bn.events),
                      fg_vars=nvar[0], max_table=max_table,
                      n_internal=res.n_internal, n_edges=res.n_edges, n_levels=res.n_levels,
-                     n_slots=len(slot_list))
+                     n_slots=len(slot_list), n_selectors=len(sel_list))
     return res
 
 
@@ -745,6 +784,14 @@ def _flatten_and_level(ac: ACBuilder, root, flatten: bool):
     # compact slot table: only slots referenced
     slot_map: Dict[int, int] = {}
     slot_list: List[Slot] = []
+    sel_map: Dict[int, int] = {}
+    sel_list: List[Tuple[int, Tuple[int, ...]]] = []
+
+    def slot_ref_id(sid):
+        if sid not in slot_map:
+            slot_map[sid] = len(slot_list)
+            slot_list.append(ac.slots[sid])
+        return slot_map[sid]
     op_arr = np.zeros(len(internal), dtype=np.uint8)
     row_ptr = np.zeros(len(internal) + 1, dtype=np.int32)
     cols: List[int] = []
@@ -758,12 +805,14 @@ def _flatten_and_level(ac: ACBuilder, root, flatten: bool):
             elif k == LEAF_IND:
                 v, val = data[c]
                 refs.append(ref_ind(v, val))
+            elif k == LEAF_SEL:
+                if c not in sel_map:
+                    v, sl = data[c]
+                    sel_map[c] = len(sel_list)
+                    sel_list.append((v, tuple(NO_SLOT if x == NO_SLOT else slot_ref_id(x) for x in sl)))
+                refs.append(ref_sel(sel_map[c]))
             else:
-                sid = data[c][0]
-                if sid not in slot_map:
-                    slot_map[sid] = len(slot_list)
-                    slot_list.append(ac.slots[sid])
-                refs.append(ref_slot(slot_map[sid]))
+                refs.append(ref_slot(slot_ref_id(data[c][0])))
         # internal children first (in index order), then leaves
         refs.sort(key=lambda r: (r >> TAG_SHIFT, r))
         cols.extend(refs)
@@ -773,4 +822,5 @@ def _flatten_and_level(ac: ACBuilder, root, flatten: bool):
     level_ptr = np.zeros(L + 1, dtype=np.int32)
     for l in range(1, L + 1):
         level_ptr[l] = int(np.searchsorted(lv, l, side="right"))
-    return op_arr, row_ptr, np.array(cols, dtype=np.uint32), level_ptr, idx[root] if root in idx else 0, slot_list
+    return (op_arr, row_ptr, np.array(cols, dtype=np.uint32), level_ptr, idx[root] if root in idx else 0,
+            slot_list, sel_list)

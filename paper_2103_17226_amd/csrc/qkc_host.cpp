@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -32,6 +33,16 @@ template <typename T>
 hipError_t launch_sample(const DevGraph &g, int grid, const double *theta, const void *wfix, void *vals,
                          size_t per_wg_elems, const SampleArgs &a, hipStream_t st);
 size_t lds_bytes(const DevGraph &g, size_t csize);
+template <typename T>
+size_t sample_lds_chain_bytes(const DevGraph &g, const LdsPlan &lp);
+size_t sample_lds_meta_bytes(const LdsPlan &lp);
+template <typename T>
+hipError_t launch_sample_stream(const DevGraph &g, const LdsPlan &lp, int grid, const double *theta,
+                                const void *wfix, void *vals, size_t per_wg_elems, const SampleArgs &a,
+                                hipStream_t st);
+template <typename T>
+hipError_t launch_sample_lds(const DevGraph &g, const LdsPlan &lp, int cpw, int grid, const double *theta,
+                             const double *noise, const SampleArgs &a, hipStream_t st);
 hipError_t launch_zero_f64(double *p, int64_t n, hipStream_t st);
 
 }  // namespace qkc
@@ -66,6 +77,9 @@ static ac_status fail_hip(hipError_t e, const char *what) {
 
 struct ac_graph {
     DevGraph dev;
+    LdsPlan plan{};
+    bool has_plan = false;
+    std::vector<uint32_t> plan_level_ptr;   // host copy (launch heuristics)
     void *dmem = nullptr;
     int device = 0;
     int n_cu = 0;
@@ -112,6 +126,185 @@ size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
 int cdiv64(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) / b); }
 
+// Node-parallel plan (see LdsPlan in qkc_internal.h), built on the host.
+struct HostPlan {
+    std::vector<uint64_t> fwd, orec, edg, fwd_u, edg_u, dterm;
+    std::vector<uint32_t> level_ptr, level_prod, brec, estart, dstart;
+    uint32_t N = 0, L = 0, root = 0, max_edges = 0;
+    bool ok = false;
+};
+
+uint32_t encode_leaf(uint32_t r, const std::vector<uint32_t> &var_field) {
+    if ((r >> 30) != TAG_IND) return r;
+    const uint32_t x = r & REF_MASK, v = x & 0xffffffu, u = x >> 24, fld = var_field[v];
+    return dev_ind_ref(u, (fld & 3u) + 1u, fld >> 8, (fld >> 2) & 63u);
+}
+
+HostPlan build_plan(uint32_t N, const uint8_t *op, const uint32_t *row_ptr, const uint32_t *col, uint32_t root,
+                    const std::vector<uint32_t> &ind_base, const std::vector<uint32_t> &var_field, uint32_t n_ind,
+                    uint32_t n_sel, uint32_t n_slots, const std::vector<uint32_t> &sel_dev,
+                    const std::vector<uint32_t> &vsel_ptr, const std::vector<uint32_t> &vsel) {
+    HostPlan P;
+    struct PN {
+        uint8_t op;
+        uint32_t a, b;       // node refs hold pre-sort plan ids (tag 0); leaves keep blob refs
+    };
+    std::vector<PN> nodes;
+    nodes.reserve(2 * static_cast<size_t>(N));
+    std::vector<uint32_t> map(N), kids, next;
+    auto make = [&](uint8_t o, uint32_t a, uint32_t b) {
+        nodes.push_back(PN{o, a, b});
+        return static_cast<uint32_t>(nodes.size() - 1);
+    };
+    for (uint32_t i = 0; i < N; ++i) {
+        kids.clear();
+        for (uint32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+            const uint32_t r = col[e];
+            kids.push_back((r >> 30) == TAG_NODE ? map[r & REF_MASK] : r);
+        }
+        if (kids.size() == 1) {
+            map[i] = make(op[i], kids[0], IDENT_REF);
+        } else if (op[i] == 1) {                       // product: chain
+            uint32_t cur = make(1, kids[0], kids[1]);
+            for (size_t j = 2; j < kids.size(); ++j) cur = make(1, cur, kids[j]);
+            map[i] = cur;
+        } else {                                       // sum: balanced tree
+            while (kids.size() > 2) {
+                next.clear();
+                for (size_t j = 0; j + 1 < kids.size(); j += 2) next.push_back(make(0, kids[j], kids[j + 1]));
+                if (kids.size() % 2) next.push_back(kids.back());
+                kids.swap(next);
+            }
+            map[i] = make(0, kids[0], kids[1]);
+        }
+    }
+    const uint32_t M = static_cast<uint32_t>(nodes.size());
+    const uint32_t proot = map[root];
+    auto is_node = [](uint32_t r) { return r != IDENT_REF && (r >> 30) == TAG_NODE; };
+    std::vector<uint32_t> lev(M), fan(M, 0);
+    uint32_t Lmax = 0;
+    for (uint32_t n = 0; n < M; ++n) {
+        uint32_t l = 0;
+        if (is_node(nodes[n].a)) l = std::max(l, lev[nodes[n].a]), fan[nodes[n].a]++;
+        if (is_node(nodes[n].b)) l = std::max(l, lev[nodes[n].b]), fan[nodes[n].b]++;
+        lev[n] = l + 1;
+        Lmax = std::max(Lmax, lev[n]);
+    }
+    uint32_t at_top = 0;
+    for (uint32_t n = 0; n < M; ++n) at_top += lev[n] == Lmax;
+    if (at_top != 1 || lev[proot] != Lmax) return P;          // unreachable nodes: no plan
+    std::vector<uint32_t> order(M), newid(M);
+    for (uint32_t n = 0; n < M; ++n) order[n] = n;
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) {
+        if (lev[x] != lev[y]) return lev[x] < lev[y];
+        if (nodes[x].op != nodes[y].op) return nodes[x].op < nodes[y].op;
+        return fan[x] < fan[y];
+    });
+    for (uint32_t j = 0; j < M; ++j) newid[order[j]] = j;
+    auto plan_ref = [&](uint32_t r) -> uint32_t {
+        if (r == IDENT_REF) return IDENT_REF;
+        return (r >> 30) == TAG_NODE ? newid[r] : encode_leaf(r, var_field);
+    };
+    P.fwd.resize(M);
+    P.level_ptr.assign(Lmax + 1, 0);
+    P.level_prod.assign(Lmax, 0);
+    std::vector<uint32_t> n_sum(Lmax + 1, 0);
+    for (uint32_t j = 0; j < M; ++j) {
+        const PN &nd = nodes[order[j]];
+        P.fwd[j] = static_cast<uint64_t>(plan_ref(nd.a)) | (static_cast<uint64_t>(plan_ref(nd.b)) << 32);
+        P.level_ptr[lev[order[j]]]++;
+        if (nd.op == 0) n_sum[lev[order[j]]]++;
+    }
+    for (uint32_t l = 1; l <= Lmax; ++l) P.level_ptr[l] += P.level_ptr[l - 1];
+    for (uint32_t l = 0; l < Lmax; ++l) P.level_prod[l] = P.level_ptr[l] + n_sum[l + 1];
+    // parent edges of nodes, indicator leaves and selectors, in increasing parent order
+    const size_t T = static_cast<size_t>(M) + n_ind + n_sel;
+    std::vector<std::vector<uint64_t>> edges(T);
+    auto target_of = [&](uint32_t r) -> int64_t {
+        if (r == IDENT_REF) return -1;
+        const uint32_t tag = r >> 30;
+        if (tag == TAG_NODE) return newid[r];
+        if (tag == TAG_IND) {
+            const uint32_t x = r & REF_MASK;
+            return static_cast<int64_t>(M) + ind_base[x & 0xffffffu] + (x >> 24);
+        }
+        if (tag == TAG_SEL) return static_cast<int64_t>(M) + n_ind + (r & REF_MASK);
+        return -1;
+    };
+    for (uint32_t j = 0; j < M; ++j) {
+        const PN &nd = nodes[order[j]];
+        const uint32_t ch[2] = {nd.a, nd.b};
+        for (int t = 0; t < 2; ++t) {
+            const int64_t tg = target_of(ch[t]);
+            if (tg < 0) continue;
+            uint32_t sib = NO_SIBLING;
+            if (nd.op == 1 && ch[1 - t] != IDENT_REF) sib = plan_ref(ch[1 - t]);
+            edges[tg].push_back(static_cast<uint64_t>(j) | (static_cast<uint64_t>(sib) << 32));
+        }
+    }
+    P.estart.assign(T + 1, 0);
+    for (size_t t = 0; t < T; ++t) {
+        P.estart[t + 1] = P.estart[t] + static_cast<uint32_t>(edges[t].size());
+        P.edg.insert(P.edg.end(), edges[t].begin(), edges[t].end());
+    }
+    for (uint32_t l = 0; l < Lmax; ++l)
+        P.max_edges = std::max(P.max_edges, P.estart[P.level_ptr[l + 1]] - P.estart[P.level_ptr[l]]);
+    P.max_edges = std::max(P.max_edges, P.estart[T] - P.estart[M]);
+    P.brec.assign(4 * T, 0);
+    for (size_t t = 0; t < T; ++t) {
+        const auto &ev = edges[t];
+        P.brec[4 * t + 0] = static_cast<uint32_t>(ev.size());
+        P.brec[4 * t + 1] = static_cast<uint32_t>(P.orec.size());
+        P.brec[4 * t + 2] = ev.empty() ? 0u : static_cast<uint32_t>(ev[0]);
+        P.brec[4 * t + 3] = ev.empty() ? NO_SIBLING : static_cast<uint32_t>(ev[0] >> 32);
+        for (size_t q = 1; q < ev.size(); ++q) P.orec.push_back(ev[q]);
+    }
+    // unified references for the LDS kernel: [node | slot | selector]
+    auto unify = [&](uint32_t r) -> uint32_t {
+        if (r == IDENT_REF || r == NO_SIBLING) return r;
+        const uint32_t tag = r >> 30, x = r & REF_MASK;
+        if (tag == TAG_SLOT) return M + x;
+        if (tag == TAG_SEL) return M + n_slots + x;
+        return r;                                   // node index (tag 0) or indicator (tag 1)
+    };
+    P.fwd_u.resize(M);
+    for (uint32_t j = 0; j < M; ++j) {
+        const uint64_t f = P.fwd[j];
+        const uint32_t a = unify(static_cast<uint32_t>(f)), b = unify(static_cast<uint32_t>(f >> 32));
+        P.fwd_u[j] = static_cast<uint64_t>(a) | (static_cast<uint64_t>(b) << 32);
+    }
+    P.edg_u.resize(P.edg.size());
+    for (size_t e = 0; e < P.edg.size(); ++e) {
+        const uint64_t rr = P.edg[e];
+        P.edg_u[e] = (rr & 0xffffffffull) | (static_cast<uint64_t>(unify(static_cast<uint32_t>(rr >> 32))) << 32);
+    }
+    // d root / d lambda terms per indicator: its own leaf edges, and every
+    // leaf edge of the selectors of its variable times the selector's weight
+    const uint32_t leaf0 = P.estart[M];
+    P.dstart.assign(n_ind + 1, 0);
+    for (uint32_t v = 0; v + 1 < ind_base.size(); ++v) {
+        for (uint32_t u = 0; u < ind_base[v + 1] - ind_base[v]; ++u) {
+            const uint32_t t = ind_base[v] + u;
+            for (uint32_t e = P.estart[M + t]; e < P.estart[M + t + 1]; ++e)
+                P.dterm.push_back(static_cast<uint64_t>(e - leaf0) | (static_cast<uint64_t>(NO_SLOT) << 32));
+            for (uint32_t qq = vsel_ptr[v]; qq < vsel_ptr[v + 1]; ++qq) {
+                const uint32_t q = vsel[qq];
+                const uint32_t sl = u < static_cast<uint32_t>(SEL_DOM) ? sel_dev[static_cast<size_t>(q) * SEL_REC + 1 + u]
+                                                                       : NO_SLOT;
+                if (sl == NO_SLOT) continue;
+                for (uint32_t e = P.estart[M + n_ind + q]; e < P.estart[M + n_ind + q + 1]; ++e)
+                    P.dterm.push_back(static_cast<uint64_t>(e - leaf0) | (static_cast<uint64_t>(sl) << 32));
+            }
+            P.dstart[t + 1] = static_cast<uint32_t>(P.dterm.size());
+        }
+    }
+    P.N = M;
+    P.L = Lmax;
+    P.root = newid[proot];
+    P.ok = true;
+    return P;
+}
+
 }  // namespace
 
 extern "C" const char *ac_last_error(void) { return g_last_error.c_str(); }
@@ -124,9 +317,10 @@ extern "C" ac_status ac_load(const void *blob, size_t nbytes, int device, ac_gra
     const uint32_t *h = rd.take_packed<uint32_t>(14);
     if (!rd.ok) return fail(AC_ERR_FORMAT, "ac_load: blob shorter than its header");
     if (std::memcmp(magic, MAGIC, 8) != 0) return fail(AC_ERR_FORMAT, "ac_load: bad magic");
-    if (h[0] != 1) return fail(AC_ERR_FORMAT, "ac_load: unsupported version %u", h[0]);
+    if (h[0] != 2) return fail(AC_ERR_FORMAT, "ac_load: unsupported version %u", h[0]);
     const uint32_t n_qubits = h[2], n_vars = h[3], n_words = h[4], n_angles = h[5], n_noise = h[6];
     const uint32_t n_slots = h[7], n_angle_slots = h[8], N = h[9], E = h[10], L = h[11], root = h[12];
+    const uint32_t n_sel = h[13];
     if (n_qubits < 1 || n_vars < n_qubits || n_vars >= (1u << 20))
         return fail(AC_ERR_FORMAT, "ac_load: bad variable counts (%u qubits, %u vars)", n_qubits, n_vars);
     if (n_words < 1 || n_words > static_cast<uint32_t>(MAX_WORDS))
@@ -142,6 +336,7 @@ extern "C" ac_status ac_load(const void *blob, size_t nbytes, int device, ac_gra
     const uint32_t *var_off = rd.take<uint32_t>(n_vars);
     const double *noise_def = rd.take<double>(n_noise);
     const SlotDesc *slots = rd.take_packed<SlotDesc>(n_slots);
+    const uint32_t *selrec = rd.take_packed<uint32_t>(static_cast<size_t>(n_sel) * (1 + SEL_DOM));
     const uint8_t *op = rd.take_packed<uint8_t>(N);
     const uint32_t *row_ptr = rd.take<uint32_t>(N + 1);
     const uint32_t *col = rd.take<uint32_t>(E);
@@ -178,6 +373,27 @@ extern "C" ac_status ac_load(const void *blob, size_t nbytes, int device, ac_gra
         if (sd.base == B_CONST && (!std::isfinite(sd.re) || !std::isfinite(sd.im)))
             return fail(AC_ERR_FORMAT, "ac_load: slot %u constant not finite", s);
     }
+    // ---- selectors: {variable, slot per value}; weights must not depend on theta
+    std::vector<uint32_t> sel_dev(static_cast<size_t>(n_sel) * SEL_REC, 0), vsel_ptr(n_vars + 1, 0), vsel(n_sel);
+    for (uint32_t q = 0; q < n_sel; ++q) {
+        const uint32_t *r = selrec + static_cast<size_t>(q) * (1 + SEL_DOM);
+        const uint32_t v = r[0];
+        if (v >= n_vars || v < n_qubits || var_dom[v] > SEL_DOM)
+            return fail(AC_ERR_FORMAT, "ac_load: selector %u variable %u", q, v);
+        sel_dev[q * SEL_REC] = var_field[v];
+        for (int u = 0; u < SEL_DOM; ++u) {
+            const uint32_t sl = r[1 + u];
+            if (sl != NO_SLOT && (sl >= n_slots || sl < n_angle_slots || u >= var_dom[v]))
+                return fail(AC_ERR_FORMAT, "ac_load: selector %u slot %u", q, sl);
+            sel_dev[q * SEL_REC + 1 + u] = sl;
+        }
+        vsel_ptr[v + 1]++;
+    }
+    for (uint32_t v = 0; v < n_vars; ++v) vsel_ptr[v + 1] += vsel_ptr[v];
+    {
+        std::vector<uint32_t> fs(vsel_ptr.begin(), vsel_ptr.end() - 1);
+        for (uint32_t q = 0; q < n_sel; ++q) vsel[fs[selrec[static_cast<size_t>(q) * (1 + SEL_DOM)]]++] = q;
+    }
     for (uint32_t m = 0; m < n_noise; ++m)
         if (!(noise_def[m] >= 0.0 && noise_def[m] <= 1.0)) return fail(AC_ERR_FORMAT, "ac_load: noise %u outside [0,1]", m);
 
@@ -194,7 +410,7 @@ extern "C" ac_status ac_load(const void *blob, size_t nbytes, int device, ac_gra
     if (level[root] != L - 1 || level_ptr[L - 1] != N - 1)
         return fail(AC_ERR_FORMAT, "ac_load: the root must be the only node of the top level");
     std::vector<uint32_t> dcol(E), edge_parent(E);
-    std::vector<uint32_t> n_par(N, 0), n_leafpar(n_ind + n_slots, 0);
+    std::vector<uint32_t> n_par(N, 0), n_leafpar(n_ind + n_slots + n_sel, 0);
     int64_t flops = 0;
     for (uint32_t i = 0; i < N; ++i) {
         if (op[i] > 1) return fail(AC_ERR_FORMAT, "ac_load: node %u op %u", i, op[i]);
@@ -219,24 +435,31 @@ extern "C" ac_status ac_load(const void *blob, size_t nbytes, int device, ac_gra
                 dcol[e] = r;
                 n_leafpar[n_ind + x]++;
             } else {
-                return fail(AC_ERR_FORMAT, "ac_load: edge %u bad tag", e);
+                if (x >= n_sel) return fail(AC_ERR_FORMAT, "ac_load: edge %u selector %u", e, x);
+                dcol[e] = r;
+                n_leafpar[n_ind + n_slots + x]++;
             }
         }
     }
     // parent CSR of internal nodes and of leaves (edges in increasing order)
-    std::vector<uint32_t> par_ptr(N + 1, 0), leaf_ptr(n_ind + n_slots + 1, 0);
+    const uint32_t n_leaves = n_ind + n_slots + n_sel;
+    std::vector<uint32_t> par_ptr(N + 1, 0), leaf_ptr(n_leaves + 1, 0);
     for (uint32_t i = 0; i < N; ++i) par_ptr[i + 1] = par_ptr[i] + n_par[i];
-    for (uint32_t i = 0; i < n_ind + n_slots; ++i) leaf_ptr[i + 1] = leaf_ptr[i] + n_leafpar[i];
-    std::vector<uint32_t> par_edge(par_ptr[N]), leaf_edge(leaf_ptr[n_ind + n_slots]);
+    for (uint32_t i = 0; i < n_leaves; ++i) leaf_ptr[i + 1] = leaf_ptr[i] + n_leafpar[i];
+    std::vector<uint32_t> par_edge(par_ptr[N]), leaf_edge(leaf_ptr[n_leaves]);
     {
         std::vector<uint32_t> fp(par_ptr.begin(), par_ptr.end() - 1), fl(leaf_ptr.begin(), leaf_ptr.end() - 1);
         for (uint32_t e = 0; e < E; ++e) {
             const uint32_t r = col[e], tag = r >> 30, x = r & REF_MASK;
             if (tag == TAG_NODE) par_edge[fp[x]++] = e;
             else if (tag == TAG_IND) leaf_edge[fl[ind_base[x & 0xffffffu] + (x >> 24)]++] = e;
-            else leaf_edge[fl[n_ind + x]++] = e;
+            else if (tag == TAG_SLOT) leaf_edge[fl[n_ind + x]++] = e;
+            else leaf_edge[fl[n_ind + n_slots + x]++] = e;
         }
     }
+
+    HostPlan hp = build_plan(N, op, row_ptr, col, root, ind_base, var_field, n_ind, n_sel, n_slots, sel_dev,
+                             vsel_ptr, vsel);
 
     // ---- device copy: one allocation, 256-byte aligned sections
     struct Sec { const void *src; size_t bytes; size_t off; };
@@ -254,6 +477,20 @@ extern "C" ac_status ac_load(const void *blob, size_t nbytes, int device, ac_gra
         {var_field.data(), n_vars * sizeof(uint32_t), 0},
         {ind_base.data(), ind_base.size() * sizeof(uint32_t), 0},
         {noise_def, n_noise * sizeof(double), 0},
+        {sel_dev.data(), sel_dev.size() * sizeof(uint32_t), 0},
+        {vsel_ptr.data(), vsel_ptr.size() * sizeof(uint32_t), 0},
+        {vsel.data(), vsel.size() * sizeof(uint32_t), 0},
+        {hp.fwd.data(), hp.fwd.size() * sizeof(uint64_t), 0},
+        {hp.level_ptr.data(), hp.level_ptr.size() * sizeof(uint32_t), 0},
+        {hp.level_prod.data(), hp.level_prod.size() * sizeof(uint32_t), 0},
+        {hp.brec.data(), hp.brec.size() * sizeof(uint32_t), 0},
+        {hp.orec.data(), hp.orec.size() * sizeof(uint64_t), 0},
+        {hp.estart.data(), hp.estart.size() * sizeof(uint32_t), 0},
+        {hp.edg.data(), hp.edg.size() * sizeof(uint64_t), 0},
+        {hp.fwd_u.data(), hp.fwd_u.size() * sizeof(uint64_t), 0},
+        {hp.edg_u.data(), hp.edg_u.size() * sizeof(uint64_t), 0},
+        {hp.dstart.data(), hp.dstart.size() * sizeof(uint32_t), 0},
+        {hp.dterm.data(), hp.dterm.size() * sizeof(uint64_t), 0},
     };
     size_t total = 0;
     for (auto &s : secs) {
@@ -308,6 +545,31 @@ extern "C" ac_status ac_load(const void *blob, size_t nbytes, int device, ac_gra
     d.var_field = reinterpret_cast<const uint32_t *>(at(10));
     d.ind_base = reinterpret_cast<const uint32_t *>(at(11));
     d.noise_default = reinterpret_cast<const double *>(at(12));
+    d.sel = reinterpret_cast<const uint32_t *>(at(13));
+    d.vsel_ptr = reinterpret_cast<const uint32_t *>(at(14));
+    d.vsel = reinterpret_cast<const uint32_t *>(at(15));
+    d.n_sel = static_cast<int32_t>(n_sel);
+    if (hp.ok) {
+        LdsPlan &lp = g->plan;
+        lp.fwd = reinterpret_cast<const uint64_t *>(at(16));
+        lp.level_ptr = reinterpret_cast<const uint32_t *>(at(17));
+        lp.level_prod = reinterpret_cast<const uint32_t *>(at(18));
+        lp.brec = reinterpret_cast<const uint32_t *>(at(19));
+        lp.orec = reinterpret_cast<const uint64_t *>(at(20));
+        lp.estart = reinterpret_cast<const uint32_t *>(at(21));
+        lp.edg = reinterpret_cast<const uint64_t *>(at(22));
+        lp.fwd_u = reinterpret_cast<const uint64_t *>(at(23));
+        lp.edg_u = reinterpret_cast<const uint64_t *>(at(24));
+        lp.dstart = reinterpret_cast<const uint32_t *>(at(25));
+        lp.dterm = reinterpret_cast<const uint64_t *>(at(26));
+        lp.max_edges = static_cast<int32_t>(hp.max_edges);
+        lp.N = static_cast<int32_t>(hp.N);
+        lp.L = static_cast<int32_t>(hp.L);
+        lp.root = static_cast<int32_t>(hp.root);
+        lp.R = static_cast<int64_t>(hp.orec.size());
+        g->has_plan = true;
+        g->plan_level_ptr = hp.level_ptr;
+    }
     d.N = static_cast<int32_t>(N);
     d.E = E;
     d.L = static_cast<int32_t>(L);
@@ -338,6 +600,7 @@ extern "C" ac_status ac_load(const void *blob, size_t nbytes, int device, ac_gra
     inf.n_levels = d.L;
     inf.max_level_width = static_cast<int32_t>(max_width);
     inf.n_indicator_leaves = d.n_ind;
+    inf.n_selectors = d.n_sel;
     inf.root = d.root;
     inf.device = device;
     inf.n_prod_flops = flops;
@@ -374,6 +637,59 @@ constexpr size_t WS_CAP = static_cast<size_t>(48) << 30;   // cap on per-call ti
 constexpr size_t LDS_LIMIT = 64 * 1024;                     // dynamic LDS per workgroup
 constexpr int WG_PER_CU = 4;
 
+constexpr size_t CU_LDS = 160 * 1024;                      // LDS per compute unit (gfx950)
+
+// Launch shape of the LDS-resident sampler, or false if a chain does not fit.
+// Sampler kernels: the batched streaming kernel on the binary plan (default),
+// the LDS-resident node-parallel kernel, or the plain streaming kernel on the
+// blob's own DAG (used when no plan exists).  QKC_SAMPLE_KERNEL = stream | lds
+// | global selects one explicitly (for comparisons and tests).
+enum SampleKernel { SK_STREAM, SK_LDS, SK_GLOBAL };
+
+SampleKernel sample_kernel(const ac_graph *g) {
+    if (!g->has_plan) return SK_GLOBAL;
+    const char *kern = std::getenv("QKC_SAMPLE_KERNEL");
+    if (kern && std::strcmp(kern, "global") == 0) return SK_GLOBAL;
+    if (kern && std::strcmp(kern, "lds") == 0) return SK_LDS;
+    return SK_STREAM;
+}
+
+bool sample_lds_shape(const ac_graph *g, ac_dtype dt, int64_t chains, int &cpw, int &grid) {
+    if (sample_kernel(g) != SK_LDS) return false;
+    const size_t cb = dt == AC_C64 ? sample_lds_chain_bytes<float>(g->dev, g->plan)
+                                   : sample_lds_chain_bytes<double>(g->dev, g->plan);
+    const size_t meta = sample_lds_meta_bytes(g->plan);
+    if (cb + meta > CU_LDS) return false;
+    // chains per wave: minimise level steps per chain at the occupancy the LDS allows
+    double best = -1.0;
+    int best_cpw = 1;
+    const char *env = std::getenv("QKC_SAMPLE_CPW");
+    const int forced = env ? std::atoi(env) : 0;
+    for (int c : {1, 2, 4}) {
+        if (cb * c + meta > CU_LDS) continue;
+        const int lpc = WAVE / c;
+        double steps = 0;
+        const auto &lvl = g->plan_level_ptr;
+        for (size_t l = 1; l < lvl.size(); ++l) steps += static_cast<double>((lvl[l] - lvl[l - 1] + lpc - 1) / lpc);
+        steps = 2.0 * steps + static_cast<double>((g->dev.n_ind + lpc - 1) / lpc);
+        const double waves = static_cast<double>(CU_LDS / (cb * c + meta));
+        const double rate = std::min(waves, 8.0) * c / steps;
+        if (rate > best) {
+            best = rate;
+            best_cpw = c;
+        }
+        if (forced == c) {
+            best = 1e300;
+            best_cpw = c;
+        }
+    }
+    cpw = best_cpw;
+    const int64_t per_cu = static_cast<int64_t>(CU_LDS / (cb * cpw + meta));
+    const int64_t want = (chains + cpw - 1) / cpw;
+    grid = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(want, per_cu * g->n_cu)));
+    return true;
+}
+
 struct Layout {
     size_t wfix_off = 0, contrib_off = 0, tiles_off = 0, total = 0;
     size_t per_wg_elems = 0;   // complex elements per workgroup buffer
@@ -386,13 +702,23 @@ bool make_layout(const ac_graph *g, ac_dtype dt, int64_t batch, int op, Layout &
     const size_t cs = dt == AC_C64 ? 8 : 16;
     size_t rows = 0;
     if (op == AC_OP_EVAL) rows = d.N;
-    else if (op == AC_OP_GRAD) rows = 2 * static_cast<size_t>(d.N) + d.S_ang;
-    else rows = 2 * static_cast<size_t>(d.N) + d.n_ind;
+    else if (op == AC_OP_GRAD) rows = 2 * static_cast<size_t>(d.N) + d.S_ang + d.n_ind;
+    else {
+        int cpw = 0, lgrid = 0;
+        const SampleKernel sk = sample_kernel(g);
+        if (sk == SK_LDS && sample_lds_shape(g, dt, batch, cpw, lgrid)) rows = 0;
+        else if (sk == SK_STREAM) rows = 2 * static_cast<size_t>(g->plan.N) + d.n_ind + d.n_sel;
+        else rows = 2 * static_cast<size_t>(d.N) + d.n_ind;
+    }
     const size_t per_wg = rows * WAVE;
     int64_t tiles = (batch + WAVE - 1) / WAVE;
-    int64_t grid = std::min<int64_t>(tiles, static_cast<int64_t>(g->n_cu) * WG_PER_CU);
-    const int64_t cap = std::max<int64_t>(1, static_cast<int64_t>(WS_CAP / (per_wg * cs)));
-    grid = std::min(grid, cap);
+    int wg_per_cu = WG_PER_CU;
+    if (const char *env = std::getenv("QKC_WG_PER_CU")) wg_per_cu = std::max(1, std::min(16, std::atoi(env)));
+    int64_t grid = std::min<int64_t>(tiles, static_cast<int64_t>(g->n_cu) * wg_per_cu);
+    if (per_wg > 0) {
+        const int64_t cap = std::max<int64_t>(1, static_cast<int64_t>(WS_CAP / (per_wg * cs)));
+        grid = std::min(grid, cap);
+    }
     if (batch > 0 && grid < 1) grid = 1;
     Layout L;
     size_t off = 0;
@@ -530,8 +856,9 @@ extern "C" ac_status ac_sample(const ac_graph *g, ac_dtype dtype, const double *
                                size_t ws_bytes, void *stream) {
     ac_status s = check_common(g, dtype, theta, P, "ac_sample");
     if (s != AC_OK) return s;
-    if (lds_bytes(g->dev, dtype == AC_C64 ? 8 : 16) > LDS_LIMIT)
-        return fail(AC_ERR_UNSUPPORTED, "ac_sample: evidence and angle tables exceed LDS");
+    if (lds_bytes(g->dev, dtype == AC_C64 ? 8 : 16) + static_cast<size_t>(g->dev.S) * (dtype == AC_C64 ? 8 : 16) >
+        LDS_LIMIT)
+        return fail(AC_ERR_UNSUPPORTED, "ac_sample: evidence and weight tables exceed LDS");
     if (!cfg) return fail(AC_ERR_INVALID_ARG, "ac_sample: null cfg");
     if (cfg->chains_per_param < 0 || cfg->samples_per_chain < 0 || cfg->burn_in_sweeps < 0 || cfg->thin_sweeps < 1)
         return fail(AC_ERR_INVALID_ARG, "ac_sample: bad chain schedule");
@@ -568,7 +895,24 @@ extern "C" ac_status ac_sample(const ac_graph *g, ac_dtype dtype, const double *
     a.rounds_out = rounds_out;
     a.nwq = (g->dev.n_qubits + 63) / 64;
     hipError_t e;
-    if (dtype == AC_C64) {
+    int cpw = 0, lgrid = 0;
+    const SampleKernel sk = sample_kernel(g);
+    if (sk == SK_LDS && sample_lds_shape(g, dtype, total, cpw, lgrid)) {
+        e = dtype == AC_C64 ? launch_sample_lds<float>(g->dev, g->plan, cpw, lgrid, theta, noise, a, st)
+                            : launch_sample_lds<double>(g->dev, g->plan, cpw, lgrid, theta, noise, a, st);
+    } else if (sk == SK_STREAM) {
+        if (dtype == AC_C64) {
+            e = launch_fixed_slots<float>(g->dev, noise, w + L.wfix_off, st);
+            if (e == hipSuccess)
+                e = launch_sample_stream<float>(g->dev, g->plan, L.grid, theta, w + L.wfix_off, w + L.tiles_off,
+                                                L.per_wg_elems, a, st);
+        } else {
+            e = launch_fixed_slots<double>(g->dev, noise, w + L.wfix_off, st);
+            if (e == hipSuccess)
+                e = launch_sample_stream<double>(g->dev, g->plan, L.grid, theta, w + L.wfix_off, w + L.tiles_off,
+                                                 L.per_wg_elems, a, st);
+        }
+    } else if (dtype == AC_C64) {
         e = launch_fixed_slots<float>(g->dev, noise, w + L.wfix_off, st);
         if (e == hipSuccess)
             e = launch_sample<float>(g->dev, L.grid, theta, w + L.wfix_off, w + L.tiles_off, L.per_wg_elems, a, st);

@@ -18,7 +18,11 @@ constexpr int MAX_DOM = 16;           // values per evidence variable
 constexpr uint32_t TAG_NODE = 0u;
 constexpr uint32_t TAG_IND = 1u;
 constexpr uint32_t TAG_SLOT = 2u;
+constexpr uint32_t TAG_SEL = 3u;      // selector leaf: sum_u lambda_{v=u} W[slot_u]
 constexpr uint32_t REF_MASK = 0x3fffffffu;
+constexpr uint32_t NO_SLOT = 0xFFFFFFFFu;
+constexpr int SEL_DOM = 4;            // values per selector variable
+constexpr int SEL_REC = 8;            // u32 per device selector record
 
 // Device encoding of an indicator reference, rewritten at load time so that
 // the kernels decode it without table lookups:
@@ -60,8 +64,54 @@ struct DevGraph {
     const uint32_t *var_field;  // [n_vars] word<<8 | shift<<2 | (width-1)
     const uint32_t *ind_base;   // [n_vars+1]
     const double *noise_default;// [n_noise]
-    int32_t N, L, root, S, S_ang, n_vars, W, n_ind, K, n_noise, n_qubits;
+    const uint32_t *sel;        // [SEL_REC * n_sel] field (word<<8|shift<<2|width-1), slot[4], pad
+    const uint32_t *vsel_ptr;   // [n_vars+1] selectors of each variable
+    const uint32_t *vsel;       // [n_sel]
+    int32_t N, L, root, S, S_ang, n_vars, W, n_ind, K, n_noise, n_qubits, n_sel;
     int64_t E;
+};
+
+// Node-parallel plan of the DAG, derived at load time for the LDS-resident
+// kernels.  Every node has at most two children: k-ary products become
+// chains and k-ary sums balanced trees of binary nodes.  Nodes are levelled
+// as soon as possible and, within a level, sums come before products.
+//   fwd[i]        children refs a | b << 32 (b = IDENT_REF for a single child)
+//   level_prod[l] first product of level l (sums are [level_ptr[l], level_prod[l]))
+//   brec[t]       for node t < N, indicator leaf t - N < n_ind or selector
+//                 t - N - n_ind: {number of parent
+//                 edges, offset of the 2nd.. in orec, first parent, first
+//                 sibling}; a parent edge contributes adj[parent] * value(sibling),
+//                 sibling = NO_SIBLING for a sum parent
+//   orec[q]       further parent edges: parent | sibling << 32
+constexpr uint32_t NO_SIBLING = 0xFFFFFFFFu;
+constexpr uint32_t IDENT_REF = 0xFFFFFFFFu;
+
+//   estart[t]     the same parent edges as one CSR sorted by target t:
+//   edg[e]        edges [estart[t], estart[t+1]) of target t, parent | sibling << 32;
+//                 the edges of one level's nodes are contiguous
+// The LDS-resident kernel keeps node values, weights and selector values in
+// one array [N | S | n_sel]; fwd_u and edg_u are fwd and edg with every
+// non-indicator reference rewritten to its index in that array (tag 0), so
+// a child is one LDS load whatever its kind.
+//   dstart[t], dterm[j]  d root / d lambda for indicator t: the sum over j in
+//                 [dstart[t], dstart[t+1]) of leafterm[j & 0xffffffff] *
+//                 W[j >> 32] (W index 0xffffffff: factor 1), where leafterm[e]
+//                 is the term of leaf edge estart[N] + e
+struct LdsPlan {
+    const uint64_t *fwd;        // [N]
+    const uint32_t *level_ptr;  // [L+1]
+    const uint32_t *level_prod; // [L]
+    const uint32_t *brec;       // [4 * (N + n_ind + n_sel)]
+    const uint64_t *orec;       // [R]
+    const uint32_t *estart;     // [N + n_ind + n_sel + 1]
+    const uint64_t *edg;        // [estart[N + n_ind + n_sel]]
+    const uint64_t *fwd_u;      // [N]
+    const uint64_t *edg_u;      // [estart[N + n_ind + n_sel]]
+    const uint32_t *dstart;     // [n_ind + 1]
+    const uint64_t *dterm;      // [dstart[n_ind]]
+    int32_t N, L, root;
+    int32_t max_edges;          // most parent edges of one level, or of all leaves
+    int64_t R;
 };
 
 // Arguments of the Gibbs sampler kernel.

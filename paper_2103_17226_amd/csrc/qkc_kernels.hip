@@ -127,11 +127,24 @@ struct Tile {
         return wfix[s];
     }
 
+    // selector leaf: the weight of its variable's current value
+    __device__ __forceinline__ cplx<T> sel(uint32_t q) const {
+        const uint32_t *rec = g.sel + static_cast<size_t>(q) * SEL_REC;
+        const uint32_t fld = rec[0];
+        const uint32_t word = fld >> 8, shift = (fld >> 2) & 63u, width = (fld & 3u) + 1u;
+        const uint32_t k = static_cast<uint32_t>((ev[word * WAVE + lane] >> shift) & ((1ull << width) - 1ull));
+        const uint32_t s0 = rec[1], s1 = rec[2], s2 = rec[3], s3 = rec[4];
+        const uint32_t s = k == 0 ? s0 : k == 1 ? s1 : k == 2 ? s2 : k == 3 ? s3 : NO_SLOT;
+        if (s == NO_SLOT) return {T(0), T(0)};
+        return wfix[s];
+    }
+
     // value of a child reference (leaves computed on the fly)
     __device__ __forceinline__ cplx<T> child(uint32_t r) const {
         uint32_t tag = r >> 30;
         if (tag == TAG_NODE) return val[(r & REF_MASK) * WAVE + lane];
         if (tag == TAG_IND) return {ind_hit(r) ? T(1) : T(0), T(0)};
+        if (tag == TAG_SEL) return sel(r & REF_MASK);
         return slot(r & REF_MASK);
     }
 
@@ -148,7 +161,7 @@ struct Tile {
                     sr += ind_hit(r) ? 1.0 : 0.0;
                     continue;
                 }
-                const cplx<T> v = (tag == TAG_NODE) ? val[(r & REF_MASK) * WAVE + lane] : slot(r & REF_MASK);
+                const cplx<T> v = child(r);
                 sr += static_cast<double>(v.re);
                 si += static_cast<double>(v.im);
             }
@@ -162,8 +175,7 @@ struct Tile {
                 if (!ind_hit(r)) acc = {T(0), T(0)};
                 continue;
             }
-            const cplx<T> v = (tag == TAG_NODE) ? val[(r & REF_MASK) * WAVE + lane] : slot(r & REF_MASK);
-            acc = cmul(acc, v);
+            acc = cmul(acc, child(r));
         }
         return acc;
     }
@@ -180,8 +192,7 @@ struct Tile {
                 if (!ind_hit(r)) acc = {T(0), T(0)};
                 continue;
             }
-            acc = cmul(acc, (r >> 30) == TAG_NODE ? val[(r & REF_MASK) * WAVE + lane]
-                                                  : slot(r & REF_MASK));
+            acc = cmul(acc, child(r));
         }
         return acc;
     }
@@ -218,6 +229,26 @@ struct Tile {
                 adj[c * WAVE + lane] = {static_cast<T>(ar), static_cast<T>(ai)};
             }
             __syncthreads();
+        }
+    }
+
+    // d root / d lambda_{v=u} for every value u of variable v, written to
+    // out[(base + u) * ostride] (indicator leaves plus selector leaves)
+    __device__ void ind_derivatives(const cplx<T> *adj, int v, cplx<T> *out, size_t ostride) const {
+        const uint32_t base = g.ind_base[v], dom = g.ind_base[v + 1] - base;
+        for (uint32_t u = 0; u < dom; ++u) out[(base + u) * ostride] = leaf_adjoint(adj, base + u);
+        const uint32_t q1 = g.vsel_ptr[v + 1];
+        for (uint32_t qq = g.vsel_ptr[v]; qq < q1; ++qq) {
+            const uint32_t q = g.vsel[qq];
+            const cplx<T> A = leaf_adjoint(adj, static_cast<uint32_t>(g.n_ind + g.S) + q);
+            const uint32_t *rec = g.sel + static_cast<size_t>(q) * SEL_REC;
+            for (uint32_t u = 0; u < dom && u < static_cast<uint32_t>(SEL_DOM); ++u) {
+                const uint32_t sl = rec[1 + u];
+                if (sl == NO_SLOT) continue;
+                const cplx<T> t = cmul(A, wfix[sl]);
+                cplx<T> &o = out[(base + u) * ostride];
+                o = cadd(o, t);
+            }
         }
     }
 
@@ -325,10 +356,12 @@ __global__ __launch_bounds__(BLOCK) void k_grad(DevGraph g, const double *theta,
             dsl[s * WAVE + lane] = cmul(a, cplx<T>{static_cast<T>(dre), static_cast<T>(dim)});
         }
         if (dind_out) {
-            for (int li = wave; li < g.n_ind; li += nwaves) {
-                cplx<T> a = t.leaf_adjoint(adj, static_cast<uint32_t>(li));
-                if (valid) dind_out[b * g.n_ind + li] = a;
-            }
+            // [n_ind][64] rows after the angle-weight rows of this tile's buffer
+            cplx<T> *Dt = dsl + static_cast<size_t>(g.S_ang) * WAVE;
+            for (int v = wave; v < g.n_vars; v += nwaves) t.ind_derivatives(adj, v, Dt + lane, WAVE);
+            __syncthreads();
+            if (valid)
+                for (int li = 0; li < g.n_ind; ++li) dind_out[b * g.n_ind + li] = Dt[static_cast<size_t>(li) * WAVE + lane];
         }
         __syncthreads();
         // cotangent of the root value
@@ -472,7 +505,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(DevGraph g, const double *thet
         __syncthreads();
         t.forward(wave, nwaves);
         t.backward(adj, wave, nwaves);
-        for (int li = wave; li < g.n_ind; li += nwaves) D[li * WAVE + lane] = t.leaf_adjoint(adj, static_cast<uint32_t>(li));
+        for (int v = wave; v < g.n_vars; v += nwaves) t.ind_derivatives(adj, v, D + lane, WAVE);
         __syncthreads();
 
         if (wave == 0 && ch >= 0) {
@@ -562,6 +595,837 @@ __global__ __launch_bounds__(BLOCK) void k_sample(DevGraph g, const double *thet
 }
 
 // ---------------------------------------------------------------------------
+// Gibbs sampler, streaming variant on the binary plan
+// ---------------------------------------------------------------------------
+//
+// Lane = chain, 64 chains per workgroup of 4 waves; node values and adjoints
+// live in a per-workgroup global buffer [node][64] (one coalesced row per
+// node).  Each wave takes a batch of KB nodes of a level at a time: it loads
+// their records with uniform (scalar) loads, issues every child-value load
+// of the batch, and only then computes and stores, so that KB rows per wave
+// are in flight instead of one.
+
+template <typename T>
+struct StreamTile {
+    DevGraph g;
+    cplx<T> *val, *adj;
+    const uint64_t *ev;      // [W][64] (LDS)
+    const cplx<T> *ang;      // [S_ang][64] (LDS)
+    const cplx<T> *wfix;     // [S] (LDS copy of the fixed weights)
+    int lane;
+
+    // row of a node reference, or row 0 (always cached) for a leaf: lets a
+    // batch issue every row load before any branch on the reference kind
+    __device__ __forceinline__ cplx<T> row(const cplx<T> *base, uint32_t r) const {
+        const uint32_t x = (r != IDENT_REF && (r >> 30) == TAG_NODE) ? (r & REF_MASK) : 0u;
+        return base[static_cast<size_t>(x) * WAVE + lane];
+    }
+    __device__ __forceinline__ cplx<T> pick(uint32_t r, const cplx<T> &rowval) const {
+        return (r >> 30) == TAG_NODE ? rowval : value(r);
+    }
+
+    __device__ __forceinline__ cplx<T> value(uint32_t r) const {
+        const uint32_t tag = r >> 30, x = r & REF_MASK;
+        if (tag == TAG_NODE) return val[static_cast<size_t>(x) * WAVE + lane];
+        if (tag == TAG_IND) {
+            const uint32_t u = (r >> 26) & 15u, width = ((r >> 24) & 3u) + 1u;
+            const uint32_t word = (r >> 6) & 0x3ffffu, shift = r & 63u;
+            const bool hit = ((ev[word * WAVE + lane] >> shift) & ((1ull << width) - 1ull)) == static_cast<uint64_t>(u);
+            return {hit ? T(1) : T(0), T(0)};
+        }
+        if (tag == TAG_SLOT) return x < static_cast<uint32_t>(g.S_ang) ? ang[x * WAVE + lane] : wfix[x];
+        const uint32_t *rec = g.sel + static_cast<size_t>(x) * SEL_REC;
+        const uint32_t fld = rec[0];
+        const uint32_t word = fld >> 8, shift = (fld >> 2) & 63u, width = (fld & 3u) + 1u;
+        const uint32_t k = static_cast<uint32_t>((ev[word * WAVE + lane] >> shift) & ((1ull << width) - 1ull));
+        const uint32_t s0 = rec[1], s1 = rec[2], s2 = rec[3], s3 = rec[4];
+        const uint32_t sl = k == 0 ? s0 : k == 1 ? s1 : k == 2 ? s2 : k == 3 ? s3 : NO_SLOT;
+        return sl == NO_SLOT ? cplx<T>{T(0), T(0)} : wfix[sl];
+    }
+
+    // sum of adj[parent] * value(sibling) over the parent edges of a record
+    __device__ __forceinline__ cplx<T> pull(const LdsPlan &lp, const uint4 br) const {
+        double ar = 0.0, ai = 0.0;
+        for (uint32_t q = 0; q < br.x; ++q) {
+            uint32_t p = br.z, sb = br.w;
+            if (q > 0) {
+                const uint64_t rr = lp.orec[br.y + q - 1];
+                p = static_cast<uint32_t>(rr);
+                sb = static_cast<uint32_t>(rr >> 32);
+            }
+            cplx<T> t = adj[static_cast<size_t>(p) * WAVE + lane];
+            if (sb != NO_SIBLING) t = cmul(t, value(sb));
+            ar += static_cast<double>(t.re);
+            ai += static_cast<double>(t.im);
+        }
+        return {static_cast<T>(ar), static_cast<T>(ai)};
+    }
+
+    __device__ void forward(const LdsPlan &lp, int wave, int nwaves) {
+        constexpr int KB = sizeof(T) == 4 ? 8 : 4;
+        for (int l = 0; l < lp.L; ++l) {
+            const uint32_t n0 = lp.level_ptr[l], n1 = lp.level_ptr[l + 1], np = lp.level_prod[l];
+            for (uint32_t b0 = n0 + static_cast<uint32_t>(wave) * KB; b0 < n1; b0 += static_cast<uint32_t>(nwaves) * KB) {
+                uint64_t rec[KB];
+                cplx<T> va[KB], vb[KB];
+#pragma unroll
+                for (int j = 0; j < KB; ++j) rec[j] = b0 + j < n1 ? lp.fwd[b0 + j] : ~0ull;
+#pragma unroll
+                for (int j = 0; j < KB; ++j) {
+                    va[j] = row(val, static_cast<uint32_t>(rec[j]));
+                    vb[j] = row(val, static_cast<uint32_t>(rec[j] >> 32));
+                }
+#pragma unroll
+                for (int j = 0; j < KB; ++j) {
+                    const uint32_t ra = static_cast<uint32_t>(rec[j]), rb = static_cast<uint32_t>(rec[j] >> 32);
+                    const bool prod = b0 + j >= np;
+                    va[j] = b0 + j < n1 ? pick(ra, va[j]) : cplx<T>{T(0), T(0)};
+                    vb[j] = rb != IDENT_REF ? pick(rb, vb[j]) : cplx<T>{prod ? T(1) : T(0), T(0)};
+                }
+#pragma unroll
+                for (int j = 0; j < KB; ++j) {
+                    if (b0 + j < n1)
+                        val[static_cast<size_t>(b0 + j) * WAVE + lane] = b0 + j >= np ? cmul(va[j], vb[j]) : cadd(va[j], vb[j]);
+                }
+            }
+            __syncthreads();
+        }
+    }
+
+    __device__ void backward(const LdsPlan &lp, int wave, int nwaves) {
+        constexpr int KB = sizeof(T) == 4 ? 8 : 4;
+        const uint4 *brec = reinterpret_cast<const uint4 *>(lp.brec);
+        for (int l = lp.L - 1; l >= 0; --l) {
+            const uint32_t n0 = lp.level_ptr[l], n1 = lp.level_ptr[l + 1];
+            for (uint32_t b0 = n0 + static_cast<uint32_t>(wave) * KB; b0 < n1; b0 += static_cast<uint32_t>(nwaves) * KB) {
+                uint4 br[KB];
+                cplx<T> ap[KB], sv[KB];
+#pragma unroll
+                for (int j = 0; j < KB; ++j) br[j] = b0 + j < n1 ? brec[b0 + j] : uint4{0, 0, 0, NO_SIBLING};
+#pragma unroll
+                for (int j = 0; j < KB; ++j) {
+                    ap[j] = adj[static_cast<size_t>(br[j].x > 0 ? br[j].z : 0u) * WAVE + lane];
+                    sv[j] = row(val, br[j].w);
+                }
+#pragma unroll
+                for (int j = 0; j < KB; ++j) {
+                    if (br[j].x == 0) ap[j] = {T(0), T(0)};
+                    sv[j] = (br[j].x > 0 && br[j].w != NO_SIBLING) ? pick(br[j].w, sv[j]) : cplx<T>{T(1), T(0)};
+                }
+#pragma unroll
+                for (int j = 0; j < KB; ++j) {
+                    const uint32_t i = b0 + j;
+                    if (i >= n1) continue;
+                    cplx<T> a;
+                    if (i == static_cast<uint32_t>(lp.root)) {
+                        a = {T(1), T(0)};
+                    } else {
+                        const cplx<T> t0 = cmul(ap[j], sv[j]);
+                        double ar = static_cast<double>(t0.re), ai = static_cast<double>(t0.im);
+                        for (uint32_t q = 1; q < br[j].x; ++q) {
+                            const uint64_t rr = lp.orec[br[j].y + q - 1];
+                            cplx<T> t = adj[static_cast<size_t>(static_cast<uint32_t>(rr)) * WAVE + lane];
+                            const uint32_t sb = static_cast<uint32_t>(rr >> 32);
+                            if (sb != NO_SIBLING) t = cmul(t, value(sb));
+                            ar += static_cast<double>(t.re);
+                            ai += static_cast<double>(t.im);
+                        }
+                        a = {static_cast<T>(ar), static_cast<T>(ai)};
+                    }
+                    adj[static_cast<size_t>(i) * WAVE + lane] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+
+    // adjoints of every indicator leaf (into D rows) and selector leaf (into
+    // A rows), batched like the downward pass; then the selector terms of
+    // d root / d lambda_{v=u} (A_q * W[slot_q(u)]) are added per variable
+    __device__ void leaf_derivatives(const LdsPlan &lp, int wave, int nwaves, cplx<T> *D, cplx<T> *A) {
+        constexpr int KB = sizeof(T) == 4 ? 8 : 4;
+        const uint4 *brec = reinterpret_cast<const uint4 *>(lp.brec);
+        const uint32_t nt = static_cast<uint32_t>(g.n_ind + g.n_sel);
+        for (uint32_t b0 = static_cast<uint32_t>(wave) * KB; b0 < nt; b0 += static_cast<uint32_t>(nwaves) * KB) {
+            uint4 br[KB];
+            cplx<T> ap[KB], sv[KB];
+#pragma unroll
+            for (int j = 0; j < KB; ++j) br[j] = b0 + j < nt ? brec[lp.N + b0 + j] : uint4{0, 0, 0, NO_SIBLING};
+#pragma unroll
+            for (int j = 0; j < KB; ++j) {
+                ap[j] = adj[static_cast<size_t>(br[j].x > 0 ? br[j].z : 0u) * WAVE + lane];
+                sv[j] = row(val, br[j].w);
+            }
+#pragma unroll
+            for (int j = 0; j < KB; ++j) {
+                const uint32_t t = b0 + j;
+                if (t >= nt) continue;
+                double ar = 0.0, ai = 0.0;
+                if (br[j].x > 0) {
+                    const cplx<T> s0 = br[j].w != NO_SIBLING ? pick(br[j].w, sv[j]) : cplx<T>{T(1), T(0)};
+                    const cplx<T> t0 = cmul(ap[j], s0);
+                    ar = static_cast<double>(t0.re);
+                    ai = static_cast<double>(t0.im);
+                    for (uint32_t q = 1; q < br[j].x; ++q) {
+                        const uint64_t rr = lp.orec[br[j].y + q - 1];
+                        cplx<T> tt = adj[static_cast<size_t>(static_cast<uint32_t>(rr)) * WAVE + lane];
+                        const uint32_t sb = static_cast<uint32_t>(rr >> 32);
+                        if (sb != NO_SIBLING) tt = cmul(tt, value(sb));
+                        ar += static_cast<double>(tt.re);
+                        ai += static_cast<double>(tt.im);
+                    }
+                }
+                const cplx<T> r = {static_cast<T>(ar), static_cast<T>(ai)};
+                if (t < static_cast<uint32_t>(g.n_ind)) D[static_cast<size_t>(t) * WAVE + lane] = r;
+                else A[static_cast<size_t>(t - g.n_ind) * WAVE + lane] = r;
+            }
+        }
+        __syncthreads();
+        for (int v = wave; v < g.n_vars; v += nwaves) {
+            const uint32_t base = g.ind_base[v], dom = g.ind_base[v + 1] - base;
+            const uint32_t q0 = g.vsel_ptr[v], q1 = g.vsel_ptr[v + 1];
+            if (q0 == q1) continue;
+            cplx<T> acc[SEL_DOM];
+#pragma unroll
+            for (int u = 0; u < SEL_DOM; ++u)
+                acc[u] = static_cast<uint32_t>(u) < dom ? D[static_cast<size_t>(base + u) * WAVE + lane] : cplx<T>{T(0), T(0)};
+            for (uint32_t qq = q0; qq < q1; ++qq) {
+                const uint32_t q = g.vsel[qq];
+                const cplx<T> Aq = A[static_cast<size_t>(q) * WAVE + lane];
+                const uint32_t *rec = g.sel + static_cast<size_t>(q) * SEL_REC;
+#pragma unroll
+                for (int u = 0; u < SEL_DOM; ++u) {
+                    const uint32_t sl = rec[1 + u];
+                    if (sl != NO_SLOT) acc[u] = cadd(acc[u], cmul(Aq, wfix[sl]));
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < SEL_DOM; ++u)
+                if (static_cast<uint32_t>(u) < dom) D[static_cast<size_t>(base + u) * WAVE + lane] = acc[u];
+        }
+    }
+
+    // d root / d lambda_{v=u} for the values of variable v -> out[(base+u) * WAVE]
+    __device__ void ind_derivatives(const LdsPlan &lp, int v, cplx<T> *out) const {
+        const uint4 *brec = reinterpret_cast<const uint4 *>(lp.brec);
+        const uint32_t base = g.ind_base[v], dom = g.ind_base[v + 1] - base;
+        for (uint32_t u = 0; u < dom; ++u) out[static_cast<size_t>(base + u) * WAVE] = pull(lp, brec[lp.N + base + u]);
+        const uint32_t q1 = g.vsel_ptr[v + 1];
+        for (uint32_t qq = g.vsel_ptr[v]; qq < q1; ++qq) {
+            const uint32_t q = g.vsel[qq];
+            const cplx<T> A = pull(lp, brec[lp.N + g.n_ind + q]);
+            const uint32_t *rec = g.sel + static_cast<size_t>(q) * SEL_REC;
+            for (uint32_t u = 0; u < dom && u < static_cast<uint32_t>(SEL_DOM); ++u) {
+                const uint32_t sl = rec[1 + u];
+                if (sl == NO_SLOT) continue;
+                cplx<T> &o = out[static_cast<size_t>(base + u) * WAVE];
+                o = cadd(o, cmul(A, wfix[sl]));
+            }
+        }
+    }
+};
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_sample_stream(DevGraph g, LdsPlan lp, const double *theta,
+                                                         const cplx<T> *wfix, cplx<T> *vals, size_t per_wg,
+                                                         SampleArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint64_t *ev_s = reinterpret_cast<uint64_t *>(smem);
+    cplx<T> *ang_s = reinterpret_cast<cplx<T> *>(smem + static_cast<size_t>(g.W) * WAVE * 8);
+    cplx<T> *fix_s = ang_s + static_cast<size_t>(g.S_ang) * WAVE;
+    __shared__ int64_t s_chain[WAVE];
+    __shared__ int32_t s_pos[WAVE];
+    __shared__ uint32_t s_sweep[WAVE];
+    __shared__ int32_t s_emitted[WAVE];
+    __shared__ int64_t s_rounds[WAVE];
+
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wave = static_cast<int>(uniform_u32(threadIdx.x / WAVE));
+    const int nwaves = blockDim.x / WAVE;
+    cplx<T> *val = vals + per_wg * blockIdx.x;
+    cplx<T> *adj = val + static_cast<size_t>(lp.N) * WAVE;
+    cplx<T> *D = adj + static_cast<size_t>(lp.N) * WAVE;    // [n_ind][64]
+    cplx<T> *Asel = D + static_cast<size_t>(g.n_ind) * WAVE;  // [n_sel][64]
+    for (int s2 = threadIdx.x; s2 < g.S; s2 += blockDim.x) fix_s[s2] = wfix[s2];
+    StreamTile<T> t{g, val, adj, ev_s, ang_s, fix_s, lane};
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * WAVE;
+    const uint32_t total_sweeps = static_cast<uint32_t>(a.burn_in) +
+                                  static_cast<uint32_t>(a.spc) * static_cast<uint32_t>(a.thin);
+    const uint64_t xmask = g.n_qubits >= 64 ? ~0ull : ((1ull << g.n_qubits) - 1ull);
+
+    auto init_chain = [&](int64_t ch) {      // wave 0
+        s_chain[lane] = ch;
+        s_pos[lane] = 0;
+        s_sweep[lane] = 0;
+        s_emitted[lane] = 0;
+        s_rounds[lane] = 0;
+        for (int w = 0; w < g.W; ++w) ev_s[w * WAVE + lane] = 0ull;
+        if (ch >= 0) {
+            uint64_t x = 0;
+            for (int q = 0; q < g.n_qubits; ++q)
+                if (rng_uniform(a.seed, static_cast<uint64_t>(ch), INIT_SWEEP, static_cast<uint64_t>(q)) < 0.5)
+                    x |= (1ull << q);
+            ev_s[lane] = x;
+        }
+    };
+
+    if (wave == 0) {
+        const int64_t ch = static_cast<int64_t>(blockIdx.x) * WAVE + lane;
+        init_chain(ch < a.total_chains ? ch : -1);
+    }
+    __syncthreads();
+
+    for (;;) {
+        const int64_t ch = s_chain[lane];
+        if (!__syncthreads_or(ch >= 0 ? 1 : 0)) break;
+        const int p = ch >= 0 ? static_cast<int>(ch / a.cpp) : 0;
+        const double *trow = theta + static_cast<int64_t>(p) * g.K;
+        for (int s2 = wave; s2 < g.S_ang; s2 += nwaves) {
+            double re, im;
+            slot_value(g.slots[s2], trow, nullptr, re, im);
+            ang_s[s2 * WAVE + lane] = {static_cast<T>(re), static_cast<T>(im)};
+        }
+        __syncthreads();
+        t.forward(lp, wave, nwaves);
+        t.backward(lp, wave, nwaves);
+        t.leaf_derivatives(lp, wave, nwaves, D, Asel);
+        __syncthreads();
+
+        if (wave == 0 && ch >= 0) {
+            s_rounds[lane] += 1;
+            int32_t pos = s_pos[lane];
+            uint32_t sweep = s_sweep[lane];
+            int32_t emitted = s_emitted[lane];
+            bool done = false;
+            // Gibbs weights of the next PF variables, loaded together (the
+            // derivatives do not change until the state does)
+            constexpr int PF = 4;
+            double wpf[PF][SEL_DOM];
+            int pf_pos = -1;
+            for (;;) {
+                const int v = pos;
+                if (pf_pos < 0 || v < pf_pos || v >= pf_pos + PF) {
+                    pf_pos = v;
+                    cplx<T> dv[PF][SEL_DOM];
+#pragma unroll
+                    for (int k = 0; k < PF; ++k) {
+                        const int vk = v + k < g.n_vars ? v + k : v;
+                        const uint32_t bk = g.ind_base[vk], dk = g.ind_base[vk + 1] - bk;
+#pragma unroll
+                        for (int u = 0; u < SEL_DOM; ++u)
+                            dv[k][u] = D[static_cast<size_t>(bk + (static_cast<uint32_t>(u) < dk ? u : 0)) * WAVE + lane];
+                    }
+#pragma unroll
+                    for (int k = 0; k < PF; ++k)
+#pragma unroll
+                        for (int u = 0; u < SEL_DOM; ++u) {
+                            const double re = static_cast<double>(dv[k][u].re), im = static_cast<double>(dv[k][u].im);
+                            wpf[k][u] = __dadd_rn(__dmul_rn(re, re), __dmul_rn(im, im));
+                        }
+                }
+                const uint32_t fld = g.var_field[v];
+                const uint32_t word = fld >> 8, shift = (fld >> 2) & 63u, width = (fld & 3u) + 1u;
+                const uint64_t fmask = (1ull << width) - 1ull;
+                const uint32_t cur = static_cast<uint32_t>((ev_s[word * WAVE + lane] >> shift) & fmask);
+                const uint32_t base = g.ind_base[v];
+                const int dom = static_cast<int>(g.ind_base[v + 1] - base);
+                const int kk = v - pf_pos;
+                auto weight = [&](int u) -> double {
+                    if (u < SEL_DOM) {
+                        double w = 0.0;
+#pragma unroll
+                        for (int k = 0; k < PF; ++k)
+#pragma unroll
+                            for (int u2 = 0; u2 < SEL_DOM; ++u2)
+                                if (k == kk && u2 == u) w = wpf[k][u2];
+                        return w;
+                    }
+                    const cplx<T> d = D[static_cast<size_t>(base + u) * WAVE + lane];
+                    const double re = static_cast<double>(d.re), im = static_cast<double>(d.im);
+                    return __dadd_rn(__dmul_rn(re, re), __dmul_rn(im, im));
+                };
+                double total = 0.0;
+                for (int u = 0; u < dom; ++u) total = __dadd_rn(total, weight(u));
+                uint32_t pick = cur;
+                if (total > 0.0) {
+                    const double r = rng_uniform(a.seed, static_cast<uint64_t>(ch), sweep, static_cast<uint64_t>(v));
+                    const double target = __dmul_rn(r, total);
+                    double acc = 0.0;
+                    int last_pos = -1, chosen = -1;
+                    for (int u = 0; u < dom; ++u) {
+                        const double w = weight(u);
+                        acc = __dadd_rn(acc, w);
+                        if (w > 0.0) last_pos = u;
+                        if (target < acc) {
+                            chosen = u;
+                            break;
+                        }
+                    }
+                    if (chosen < 0) chosen = last_pos;
+                    if (chosen >= 0) pick = static_cast<uint32_t>(chosen);
+                }
+                const bool changed = pick != cur;
+                if (changed) {
+                    uint64_t wv = ev_s[word * WAVE + lane];
+                    ev_s[word * WAVE + lane] = (wv & ~(fmask << shift)) | (static_cast<uint64_t>(pick) << shift);
+                }
+                pos += 1;
+                if (pos == g.n_vars) {
+                    pos = 0;
+                    sweep += 1;
+                    if (sweep > static_cast<uint32_t>(a.burn_in) &&
+                        (sweep - static_cast<uint32_t>(a.burn_in)) % static_cast<uint32_t>(a.thin) == 0u) {
+                        const int64_t S = static_cast<int64_t>(a.cpp) * a.spc;
+                        const int64_t idx = static_cast<int64_t>(p) * S + (ch % a.cpp) * a.spc + emitted;
+                        const uint64_t x = ev_s[lane] & xmask;
+                        a.samples[idx * a.nwq] = x;
+                        for (int w2 = 1; w2 < a.nwq; ++w2) a.samples[idx * a.nwq + w2] = 0ull;
+                        if (a.states_out)
+                            for (int w2 = 0; w2 < g.W; ++w2) a.states_out[idx * g.W + w2] = ev_s[w2 * WAVE + lane];
+                        if (a.cost_out) {
+                            int cst = 0;
+                            for (int e = 0; e < a.n_cost_edges; ++e) {
+                                const int i0 = a.cost_edges[2 * e], i1 = a.cost_edges[2 * e + 1];
+                                cst += static_cast<int>(((x >> i0) ^ (x >> i1)) & 1ull);
+                            }
+                            a.cost_out[idx] = static_cast<double>(cst);
+                        }
+                        emitted += 1;
+                    }
+                    if (sweep >= total_sweeps) {
+                        done = true;
+                        break;
+                    }
+                }
+                if (changed) break;
+            }
+            if (done) {
+                if (a.rounds_out) a.rounds_out[ch] = s_rounds[lane];
+                const int64_t nxt = ch + stride;
+                init_chain(nxt < a.total_chains ? nxt : -1);
+            } else {
+                s_pos[lane] = pos;
+                s_sweep[lane] = sweep;
+                s_emitted[lane] = emitted;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Gibbs sampler, LDS-resident node-parallel variant
+// ---------------------------------------------------------------------------
+//
+// One wavefront works on CPW chains at once; each chain owns 64/CPW lanes and
+// a private LDS block holding every node value and adjoint of the DAG plan,
+// the indicator derivatives, its weights, its evidence words and its
+// bookkeeping.  Lanes split the nodes of a level, so nothing but the DAG
+// structure (read-only, cached) and the outputs touches global memory.
+
+__host__ __device__ inline size_t al16(size_t x) { return (x + 15) & ~static_cast<size_t>(15); }
+
+template <typename T>
+__host__ __device__ inline size_t chain_values(int N, int n_ind, int S, int n_sel, int max_edges) {
+    return 2 * static_cast<size_t>(N) + n_ind + S + n_sel + max_edges;
+}
+
+template <typename T>
+__host__ __device__ inline size_t chain_lds_bytes(int N, int n_ind, int S, int n_sel, int max_edges, int W) {
+    return al16(al16(chain_values<T>(N, n_ind, S, n_sel, max_edges) * sizeof(cplx<T>)) + static_cast<size_t>(W) * 8 +
+                8 * 8);
+}
+
+// per-workgroup level table in LDS: level_ptr[L+1], level_prod[L+1], first edge[L+1]
+__host__ __device__ inline size_t level_meta_bytes(int L) { return al16(3 * (static_cast<size_t>(L) + 1) * 4); }
+
+template <typename T>
+struct ChainView {
+    cplx<T> *val, *adj, *D, *sv, *selv, *tmp;
+    uint64_t *ev;
+    int64_t *st;      // 0 chain (-1: none), 1 pos, 2 sweep, 3 emitted, 4 rounds, 5 param set, 6 restage
+
+    __device__ __forceinline__ bool ind_hit(uint32_t r) const {
+        const uint32_t u = (r >> 26) & 15u, width = ((r >> 24) & 3u) + 1u;
+        const uint32_t word = (r >> 6) & 0x3ffffu, shift = r & 63u;
+        return ((ev[word] >> shift) & ((1ull << width) - 1ull)) == static_cast<uint64_t>(u);
+    }
+    __device__ __forceinline__ cplx<T> value(uint32_t r) const {
+        const uint32_t tag = r >> 30;
+        if (tag == TAG_NODE) return val[r & REF_MASK];
+        if (tag == TAG_IND) return {ind_hit(r) ? T(1) : T(0), T(0)};
+        if (tag == TAG_SEL) return selv[r & REF_MASK];
+        return sv[r & REF_MASK];
+    }
+    // unified reference (index into [node | slot | selector] values, or an
+    // indicator): both loads are issued unconditionally and the result is
+    // selected, so lanes holding different kinds of children do not serialise
+    __device__ __forceinline__ cplx<T> uval(uint32_t r) const {
+        const uint32_t tag = r >> 30;
+        const cplx<T> v = val[tag == TAG_NODE ? r : 0u];
+        const uint32_t word = tag == TAG_IND ? ((r >> 6) & 0x3ffffu) : 0u;
+        const uint64_t w = ev[word];
+        const uint32_t u = (r >> 26) & 15u, width = ((r >> 24) & 3u) + 1u, shift = r & 63u;
+        const bool hit = ((w >> shift) & ((1ull << width) - 1ull)) == static_cast<uint64_t>(u);
+        if (tag == TAG_IND) return {hit ? T(1) : T(0), T(0)};
+        return v;
+    }
+};
+
+// Output of one emitted sample (the state words are read from `ev`, except
+// that word `cw` is replaced by `cval` when cw < W).
+__device__ inline void emit_sample(const DevGraph &g, const SampleArgs &a, int64_t idx, const uint64_t *ev,
+                                   int cw, uint64_t cval, uint64_t xmask) {
+    const uint64_t w0 = cw == 0 ? cval : ev[0];
+    const uint64_t x = w0 & xmask;
+    a.samples[idx * a.nwq] = x;
+    for (int w2 = 1; w2 < a.nwq; ++w2) a.samples[idx * a.nwq + w2] = 0ull;
+    if (a.states_out)
+        for (int w2 = 0; w2 < g.W; ++w2) a.states_out[idx * g.W + w2] = w2 == cw ? cval : ev[w2];
+    if (a.cost_out) {
+        int cst = 0;
+        for (int e = 0; e < a.n_cost_edges; ++e) {
+            const int i0 = a.cost_edges[2 * e], i1 = a.cost_edges[2 * e + 1];
+            cst += static_cast<int>(((x >> i0) ^ (x >> i1)) & 1ull);
+        }
+        a.cost_out[idx] = static_cast<double>(cst);
+    }
+}
+
+// The LDS-resident kernels run one wavefront per workgroup: the LDS accesses
+// of a wave execute in order, so lanes only need the compiler to keep program
+// order here.  A wavefront-scope fence does that without waiting for
+// outstanding global loads (a workgroup barrier would also wait for the
+// records prefetched for later levels).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+template <typename T, int CPW>
+__global__ __launch_bounds__(WAVE) void k_sample_lds(DevGraph g, LdsPlan lp, const double *theta,
+                                                     const double *noise, SampleArgs a, uint32_t chain_bytes) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int LPC = WAVE / CPW;
+    const int lane = threadIdx.x;
+    const int sub = lane / LPC;
+    const int cl = lane - sub * LPC;
+    const int L = lp.L;
+    uint32_t *lv_ptr = reinterpret_cast<uint32_t *>(smem);
+    uint32_t *lv_prod = lv_ptr + (L + 1);
+    uint32_t *lv_edge = lv_prod + (L + 1);
+    for (int l = lane; l <= L; l += WAVE) {
+        lv_ptr[l] = lp.level_ptr[l];
+        lv_prod[l] = l < L ? lp.level_prod[l] : lp.level_ptr[L];
+        lv_edge[l] = lp.estart[lp.level_ptr[l]];
+    }
+    unsigned char *blk = smem + level_meta_bytes(L) + static_cast<size_t>(sub) * chain_bytes;
+    ChainView<T> c;
+    c.val = reinterpret_cast<cplx<T> *>(blk);      // [node | slot | selector] values
+    c.sv = c.val + lp.N;
+    c.selv = c.sv + g.S;
+    c.adj = c.selv + g.n_sel;
+    c.D = c.adj + lp.N;
+    c.tmp = c.D + g.n_ind;
+    c.ev = reinterpret_cast<uint64_t *>(
+        blk + al16(chain_values<T>(lp.N, g.n_ind, g.S, g.n_sel, lp.max_edges) * sizeof(cplx<T>)));
+    c.st = reinterpret_cast<int64_t *>(c.ev + g.W);
+    const double *nz = noise ? noise : g.noise_default;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * CPW;
+    const uint32_t total_sweeps = static_cast<uint32_t>(a.burn_in) +
+                                  static_cast<uint32_t>(a.spc) * static_cast<uint32_t>(a.thin);
+    const uint64_t xmask = g.n_qubits >= 64 ? ~0ull : ((1ull << g.n_qubits) - 1ull);
+    const int shift_sub = sub * LPC;
+    const uint64_t gmask = LPC == WAVE ? ~0ull : (((1ull << LPC) - 1ull) << shift_sub);
+    const uint32_t T_all = static_cast<uint32_t>(lp.N + g.n_ind + g.n_sel);
+    const uint32_t leaf_e0 = lp.estart[lp.N], leaf_e1 = lp.estart[T_all];
+
+    auto init_chain = [&](int64_t ch) {      // lane cl == 0 of the chain group
+        c.st[0] = ch;
+        c.st[1] = 0;
+        c.st[2] = 0;
+        c.st[3] = 0;
+        c.st[4] = 0;
+        c.st[5] = ch >= 0 ? ch / a.cpp : 0;
+        c.st[6] = 1;
+        for (int w = 0; w < g.W; ++w) c.ev[w] = 0ull;
+        if (ch >= 0) {
+            uint64_t x = 0;
+            for (int q = 0; q < g.n_qubits; ++q)
+                if (rng_uniform(a.seed, static_cast<uint64_t>(ch), INIT_SWEEP, static_cast<uint64_t>(q)) < 0.5)
+                    x |= (1ull << q);
+            c.ev[0] = x;
+        }
+    };
+    // adj[parent] * value(sibling) of one parent edge
+    auto edge_term = [&](uint64_t rr) {
+        const cplx<T> t = c.adj[static_cast<uint32_t>(rr)];
+        const uint32_t sib = static_cast<uint32_t>(rr >> 32);
+        const cplx<T> sv = c.uval(sib);
+        return sib == NO_SIBLING ? t : cmul(t, sv);
+    };
+    auto sum_tmp = [&](uint32_t s0, uint32_t s1) {
+        double ar = 0.0, ai = 0.0;
+        for (uint32_t q = s0; q < s1; ++q) {
+            ar += static_cast<double>(c.tmp[q].re);
+            ai += static_cast<double>(c.tmp[q].im);
+        }
+        return cplx<T>{static_cast<T>(ar), static_cast<T>(ai)};
+    };
+    // first record of level l for this lane (prefetch helpers)
+    auto fwd_first = [&](int l) -> uint64_t {
+        if (l >= L) return ~0ull;
+        const uint32_t i = lv_ptr[l] + cl;
+        return i < lv_ptr[l + 1] ? lp.fwd_u[i] : ~0ull;
+    };
+    auto edge_first = [&](int l) -> uint64_t {
+        if (l < 0) return 0ull;
+        const uint32_t e = lv_edge[l] + cl;
+        return e < lv_edge[l + 1] ? lp.edg_u[e] : 0ull;
+    };
+    auto bound_first = [&](int l) -> uint64_t {
+        if (l < 0) return 0ull;
+        const uint32_t i = lv_ptr[l] + cl;
+        return i < lv_ptr[l + 1] ? (static_cast<uint64_t>(lp.estart[i]) | (static_cast<uint64_t>(lp.estart[i + 1]) << 32))
+                                 : 0ull;
+    };
+
+    if (cl == 0) {
+        const int64_t ch = static_cast<int64_t>(blockIdx.x) * CPW + sub;
+        init_chain(ch < a.total_chains ? ch : -1);
+    }
+    wave_sync();
+
+    for (;;) {
+        if (c.st[6] != 0) {                  // weights of a chain that just started
+            const double *trow = theta + c.st[5] * g.K;
+            for (int s = cl; s < g.S; s += LPC) {
+                double re, im;
+                slot_value(g.slots[s], trow, nz, re, im);
+                c.sv[s] = {static_cast<T>(re), static_cast<T>(im)};
+            }
+        }
+        wave_sync();
+        if (cl == 0) c.st[6] = 0;
+        const bool active = c.st[0] >= 0;
+        if (__ballot(active) == 0ull) break;
+
+        // ---- selector leaves of this round's state
+        if (active) {
+            for (int q = cl; q < g.n_sel; q += LPC) {
+                const uint4 sr = *reinterpret_cast<const uint4 *>(g.sel + static_cast<size_t>(q) * SEL_REC);
+                const uint32_t s4 = g.sel[static_cast<size_t>(q) * SEL_REC + 4];
+                const uint32_t word = sr.x >> 8, shift = (sr.x >> 2) & 63u, width = (sr.x & 3u) + 1u;
+                const uint32_t k = static_cast<uint32_t>((c.ev[word] >> shift) & ((1ull << width) - 1ull));
+                const uint32_t sl = k == 0 ? sr.y : k == 1 ? sr.z : k == 2 ? sr.w : k == 3 ? s4 : NO_SLOT;
+                c.selv[q] = sl == NO_SLOT ? cplx<T>{T(0), T(0)} : c.sv[sl];
+            }
+        }
+        wave_sync();
+
+        // ---- upward pass; the first record of a level is loaded two levels ahead
+        {
+            uint64_t r0 = active ? fwd_first(0) : ~0ull;
+            uint64_t r1 = active ? fwd_first(1) : ~0ull;
+            for (int l = 0; l < L; ++l) {
+                const uint64_t r2 = active ? fwd_first(l + 2) : ~0ull;
+                const uint32_t n1 = lv_ptr[l + 1], np = lv_prod[l];
+                if (active) {
+                    uint64_t rec = r0;
+                    for (uint32_t i = lv_ptr[l] + cl; i < n1; i += LPC) {
+                        const uint32_t inext = i + LPC;
+                        const uint64_t rnext = inext < n1 ? lp.fwd_u[inext] : ~0ull;
+                        const uint32_t ra = static_cast<uint32_t>(rec), rb = static_cast<uint32_t>(rec >> 32);
+                        const cplx<T> va = c.uval(ra);
+                        const cplx<T> vb = c.uval(rb);
+                        const bool prod = i >= np;
+                        const cplx<T> pr = cmul(va, vb), sm = cadd(va, vb);
+                        c.val[i] = rb == IDENT_REF ? va : (prod ? pr : sm);
+                        rec = rnext;
+                    }
+                }
+                r0 = r1;
+                r1 = r2;
+                wave_sync();
+            }
+        }
+        // ---- downward pass, level by level: every parent edge of the level's
+        // nodes in parallel into tmp, then each node sums its edge range
+        {
+            uint64_t e0r = active ? edge_first(L - 1) : 0ull, e1r = active ? edge_first(L - 2) : 0ull;
+            uint64_t b0r = active ? bound_first(L - 1) : 0ull, b1r = active ? bound_first(L - 2) : 0ull;
+            for (int l = L - 1; l >= 0; --l) {
+                const uint64_t e2r = active ? edge_first(l - 2) : 0ull;
+                const uint64_t b2r = active ? bound_first(l - 2) : 0ull;
+                const uint32_t eb0 = lv_edge[l], eb1 = lv_edge[l + 1];
+                if (active) {
+                    uint64_t rr = e0r;
+                    for (uint32_t e = eb0 + cl; e < eb1; e += LPC) {
+                        const uint32_t enext = e + LPC;
+                        const uint64_t rnext = enext < eb1 ? lp.edg_u[enext] : 0ull;
+                        c.tmp[e - eb0] = edge_term(rr);
+                        rr = rnext;
+                    }
+                }
+                wave_sync();
+                if (active) {
+                    const uint32_t n1 = lv_ptr[l + 1];
+                    uint64_t bb = b0r;
+                    for (uint32_t i = lv_ptr[l] + cl; i < n1; i += LPC) {
+                        const uint32_t inext = i + LPC;
+                        const uint64_t bnext =
+                            inext < n1 ? (static_cast<uint64_t>(lp.estart[inext]) |
+                                          (static_cast<uint64_t>(lp.estart[inext + 1]) << 32))
+                                       : 0ull;
+                        c.adj[i] = i == static_cast<uint32_t>(lp.root)
+                                       ? cplx<T>{T(1), T(0)}
+                                       : sum_tmp(static_cast<uint32_t>(bb) - eb0, static_cast<uint32_t>(bb >> 32) - eb0);
+                        bb = bnext;
+                    }
+                }
+                e0r = e1r;
+                e1r = e2r;
+                b0r = b1r;
+                b1r = b2r;
+                wave_sync();
+            }
+            // leaves: every parent edge of indicator and selector leaves, then
+            // d root / d lambda_{v=u} per variable
+            if (active) {
+                for (uint32_t e = leaf_e0 + cl; e < leaf_e1; e += LPC) c.tmp[e - leaf_e0] = edge_term(lp.edg_u[e]);
+            }
+            wave_sync();
+            if (active) {
+                for (int t0 = cl; t0 < g.n_ind; t0 += LPC) {
+                    double ar = 0.0, ai = 0.0;
+                    const uint32_t j1 = lp.dstart[t0 + 1];
+                    for (uint32_t j = lp.dstart[t0]; j < j1; ++j) {
+                        const uint64_t dt = lp.dterm[j];
+                        const uint32_t sl = static_cast<uint32_t>(dt >> 32);
+                        const cplx<T> term = c.tmp[static_cast<uint32_t>(dt)];
+                        const cplx<T> wv = c.sv[sl == NO_SLOT ? 0u : sl];
+                        const cplx<T> x = sl == NO_SLOT ? term : cmul(term, wv);
+                        ar += static_cast<double>(x.re);
+                        ai += static_cast<double>(x.im);
+                    }
+                    c.D[t0] = {static_cast<T>(ar), static_cast<T>(ai)};
+                }
+            }
+            wave_sync();
+        }
+
+        // ---- Gibbs decisions: lane k decides the k-th next variable of the
+        // scan; the first lane whose decision changes the state ends the round.
+        if (active) {
+            const int64_t ch = c.st[0];
+            const int p = static_cast<int>(c.st[5]);
+            int64_t pos = c.st[1];
+            uint32_t sweep = static_cast<uint32_t>(c.st[2]);
+            int32_t emitted = static_cast<int32_t>(c.st[3]);
+            const int V = g.n_vars;
+            const int64_t S = static_cast<int64_t>(a.cpp) * a.spc;
+            const int64_t out0 = static_cast<int64_t>(p) * S + (ch % a.cpp) * a.spc;
+            bool done = false;
+            for (;;) {
+                const int64_t t = pos + cl;
+                const uint32_t sw = sweep + static_cast<uint32_t>(t / V);
+                const int v = static_cast<int>(t % V);
+                const bool valid = sw < total_sweeps;
+                uint32_t cur = 0, pick = 0, word = 0, shift = 0;
+                uint64_t fmask = 0;
+                if (valid) {
+                    const uint32_t fld = g.var_field[v];
+                    word = fld >> 8;
+                    shift = (fld >> 2) & 63u;
+                    fmask = (1ull << ((fld & 3u) + 1u)) - 1ull;
+                    cur = static_cast<uint32_t>((c.ev[word] >> shift) & fmask);
+                    pick = cur;
+                    const uint32_t base = g.ind_base[v];
+                    const int dom = static_cast<int>(g.ind_base[v + 1] - base);
+                    double total = 0.0;
+                    for (int u = 0; u < dom; ++u) {
+                        const cplx<T> d = c.D[base + u];
+                        const double re = static_cast<double>(d.re), im = static_cast<double>(d.im);
+                        total = __dadd_rn(total, __dadd_rn(__dmul_rn(re, re), __dmul_rn(im, im)));
+                    }
+                    if (total > 0.0) {
+                        const double r = rng_uniform(a.seed, static_cast<uint64_t>(ch), sw, static_cast<uint64_t>(v));
+                        const double target = __dmul_rn(r, total);
+                        double acc = 0.0;
+                        int last_pos = -1, chosen = -1;
+                        for (int u = 0; u < dom; ++u) {
+                            const cplx<T> d = c.D[base + u];
+                            const double re = static_cast<double>(d.re), im = static_cast<double>(d.im);
+                            const double w = __dadd_rn(__dmul_rn(re, re), __dmul_rn(im, im));
+                            acc = __dadd_rn(acc, w);
+                            if (w > 0.0) last_pos = u;
+                            if (target < acc) {
+                                chosen = u;
+                                break;
+                            }
+                        }
+                        if (chosen < 0) chosen = last_pos;
+                        if (chosen >= 0) pick = static_cast<uint32_t>(chosen);
+                    }
+                }
+                const bool changed = valid && pick != cur;
+                const uint64_t chg = (__ballot(changed) & gmask) >> shift_sub;
+                const uint64_t vld = (__ballot(valid) & gmask) >> shift_sub;
+                const int f = chg ? __ffsll(static_cast<unsigned long long>(chg)) - 1 : -1;
+                const int last = vld ? 63 - __clzll(static_cast<unsigned long long>(vld)) : -1;
+                const int end = f >= 0 ? f : last;
+                bool emit = false;
+                if (valid && cl <= end && v == V - 1) {
+                    const uint32_t done_sw = sw + 1;
+                    emit = done_sw > static_cast<uint32_t>(a.burn_in) &&
+                           (done_sw - static_cast<uint32_t>(a.burn_in)) % static_cast<uint32_t>(a.thin) == 0u;
+                }
+                const uint64_t em = (__ballot(emit) & gmask) >> shift_sub;
+                const uint64_t newword = (cl == f) ? ((c.ev[word] & ~(fmask << shift)) |
+                                                      (static_cast<uint64_t>(pick) << shift)) : 0ull;
+                if (emit) {
+                    const int rank = __popcll(static_cast<unsigned long long>(em & ((1ull << cl) - 1ull)));
+                    emit_sample(g, a, out0 + emitted + rank, c.ev, cl == f ? static_cast<int>(word) : g.W,
+                                newword, xmask);
+                }
+                emitted += __popcll(static_cast<unsigned long long>(em));
+                // one wavefront per workgroup: LDS accesses of the wave execute in
+                // order; the fences keep the compiler from reordering them and wait
+                // for completion (every emission reads the old state first)
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+                if (cl == f) c.ev[word] = newword;
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+                if (end < 0) {                   // nothing left to decide
+                    done = true;
+                    break;
+                }
+                const int64_t tn = pos + end + 1;
+                sweep += static_cast<uint32_t>(tn / V);
+                pos = tn % V;
+                if (sweep >= total_sweeps) {
+                    done = true;
+                    break;
+                }
+                if (f >= 0) break;
+            }
+            if (cl == 0) {
+                c.st[4] += 1;
+                if (done) {
+                    if (a.rounds_out) a.rounds_out[ch] = c.st[4];
+                    const int64_t nxt = ch + stride;
+                    init_chain(nxt < a.total_chains ? nxt : -1);
+                } else {
+                    c.st[1] = pos;
+                    c.st[2] = sweep;
+                    c.st[3] = emitted;
+                }
+            }
+        }
+        wave_sync();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // launch wrappers (called by the host runtime)
 // ---------------------------------------------------------------------------
 
@@ -632,6 +1496,59 @@ hipError_t launch_sample(const DevGraph &g, int grid, const double *theta, const
                        per_wg_elems, a);
     return hipGetLastError();
 }
+
+
+template <typename T>
+size_t sample_lds_chain_bytes(const DevGraph &g, const LdsPlan &lp) {
+    return chain_lds_bytes<T>(lp.N, g.n_ind, g.S, g.n_sel, lp.max_edges, g.W);
+}
+
+size_t sample_lds_meta_bytes(const LdsPlan &lp) { return level_meta_bytes(lp.L); }
+
+template <typename T, int CPW>
+hipError_t launch_sample_lds_cpw(const DevGraph &g, const LdsPlan &lp, int grid, const double *theta,
+                                 const double *noise, const SampleArgs &a, hipStream_t st) {
+    const uint32_t cb = static_cast<uint32_t>(chain_lds_bytes<T>(lp.N, g.n_ind, g.S, g.n_sel, lp.max_edges, g.W));
+    const size_t lds = static_cast<size_t>(cb) * CPW + level_meta_bytes(lp.L);
+    hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sample_lds<T, CPW>),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL((k_sample_lds<T, CPW>), dim3(grid), dim3(WAVE), lds, st, g, lp, theta, noise, a, cb);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_sample_lds(const DevGraph &g, const LdsPlan &lp, int cpw, int grid, const double *theta,
+                             const double *noise, const SampleArgs &a, hipStream_t st) {
+    switch (cpw) {
+        case 1: return launch_sample_lds_cpw<T, 1>(g, lp, grid, theta, noise, a, st);
+        case 2: return launch_sample_lds_cpw<T, 2>(g, lp, grid, theta, noise, a, st);
+        case 4: return launch_sample_lds_cpw<T, 4>(g, lp, grid, theta, noise, a, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template size_t sample_lds_chain_bytes<float>(const DevGraph &, const LdsPlan &);
+template size_t sample_lds_chain_bytes<double>(const DevGraph &, const LdsPlan &);
+template hipError_t launch_sample_lds<float>(const DevGraph &, const LdsPlan &, int, int, const double *,
+                                             const double *, const SampleArgs &, hipStream_t);
+template hipError_t launch_sample_lds<double>(const DevGraph &, const LdsPlan &, int, int, const double *,
+                                              const double *, const SampleArgs &, hipStream_t);
+
+
+template <typename T>
+hipError_t launch_sample_stream(const DevGraph &g, const LdsPlan &lp, int grid, const double *theta,
+                                const void *wfix, void *vals, size_t per_wg_elems, const SampleArgs &a,
+                                hipStream_t st) {
+    size_t lds = lds_bytes(g, sizeof(cplx<T>)) + static_cast<size_t>(g.S) * sizeof(cplx<T>);
+    hipLaunchKernelGGL(k_sample_stream<T>, dim3(grid), dim3(BLOCK), lds, st, g, lp, theta,
+                       reinterpret_cast<const cplx<T> *>(wfix), reinterpret_cast<cplx<T> *>(vals), per_wg_elems, a);
+    return hipGetLastError();
+}
+template hipError_t launch_sample_stream<float>(const DevGraph &, const LdsPlan &, int, const double *, const void *,
+                                                void *, size_t, const SampleArgs &, hipStream_t);
+template hipError_t launch_sample_stream<double>(const DevGraph &, const LdsPlan &, int, const double *, const void *,
+                                                 void *, size_t, const SampleArgs &, hipStream_t);
 
 template hipError_t launch_fixed_slots<float>(const DevGraph &, const double *, void *, hipStream_t);
 template hipError_t launch_fixed_slots<double>(const DevGraph &, const double *, void *, hipStream_t);

@@ -6,7 +6,7 @@ test needs).  The GPU library never uses it.
 """
 import numpy as np
 
-from paper_2103_17226_amd.compiler import TAG_IND, TAG_NODE, TAG_SHIFT, IND_VAL_SHIFT
+from paper_2103_17226_amd.compiler import IND_VAL_SHIFT, NO_SLOT, TAG_IND, TAG_NODE, TAG_SEL, TAG_SHIFT
 
 
 def slot_values(ac, theta, noise=None):
@@ -28,6 +28,9 @@ def evaluate(ac, theta, lam, noise=None):
                 kids.append(val[x])
             elif tag == TAG_IND:
                 kids.append(lam[x & ((1 << IND_VAL_SHIFT) - 1)][x >> IND_VAL_SHIFT])
+            elif tag == TAG_SEL:
+                v, sl = ac.selectors[x]
+                kids.append(sum(lam[v][u] * (0 if s == NO_SLOT else W[s]) for u, s in enumerate(sl)))
             else:
                 kids.append(W[x])
         val[i] = np.sum(kids) if ac.op[i] == 0 else np.prod(kids)

@@ -74,7 +74,7 @@ def test_corrupt_blobs_are_rejected_before_the_device(good_blob):
     nv, nn, S, N = h["n_vars"], h["n_noise"], h["n_slots"], h["n_int"]
     off = a8(64 + 2 * nv)
     off = a8(off + 4 * nv)
-    off = a8(off + 8 * nn + 32 * S + N)
+    off = a8(off + 8 * nn + 32 * S + 20 * h["n_selectors"] + N)
     off = a8(off + 4 * (N + 1))
     patched = bytearray(good_blob)
     struct.pack_into("<I", patched, off, (C.TAG_SLOT << C.TAG_SHIFT) | 999)

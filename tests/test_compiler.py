@@ -129,10 +129,11 @@ def test_cnf_weighted_model_count_is_branch_amplitude():
 
 # ------------------------------------------------------------------ AC
 
+@pytest.mark.parametrize("selectors", [True, False])
 @pytest.mark.parametrize("name", sorted(CIRCUITS))
-def test_ac_matches_oracle_on_every_assignment(name):
+def test_ac_matches_oracle_on_every_assignment(name, selectors):
     circ = CIRCUITS[name]()
-    ac = C.compile_circuit(circ)
+    ac = C.compile_circuit(circ, selectors=selectors)
     rng = np.random.default_rng(3)
     theta = rng.uniform(0, 2 * np.pi, size=circ.n_angles)
     for vals in all_assignments(circ):
@@ -140,11 +141,12 @@ def test_ac_matches_oracle_on_every_assignment(name):
         assert abs(got - oracle_amp(circ, theta, vals)) < 1e-13, vals
 
 
+@pytest.mark.parametrize("selectors", [True, False])
 @pytest.mark.parametrize("name", ["bell", "tiny", "ring3_dep"])
-def test_ac_polynomial_identity_random_indicators(name):
+def test_ac_polynomial_identity_random_indicators(name, selectors):
     # Smooth and multilinear: AC(lambda) = sum_s f(s) prod_v lambda_{v, s_v}
     circ = CIRCUITS[name]()
-    ac = C.compile_circuit(circ)
+    ac = C.compile_circuit(circ, selectors=selectors)
     rng = np.random.default_rng(5)
     theta = rng.uniform(0, 2 * np.pi, size=circ.n_angles)
     doms = circ.var_domains()
@@ -204,7 +206,8 @@ def test_blob_header_and_layout():
     ac = C.compile_circuit(circ)
     b = blobmod.to_blob(ac)
     h = blobmod.blob_summary(b)
-    assert h["magic"] == blobmod.MAGIC and h["version"] == 1
+    assert h["magic"] == blobmod.MAGIC and h["version"] == 2
+    assert h["n_selectors"] == len(ac.selectors) > 0
     assert h["n_int"] == ac.n_internal and h["n_edges"] == ac.n_edges
     assert h["n_vars"] == circ.n_vars and h["n_words"] == circ.n_words
     offs, widths, W_ = circ.var_layout()

@@ -209,3 +209,26 @@ def test_eval_is_deterministic():
     a1, _ = g.eval(cfg["theta"], ev, po)
     a2, _ = g.eval(cfg["theta"], ev, po)
     assert torch.equal(a1, a2)
+
+
+@pytest.mark.parametrize("cfg_id", [2, 3])
+def test_selector_and_indicator_forms_agree(cfg_id):
+    # the same circuit compiled with selector leaves and with plain
+    # indicator x weight products gives the same amplitudes on the GPU
+    note(f"selector vs indicator compile, config {cfg_id}")
+    from paper_2103_17226_amd import compiler as C
+    from paper_2103_17226_amd.api import ACGraph
+    cfg = W.config(cfg_id, small=True)
+    circ = cfg["circuit"]
+    rng = np.random.default_rng(31)
+    B = 200
+    vals = np.concatenate([rng.integers(0, 2, size=(B, circ.n)),
+                           W.sample_channel_prior(circ, B, rng)], axis=1)
+    vals[::3, circ.n::5] = 1
+    ev = W.pack_evidence(circ, vals)
+    P = 3
+    theta = W.uniform_angles(P, circ.n_angles, 5)
+    po = (np.arange(B) % P).astype(np.int32)
+    a1, _ = ACGraph(C.compile_circuit(circ, selectors=True)).eval(theta, ev, po, dtype="c128")
+    a2, _ = ACGraph(C.compile_circuit(circ, selectors=False)).eval(theta, ev, po, dtype="c128")
+    assert np.max(np.abs(a1.cpu().numpy() - a2.cpu().numpy())) <= 1e-12

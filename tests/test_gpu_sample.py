@@ -23,8 +23,14 @@ def _gpu():
     require_gpu()
 
 
-def test_same_chain_bitwise_c128():
-    note("same-chain bitwise")
+@pytest.mark.parametrize("variant", ["auto", "lds-cpw1", "lds-cpw2", "lds-cpw4", "global"])
+def test_same_chain_bitwise_c128(variant, monkeypatch):
+    note(f"same-chain bitwise ({variant})")
+    if variant == "global":
+        monkeypatch.setenv("QKC_SAMPLE_KERNEL", "global")
+    elif variant != "auto":
+        monkeypatch.setenv("QKC_SAMPLE_KERNEL", "lds")
+        monkeypatch.setenv("QKC_SAMPLE_CPW", variant[-1])
     circ = W.qaoa_maxcut(3, W.ring_graph(3), 1, dep=0.05, ad=0.03)
     g = graph(circ)
     theta = np.array([[0.7, 0.4], [2.2, 1.3]])
@@ -84,6 +90,20 @@ def test_stationary_distribution_noisy_qaoa_n8():
         note(f"  param {p}: p = {pv:.3g}, KL = {stats.kl_divergence(counts, probs):.3g}")
     note(f"  mean rounds per chain {out['rounds'].double().mean().item():.1f}")
     assert min(pvals) > 1e-4
+
+
+@pytest.mark.parametrize("other", ["lds", "global"])
+def test_sampler_kernels_agree_c128(other, monkeypatch):
+    note(f"default sampler kernel vs {other}")
+    cfg = W.config(2, small=True)
+    g = graph(cfg["circuit"])
+    theta = cfg["theta"][:3]
+    kw = dict(chains_per_param=40, samples_per_chain=2, burn_in=3, thin=1, seed=11, dtype="c128",
+              want_states=True, want_rounds=True)
+    a = g.sample(theta, **kw)
+    monkeypatch.setenv("QKC_SAMPLE_KERNEL", other)
+    b = g.sample(theta, **kw)
+    assert torch.equal(a["states"], b["states"]) and torch.equal(a["rounds"], b["rounds"])
 
 
 def test_sampler_determinism_and_cost():
