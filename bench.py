@@ -16,6 +16,17 @@ One step = one pass of the whole hot path over that batch:
      FP64 reduction, i.e. the score-function estimate of d<C>/d theta
      (times the sample count).
 
+Serving leg (after the timed steps, reported under "serving"): the
+serving mix -- a pool of noisy QAOA circuits (p in {1,2}, n in
+{6,8,12,16,20}, 4 seeded 3-regular graphs each, depolarizing strength ~
+U[1e-3,1e-2] per circuit), Poisson arrivals, per request a circuit uniform
+from the pool, P ~ log-uniform{1..256} parameter sets, an amplitude request
+(64 outputs per set) w.p. 0.1 else S ~ log-uniform{1..4096} samples per set,
+a gradient w.p. 0.5 -- through the continuous-batching loop; p50/p99
+latency from arrival to completion, throughput and rejections per offered
+rate.  The default pool leaves out the p=2, n=20 circuits (ACs of 1-2.4M
+nodes that take minutes to compile); --serve-pool full keeps them.
+
 Prints one JSON line.  --gpus > 1 is refused: this build runs on one GPU.
 """
 from __future__ import annotations
@@ -44,6 +55,20 @@ def parse():
     ap.add_argument("--dtype", default="c64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-eval", action="store_true")
+    ap.add_argument("--eval-steps", type=int, default=5)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-rates", default="200,1000,2000",
+                    help="offered request rates (req/s), one serving run each")
+    ap.add_argument("--serve-seconds", type=float, default=6.0)
+    ap.add_argument("--serve-warmup", type=float, default=2.0)
+    ap.add_argument("--serve-drain", type=float, default=60.0)
+    ap.add_argument("--serve-pool", choices=["fast", "full"], default="fast")
+    ap.add_argument("--serve-streams", type=int, default=8)
+    ap.add_argument("--serve-queue", type=int, default=16)
+    ap.add_argument("--serve-budget-gib", type=float, default=64.0)
+    ap.add_argument("--serve-max-work", type=float, default=1e11,
+                    help="reject requests estimated above this many node evaluations")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device-to-device three times (calibrates the HBM "
                          "byte counters of a profiler run) and exit")
@@ -58,6 +83,163 @@ def copy_probe():
         b.copy_(a)
     torch.cuda.synchronize()
     print(json.dumps({"copy_probe_bytes": 3 * (1 << 30)}))
+
+
+def compile_pool(full: bool):
+    """Blobs of the serving pool, compiled in worker processes (started
+    before this process touches the GPU)."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+
+    import workloads as W
+    from paper_2103_17226_amd.blob import compile_blob
+    pool = W.serving_pool()
+    if not full:
+        pool = [c for c in pool if not (c.n >= 20 and c.n_angles == 4)]
+    t0 = time.perf_counter()
+    workers = max(1, min(8, (os.cpu_count() or 1)))
+    with ProcessPoolExecutor(workers, mp_context=mp.get_context("spawn")) as ex:
+        blobs = list(ex.map(compile_blob, pool))
+    return pool, blobs, time.perf_counter() - t0
+
+
+def serve_run(graphs, pool, rate, args):
+    """One serving run at an offered rate; returns its summary (requests
+    that arrive in the warm-up window are served but not counted)."""
+    import torch
+
+    import workloads as W
+    from paper_2103_17226_amd.serve import GraphExecutor, Request, Server
+    edges = {c.name: c.edges for c in pool}
+    ex = GraphExecutor(graphs, edges, n_streams=args.serve_streams)
+    srv = Server(ex, mem_budget=int(args.serve_budget_gib * (1 << 30)), max_queue=args.serve_queue,
+                 max_work=args.serve_max_work)
+    total = args.serve_warmup + args.serve_seconds
+    reqs = W.serving_requests(pool, rate, total, seed=W.sub_seed("arrivals", 5) + int(rate))
+    srv.start()
+    t0 = time.perf_counter()
+    futs = []
+    for r in reqs:
+        delay = t0 + r["t"] - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        q = Request(graph=pool[r["circuit"]].name, theta=r["theta"], evidence=r.get("evidence"),
+                    param_of=r.get("param_of"), weight=r.get("weight"), samples=r["samples"], grad=r["grad"],
+                    burn_in=10, seed=r["seed"])
+        srv.submit(q, t_arrive=t0 + r["t"])
+        futs.append(q)
+    t_end = time.perf_counter()
+    srv.stop(drain=True, timeout=args.serve_drain)
+    torch.cuda.synchronize()
+    since = t0 + args.serve_warmup
+    st = srv.latency_stats(since=since)
+    window = [q for q in futs if q.t_arrive >= since]
+
+    def outcome(q):
+        f = q.future
+        if f.cancelled() or not f.done():
+            return "unfinished"
+        e = f.exception()
+        if e is None:
+            return "completed"
+        msg = str(e)
+        if "queue full" in msg:
+            return "rejected_queue"
+        if "node evaluations" in msg:
+            return "rejected_work"
+        if "device memory" in msg:
+            return "rejected_memory"
+        return "failed"
+
+    counts = {k: 0 for k in ("completed", "rejected_queue", "rejected_work", "rejected_memory", "failed",
+                             "unfinished")}
+    for q in window:
+        counts[outcome(q)] += 1
+    ok = [q for q in window if outcome(q) == "completed"]
+    span = max([q.t_done for q in ok] + [t_end]) - since
+    out = {"offered_rps": rate, "arrivals": len(window), **counts,
+           "p50_ms": st.get("p50_ms"), "p99_ms": st.get("p99_ms"), "mean_ms": st.get("mean_ms"),
+           "throughput_rps": len(ok) / span,
+           "samples_per_s": sum(q.n_params * q.samples for q in ok) / span,
+           "amplitudes_per_s": sum(q.n_rows for q in ok) / span,
+           "launches": st["launches"], "merged": st["merged"], "max_inflight": st["max_inflight"],
+           "peak_gib": st["peak_bytes"] / (1 << 30)}
+    return out
+
+
+def byte_model(comp, W: int, cs: int):
+    """Algorithmic bytes of the streaming model for one element: upward pass
+    (every node value written once, every internal child read once, the
+    evidence words read once, the amplitude written) and downward pass (node
+    values and parent adjoints read, every adjoint written, one derivative per
+    indicator value)."""
+    tags = comp.col >> 30
+    E_ii = int((tags == 0).sum())
+    N = comp.n_internal
+    up = cs * (E_ii + N) + 8 * W + cs
+    down = cs * (N + 2 * E_ii)
+    return up, down, E_ii
+
+
+def eval_leg(args, circ_cfg):
+    """Amplitudes and gradients over the batch of the 16-qubit p=2 workload:
+    4096 parameter sets x 64 seeded (x, k) with k from the channel priors."""
+    import numpy as np
+    import torch
+
+    from paper_2103_17226_amd import _lib
+    from paper_2103_17226_amd.api import ACGraph
+    from paper_2103_17226_amd.compiler import compile_circuit
+    t0 = time.perf_counter()
+    comp = compile_circuit(circ_cfg["circuit"])
+    t_comp = time.perf_counter() - t0
+    g = ACGraph(comp, device=0)
+    dev = g.torch_device
+    theta = torch.as_tensor(circ_cfg["theta"], device=dev)
+    ev = torch.as_tensor(circ_cfg["evidence"].view(np.int64), device=dev)
+    po = torch.as_tensor(circ_cfg["param_of"], device=dev)
+    B = ev.shape[0]
+    info = g.info
+    ws_e = g.workspace("c64", B, _lib.AC_OP_EVAL)
+    wgt = torch.ones(B, dtype=torch.float64, device=dev)
+
+    def timed(fn, n):
+        fn()
+        torch.cuda.synchronize()
+        evs = []
+        for _ in range(n):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            evs.append((a, b))
+        torch.cuda.synchronize()
+        return float(np.mean([a.elapsed_time(b) for a, b in evs])) / 1e3
+
+    t_eval = timed(lambda: g.eval(theta, ev, po, dtype="c64", validate=False, ws=ws_e), args.eval_steps)
+    t_grad = timed(lambda: g.grad(theta, ev, po, mode="prob", weight=wgt, dtype="c64", validate=False),
+                   args.eval_steps)
+    up, down, E_ii = byte_model(comp, info["n_words"], 8)
+    N = info["n_internal"]
+    achieved = up * B / t_eval / 1e9
+    out = {
+        "workload": "noisy QAOA p=2 MaxCut, seeded random 3-regular graph, 16 qubits, depolarizing "
+                    "p_c~U[1e-3,1e-2] + amplitude damping 5e-3 after every gate; 4096 angle sets x 64 "
+                    "seeded (x,k) = 262,144 amplitudes, c64 with FP64 |f|^2",
+        "ac_internal_nodes": N, "ac_edges": info["n_edges"], "ac_levels": info["n_levels"],
+        "compile_s": t_comp, "batch": B,
+        "eval_ms": t_eval * 1e3, "amplitudes_per_s": B / t_eval, "node_evals_per_s": N * B / t_eval,
+        "grad_ms": t_grad * 1e3, "grad_elements_per_s": B / t_grad,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "kernel": "k_eval (upward pass)",
+                     "bytes_per_element": up},
+        "grad_model_GBps": (up + down) * B / t_grad / 1e9,
+    }
+    g.close()
+    del ws_e
+    torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(circ, theta, chains, budget_s):
@@ -97,6 +279,10 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus_requested": args.gpus}))
         sys.exit(2)
+    pool = blobs = None
+    t_pool = 0.0
+    if not args.no_serve:
+        pool, blobs, t_pool = compile_pool(args.serve_pool == "full")
     import numpy as np
     import torch
 
@@ -121,6 +307,7 @@ def main():
     param_of = torch.arange(P, dtype=torch.int32, device=dev).repeat_interleave(S)
     Wn = info["n_words"]
     ev_t = {}
+    ws_sample = g.workspace(args.dtype, P * chains, _lib.AC_OP_SAMPLE)
 
     def step(seed):
         ev0 = torch.cuda.Event(enable_timing=True)
@@ -129,7 +316,7 @@ def main():
         ev0.record()
         s = g.sample(theta, chains_per_param=chains, samples_per_chain=1, burn_in=args.burn_in, thin=1,
                      seed=seed, cost_edges=edges, dtype=args.dtype, want_states=True, want_cost=True,
-                     want_rounds=True, validate=False)
+                     want_rounds=True, validate=False, ws=ws_sample)
         ev1.record()
         out = g.grad(theta, s["states"].view(P * S, Wn), param_of, mode="logprob",
                      weight=s["cost"].view(P * S), dtype=args.dtype, validate=False)
@@ -200,12 +387,40 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": None,
-            "kernel": "k_sample (Gibbs: upward + downward pass + decisions)",
+            "kernel": "k_sample_stream (Gibbs rounds: upward + downward pass + decisions; "
+                      "timed with HIP events around ac_sample on its stream)",
             "bytes_per_chain_round": bytes_round,
         },
     }
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(circ, theta_np, chains, args.cpu_seconds)
+    del s, out, last
+    g.close()
+    ws_sample = None
+    torch.cuda.empty_cache()
+    if not args.no_eval:
+        print("# amplitude/gradient leg (16 qubits, p=2)", file=sys.stderr, flush=True)
+        res["eval"] = eval_leg(args, W.config(3))
+    if pool is not None:
+        graphs = {c.name: ACGraph(b, device=0) for c, b in zip(pool, blobs)}
+        runs = []
+        for rate in [float(x) for x in args.serve_rates.split(",") if x]:
+            print(f"# serving at {rate:g} req/s", file=sys.stderr, flush=True)
+            runs.append(serve_run(graphs, pool, rate, args))
+        res["serving"] = {
+            "workload": "serving mix: noisy QAOA p in {1,2}, n in {6,8,12,16,20}, 4 graphs each, "
+                        "Poisson arrivals; P~logU{1..256}, eval(64 x/set) w.p. 0.1 else S~logU{1..4096} "
+                        "samples/set, gradient w.p. 0.5; c64",
+            "pool_circuits": len(pool), "pool_compile_s": t_pool,
+            "pool_ac_nodes_max": max(gr.info["n_internal"] for gr in graphs.values()),
+            "streams": args.serve_streams, "queue_limit": args.serve_queue,
+            "budget_gib": args.serve_budget_gib, "max_work_node_evals": args.serve_max_work,
+            "warmup_s": args.serve_warmup, "measured_s": args.serve_seconds,
+            "runs": runs,
+        }
+        main_run = max(runs, key=lambda r: r["offered_rps"]) if runs else {}
+        res["serving"]["p50_ms"] = main_run.get("p50_ms")
+        res["serving"]["p99_ms"] = main_run.get("p99_ms")
     print(json.dumps(res), flush=True)
 
 

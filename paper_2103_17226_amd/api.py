@@ -75,8 +75,16 @@ class ACGraph:
     def workspace_size(self, dtype: str, batch: int, op: int) -> int:
         return int(L.lib().ac_workspace_size(self._h, _CDTYPE[dtype][0], int(batch), int(op)))
 
-    def workspace(self, dtype: str, batch: int, op: int) -> torch.Tensor:
+    def workspace(self, dtype: str, batch: int, op: int, ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """The workspace for one call: ``ws`` if given (checked for size), else
+        a buffer cached per (dtype, op) on this graph.  The cached buffer is
+        shared by every call on the graph, so callers that run the same graph
+        on several streams at once pass their own ``ws``."""
         need = self.workspace_size(dtype, batch, op)
+        if ws is not None:
+            if ws.device != self.torch_device or ws.dtype != torch.uint8 or ws.numel() < need:
+                raise ValueError(f"workspace must be a uint8 tensor on {self.torch_device} of >= {need} bytes")
+            return ws
         key = (dtype, op)
         ws = self._ws.get(key)
         if ws is None or ws.numel() < need:
@@ -125,7 +133,7 @@ class ACGraph:
 
     # ------------------------------------------------------------- queries
     def eval(self, theta, evidence, param_of=None, noise=None, dtype: str = "c64", prob: bool = True,
-             validate: bool = True):
+             validate: bool = True, ws: Optional[torch.Tensor] = None):
         """Amplitudes f(evidence[b]; theta[param_of[b]]) and optionally |f|^2 (FP64).
         validate=False skips the host-side range checks of param_of and noise
         (they synchronise with the device); only for inputs known to be valid."""
@@ -133,7 +141,7 @@ class ACGraph:
         theta, evidence, param_of, noise, P, B = self._inputs(theta, evidence, param_of, noise, validate)
         amp = torch.empty(B, dtype=cdt, device=self.torch_device)
         pr = torch.empty(B, dtype=torch.float64, device=self.torch_device) if prob else None
-        ws = self.workspace(dtype, B, L.AC_OP_EVAL)
+        ws = self.workspace(dtype, B, L.AC_OP_EVAL, ws)
         L.check(L.lib().ac_eval_batch(self._h, code, _ptr(theta), P, _ptr(noise), _ptr(param_of),
                                       _ptr(evidence), B, _ptr(amp), _ptr(pr), _ptr(ws), ws.numel(),
                                       self._stream()))
@@ -141,7 +149,7 @@ class ACGraph:
 
     def grad(self, theta, evidence, param_of=None, mode: str = "cotangent", cotangent=None,
              weight=None, noise=None, dtype: str = "c64", want_amp=False, want_dfdtheta=False,
-             want_dind=False, validate: bool = True):
+             want_dind=False, validate: bool = True, ws: Optional[torch.Tensor] = None):
         """Gradient in theta of a loss of the amplitudes (see ac_grad_batch)."""
         code, cdt = _CDTYPE[dtype]
         theta, evidence, param_of, noise, P, B = self._inputs(theta, evidence, param_of, noise, validate)
@@ -154,7 +162,7 @@ class ACGraph:
         amp = torch.empty(B, dtype=cdt, device=dev) if want_amp else None
         dft = torch.empty((B, K), dtype=cdt, device=dev) if want_dfdtheta else None
         dind = torch.empty((B, self.info["n_indicator_leaves"]), dtype=cdt, device=dev) if want_dind else None
-        ws = self.workspace(dtype, B, L.AC_OP_GRAD)
+        ws = self.workspace(dtype, B, L.AC_OP_GRAD, ws)
         L.check(L.lib().ac_grad_batch(self._h, code, _ptr(theta), P, _ptr(noise), _ptr(param_of),
                                       _ptr(evidence), B, m, _ptr(cot), _ptr(w), _ptr(grad), _ptr(amp),
                                       _ptr(dft), _ptr(dind), _ptr(ws), ws.numel(), self._stream()))
@@ -163,7 +171,7 @@ class ACGraph:
     def sample(self, theta, chains_per_param: int, samples_per_chain: int = 1, burn_in: int = 20,
                thin: int = 1, seed: int = 1, cost_edges: Optional[Sequence] = None, noise=None,
                dtype: str = "c64", want_states=False, want_cost=False, want_rounds=False,
-               validate: bool = True):
+               validate: bool = True, ws: Optional[torch.Tensor] = None):
         """Gibbs samples of the output bits (see ac_sample)."""
         code, _ = _CDTYPE[dtype]
         K = self.info["n_angles"]
@@ -193,7 +201,7 @@ class ACGraph:
         cfg = L.SampleCfg(int(chains_per_param), int(samples_per_chain), int(burn_in), int(thin),
                           int(seed) & ((1 << 64) - 1), 0 if edges_t is None else int(edges_t.shape[0]), 0,
                           None if edges_t is None else edges_t.data_ptr())
-        ws = self.workspace(dtype, P * chains_per_param, L.AC_OP_SAMPLE)
+        ws = self.workspace(dtype, P * chains_per_param, L.AC_OP_SAMPLE, ws)
         L.check(L.lib().ac_sample(self._h, code, _ptr(theta), P, _ptr(noise), ctypes.byref(cfg),
                                   _ptr(samples), _ptr(states), _ptr(cost), _ptr(rounds), _ptr(ws),
                                   ws.numel(), self._stream()))

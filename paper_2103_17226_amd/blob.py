@@ -69,3 +69,10 @@ def blob_summary(blob: bytes) -> dict:
     keys = ["magic", "version", "flags", "n_qubits", "n_vars", "n_words", "n_angles", "n_noise",
             "n_slots", "n_angle_slots", "n_int", "n_edges", "n_levels", "root", "n_selectors"]
     return dict(zip(keys, f))
+
+
+def compile_blob(circ, **kw) -> bytes:
+    """Compile a circuit and serialise its AC (picklable entry point for
+    compiling many circuits in worker processes)."""
+    from .compiler import compile_circuit
+    return to_blob(compile_circuit(circ, **kw))

@@ -25,8 +25,9 @@ Stages
    the authors started from, Sec. 3.2), with sparse tables (deterministic
    zeros never stored), hash-consing, folding of constants, elision of
    intermediate qubit states by summing them out without indicators
-   (Sec. 3.2.2, "qubit state elision") and a min-weight/min-fill elimination
-   order (Sec. 3.2.2, "elimination order").  Gates whose tables are diagonal
+   (Sec. 3.2.2, "qubit state elision") and an elimination order (Sec. 3.2.2,
+   "elimination order") chosen as the cheapest of several seeded greedy runs
+   (min-weight, min-fill, min-degree, randomised tie-breaks).  Gates whose tables are diagonal
    (RZ, phase damping, the control side of CNOT) do not open a new variable,
    which is the deterministic-entry simplification applied to qubit states.
 
@@ -37,7 +38,9 @@ s with v set to u (Sec. 3.3.2, downward pass).
 """
 from __future__ import annotations
 
+import heapq
 import math
+import random
 from collections import defaultdict
 from dataclasses import dataclass, field
 from typing import Dict, List, Optional, Tuple
@@ -435,8 +438,13 @@ def _join_sum(ac: ACBuilder, factors: List[Factor], x: int, dom: Dict[int, int],
     return Factor(rest, tab)
 
 
-def _elimination_order(factors: List[Factor], dom: Dict[int, int], keep_last=()) -> List[int]:
-    """Greedy min-weight (size of the eliminated clique), ties by min-fill."""
+def _greedy_order(factors: List[Factor], dom: Dict[int, int], crit: str, rng) -> Tuple[List[int], int]:
+    """One greedy elimination order and its cost, the summed size of the
+    eliminated cliques (the dense bound on every intermediate table).
+
+    crit picks the primary score: "wf" = clique weight then fill-in, "fw" =
+    fill-in then weight, "deg" = degree then weight; rng (or None) breaks the
+    remaining ties at random."""
     adj: Dict[int, set] = defaultdict(set)
     for f in factors:
         for v in f.vars:
@@ -444,32 +452,40 @@ def _elimination_order(factors: List[Factor], dom: Dict[int, int], keep_last=())
             for w in f.vars:
                 if w != v:
                     adj[v].add(w)
-    order = []
     alive = set(adj)
-    import heapq
+
+    def weight(v):
+        w = dom[v]
+        for u in adj[v]:
+            w *= dom[u]
+        return w
 
     def score(v):
-        nb = adj[v]
-        w = dom[v]
-        for u in nb:
-            w *= dom[u]
+        nb = list(adj[v])
         fill = 0
-        nbl = list(nb)
-        for i in range(len(nbl)):
-            ai = adj[nbl[i]]
-            for j in range(i + 1, len(nbl)):
-                if nbl[j] not in ai:
+        for i in range(len(nb)):
+            ai = adj[nb[i]]
+            for j in range(i + 1, len(nb)):
+                if nb[j] not in ai:
                     fill += 1
-        return (w, fill, v)
+        w = weight(v)
+        tie = rng.random() if rng is not None else 0.0
+        if crit == "wf":
+            return (w, fill, tie, v)
+        if crit == "fw":
+            return (fill, w, tie, v)
+        return (len(nb), w, tie, v)
 
-    heap = [score(v) for v in alive]
-    heapq.heapify(heap)
     current = {v: score(v) for v in alive}
+    heap = list(current.values())
+    heapq.heapify(heap)
+    order, cost = [], 0
     while heap:
         s = heapq.heappop(heap)
-        v = s[2]
+        v = s[-1]
         if v not in alive or current[v] != s:
             continue
+        cost += weight(v)
         order.append(v)
         alive.discard(v)
         nb = list(adj[v])
@@ -486,7 +502,24 @@ def _elimination_order(factors: List[Factor], dom: Dict[int, int], keep_last=())
             if u in alive:
                 current[u] = score(u)
                 heapq.heappush(heap, current[u])
-    return order
+    return order, cost
+
+
+def _elimination_order(factors: List[Factor], dom: Dict[int, int], trials: int = 64,
+                       seed: int = 0x5EED) -> List[int]:
+    """Elimination order (Sec. 3.2.2): the cheapest of several greedy runs.
+
+    The three deterministic heuristics run first, then randomised tie-breaks
+    of each in turn; the order with the smallest summed clique size wins
+    (earliest on ties), so the result is reproducible."""
+    rng = random.Random(seed)
+    crits = ("wf", "fw", "deg")
+    best = None
+    for t in range(max(1, trials)):
+        order, cost = _greedy_order(factors, dom, crits[t % 3], rng if t >= 3 else None)
+        if best is None or cost < best[1]:
+            best = (order, cost)
+    return best[0]
 
 
 @dataclass
@@ -559,12 +592,15 @@ def _var_layout(doms):
     return offs, max(1, (pos + 63) // 64)
 
 
-def compile_circuit(circ, flatten: bool = True, selectors: bool = True) -> CompiledAC:
+def compile_circuit(circ, flatten: bool = True, selectors: bool = True,
+                    order_trials: int = 64) -> CompiledAC:
     """Compile a circuit (op-list form) into a flat level-ordered AC.
 
     selectors=True folds each channel's event indicators and Kraus entries
     into selector leaves (one per matrix entry); False keeps them as sums of
-    indicator x weight products.  Both give the same polynomial."""
+    indicator x weight products.  Both give the same polynomial.
+    order_trials is the number of greedy elimination-order runs to pick from
+    (1 = plain min-weight/min-fill)."""
     bn = circuit_to_bn(circ)
     ac = ACBuilder()
 
@@ -668,7 +704,7 @@ def compile_circuit(circ, flatten: bool = True, selectors: bool = True) -> Compi
     # merge factors over identical scopes is implicit in VE
     live = [f for f in factors if f.vars]
     const_parts = [f.table.get(()) for f in factors if not f.vars]
-    order = _elimination_order(live, dom)
+    order = _elimination_order(live, dom, order_trials)
     # variables that appear in no factor but are evidence: they must still carry an indicator
     bucket: Dict[int, List[Factor]] = defaultdict(list)
     pos = {v: i for i, v in enumerate(order)}

@@ -184,6 +184,27 @@ def test_qaoa_n32_p1_ac_is_paper_sized():
     assert 500 < ac.n_internal < 20000 and ac.n_edges < 60000
 
 
+def test_order_search_shrinks_ac_and_keeps_values():
+    # The multi-start order may only lower the summed clique size of the
+    # plain greedy run, and the AC it yields is the same polynomial.
+    circ = W.qaoa_maxcut(8, W.random_regular_graph(8, 3, 11), 2, dep=0.004)
+    one = C.compile_circuit(circ, order_trials=1)
+    many = C.compile_circuit(circ, order_trials=64)
+    assert many.n_internal <= one.n_internal
+    rng = np.random.default_rng(2)
+    theta = rng.uniform(0, 2 * np.pi, size=circ.n_angles)
+    doms = circ.var_domains()
+    for _ in range(20):
+        vals = [0] * len(doms)
+        vals[:circ.n] = [int(b) for b in rng.integers(0, 2, size=circ.n)]
+        for v in rng.choice(np.arange(circ.n, len(doms)), size=3, replace=False):
+            vals[int(v)] = int(rng.integers(0, doms[int(v)]))
+        a = H.evaluate_assignment(many, theta, vals)
+        b = oracle_amp(circ, theta, vals)
+        assert abs(a - b) < 1e-13
+        assert abs(H.evaluate_assignment(one, theta, vals) - b) < 1e-13
+
+
 def test_c4_spot_amplitudes_match_path_sum():
     from oracle import pathsum
     n = 20

@@ -1,0 +1,167 @@
+"""Served results equal the plain calls: every request of a mixed stream
+(amplitudes, gradients, samples, sampled gradients over several resident
+graphs) gets, through the continuous-batching loop with merged launches and
+overlapping streams, what the same request gets from the plain binding calls
+on its own.  Amplitudes and samples are compared bit for bit, gradients to
+1e-12 relative (the merged reduction is arranged to add the same terms in the
+same order, so they are expected to agree bit for bit too)."""
+import threading
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from tests.gpu_common import graph, note, oracle_amplitudes, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _pool():
+    pool = W.serving_pool()
+    pick = [pool[0], pool[4], pool[20]]          # n=6 p=1, n=8 p=1, n=6 p=2
+    return {c.name: c for c in pick}
+
+
+def _requests(circs, n, seed):
+    names = sorted(circs)
+    pool = [circs[k] for k in names]
+    raw = W.serving_requests(pool, rate=200.0, duration=2.0 * n / 200.0, seed=seed, max_params=12, max_samples=96,
+                             p_eval=0.5)[:n]
+    return [(names[r["circuit"]], r) for r in raw]
+
+
+def _plain(g, circ, r, dtype="c64"):
+    """The request through the plain binding calls, on its own."""
+    theta = r["theta"]
+    out = {}
+    if r["samples"] == 0:
+        if r["grad"]:
+            res = g.grad(theta, r["evidence"], r["param_of"], mode="prob", weight=r["weight"], dtype=dtype,
+                         want_amp=True)
+            out = {"amp": res["amp"].cpu().numpy(), "grad": res["grad"].cpu().numpy()}
+        else:
+            amp, prob = g.eval(theta, r["evidence"], r["param_of"], dtype=dtype)
+            out = {"amp": amp.cpu().numpy(), "prob": prob.cpu().numpy()}
+        return out
+    S, P = r["samples"], theta.shape[0]
+    res = g.sample(theta, chains_per_param=S, samples_per_chain=1, burn_in=10, thin=1, seed=r["seed"],
+                   cost_edges=circ.edges, dtype=dtype, want_cost=True, want_states=r["grad"])
+    out = {"samples": res["samples"].cpu().numpy(), "cost": res["cost"].cpu().numpy()}
+    if r["grad"]:
+        cost = res["cost"]
+        wgt = ((cost - cost.mean(dim=1, keepdim=True)) / S).reshape(-1).contiguous()
+        po = torch.arange(P, dtype=torch.int32, device=cost.device).repeat_interleave(S)
+        gr = g.grad(theta, res["states"].reshape(P * S, -1), po, mode="logprob", weight=wgt, dtype=dtype)
+        out["grad"] = gr["grad"].cpu().numpy()
+    return out
+
+
+def _request(name, r):
+    from paper_2103_17226_amd.serve import Request
+    return Request(graph=name, theta=r["theta"], evidence=r.get("evidence"), param_of=r.get("param_of"),
+                   weight=r.get("weight"), samples=r["samples"], grad=r["grad"], burn_in=10, seed=r["seed"])
+
+
+def _same(served, plain, what):
+    assert set(served) == set(plain), what
+    for k in plain:
+        a, b = np.asarray(served[k]), np.asarray(plain[k])
+        assert a.shape == b.shape, (what, k)
+        if k == "grad":
+            scale = max(np.max(np.abs(b)), 1e-30)
+            assert np.max(np.abs(a - b)) <= 1e-12 * scale, (what, k, np.max(np.abs(a - b)) / scale)
+        else:
+            assert np.array_equal(a.view(np.uint8), b.view(np.uint8)), (what, k)
+
+
+def test_served_equals_alone_in_a_mixed_stream():
+    from paper_2103_17226_amd.serve import GraphExecutor, Server
+    circs = _pool()
+    note("serve: compile and load 3 graphs")
+    graphs = {k: graph(c) for k, c in circs.items()}
+    reqs = _requests(circs, 60, seed=77)
+    kinds = {(r["samples"] > 0, r["grad"]) for _, r in reqs}
+    assert len(kinds) == 4, kinds
+    note(f"serve: plain calls for {len(reqs)} requests")
+    plain = [_plain(graphs[k], circs[k], r) for k, r in reqs]
+    torch.cuda.synchronize()
+    note("serve: the same requests through the loop (4 streams, merging)")
+    ex = GraphExecutor(graphs, {k: c.edges for k, c in circs.items()}, n_streams=4)
+    srv = Server(ex, mem_budget=8 << 30, max_merge=16)
+    futs = [srv.submit(_request(k, r)) for k, r in reqs]      # queued before the loop starts: merges
+    srv.start()
+    results = [f.result(timeout=120) for f in futs]
+    srv.stop()
+    st = srv.latency_stats()
+    note(f"serve: {st}")
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    assert st["merged"] > 0 and st["max_inflight"] > 1
+    for i, ((k, r), got, want) in enumerate(zip(reqs, results, plain)):
+        _same(got, want, f"request {i} on {k} (samples={r['samples']}, grad={r['grad']})")
+
+
+def test_served_amplitudes_match_the_oracle():
+    from paper_2103_17226_amd.serve import GraphExecutor, Request, Server
+    circs = _pool()
+    name = sorted(circs)[0]
+    circ = circs[name]
+    note(f"serve vs oracle on {name}")
+    g = graph(circ)
+    rng = np.random.default_rng(5)
+    ex = GraphExecutor({name: g}, n_streams=2)
+    srv = Server(ex, mem_budget=1 << 30)
+    srv.start()
+    futs, inputs = [], []
+    for i in range(6):
+        P, B = 1 + i, 10 + 7 * i
+        theta = rng.uniform(0, 2 * np.pi, size=(P, circ.n_angles))
+        vals = np.zeros((B, circ.n_vars), dtype=np.int64)
+        vals[:, :circ.n] = rng.integers(0, 2, size=(B, circ.n))
+        doms = circ.var_domains()
+        for v in range(circ.n, circ.n_vars):
+            vals[:, v] = rng.integers(0, doms[v], size=B) * (rng.random(B) < 0.1)
+        po = rng.integers(0, P, size=B).astype(np.int32)
+        inputs.append((theta, vals, po))
+        futs.append(srv.submit(Request(graph=name, theta=theta, evidence=W.pack_evidence(circ, vals),
+                                       param_of=po, dtype="c128")))
+    out = [f.result(timeout=60) for f in futs]
+    srv.stop()
+    for (theta, vals, po), res in zip(inputs, out):
+        ref = np.array([oracle_amplitudes(circ, theta[po[b]], vals[b:b + 1])[0] for b in range(len(po))])
+        assert np.max(np.abs(res["amp"] - ref)) <= 1e-12
+        np.testing.assert_allclose(res["prob"], np.abs(ref) ** 2, rtol=1e-10, atol=1e-15)
+
+
+def test_loop_admits_while_others_run_and_reports_latency():
+    from paper_2103_17226_amd.serve import GraphExecutor, Server
+    circs = _pool()
+    graphs = {k: graph(c) for k, c in circs.items()}
+    reqs = _requests(circs, 40, seed=91)
+    note("serve: timed arrivals")
+    ex = GraphExecutor(graphs, {k: c.edges for k, c in circs.items()}, n_streams=4)
+    srv = Server(ex, mem_budget=8 << 30)
+    srv.start()
+    t0 = time.perf_counter()
+    futs = []
+    for k, r in reqs:
+        delay = t0 + r["t"] - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        futs.append(srv.submit(_request(k, r)))
+    for f in futs:
+        f.result(timeout=120)
+    srv.stop()
+    st = srv.latency_stats()
+    note(f"serve: {st}")
+    assert st["completed"] == len(reqs)
+    assert 0 < st["p50_ms"] <= st["p99_ms"]
+    # some request started before an earlier one had finished: launches overlapped
+    done = sorted(srv.completed, key=lambda r: r.t_start)
+    assert any(b.t_start < a.t_done for a, b in zip(done, done[1:]))

@@ -1,0 +1,302 @@
+"""Host logic of the request loop: admission by memory, arrival order,
+merging, stream limits, cancellation, failures and latency bookkeeping.
+
+The device is replaced by an executor written here, driven by a clock the
+test advances, so every decision of the scheduler is checked on the CPU.
+"""
+import threading
+import time
+from concurrent.futures import CancelledError
+
+import numpy as np
+import pytest
+
+from paper_2103_17226_amd.serve import (GRAD_ALIGN, AdmissionError, Request, Server, padded_rows,
+                                        stack_eval_batch)
+
+
+class Clock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+
+class FakeExecutor:
+    """Requests carry their footprint and latency in ``theta``'s first entries
+    ([footprint, latency, value]); the result of a request is value * 2."""
+
+    def __init__(self, clock, n_streams=4, fail_launch=(), fail_results=(), fail_done=()):
+        self.clock = clock
+        self.n_streams = n_streams
+        self.launched = []                # (rids, stream, time)
+        self.fail_launch = set(fail_launch)
+        self.fail_results = set(fail_results)
+        self.fail_done = set(fail_done)
+        self.live_streams = set()
+
+    def footprint(self, req):
+        return int(req.theta[0, 0])
+
+    def work(self, req):
+        return float(req.theta[0, 1]) * 1000
+
+    def can_merge(self, a, b):
+        return a.kind == b.kind == "eval" and a.graph == b.graph and a.grad == b.grad and a.dtype == b.dtype
+
+    def launch(self, batch, stream):
+        assert stream not in self.live_streams, "stream reused while busy"
+        if any(float(r.theta[0, 2]) in self.fail_launch for r in batch):
+            raise RuntimeError("launch failed")
+        self.live_streams.add(stream)
+        lat = max(float(r.theta[0, 1]) for r in batch)
+        self.launched.append(([r.rid for r in batch], stream, self.clock()))
+        return {"end": self.clock() + lat, "batch": batch, "stream": stream}
+
+    def done(self, h):
+        ok = self.clock() >= h["end"]
+        if ok:
+            self.live_streams.discard(h["stream"])
+            if any(float(r.theta[0, 2]) in self.fail_done for r in h["batch"]):
+                raise RuntimeError("device error")
+        return ok
+
+    def results(self, h):
+        if any(float(r.theta[0, 2]) in self.fail_results for r in h["batch"]):
+            raise RuntimeError("copy-back failed")
+        return [float(r.theta[0, 2]) * 2 for r in h["batch"]]
+
+
+def req(fp, lat, val=1.0, graph="g", samples=1, grad=False):
+    return Request(graph=graph, theta=np.array([[fp, lat, val]]), samples=samples, grad=grad)
+
+
+def ev_req(fp, lat, val=1.0, graph="g", grad=False):
+    return Request(graph=graph, theta=np.array([[fp, lat, val]]), evidence=np.zeros((1, 1), np.uint64),
+                   grad=grad)
+
+
+def run_until_idle(srv, clock, dt=0.5, limit=1000):
+    for _ in range(limit):
+        srv.step()
+        if srv.idle():
+            return
+        clock.t += dt
+    raise AssertionError("scheduler did not drain")
+
+
+def test_admission_never_exceeds_budget():
+    clock = Clock()
+    ex = FakeExecutor(clock, n_streams=8)
+    srv = Server(ex, mem_budget=100, clock=clock)
+    futs = [srv.submit(req(40, 1.0, val=i)) for i in range(5)]
+    srv.step()
+    assert srv.used == 80 and len(ex.launched) == 2          # third does not fit yet
+    clock.t = 1.0
+    srv.step()
+    assert [f.result() for f in futs[:2]] == [0.0, 2.0]
+    assert len(ex.launched) == 4 and srv.used == 80
+    run_until_idle(srv, clock)
+    assert [f.result() for f in futs] == [2.0 * i for i in range(5)]
+    assert srv.peak_used == 80 and srv.used == 0
+
+
+def test_arrival_order_head_is_never_overtaken():
+    clock = Clock()
+    ex = FakeExecutor(clock, n_streams=8)
+    srv = Server(ex, mem_budget=100, clock=clock)
+    srv.submit(req(60, 1.0, val=1))
+    srv.submit(req(60, 1.0, val=2))
+    srv.submit(req(10, 1.0, val=3))          # would fit next to the first, but must wait
+    srv.step()
+    assert [x[0] for x in ex.launched] == [[0]]
+    clock.t = 1.0
+    srv.step()
+    assert [x[0] for x in ex.launched] == [[0], [1], [2]]
+
+
+def test_oversized_and_queue_full_are_rejected():
+    clock = Clock()
+    srv = Server(FakeExecutor(clock), mem_budget=100, clock=clock, max_queue=2)
+    f = srv.submit(req(101, 1.0))
+    with pytest.raises(AdmissionError):
+        f.result(timeout=0)
+    srv.submit(req(10, 1.0))
+    srv.submit(req(10, 1.0))
+    f3 = srv.submit(req(10, 1.0))
+    with pytest.raises(AdmissionError, match="queue full"):
+        f3.result(timeout=0)
+    assert srv.rejected_memory == 1 and srv.rejected_queue == 1
+    run_until_idle(srv, clock)
+    assert srv.latency_stats()["completed"] == 2
+
+
+def test_work_limit_rejects_long_requests():
+    clock = Clock()
+    srv = Server(FakeExecutor(clock), mem_budget=100, clock=clock, max_work=5000)
+    f = srv.submit(req(10, 6.0))
+    ok = srv.submit(req(10, 4.0, val=3))
+    with pytest.raises(AdmissionError, match="node evaluations"):
+        f.result(timeout=0)
+    run_until_idle(srv, clock)
+    assert ok.result() == 6.0 and srv.latency_stats()["rejected_work"] == 1
+
+
+def test_streams_bound_the_launches_in_flight():
+    clock = Clock()
+    ex = FakeExecutor(clock, n_streams=2)
+    srv = Server(ex, mem_budget=10 ** 6, clock=clock)
+    futs = [srv.submit(req(1, 1.0, val=i)) for i in range(5)]
+    srv.step()
+    assert len(srv.inflight) == 2
+    run_until_idle(srv, clock)
+    assert srv.max_inflight == 2 and all(f.done() for f in futs)
+
+
+def test_eval_requests_of_one_graph_merge_others_do_not():
+    clock = Clock()
+    ex = FakeExecutor(clock, n_streams=4)
+    srv = Server(ex, mem_budget=10 ** 6, clock=clock, max_merge=3)
+    fa = [srv.submit(ev_req(1, 1.0, val=i, graph="a")) for i in range(2)]
+    fb = srv.submit(ev_req(1, 1.0, val=9, graph="b"))
+    fa += [srv.submit(ev_req(1, 1.0, val=i, graph="a")) for i in range(2, 5)]
+    fg = srv.submit(ev_req(1, 1.0, val=7, graph="a", grad=True))
+    fs = srv.submit(req(1, 1.0, val=8, graph="a"))             # a sampling request: alone
+    srv.step()
+    batches = [x[0] for x in ex.launched]
+    assert batches == [[0, 1, 3], [2], [4, 5], [6]]
+    srv.step()
+    run_until_idle(srv, clock)
+    assert [f.result() for f in fa] == [0.0, 2.0, 4.0, 6.0, 8.0]
+    assert fb.result() == 18.0 and fg.result() == 14.0 and fs.result() == 16.0
+    assert sorted(sum((x[0] for x in ex.launched), [])) == list(range(8))
+    assert srv.merged == 3
+
+
+def test_cancel_waiting_but_not_running():
+    clock = Clock()
+    srv = Server(FakeExecutor(clock, n_streams=1), mem_budget=100, clock=clock)
+    f0 = srv.submit(req(10, 1.0, val=1))
+    f1 = srv.submit(req(10, 1.0, val=2))
+    srv.step()
+    assert not srv.cancel(f0)                 # already on the device
+    assert srv.cancel(f1)
+    with pytest.raises(CancelledError):
+        f1.result(timeout=0)
+    run_until_idle(srv, clock)
+    assert f0.result() == 2.0 and srv.cancelled == 1
+
+
+@pytest.mark.parametrize("where", ["launch", "done", "results"])
+def test_failures_fail_the_batch_and_free_resources(where):
+    clock = Clock()
+    kw = {"fail_" + where: {5.0}}
+    ex = FakeExecutor(clock, n_streams=1, **kw)
+    srv = Server(ex, mem_budget=100, clock=clock)
+    bad = srv.submit(req(60, 1.0, val=5.0))
+    good = srv.submit(req(60, 1.0, val=1.0))
+    run_until_idle(srv, clock)
+    with pytest.raises(RuntimeError):
+        bad.result(timeout=0)
+    assert good.result() == 2.0
+    assert srv.used == 0 and srv.free_streams == [0] and srv.failed == 1
+
+
+def test_latency_percentiles_and_warmup_window():
+    clock = Clock()
+    srv = Server(FakeExecutor(clock, n_streams=100), mem_budget=10 ** 6, clock=clock)
+    for i in range(100):
+        clock.t = float(i)
+        srv.submit(req(1, 0.0 if i < 10 else float(i - 9), val=i))
+        srv.step()
+    run_until_idle(srv, clock, dt=0.25)
+    st = srv.latency_stats(since=10.0)
+    assert st["completed"] == 90
+    lat = np.array([r.t_done - r.t_arrive for r in srv.completed if r.t_arrive >= 10.0])
+    assert st["p50_ms"] == pytest.approx(np.percentile(lat, 50) * 1e3)
+    assert st["p99_ms"] == pytest.approx(np.percentile(lat, 99) * 1e3)
+    # completions are seen at the first tick at or after the device finishes
+    assert np.all(lat >= np.arange(1, 91) - 1e-9) and np.all(lat <= np.arange(1, 91) + 0.25 + 1e-9)
+
+
+def test_threaded_loop_serves_concurrent_clients():
+    ex = FakeExecutor(time.perf_counter, n_streams=4)
+    srv = Server(ex, mem_budget=1000, clock=time.perf_counter)
+    srv.start()
+    out = {}
+
+    def client(c):
+        futs = []
+        for i in range(50):
+            r = ev_req(30, 1e-3, val=c * 100 + i, graph=f"g{c % 2}") if i % 3 else req(30, 2e-3, val=c * 100 + i)
+            futs.append((c * 100 + i, srv.submit(r)))
+            time.sleep(1e-4)
+        out[c] = [(v, f.result(timeout=30)) for v, f in futs]
+
+    th = [threading.Thread(target=client, args=(c,)) for c in range(4)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join(60)
+    srv.stop()
+    for c in range(4):
+        assert [2.0 * v for v, _ in out[c]] == [r for _, r in out[c]]
+    st = srv.latency_stats()
+    assert st["completed"] == 200 and st["failed"] == 0 and srv.used == 0
+
+
+def test_stop_without_drain_cancels_waiting():
+    clock = Clock()
+    srv = Server(FakeExecutor(clock, n_streams=1), mem_budget=100, clock=clock)
+    srv.start()
+    f0 = srv.submit(req(10, 1e9))
+    f1 = srv.submit(req(10, 1.0))
+    time.sleep(0.05)
+    srv.stop(drain=False)
+    assert f1.cancelled() and not f0.done()
+
+
+# ------------------------------------------------------------- batch stacking
+
+def _eval_request(rng, P, B, K=2, W=3, grad=True):
+    return Request(graph="g", theta=rng.uniform(0, 6, size=(P, K)),
+                   evidence=rng.integers(0, 1 << 62, size=(B, W), dtype=np.uint64),
+                   param_of=rng.integers(0, P, size=B).astype(np.int32),
+                   weight=rng.normal(size=B), grad=grad)
+
+
+@pytest.mark.parametrize("grad", [False, True])
+def test_stacked_batch_keeps_every_request_intact(grad):
+    rng = np.random.default_rng(4)
+    batch = [_eval_request(rng, P, B, grad=grad) for P, B in [(3, 5), (1, 256), (7, 300), (2, 0), (4, 64)]]
+    theta, ev, po, wt, spans = stack_eval_batch(batch, 2, 3, grad)
+    assert len(po) == len(ev) == sum(padded_rows(r.n_rows, grad) for r in batch)
+    extra = 1 if grad else 0
+    assert theta.shape == (sum(r.n_params for r in batch) + extra, 2)
+    for r, (p0, P, b0, B) in zip(batch, spans):
+        assert (P, B) == (r.n_params, r.n_rows)
+        if grad:
+            assert b0 % GRAD_ALIGN == 0
+        np.testing.assert_array_equal(theta[p0:p0 + P], r.theta)
+        np.testing.assert_array_equal(ev[b0:b0 + B], r.evidence)
+        np.testing.assert_array_equal(po[b0:b0 + B], r.param_of + p0)
+        if grad:
+            np.testing.assert_array_equal(wt[b0:b0 + B], r.weight)
+    covered = np.zeros(len(po), bool)
+    for p0, P, b0, B in spans:
+        covered[b0:b0 + B] = True
+    if grad:
+        # padding rows: weight 0, the extra all-zero parameter row
+        assert np.all(wt[~covered] == 0) and np.all(po[~covered] == theta.shape[0] - 1)
+        assert np.all(theta[-1] == 0)
+    else:
+        assert covered.all() and wt is None
+
+
+def test_stacking_rejects_bad_param_rows():
+    rng = np.random.default_rng(1)
+    r = _eval_request(rng, 2, 4)
+    r.param_of = np.array([0, 1, 2, 0], np.int32)
+    with pytest.raises(ValueError):
+        stack_eval_batch([r], 2, 3, True)

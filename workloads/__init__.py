@@ -348,3 +348,49 @@ def serving_pool(seed: int = None) -> List[Circuit]:
                 pr = float(rng.uniform(1e-3, 1e-2))
                 pool.append(qaoa_maxcut(n, edges, p, dep=pr, name=f"qaoa_n{n}_p{p}_g{g}"))
     return pool
+
+
+def log_uniform_int(rng, hi: int, size=None):
+    """Integers in [1, hi] with log-uniform density: floor(exp(U[0, ln(hi+1))))."""
+    v = np.floor(np.exp(rng.uniform(0.0, np.log(hi + 1.0), size=size))).astype(np.int64)
+    return np.clip(v, 1, hi)
+
+
+def serving_requests(pool: Sequence[Circuit], rate: float, duration: float, seed: int = None,
+                     max_params: int = 256, max_samples: int = 4096, eval_rows: int = 64,
+                     p_eval: float = 0.1, p_grad: float = 0.5) -> List[dict]:
+    """Seeded request stream of the serving mix.
+
+    Poisson arrivals at ``rate`` per second over ``duration`` seconds.  Each
+    request: a circuit uniform from the pool; P ~ log-uniform{1..max_params}
+    parameter sets ~ U[0, 2pi); with probability ``p_eval`` an amplitude
+    request over ``eval_rows`` uniform outputs x with every noise event at
+    its first value (k = 0) per parameter set, else S ~
+    log-uniform{1..max_samples} samples per parameter set; a gradient with
+    probability ``p_grad`` (for amplitude requests: of sum_b C(x_b) |f_b|^2).
+    """
+    seed = sub_seed("arrivals", 5) if seed is None else seed
+    rng = np.random.default_rng(seed)
+    out = []
+    t = 0.0
+    while True:
+        t += float(rng.exponential(1.0 / rate))
+        if t >= duration:
+            break
+        ci = int(rng.integers(len(pool)))
+        circ = pool[ci]
+        P = int(log_uniform_int(rng, max_params))
+        theta = rng.uniform(0.0, 2.0 * np.pi, size=(P, circ.n_angles))
+        grad = bool(rng.random() < p_grad)
+        r = dict(t=t, circuit=ci, theta=theta, grad=grad, samples=0, seed=int(rng.integers(1, 1 << 62)))
+        if rng.random() < p_eval:
+            B = P * eval_rows
+            vals = np.zeros((B, circ.n_vars), dtype=np.int64)
+            vals[:, :circ.n] = rng.integers(0, 2, size=(B, circ.n))
+            r["evidence"] = pack_evidence(circ, vals)
+            r["param_of"] = np.repeat(np.arange(P, dtype=np.int32), eval_rows)
+            r["weight"] = maxcut_cost(circ.edges, vals[:, :circ.n]).astype(np.float64)
+        else:
+            r["samples"] = int(log_uniform_int(rng, max_samples))
+        out.append(r)
+    return out
