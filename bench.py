@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--params", type=int, default=1024)
     ap.add_argument("--chains", type=int, default=1000)
     ap.add_argument("--dtype", default="c64")
+    ap.add_argument("--order-trials", type=int, default=64,
+                    help="greedy elimination-order runs the compiler picks from")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-eval", action="store_true")
@@ -299,7 +301,8 @@ def main():
     circ = cfg["circuit"]
     P, chains = args.params, args.chains
     theta_np = cfg["theta"][:P]
-    g = ACGraph(circ, device=0)
+    from paper_2103_17226_amd.compiler import compile_circuit
+    g = ACGraph(compile_circuit(circ, order_trials=args.order_trials), device=0)
     info = g.info
     theta = torch.as_tensor(theta_np, dtype=torch.float64, device=dev)
     edges = torch.as_tensor(np.asarray(circ.edges, dtype=np.int32), device=dev)

@@ -44,6 +44,8 @@ template <typename T>
 hipError_t launch_sample_lds(const DevGraph &g, const LdsPlan &lp, int cpw, int grid, const double *theta,
                              const double *noise, const SampleArgs &a, hipStream_t st);
 hipError_t launch_zero_f64(double *p, int64_t n, hipStream_t st);
+template <typename T>
+int resident_blocks(const DevGraph &g, int which);
 
 }  // namespace qkc
 
@@ -83,6 +85,7 @@ struct ac_graph {
     void *dmem = nullptr;
     int device = 0;
     int n_cu = 0;
+    int resident[2][4] = {{1, 1, 1, 1}, {1, 1, 1, 1}};   // [dtype][eval, grad, sample, stream] per CU
     ac_info_t info{};
     std::vector<uint8_t> var_dom;
     std::vector<uint32_t> var_offset;
@@ -585,6 +588,10 @@ extern "C" ac_status ac_load(const void *blob, size_t nbytes, int device, ac_gra
     g->dmem = dmem;
     g->device = device;
     g->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;
+    for (int k = 0; k < 4; ++k) {
+        g->resident[AC_C64][k] = resident_blocks<float>(d, k);
+        g->resident[AC_C128][k] = resident_blocks<double>(d, k);
+    }
     g->var_dom.assign(var_dom, var_dom + n_vars);
     g->var_offset.assign(var_off, var_off + n_vars);
     ac_info_t &inf = g->info;
@@ -635,27 +642,41 @@ namespace {
 
 constexpr size_t WS_CAP = static_cast<size_t>(48) << 30;   // cap on per-call tile buffers
 constexpr size_t LDS_LIMIT = 64 * 1024;                     // dynamic LDS per workgroup
-constexpr int WG_PER_CU = 4;
 
 constexpr size_t CU_LDS = 160 * 1024;                      // LDS per compute unit (gfx950)
 
-// Launch shape of the LDS-resident sampler, or false if a chain does not fit.
-// Sampler kernels: the batched streaming kernel on the binary plan (default),
-// the LDS-resident node-parallel kernel, or the plain streaming kernel on the
-// blob's own DAG (used when no plan exists).  QKC_SAMPLE_KERNEL = stream | lds
-// | global selects one explicitly (for comparisons and tests).
+// Sampler kernels: the batched streaming kernel on the binary plan, the
+// LDS-resident node-parallel kernel, or the plain streaming kernel on the
+// blob's own DAG (used when no plan exists).  The streaming kernel has the
+// higher throughput once the batch fills the chip; the LDS-resident one has a
+// much shorter time per chain (its node values never leave the CU), so it
+// wins for batches up to a few times the number of chains it holds at once.
+// QKC_SAMPLE_KERNEL = stream | lds | global forces one (comparisons, tests).
 enum SampleKernel { SK_STREAM, SK_LDS, SK_GLOBAL };
 
-SampleKernel sample_kernel(const ac_graph *g) {
+constexpr int64_t LDS_BATCH_FACTOR = 6;   // LDS kernel up to this many rounds of resident chains
+
+bool lds_capacity(const ac_graph *g, ac_dtype dt, int &cpw, int64_t &per_cu);
+
+SampleKernel sample_kernel(const ac_graph *g, ac_dtype dt, int64_t chains) {
     if (!g->has_plan) return SK_GLOBAL;
     const char *kern = std::getenv("QKC_SAMPLE_KERNEL");
     if (kern && std::strcmp(kern, "global") == 0) return SK_GLOBAL;
     if (kern && std::strcmp(kern, "lds") == 0) return SK_LDS;
+    if (kern && std::strcmp(kern, "stream") == 0) return SK_STREAM;
+    int cpw = 0;
+    int64_t per_cu = 0;
+    if (lds_capacity(g, dt, cpw, per_cu) &&
+        chains <= LDS_BATCH_FACTOR * per_cu * cpw * static_cast<int64_t>(g->n_cu))
+        return SK_LDS;
     return SK_STREAM;
 }
 
-bool sample_lds_shape(const ac_graph *g, ac_dtype dt, int64_t chains, int &cpw, int &grid) {
-    if (sample_kernel(g) != SK_LDS) return false;
+// Launch shape of the LDS-resident sampler, or false if a chain does not fit.
+// Chains per wave and workgroups per CU of the LDS-resident sampler, or false
+// if one chain's state does not fit in a CU's LDS.
+bool lds_capacity(const ac_graph *g, ac_dtype dt, int &cpw, int64_t &per_cu) {
+    if (!g->has_plan) return false;
     const size_t cb = dt == AC_C64 ? sample_lds_chain_bytes<float>(g->dev, g->plan)
                                    : sample_lds_chain_bytes<double>(g->dev, g->plan);
     const size_t meta = sample_lds_meta_bytes(g->plan);
@@ -684,7 +705,13 @@ bool sample_lds_shape(const ac_graph *g, ac_dtype dt, int64_t chains, int &cpw, 
         }
     }
     cpw = best_cpw;
-    const int64_t per_cu = static_cast<int64_t>(CU_LDS / (cb * cpw + meta));
+    per_cu = static_cast<int64_t>(CU_LDS / (cb * cpw + meta));
+    return true;
+}
+
+bool sample_lds_shape(const ac_graph *g, ac_dtype dt, int64_t chains, int &cpw, int &grid) {
+    int64_t per_cu = 0;
+    if (!lds_capacity(g, dt, cpw, per_cu)) return false;
     const int64_t want = (chains + cpw - 1) / cpw;
     grid = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(want, per_cu * g->n_cu)));
     return true;
@@ -701,18 +728,27 @@ bool make_layout(const ac_graph *g, ac_dtype dt, int64_t batch, int op, Layout &
     const DevGraph &d = g->dev;
     const size_t cs = dt == AC_C64 ? 8 : 16;
     size_t rows = 0;
+    int kid = 0;
     if (op == AC_OP_EVAL) rows = d.N;
-    else if (op == AC_OP_GRAD) rows = 2 * static_cast<size_t>(d.N) + d.S_ang + d.n_ind;
-    else {
+    else if (op == AC_OP_GRAD) {
+        rows = 2 * static_cast<size_t>(d.N) + d.S_ang + d.n_ind;
+        kid = 1;
+    } else {
         int cpw = 0, lgrid = 0;
-        const SampleKernel sk = sample_kernel(g);
+        const SampleKernel sk = sample_kernel(g, dt, batch);
         if (sk == SK_LDS && sample_lds_shape(g, dt, batch, cpw, lgrid)) rows = 0;
-        else if (sk == SK_STREAM) rows = 2 * static_cast<size_t>(g->plan.N) + d.n_ind + d.n_sel;
-        else rows = 2 * static_cast<size_t>(d.N) + d.n_ind;
+        else if (sk == SK_STREAM) {
+            rows = 2 * static_cast<size_t>(g->plan.N) + d.n_ind + d.n_sel;
+            kid = 3;
+        } else {
+            rows = 2 * static_cast<size_t>(d.N) + d.n_ind;
+            kid = 2;
+        }
     }
     const size_t per_wg = rows * WAVE;
     int64_t tiles = (batch + WAVE - 1) / WAVE;
-    int wg_per_cu = WG_PER_CU;
+    // persistent grids: exactly the workgroups that are resident together
+    int wg_per_cu = g->resident[dt][kid];
     if (const char *env = std::getenv("QKC_WG_PER_CU")) wg_per_cu = std::max(1, std::min(16, std::atoi(env)));
     int64_t grid = std::min<int64_t>(tiles, static_cast<int64_t>(g->n_cu) * wg_per_cu);
     if (per_wg > 0) {
@@ -896,7 +932,7 @@ extern "C" ac_status ac_sample(const ac_graph *g, ac_dtype dtype, const double *
     a.nwq = (g->dev.n_qubits + 63) / 64;
     hipError_t e;
     int cpw = 0, lgrid = 0;
-    const SampleKernel sk = sample_kernel(g);
+    const SampleKernel sk = sample_kernel(g, dtype, total);
     if (sk == SK_LDS && sample_lds_shape(g, dtype, total, cpw, lgrid)) {
         e = dtype == AC_C64 ? launch_sample_lds<float>(g->dev, g->plan, cpw, lgrid, theta, noise, a, st)
                             : launch_sample_lds<double>(g->dev, g->plan, cpw, lgrid, theta, noise, a, st);

@@ -1528,6 +1528,31 @@ hipError_t launch_sample_lds(const DevGraph &g, const LdsPlan &lp, int cpw, int 
     }
 }
 
+// Workgroups of one kernel that fit on a compute unit at once (registers,
+// LDS and wave slots), for grids of exactly the co-resident size.
+// which: 0 = k_eval, 1 = k_grad, 2 = k_sample, 3 = k_sample_stream.
+template <typename T>
+int resident_blocks(const DevGraph &g, int which) {
+    const size_t base = lds_bytes(g, sizeof(cplx<T>));
+    const void *fn = nullptr;
+    size_t lds = base;
+    switch (which) {
+        case 0: fn = reinterpret_cast<const void *>(&k_eval<T>); break;
+        case 1: fn = reinterpret_cast<const void *>(&k_grad<T>); break;
+        case 2: fn = reinterpret_cast<const void *>(&k_sample<T>); break;
+        case 3:
+            fn = reinterpret_cast<const void *>(&k_sample_stream<T>);
+            lds = base + static_cast<size_t>(g.S) * sizeof(cplx<T>);
+            break;
+        default: return 1;
+    }
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, BLOCK, lds) != hipSuccess || n < 1) return 1;
+    return n;
+}
+template int resident_blocks<float>(const DevGraph &, int);
+template int resident_blocks<double>(const DevGraph &, int);
+
 template size_t sample_lds_chain_bytes<float>(const DevGraph &, const LdsPlan &);
 template size_t sample_lds_chain_bytes<double>(const DevGraph &, const LdsPlan &);
 template hipError_t launch_sample_lds<float>(const DevGraph &, const LdsPlan &, int, int, const double *,

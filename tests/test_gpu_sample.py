@@ -23,11 +23,11 @@ def _gpu():
     require_gpu()
 
 
-@pytest.mark.parametrize("variant", ["auto", "lds-cpw1", "lds-cpw2", "lds-cpw4", "global"])
+@pytest.mark.parametrize("variant", ["auto", "stream", "lds-cpw1", "lds-cpw2", "lds-cpw4", "global"])
 def test_same_chain_bitwise_c128(variant, monkeypatch):
     note(f"same-chain bitwise ({variant})")
-    if variant == "global":
-        monkeypatch.setenv("QKC_SAMPLE_KERNEL", "global")
+    if variant in ("global", "stream"):
+        monkeypatch.setenv("QKC_SAMPLE_KERNEL", variant)
     elif variant != "auto":
         monkeypatch.setenv("QKC_SAMPLE_KERNEL", "lds")
         monkeypatch.setenv("QKC_SAMPLE_CPW", variant[-1])
@@ -92,16 +92,20 @@ def test_stationary_distribution_noisy_qaoa_n8():
     assert min(pvals) > 1e-4
 
 
-@pytest.mark.parametrize("other", ["lds", "global"])
+@pytest.mark.parametrize("other", ["lds", "global", "auto"])
 def test_sampler_kernels_agree_c128(other, monkeypatch):
-    note(f"default sampler kernel vs {other}")
+    note(f"streaming sampler kernel vs {other}")
     cfg = W.config(2, small=True)
     g = graph(cfg["circuit"])
     theta = cfg["theta"][:3]
     kw = dict(chains_per_param=40, samples_per_chain=2, burn_in=3, thin=1, seed=11, dtype="c128",
               want_states=True, want_rounds=True)
+    monkeypatch.setenv("QKC_SAMPLE_KERNEL", "stream")
     a = g.sample(theta, **kw)
-    monkeypatch.setenv("QKC_SAMPLE_KERNEL", other)
+    if other == "auto":
+        monkeypatch.delenv("QKC_SAMPLE_KERNEL")
+    else:
+        monkeypatch.setenv("QKC_SAMPLE_KERNEL", other)
     b = g.sample(theta, **kw)
     assert torch.equal(a["states"], b["states"]) and torch.equal(a["rounds"], b["rounds"])
 
