@@ -207,11 +207,20 @@ ac_status ac_grad_batch(const ac_graph *g, ac_dtype dtype,
  *
  * Randomness: r = (mix(seed ^ mix(chain ^ mix((sweep << 20) ^ var))) >> 11) * 2^-53
  * with mix(z) the SplitMix64 finaliser of z + 0x9E3779B97F4A7C15 (Steele, Lea
- * and Flood, OOPSLA 2014); chain = p * chains_per_param + c.  Initial state:
- * output bit q = [r(seed, chain, 0xFFFFFFFF, q) < 1/2], every noise event 0.
- * Chain c of parameter set p runs burn_in + samples_per_chain * thin sweeps
- * and records its state after sweep burn_in + (j + 1) * thin as sample j.
- * Results are deterministic for fixed inputs and independent of other work.
+ * and Flood, OOPSLA 2014); chain = p * chains_per_param + c; the sweeps of a
+ * call are numbered first_sweep, first_sweep + 1, ...  Initial state:
+ * init_states[chain] (all n_words words: outputs and noise events) if
+ * init_states is given, else output bit q = [r(seed, chain, 0xFFFFFFFF, q) < 1/2]
+ * and every noise event 0.  Chain c of parameter set p runs burn_in +
+ * samples_per_chain * thin sweeps and records its state after sweep burn_in +
+ * (j + 1) * thin of the call as sample j.  Results are deterministic for fixed
+ * inputs and independent of other work.
+ *
+ * Resuming chains: a call started from the last recorded state of each chain
+ * (states_out of sample samples_per_chain - 1) with first_sweep advanced by
+ * the previous call's sweeps and the same seed continues exactly the chains of
+ * one longer call; the caller owns those states, so they can stay resident in
+ * device memory between the optimiser's iterations.
  *
  * Outputs, with S = chains_per_param * samples_per_chain and sample index
  * c * samples_per_chain + j:
@@ -219,9 +228,11 @@ ac_status ac_grad_batch(const ac_graph *g, ac_dtype dtype,
  *   states_out uint64 [P][S][n_words]            full evidence words (optional)
  *   cost_out   float64 [P][S]  MaxCut cost of the sample over cost_edges (optional)
  *   rounds_out int64 [P * chains_per_param] downward passes each chain used (optional)
- * cost_edges is a device int32 [n_cost_edges][2] array (NULL if n_cost_edges = 0).
- * Requires n_qubits <= 64, seed < 2^64, sweeps per chain < 2^32 - 1,
- * n_vars < 2^20.
+ * cost_edges is a device int32 [n_cost_edges][2] array (NULL if n_cost_edges = 0);
+ * init_states is a device uint64 [P * chains_per_param][n_words] array or NULL.
+ * Any bit pattern is a valid state (every domain is a power of two).
+ * Requires n_qubits <= 64, seed < 2^64, first_sweep + sweeps per chain < 2^32 - 1,
+ * n_vars < 2^20, reserved fields 0.
  */
 typedef struct {
     int32_t chains_per_param;
@@ -232,6 +243,9 @@ typedef struct {
     int32_t n_cost_edges;
     int32_t reserved;
     const int32_t *cost_edges;
+    const uint64_t *init_states;
+    uint32_t first_sweep;
+    uint32_t reserved2;
 } ac_sample_cfg;
 
 ac_status ac_sample(const ac_graph *g, ac_dtype dtype,

@@ -121,17 +121,22 @@ def init_state(circ, seed, chain):
     return s
 
 
-def run_chain(circ, theta, seed, chain, burn_in, thin, n_samples, noise=None):
-    """Reference systematic-scan chain; returns (samples [S, n_vars], final state)."""
+def run_chain(circ, theta, seed, chain, burn_in, thin, n_samples, noise=None, init=None, first_sweep=0):
+    """Reference systematic-scan chain; returns (samples [S, n_vars], final state).
+
+    ``init`` (one value per variable) replaces the seeded start and
+    ``first_sweep`` numbers the first sweep of this run in the random stream,
+    so a run resumed from another run's final state with its sweep count
+    continues that chain."""
     bc = BranchCache(circ, theta, noise)
-    s = init_state(circ, seed, chain)
+    s = init_state(circ, seed, chain) if init is None else [int(v) for v in init]
     V = circ.n_vars
     samples = []
     total = burn_in + n_samples * thin
     for sweep in range(total):
         for v in range(V):
             w = conditional_weights(bc, s, v)
-            u = choose(w, uniform(seed, chain, sweep, v))
+            u = choose(w, uniform(seed, chain, first_sweep + sweep, v))
             if u is not None:
                 s[v] = u
         done = sweep + 1

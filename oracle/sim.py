@@ -240,3 +240,42 @@ def cost_vector(circ):
 
 def expected_cost(circ, theta, noise=None, shift=None):
     return float(np.dot(probabilities(circ, theta, noise, shift), cost_vector(circ)))
+
+
+# ---------------------------------------------------------------------------
+# local observables of large noise-free QAOA circuits
+# ---------------------------------------------------------------------------
+
+class _Ops:
+    """Minimal circuit record (n, ops, noise) for the simulators above."""
+
+    def __init__(self, n, ops):
+        self.n, self.ops, self.noise = n, ops, []
+
+
+def zz_expectation(psi, i, j, n):
+    """<Z_i Z_j> of a state vector (qubit q = bit q of the index)."""
+    idx = np.arange(1 << n)
+    sign = 1.0 - 2.0 * (((idx >> i) ^ (idx >> j)) & 1)
+    return float(np.dot(np.abs(psi) ** 2, sign))
+
+
+def qaoa_p1_zz_lightcone(edges, gamma, beta, i, j):
+    """<Z_i Z_j> after one QAOA layer (H on all, exp(-i gamma Z_a Z_b) per edge
+    as CNOT-RZ(2 gamma)-CNOT, RX(2 beta) on all) from the reverse light cone.
+
+    In U^dag Z_i Z_j U the mixers on qubits other than i, j commute with
+    Z_i Z_j and cancel, and so do the phase gates of edges touching neither i
+    nor j; what remains acts on i, j and their neighbours only, so the value
+    is that of the same circuit on those qubits with the edges incident to
+    i or j (textbook locality of p = 1 QAOA)."""
+    inc = sorted({tuple(sorted(e)) for e in edges if i in e or j in e})
+    cone = sorted({q for e in inc for q in e} | {i, j})
+    pos = {q: k for k, q in enumerate(cone)}
+    m = len(cone)
+    ops = [("H", q) for q in range(m)]
+    for a, b in inc:
+        ops += [("CNOT", pos[a], pos[b]), ("RZ", pos[b], 0, 2.0), ("CNOT", pos[a], pos[b])]
+    ops += [("RX", q, 1, 2.0) for q in range(m)]
+    psi = branch_state(_Ops(m, ops), [gamma, beta])
+    return zz_expectation(psi, pos[i], pos[j], m)

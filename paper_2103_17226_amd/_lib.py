@@ -42,7 +42,9 @@ class SampleCfg(ctypes.Structure):
     _fields_ = [("chains_per_param", ctypes.c_int32), ("samples_per_chain", ctypes.c_int32),
                 ("burn_in_sweeps", ctypes.c_int32), ("thin_sweeps", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("n_cost_edges", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("cost_edges", ctypes.c_void_p)]
+                ("reserved", ctypes.c_int32), ("cost_edges", ctypes.c_void_p),
+                ("init_states", ctypes.c_void_p), ("first_sweep", ctypes.c_uint32),
+                ("reserved2", ctypes.c_uint32)]
 
 
 class ACError(RuntimeError):

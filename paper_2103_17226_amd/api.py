@@ -171,8 +171,13 @@ class ACGraph:
     def sample(self, theta, chains_per_param: int, samples_per_chain: int = 1, burn_in: int = 20,
                thin: int = 1, seed: int = 1, cost_edges: Optional[Sequence] = None, noise=None,
                dtype: str = "c64", want_states=False, want_cost=False, want_rounds=False,
-               validate: bool = True, ws: Optional[torch.Tensor] = None):
-        """Gibbs samples of the output bits (see ac_sample)."""
+               validate: bool = True, ws: Optional[torch.Tensor] = None, init_states=None,
+               first_sweep: int = 0):
+        """Gibbs samples of the output bits (see ac_sample).  ``init_states``
+        (uint64/int64 [P * chains_per_param, n_words], e.g. the last sample's
+        ``states`` of a previous call) starts every chain from a given state;
+        ``first_sweep`` numbers this call's first sweep for the RNG, so a call
+        resumed with the previous call's sweep count continues its chains."""
         code, _ = _CDTYPE[dtype]
         K = self.info["n_angles"]
         theta = self._dev(theta, torch.float64, "theta")
@@ -198,9 +203,17 @@ class ACGraph:
         if want_cost and edges_t is None:
             raise ValueError("want_cost needs cost_edges")
         rounds = torch.empty(P * chains_per_param, dtype=i64, device=dev) if want_rounds else None
+        init_t = None
+        if init_states is not None:
+            init_t = torch.as_tensor(_as_words(init_states))
+            if init_t.numel() != P * chains_per_param * self.info["n_words"]:
+                raise ValueError(f"init_states must hold {P * chains_per_param} x {self.info['n_words']} words")
+            init_t = self._dev(init_t.reshape(P * chains_per_param, self.info["n_words"]), torch.int64,
+                               "init_states")
         cfg = L.SampleCfg(int(chains_per_param), int(samples_per_chain), int(burn_in), int(thin),
                           int(seed) & ((1 << 64) - 1), 0 if edges_t is None else int(edges_t.shape[0]), 0,
-                          None if edges_t is None else edges_t.data_ptr())
+                          None if edges_t is None else edges_t.data_ptr(),
+                          None if init_t is None else init_t.data_ptr(), int(first_sweep), 0)
         ws = self.workspace(dtype, P * chains_per_param, L.AC_OP_SAMPLE, ws)
         L.check(L.lib().ac_sample(self._h, code, _ptr(theta), P, _ptr(noise), ctypes.byref(cfg),
                                   _ptr(samples), _ptr(states), _ptr(cost), _ptr(rounds), _ptr(ws),

@@ -900,7 +900,10 @@ extern "C" ac_status ac_sample(const ac_graph *g, ac_dtype dtype, const double *
         return fail(AC_ERR_INVALID_ARG, "ac_sample: bad chain schedule");
     const uint64_t sweeps = static_cast<uint64_t>(cfg->burn_in_sweeps) +
                             static_cast<uint64_t>(cfg->samples_per_chain) * static_cast<uint64_t>(cfg->thin_sweeps);
-    if (sweeps >= 0xFFFFFFFFull) return fail(AC_ERR_INVALID_ARG, "ac_sample: too many sweeps per chain");
+    if (static_cast<uint64_t>(cfg->first_sweep) + sweeps >= 0xFFFFFFFFull)
+        return fail(AC_ERR_INVALID_ARG, "ac_sample: first_sweep + sweeps per chain must stay below 2^32 - 1");
+    if (cfg->reserved != 0 || cfg->reserved2 != 0)
+        return fail(AC_ERR_INVALID_ARG, "ac_sample: reserved fields must be 0");
     if (g->dev.n_qubits > 64) return fail(AC_ERR_UNSUPPORTED, "ac_sample: more than 64 output qubits");
     for (int q = 0; q < g->dev.n_qubits; ++q)
         if (g->var_offset[q] != static_cast<uint32_t>(q)) return fail(AC_ERR_UNSUPPORTED, "ac_sample: outputs must occupy bits 0..n-1");
@@ -930,6 +933,8 @@ extern "C" ac_status ac_sample(const ac_graph *g, ac_dtype dtype, const double *
     a.cost_out = cost_out;
     a.rounds_out = rounds_out;
     a.nwq = (g->dev.n_qubits + 63) / 64;
+    a.init_states = cfg->init_states;
+    a.first_sweep = cfg->first_sweep;
     hipError_t e;
     int cpw = 0, lgrid = 0;
     const SampleKernel sk = sample_kernel(g, dtype, total);

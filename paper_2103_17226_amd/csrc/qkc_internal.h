@@ -126,6 +126,8 @@ struct SampleArgs {
     double *cost_out;
     int64_t *rounds_out;
     int32_t nwq;
+    const uint64_t *init_states;   // [total_chains][W] start states, or null for the seeded start
+    uint64_t first_sweep;          // RNG sweep number of this call's first sweep
 };
 
 }  // namespace qkc

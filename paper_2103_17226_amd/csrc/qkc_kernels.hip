@@ -473,8 +473,9 @@ __global__ __launch_bounds__(BLOCK) void k_sample(DevGraph g, const double *thet
         s_sweep[lane] = 0;
         s_emitted[lane] = 0;
         s_rounds[lane] = 0;
-        for (int w = 0; w < g.W; ++w) ev_s[w * WAVE + lane] = 0ull;
-        if (ch >= 0) {
+        for (int w = 0; w < g.W; ++w)
+            ev_s[w * WAVE + lane] = (ch >= 0 && a.init_states) ? a.init_states[ch * g.W + w] : 0ull;
+        if (ch >= 0 && !a.init_states) {
             uint64_t x = 0;
             for (int q = 0; q < g.n_qubits; ++q) {
                 if (rng_uniform(a.seed, static_cast<uint64_t>(ch), INIT_SWEEP, static_cast<uint64_t>(q)) < 0.5)
@@ -532,7 +533,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(DevGraph g, const double *thet
                 }
                 uint32_t pick = cur;
                 if (total > 0.0) {
-                    const double r = rng_uniform(a.seed, static_cast<uint64_t>(ch), sweep, static_cast<uint64_t>(v));
+                    const double r = rng_uniform(a.seed, static_cast<uint64_t>(ch), a.first_sweep + sweep, static_cast<uint64_t>(v));
                     const double target = __dmul_rn(r, total);
                     double acc = 0.0;
                     int last_pos = -1;
@@ -859,8 +860,9 @@ __global__ __launch_bounds__(BLOCK) void k_sample_stream(DevGraph g, LdsPlan lp,
         s_sweep[lane] = 0;
         s_emitted[lane] = 0;
         s_rounds[lane] = 0;
-        for (int w = 0; w < g.W; ++w) ev_s[w * WAVE + lane] = 0ull;
-        if (ch >= 0) {
+        for (int w = 0; w < g.W; ++w)
+            ev_s[w * WAVE + lane] = (ch >= 0 && a.init_states) ? a.init_states[ch * g.W + w] : 0ull;
+        if (ch >= 0 && !a.init_states) {
             uint64_t x = 0;
             for (int q = 0; q < g.n_qubits; ++q)
                 if (rng_uniform(a.seed, static_cast<uint64_t>(ch), INIT_SWEEP, static_cast<uint64_t>(q)) < 0.5)
@@ -948,7 +950,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample_stream(DevGraph g, LdsPlan lp,
                 for (int u = 0; u < dom; ++u) total = __dadd_rn(total, weight(u));
                 uint32_t pick = cur;
                 if (total > 0.0) {
-                    const double r = rng_uniform(a.seed, static_cast<uint64_t>(ch), sweep, static_cast<uint64_t>(v));
+                    const double r = rng_uniform(a.seed, static_cast<uint64_t>(ch), a.first_sweep + sweep, static_cast<uint64_t>(v));
                     const double target = __dmul_rn(r, total);
                     double acc = 0.0;
                     int last_pos = -1, chosen = -1;
@@ -1148,8 +1150,8 @@ __global__ __launch_bounds__(WAVE) void k_sample_lds(DevGraph g, LdsPlan lp, con
         c.st[4] = 0;
         c.st[5] = ch >= 0 ? ch / a.cpp : 0;
         c.st[6] = 1;
-        for (int w = 0; w < g.W; ++w) c.ev[w] = 0ull;
-        if (ch >= 0) {
+        for (int w = 0; w < g.W; ++w) c.ev[w] = (ch >= 0 && a.init_states) ? a.init_states[ch * g.W + w] : 0ull;
+        if (ch >= 0 && !a.init_states) {
             uint64_t x = 0;
             for (int q = 0; q < g.n_qubits; ++q)
                 if (rng_uniform(a.seed, static_cast<uint64_t>(ch), INIT_SWEEP, static_cast<uint64_t>(q)) < 0.5)
@@ -1349,7 +1351,7 @@ __global__ __launch_bounds__(WAVE) void k_sample_lds(DevGraph g, LdsPlan lp, con
                         total = __dadd_rn(total, __dadd_rn(__dmul_rn(re, re), __dmul_rn(im, im)));
                     }
                     if (total > 0.0) {
-                        const double r = rng_uniform(a.seed, static_cast<uint64_t>(ch), sw, static_cast<uint64_t>(v));
+                        const double r = rng_uniform(a.seed, static_cast<uint64_t>(ch), a.first_sweep + sw, static_cast<uint64_t>(v));
                         const double target = __dmul_rn(r, total);
                         double acc = 0.0;
                         int last_pos = -1, chosen = -1;

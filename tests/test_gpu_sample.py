@@ -126,3 +126,47 @@ def test_sampler_determinism_and_cost():
     x = a["samples"].cpu().numpy().reshape(-1).view(np.uint64)
     bits = np.array([W.x_bits(int(v), circ.n) for v in x])
     assert np.array_equal(a["cost"].cpu().numpy().reshape(-1), W.maxcut_cost(circ.edges, bits))
+
+
+@pytest.mark.parametrize("variant", ["stream", "lds", "global"])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_resumed_chains_continue_one_long_run(variant, dtype, monkeypatch):
+    # Two calls, the second started from the first call's last states with
+    # first_sweep advanced, reproduce the later samples of one longer call.
+    note(f"resumed chains ({variant}, {dtype})")
+    monkeypatch.setenv("QKC_SAMPLE_KERNEL", variant)
+    cfg = W.config(2, small=True)
+    g = graph(cfg["circuit"])
+    theta = cfg["theta"][:3]
+    P, C = theta.shape[0], 40
+    common = dict(chains_per_param=C, burn_in=3, thin=2, seed=77, dtype=dtype, want_states=True)
+    whole = g.sample(theta, samples_per_chain=4, **common)
+    first = g.sample(theta, samples_per_chain=2, **common)
+    Wn = g.info["n_words"]
+    st1 = first["states"].reshape(P, C, 2, Wn)
+    assert torch.equal(st1, whole["states"].reshape(P, C, 4, Wn)[:, :, :2])
+    last = st1[:, :, 1].reshape(P * C, Wn)
+    second = g.sample(theta, chains_per_param=C, samples_per_chain=2, burn_in=0, thin=2, seed=77, dtype=dtype,
+                      want_states=True, init_states=last, first_sweep=3 + 2 * 2)
+    want = whole["states"].reshape(P, C, 4, Wn)[:, :, 2:]
+    assert torch.equal(second["states"].reshape(P, C, 2, Wn), want)
+    assert torch.equal(second["samples"].reshape(P, C, 2, -1), whole["samples"].reshape(P, C, 4, -1)[:, :, 2:])
+
+
+def test_resumed_chains_from_arbitrary_states_follow_the_oracle_chain():
+    # A chain started from a given state makes the oracle's decisions from that state.
+    note("warm start vs oracle chain")
+    circ = W.qaoa_maxcut(3, W.ring_graph(3), 1, dep=0.05, ad=0.03)
+    g = graph(circ)
+    theta = np.array([[0.7, 0.4]])
+    rng = np.random.default_rng(3)
+    doms = circ.var_domains()
+    C = 6
+    vals = np.stack([[rng.integers(0, d) for d in doms] for _ in range(C)])
+    init = W.pack_evidence(circ, vals)
+    out = g.sample(theta, C, 1, 2, 1, 99, dtype="c128", want_states=True, init_states=init, first_sweep=5)
+    got = W.unpack_evidence(circ, out["states"].cpu().numpy().reshape(C, -1).view(np.uint64))
+    for c in range(C):
+        ref, _ = gibbs.run_chain(circ, theta[0], seed=99, chain=c, burn_in=2, thin=1, n_samples=1,
+                                 init=vals[c], first_sweep=5)
+        assert np.array_equal(got[c], ref[0]), c

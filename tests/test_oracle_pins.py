@@ -289,6 +289,79 @@ def test_reference_chain_matches_exact_sweep_distribution():
     assert pval > 1e-3
 
 
+def test_resumed_reference_chain_is_the_same_chain():
+    # Resuming from the final state with the sweep count continues the chain;
+    # a wrong sweep number changes the random stream and the samples.
+    c = W.qaoa_maxcut(3, W.ring_graph(3), 1, dep=0.05, ad=0.03)
+    th = [0.9, 0.3]
+    for ch in range(5):
+        whole, _ = gibbs.run_chain(c, th, seed=8, chain=ch, burn_in=2, thin=1, n_samples=6)
+        part, last = gibbs.run_chain(c, th, seed=8, chain=ch, burn_in=2, thin=1, n_samples=3)
+        rest, _ = gibbs.run_chain(c, th, seed=8, chain=ch, burn_in=0, thin=1, n_samples=3, init=last,
+                                  first_sweep=5)
+        assert np.array_equal(np.concatenate([part, rest]), whole)
+    # the exact kernel from a point mass: the resumed reference chain from
+    # state s has the law of one sweep from s (chi-square over many chains)
+    c = W.Circuit(n=2, ops=[("H", 0), ("DEP", 0, 0), ("H", 1), ("CNOT", 0, 1), ("AD", 1, 1),
+                            ("RX", 0, 1, 2.0), ("RZ", 1, 0, 2.0)],
+                  n_angles=2, noise=[0.3, 0.25], edges=[(0, 1)])
+    s0 = [1, 0, 2, 1]
+    counts = {}
+    for ch in range(2000):
+        smp, _ = gibbs.run_chain(c, th, seed=3, chain=ch, burn_in=0, thin=1, n_samples=1, init=s0,
+                                 first_sweep=11)
+        counts[tuple(smp[0])] = counts.get(tuple(smp[0]), 0) + 1
+    law = _one_sweep_law(c, th, s0)
+    keys = sorted(law)
+    obs = np.array([counts.get(k, 0) for k in keys])
+    assert sum(counts.get(k, 0) for k in counts if k not in law) == 0
+    _, _, pval = stats.chi2_pooled(obs, np.array([law[k] for k in keys]))
+    assert pval > 1e-3
+
+
+def _one_sweep_law(c, th, s0):
+    """Law of one systematic sweep from s0, by enumerating every branch of the
+    single-site updates (each update draws u with |f(s[v<-u])|^2 / sum)."""
+    bc = gibbs.BranchCache(c, th)
+    doms = c.var_domains()
+    law = {tuple(s0): 1.0}
+    for v in range(c.n_vars):
+        nxt = {}
+        for s, p in law.items():
+            w = []
+            for u in range(doms[v]):
+                t = list(s)
+                t[v] = u
+                w.append(abs(bc.amp(t)) ** 2)
+            tot = sum(w)
+            if tot == 0:
+                nxt[s] = nxt.get(s, 0) + p
+                continue
+            for u in range(doms[v]):
+                if w[u] > 0:
+                    t = list(s)
+                    t[v] = u
+                    nxt[tuple(t)] = nxt.get(tuple(t), 0) + p * w[u] / tot
+        law = nxt
+    return law
+
+
+def test_lightcone_zz_equals_full_state_vector():
+    # p = 1 QAOA: the light-cone value of <Z_i Z_j> equals the full state
+    # vector's on every edge and on non-edges (n = 10, 3-regular).
+    edges = W.random_regular_graph(10, 3, 21)
+    circ = W.qaoa_maxcut(10, edges, 1)
+    rng = np.random.default_rng(6)
+    for _ in range(3):
+        g, b = rng.uniform(0, 2 * np.pi, size=2)
+        psi = sim.statevector(circ, [g, b])
+        for (i, j) in list(edges) + [(0, 5), (2, 9)]:
+            full = sim.zz_expectation(psi, i, j, 10)
+            assert abs(sim.qaoa_p1_zz_lightcone(edges, g, b, i, j) - full) < 1e-12
+    # closed form at gamma = 0 (no entanglement): <ZZ> = 0
+    assert abs(sim.qaoa_p1_zz_lightcone(edges, 0.0, 0.7, *edges[0])) < 1e-12
+
+
 def test_chi2_detects_bias_and_accepts_truth():
     rng = np.random.default_rng(0)
     p = rng.dirichlet(np.ones(20))
