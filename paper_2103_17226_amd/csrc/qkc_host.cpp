@@ -37,7 +37,7 @@ template <typename T>
 size_t sample_lds_chain_bytes(const DevGraph &g, const LdsPlan &lp);
 size_t sample_lds_meta_bytes(const LdsPlan &lp);
 template <typename T>
-hipError_t launch_sample_stream(const DevGraph &g, const LdsPlan &lp, int grid, const double *theta,
+hipError_t launch_sample_stream(const DevGraph &g, const LdsPlan &lp, int grid, int block, const double *theta,
                                 const void *wfix, void *vals, size_t per_wg_elems, const SampleArgs &a,
                                 hipStream_t st);
 template <typename T>
@@ -45,7 +45,7 @@ hipError_t launch_sample_lds(const DevGraph &g, const LdsPlan &lp, int cpw, int 
                              const double *noise, const SampleArgs &a, hipStream_t st);
 hipError_t launch_zero_f64(double *p, int64_t n, hipStream_t st);
 template <typename T>
-int resident_blocks(const DevGraph &g, int which);
+int resident_blocks(const DevGraph &g, int which, int block);
 
 }  // namespace qkc
 
@@ -86,6 +86,7 @@ struct ac_graph {
     int device = 0;
     int n_cu = 0;
     int resident[2][4] = {{1, 1, 1, 1}, {1, 1, 1, 1}};   // [dtype][eval, grad, sample, stream] per CU
+    int stream_block = BLOCK;                             // threads per workgroup of the streaming sampler
     ac_info_t info{};
     std::vector<uint8_t> var_dom;
     std::vector<uint32_t> var_offset;
@@ -588,9 +589,14 @@ extern "C" ac_status ac_load(const void *blob, size_t nbytes, int device, ac_gra
     g->dmem = dmem;
     g->device = device;
     g->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;
+    if (const char *env = std::getenv("QKC_STREAM_WAVES")) {
+        const int nw = std::atoi(env);
+        if (nw >= 1 && nw <= BLOCK / WAVE) g->stream_block = nw * WAVE;
+    }
     for (int k = 0; k < 4; ++k) {
-        g->resident[AC_C64][k] = resident_blocks<float>(d, k);
-        g->resident[AC_C128][k] = resident_blocks<double>(d, k);
+        const int blk = k == 3 ? g->stream_block : BLOCK;
+        g->resident[AC_C64][k] = resident_blocks<float>(d, k, blk);
+        g->resident[AC_C128][k] = resident_blocks<double>(d, k, blk);
     }
     g->var_dom.assign(var_dom, var_dom + n_vars);
     g->var_offset.assign(var_off, var_off + n_vars);
@@ -945,12 +951,14 @@ extern "C" ac_status ac_sample(const ac_graph *g, ac_dtype dtype, const double *
         if (dtype == AC_C64) {
             e = launch_fixed_slots<float>(g->dev, noise, w + L.wfix_off, st);
             if (e == hipSuccess)
-                e = launch_sample_stream<float>(g->dev, g->plan, L.grid, theta, w + L.wfix_off, w + L.tiles_off,
+                e = launch_sample_stream<float>(g->dev, g->plan, L.grid, g->stream_block, theta, w + L.wfix_off,
+                                                w + L.tiles_off,
                                                 L.per_wg_elems, a, st);
         } else {
             e = launch_fixed_slots<double>(g->dev, noise, w + L.wfix_off, st);
             if (e == hipSuccess)
-                e = launch_sample_stream<double>(g->dev, g->plan, L.grid, theta, w + L.wfix_off, w + L.tiles_off,
+                e = launch_sample_stream<double>(g->dev, g->plan, L.grid, g->stream_block, theta, w + L.wfix_off,
+                                                 w + L.tiles_off,
                                                  L.per_wg_elems, a, st);
         }
     } else if (dtype == AC_C64) {

@@ -605,6 +605,16 @@ __global__ __launch_bounds__(BLOCK) void k_sample(DevGraph g, const double *thet
 // their records with uniform (scalar) loads, issues every child-value load
 // of the batch, and only then computes and stores, so that KB rows per wave
 // are in flight instead of one.
+//
+// Every lane reads only the column it wrote itself (lane = chain), so a
+// workgroup of one wavefront needs no barrier between levels: the wave's own
+// stores and loads of one address stay in program order, and the next level's
+// loads can issue while this level's stores drain.  With several waves per
+// tile a level's rows come from other waves and the barrier is required.
+
+__device__ __forceinline__ void level_sync(int nwaves) {
+    if (nwaves > 1) __syncthreads();
+}
 
 template <typename T>
 struct StreamTile {
@@ -644,24 +654,6 @@ struct StreamTile {
         return sl == NO_SLOT ? cplx<T>{T(0), T(0)} : wfix[sl];
     }
 
-    // sum of adj[parent] * value(sibling) over the parent edges of a record
-    __device__ __forceinline__ cplx<T> pull(const LdsPlan &lp, const uint4 br) const {
-        double ar = 0.0, ai = 0.0;
-        for (uint32_t q = 0; q < br.x; ++q) {
-            uint32_t p = br.z, sb = br.w;
-            if (q > 0) {
-                const uint64_t rr = lp.orec[br.y + q - 1];
-                p = static_cast<uint32_t>(rr);
-                sb = static_cast<uint32_t>(rr >> 32);
-            }
-            cplx<T> t = adj[static_cast<size_t>(p) * WAVE + lane];
-            if (sb != NO_SIBLING) t = cmul(t, value(sb));
-            ar += static_cast<double>(t.re);
-            ai += static_cast<double>(t.im);
-        }
-        return {static_cast<T>(ar), static_cast<T>(ai)};
-    }
-
     __device__ void forward(const LdsPlan &lp, int wave, int nwaves) {
         constexpr int KB = sizeof(T) == 4 ? 8 : 4;
         for (int l = 0; l < lp.L; ++l) {
@@ -689,54 +681,72 @@ struct StreamTile {
                         val[static_cast<size_t>(b0 + j) * WAVE + lane] = b0 + j >= np ? cmul(va[j], vb[j]) : cadd(va[j], vb[j]);
                 }
             }
-            __syncthreads();
+            level_sync(nwaves);
+        }
+    }
+
+    // Adjoint sums of the targets [t0, t1) (plan nodes, then indicator and
+    // selector leaves): out(t, sum over the parent edges of t of
+    // adj[parent] * value(sibling)), the edges in increasing parent order.
+    // The edges of the whole range are walked in batches of KE whose row
+    // loads are all issued before any term is added, so a target with many
+    // parents costs batches, not one dependent load per parent.
+    template <typename Out>
+    __device__ __forceinline__ void pull_targets(const LdsPlan &lp, uint32_t t0, uint32_t t1, Out out) const {
+        constexpr int KE = sizeof(T) == 4 ? 8 : 4;
+        const uint32_t e_end = lp.estart[t1];
+        uint32_t t = t0;
+        uint32_t t_next = lp.estart[t0 + 1];      // first edge past target t
+        double ar = 0.0, ai = 0.0;
+        for (uint32_t e = lp.estart[t0]; e < e_end; e += KE) {
+            uint64_t rr[KE];
+            cplx<T> ap[KE], sv[KE];
+#pragma unroll
+            for (int j = 0; j < KE; ++j)
+                rr[j] = e + j < e_end ? lp.edg[e + j] : (static_cast<uint64_t>(NO_SIBLING) << 32);
+#pragma unroll
+            for (int j = 0; j < KE; ++j) {
+                ap[j] = adj[static_cast<size_t>(static_cast<uint32_t>(rr[j])) * WAVE + lane];
+                sv[j] = row(val, static_cast<uint32_t>(rr[j] >> 32));
+            }
+#pragma unroll
+            for (int j = 0; j < KE; ++j) {
+                const uint32_t ee = e + static_cast<uint32_t>(j);
+                if (ee >= e_end) break;
+                while (ee >= t_next) {            // every edge of target t is in
+                    out(t, cplx<T>{static_cast<T>(ar), static_cast<T>(ai)});
+                    ar = 0.0;
+                    ai = 0.0;
+                    ++t;
+                    t_next = lp.estart[t + 1];
+                }
+                const uint32_t sb = static_cast<uint32_t>(rr[j] >> 32);
+                const cplx<T> term = sb != NO_SIBLING ? cmul(ap[j], pick(sb, sv[j])) : ap[j];
+                ar += static_cast<double>(term.re);
+                ai += static_cast<double>(term.im);
+            }
+        }
+        for (; t < t1; ++t) {                      // the last target with edges, and any without
+            out(t, cplx<T>{static_cast<T>(ar), static_cast<T>(ai)});
+            ar = 0.0;
+            ai = 0.0;
         }
     }
 
     __device__ void backward(const LdsPlan &lp, int wave, int nwaves) {
         constexpr int KB = sizeof(T) == 4 ? 8 : 4;
-        const uint4 *brec = reinterpret_cast<const uint4 *>(lp.brec);
+        const uint32_t root = static_cast<uint32_t>(lp.root);
+        cplx<T> *a = adj;
+        const int ln = lane;
         for (int l = lp.L - 1; l >= 0; --l) {
             const uint32_t n0 = lp.level_ptr[l], n1 = lp.level_ptr[l + 1];
             for (uint32_t b0 = n0 + static_cast<uint32_t>(wave) * KB; b0 < n1; b0 += static_cast<uint32_t>(nwaves) * KB) {
-                uint4 br[KB];
-                cplx<T> ap[KB], sv[KB];
-#pragma unroll
-                for (int j = 0; j < KB; ++j) br[j] = b0 + j < n1 ? brec[b0 + j] : uint4{0, 0, 0, NO_SIBLING};
-#pragma unroll
-                for (int j = 0; j < KB; ++j) {
-                    ap[j] = adj[static_cast<size_t>(br[j].x > 0 ? br[j].z : 0u) * WAVE + lane];
-                    sv[j] = row(val, br[j].w);
-                }
-#pragma unroll
-                for (int j = 0; j < KB; ++j) {
-                    if (br[j].x == 0) ap[j] = {T(0), T(0)};
-                    sv[j] = (br[j].x > 0 && br[j].w != NO_SIBLING) ? pick(br[j].w, sv[j]) : cplx<T>{T(1), T(0)};
-                }
-#pragma unroll
-                for (int j = 0; j < KB; ++j) {
-                    const uint32_t i = b0 + j;
-                    if (i >= n1) continue;
-                    cplx<T> a;
-                    if (i == static_cast<uint32_t>(lp.root)) {
-                        a = {T(1), T(0)};
-                    } else {
-                        const cplx<T> t0 = cmul(ap[j], sv[j]);
-                        double ar = static_cast<double>(t0.re), ai = static_cast<double>(t0.im);
-                        for (uint32_t q = 1; q < br[j].x; ++q) {
-                            const uint64_t rr = lp.orec[br[j].y + q - 1];
-                            cplx<T> t = adj[static_cast<size_t>(static_cast<uint32_t>(rr)) * WAVE + lane];
-                            const uint32_t sb = static_cast<uint32_t>(rr >> 32);
-                            if (sb != NO_SIBLING) t = cmul(t, value(sb));
-                            ar += static_cast<double>(t.re);
-                            ai += static_cast<double>(t.im);
-                        }
-                        a = {static_cast<T>(ar), static_cast<T>(ai)};
-                    }
-                    adj[static_cast<size_t>(i) * WAVE + lane] = a;
-                }
+                const uint32_t b1 = b0 + KB < n1 ? b0 + KB : n1;
+                pull_targets(lp, b0, b1, [&](uint32_t i, cplx<T> v) {
+                    a[static_cast<size_t>(i) * WAVE + ln] = i == root ? cplx<T>{T(1), T(0)} : v;
+                });
             }
-            __syncthreads();
+            level_sync(nwaves);
         }
     }
 
@@ -745,43 +755,19 @@ struct StreamTile {
     // d root / d lambda_{v=u} (A_q * W[slot_q(u)]) are added per variable
     __device__ void leaf_derivatives(const LdsPlan &lp, int wave, int nwaves, cplx<T> *D, cplx<T> *A) {
         constexpr int KB = sizeof(T) == 4 ? 8 : 4;
-        const uint4 *brec = reinterpret_cast<const uint4 *>(lp.brec);
+        const uint32_t M = static_cast<uint32_t>(lp.N);
         const uint32_t nt = static_cast<uint32_t>(g.n_ind + g.n_sel);
+        const uint32_t n_ind = static_cast<uint32_t>(g.n_ind);
+        const int ln = lane;
         for (uint32_t b0 = static_cast<uint32_t>(wave) * KB; b0 < nt; b0 += static_cast<uint32_t>(nwaves) * KB) {
-            uint4 br[KB];
-            cplx<T> ap[KB], sv[KB];
-#pragma unroll
-            for (int j = 0; j < KB; ++j) br[j] = b0 + j < nt ? brec[lp.N + b0 + j] : uint4{0, 0, 0, NO_SIBLING};
-#pragma unroll
-            for (int j = 0; j < KB; ++j) {
-                ap[j] = adj[static_cast<size_t>(br[j].x > 0 ? br[j].z : 0u) * WAVE + lane];
-                sv[j] = row(val, br[j].w);
-            }
-#pragma unroll
-            for (int j = 0; j < KB; ++j) {
-                const uint32_t t = b0 + j;
-                if (t >= nt) continue;
-                double ar = 0.0, ai = 0.0;
-                if (br[j].x > 0) {
-                    const cplx<T> s0 = br[j].w != NO_SIBLING ? pick(br[j].w, sv[j]) : cplx<T>{T(1), T(0)};
-                    const cplx<T> t0 = cmul(ap[j], s0);
-                    ar = static_cast<double>(t0.re);
-                    ai = static_cast<double>(t0.im);
-                    for (uint32_t q = 1; q < br[j].x; ++q) {
-                        const uint64_t rr = lp.orec[br[j].y + q - 1];
-                        cplx<T> tt = adj[static_cast<size_t>(static_cast<uint32_t>(rr)) * WAVE + lane];
-                        const uint32_t sb = static_cast<uint32_t>(rr >> 32);
-                        if (sb != NO_SIBLING) tt = cmul(tt, value(sb));
-                        ar += static_cast<double>(tt.re);
-                        ai += static_cast<double>(tt.im);
-                    }
-                }
-                const cplx<T> r = {static_cast<T>(ar), static_cast<T>(ai)};
-                if (t < static_cast<uint32_t>(g.n_ind)) D[static_cast<size_t>(t) * WAVE + lane] = r;
-                else A[static_cast<size_t>(t - g.n_ind) * WAVE + lane] = r;
-            }
+            const uint32_t b1 = b0 + KB < nt ? b0 + KB : nt;
+            pull_targets(lp, M + b0, M + b1, [&](uint32_t i, cplx<T> v) {
+                const uint32_t t = i - M;
+                if (t < n_ind) D[static_cast<size_t>(t) * WAVE + ln] = v;
+                else A[static_cast<size_t>(t - n_ind) * WAVE + ln] = v;
+            });
         }
-        __syncthreads();
+        level_sync(nwaves);
         for (int v = wave; v < g.n_vars; v += nwaves) {
             const uint32_t base = g.ind_base[v], dom = g.ind_base[v + 1] - base;
             const uint32_t q0 = g.vsel_ptr[v], q1 = g.vsel_ptr[v + 1];
@@ -803,25 +789,6 @@ struct StreamTile {
 #pragma unroll
             for (int u = 0; u < SEL_DOM; ++u)
                 if (static_cast<uint32_t>(u) < dom) D[static_cast<size_t>(base + u) * WAVE + lane] = acc[u];
-        }
-    }
-
-    // d root / d lambda_{v=u} for the values of variable v -> out[(base+u) * WAVE]
-    __device__ void ind_derivatives(const LdsPlan &lp, int v, cplx<T> *out) const {
-        const uint4 *brec = reinterpret_cast<const uint4 *>(lp.brec);
-        const uint32_t base = g.ind_base[v], dom = g.ind_base[v + 1] - base;
-        for (uint32_t u = 0; u < dom; ++u) out[static_cast<size_t>(base + u) * WAVE] = pull(lp, brec[lp.N + base + u]);
-        const uint32_t q1 = g.vsel_ptr[v + 1];
-        for (uint32_t qq = g.vsel_ptr[v]; qq < q1; ++qq) {
-            const uint32_t q = g.vsel[qq];
-            const cplx<T> A = pull(lp, brec[lp.N + g.n_ind + q]);
-            const uint32_t *rec = g.sel + static_cast<size_t>(q) * SEL_REC;
-            for (uint32_t u = 0; u < dom && u < static_cast<uint32_t>(SEL_DOM); ++u) {
-                const uint32_t sl = rec[1 + u];
-                if (sl == NO_SLOT) continue;
-                cplx<T> &o = out[static_cast<size_t>(base + u) * WAVE];
-                o = cadd(o, cmul(A, wfix[sl]));
-            }
         }
     }
 };
@@ -1532,9 +1499,10 @@ hipError_t launch_sample_lds(const DevGraph &g, const LdsPlan &lp, int cpw, int 
 
 // Workgroups of one kernel that fit on a compute unit at once (registers,
 // LDS and wave slots), for grids of exactly the co-resident size.
-// which: 0 = k_eval, 1 = k_grad, 2 = k_sample, 3 = k_sample_stream.
+// which: 0 = k_eval, 1 = k_grad, 2 = k_sample, 3 = k_sample_stream; block =
+// threads per workgroup.
 template <typename T>
-int resident_blocks(const DevGraph &g, int which) {
+int resident_blocks(const DevGraph &g, int which, int block) {
     const size_t base = lds_bytes(g, sizeof(cplx<T>));
     const void *fn = nullptr;
     size_t lds = base;
@@ -1549,11 +1517,11 @@ int resident_blocks(const DevGraph &g, int which) {
         default: return 1;
     }
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, BLOCK, lds) != hipSuccess || n < 1) return 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, block, lds) != hipSuccess || n < 1) return 1;
     return n;
 }
-template int resident_blocks<float>(const DevGraph &, int);
-template int resident_blocks<double>(const DevGraph &, int);
+template int resident_blocks<float>(const DevGraph &, int, int);
+template int resident_blocks<double>(const DevGraph &, int, int);
 
 template size_t sample_lds_chain_bytes<float>(const DevGraph &, const LdsPlan &);
 template size_t sample_lds_chain_bytes<double>(const DevGraph &, const LdsPlan &);
@@ -1564,18 +1532,19 @@ template hipError_t launch_sample_lds<double>(const DevGraph &, const LdsPlan &,
 
 
 template <typename T>
-hipError_t launch_sample_stream(const DevGraph &g, const LdsPlan &lp, int grid, const double *theta,
+hipError_t launch_sample_stream(const DevGraph &g, const LdsPlan &lp, int grid, int block, const double *theta,
                                 const void *wfix, void *vals, size_t per_wg_elems, const SampleArgs &a,
                                 hipStream_t st) {
+    if (block < WAVE || block > BLOCK || block % WAVE != 0) return hipErrorInvalidValue;
     size_t lds = lds_bytes(g, sizeof(cplx<T>)) + static_cast<size_t>(g.S) * sizeof(cplx<T>);
-    hipLaunchKernelGGL(k_sample_stream<T>, dim3(grid), dim3(BLOCK), lds, st, g, lp, theta,
+    hipLaunchKernelGGL(k_sample_stream<T>, dim3(grid), dim3(block), lds, st, g, lp, theta,
                        reinterpret_cast<const cplx<T> *>(wfix), reinterpret_cast<cplx<T> *>(vals), per_wg_elems, a);
     return hipGetLastError();
 }
-template hipError_t launch_sample_stream<float>(const DevGraph &, const LdsPlan &, int, const double *, const void *,
-                                                void *, size_t, const SampleArgs &, hipStream_t);
-template hipError_t launch_sample_stream<double>(const DevGraph &, const LdsPlan &, int, const double *, const void *,
-                                                 void *, size_t, const SampleArgs &, hipStream_t);
+template hipError_t launch_sample_stream<float>(const DevGraph &, const LdsPlan &, int, int, const double *,
+                                                const void *, void *, size_t, const SampleArgs &, hipStream_t);
+template hipError_t launch_sample_stream<double>(const DevGraph &, const LdsPlan &, int, int, const double *,
+                                                 const void *, void *, size_t, const SampleArgs &, hipStream_t);
 
 template hipError_t launch_fixed_slots<float>(const DevGraph &, const double *, void *, hipStream_t);
 template hipError_t launch_fixed_slots<double>(const DevGraph &, const double *, void *, hipStream_t);

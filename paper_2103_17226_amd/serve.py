@@ -22,7 +22,10 @@ resident on the device and a scheduler thread that, on every tick,
      the same terms in the same order (padding rows carry weight 0 and a
      parameter row of their own that is dropped).  Sampling requests run
      alone: their chains are numbered from 0 within the request, which is
-     what makes them reproducible from the seed.
+     what makes them reproducible from the seed.  A sampling request of a
+     session resumes the chains that session left on the device; requests of
+     one session run one at a time, in arrival order, and the chain states
+     count against the memory budget until the session is closed.
 
 Requests that arrive while others are on the device therefore start as soon
 as a stream and memory free up, and their kernels overlap on the device.
@@ -57,7 +60,10 @@ class Request:
     if ``grad``, the gradient of sum_b weight[b] |f_b|^2 in theta.
     ``samples > 0``: that many Gibbs chains per parameter set, one sample per
     chain after ``burn_in`` sweeps, with the MaxCut cost of every sample, plus,
-    if ``grad``, the score-function estimate of d<C>/dtheta from them."""
+    if ``grad``, the score-function estimate of d<C>/dtheta from them.
+    A sampling request with a ``session`` resumes that session's chains on the
+    graph (kept on the device since its previous request) when P and S match,
+    so consecutive optimiser iterations need little burn-in."""
     graph: str
     theta: np.ndarray                        # float64 [P, K]
     evidence: Optional[np.ndarray] = None    # uint64 [B, W]
@@ -68,6 +74,7 @@ class Request:
     burn_in: int = 10
     seed: int = 1
     dtype: str = "c64"
+    session: Optional[str] = None
     # filled in by the server
     rid: int = -1
     t_arrive: float = 0.0
@@ -133,6 +140,7 @@ class Server:
         self.launches = 0
         self.merged = 0
         self.max_inflight = 0
+        self.busy_sessions = set()
 
     # ------------------------------------------------------------------ API
     def submit(self, req: Request, t_arrive: Optional[float] = None) -> Future:
@@ -237,34 +245,55 @@ class Server:
             with self.lock:
                 self.used -= nbytes
                 self.free_streams.append(stream)
+                self._release(reqs)
         self.inflight = still
         return finished
 
+    def _release(self, reqs):
+        for r in reqs:
+            if r.session is not None:
+                self.busy_sessions.discard((r.graph, r.session))
+
+    def _session_busy(self, r: Request) -> bool:
+        return r.session is not None and (r.graph, r.session) in self.busy_sessions
+
     def _take_batch(self):
-        """Pop the next launch (head request plus mergeable followers) if it
-        fits; called with the lock held."""
+        """Pop the next launch if it fits; called with the lock held.  The
+        first request whose session is idle leads (requests of a busy session
+        keep their place); later requests never overtake it for memory."""
         if not self.queue or not self.free_streams:
             return None
-        head = self.queue[0]
-        if self.used + head.footprint > self.budget:
+        idx = next((k for k, r in enumerate(self.queue) if not self._session_busy(r)), None)
+        if idx is None:
             return None
-        self.queue.popleft()
+        head = self.queue[idx]
+        resident = self.ex.resident_bytes() if hasattr(self.ex, "resident_bytes") else 0
+        if self.used + resident + head.footprint > self.budget:
+            return None
+        del self.queue[idx]
         batch, total = [head], head.footprint
         if head.kind == "eval" and self.max_merge > 1:
             keep = collections.deque()
             while self.queue and len(batch) < self.max_merge:
                 r = self.queue.popleft()
-                if self.ex.can_merge(head, r) and self.used + total + r.footprint <= self.budget:
+                if self.ex.can_merge(head, r) and self.used + resident + total + r.footprint <= self.budget:
                     batch.append(r)
                     total += r.footprint
                 else:
                     keep.append(r)
             keep.extend(self.queue)
             self.queue = keep
+        if head.session is not None:
+            self.busy_sessions.add((head.graph, head.session))
         stream = self.free_streams.pop(0)
         self.used += total
         self.peak_used = max(self.peak_used, self.used)
         return batch, stream, total
+
+    def close_session(self, graph: str, session: str):
+        """Drop a session's resident chains (after its requests complete)."""
+        if hasattr(self.ex, "drop_session"):
+            self.ex.drop_session(graph, session)
 
     def step(self) -> int:
         """One scheduler tick; returns the number of requests completed."""
@@ -285,6 +314,7 @@ class Server:
                 with self.lock:
                     self.used -= total
                     self.free_streams.append(stream)
+                    self._release(batch)
                 continue
             self.launches += 1
             self.merged += len(batch) - 1
@@ -390,6 +420,8 @@ class GraphExecutor:
         self.n_streams = int(n_streams)
         self.device = torch.device("cuda", device)
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(self.n_streams)]
+        self.sessions = {}        # (graph, session) -> [states [P*S, W] int64 on device, next sweep, P, S]
+        self._sess_lock = threading.Lock()
         self.edges = {}
         for name, e in (cost_edges or {}).items():
             self.edges[name] = torch.as_tensor(np.asarray(e, dtype=np.int32).reshape(-1, 2)).to(self.device)
@@ -433,6 +465,15 @@ class GraphExecutor:
             return chains * 3.0 * N * (rounds + (1 if req.grad else 0))
         return req.n_rows * N * (3.0 if req.grad else 1.0)
 
+    def resident_bytes(self) -> int:
+        """Device bytes of the resident session chains."""
+        with self._sess_lock:
+            return sum(int(v[0].numel()) * 8 for v in self.sessions.values())
+
+    def drop_session(self, graph: str, session: str):
+        with self._sess_lock:
+            self.sessions.pop((graph, session), None)
+
     # ---------------------------------------------------------- launch
     def _to_dev(self, a, dtype):
         t = self.torch.as_tensor(np.ascontiguousarray(a)).to(dtype).pin_memory()
@@ -466,10 +507,24 @@ class GraphExecutor:
         ws = torch.empty(max(g.workspace_size(r.dtype, chains, L.AC_OP_SAMPLE), 256), dtype=torch.uint8,
                          device=self.device)
         edges = self.edges.get(r.graph)
+        init, first = None, 0
+        key = (r.graph, r.session)
+        if r.session is not None:
+            with self._sess_lock:
+                prev = self.sessions.get(key)
+            if prev is not None and prev[2] == P and prev[3] == S:
+                init, first = prev[0], prev[1]
         res = g.sample(theta, chains_per_param=S, samples_per_chain=1, burn_in=r.burn_in, thin=1,
                        seed=r.seed, cost_edges=edges, dtype=r.dtype, want_cost=edges is not None,
-                       want_states=r.grad, validate=False, ws=ws)
+                       want_states=r.grad or r.session is not None, validate=False, ws=ws,
+                       init_states=init, first_sweep=first)
         keep += [theta, ws, res]
+        if init is not None:
+            keep.append(init)      # read on this stream: live until the launch completes
+        if r.session is not None:
+            # the chains' last states stay on the device for the next request
+            with self._sess_lock:
+                self.sessions[key] = [res["states"].reshape(chains, -1), first + r.burn_in + 1, P, S]
         out = {"samples": self._to_host(res["samples"])}
         if res["cost"] is not None:
             out["cost"] = self._to_host(res["cost"])

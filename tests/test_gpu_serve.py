@@ -165,3 +165,31 @@ def test_loop_admits_while_others_run_and_reports_latency():
     # some request started before an earlier one had finished: launches overlapped
     done = sorted(srv.completed, key=lambda r: r.t_start)
     assert any(b.t_start < a.t_done for a, b in zip(done, done[1:]))
+
+
+def test_session_resumes_its_resident_chains():
+    from paper_2103_17226_amd.serve import GraphExecutor, Request, Server
+    circs = _pool()
+    name = sorted(circs)[1]
+    circ = circs[name]
+    note(f"serve: session chains on {name}")
+    g = graph(circ)
+    rng = np.random.default_rng(12)
+    th1 = rng.uniform(0, 2 * np.pi, size=(2, circ.n_angles))
+    th2 = th1 + 0.05                                   # the optimiser's next iterate
+    ex = GraphExecutor({name: g}, {name: circ.edges}, n_streams=2)
+    srv = Server(ex, mem_budget=1 << 30)
+    srv.start()
+    f1 = srv.submit(Request(graph=name, theta=th1, samples=50, burn_in=5, seed=9, session="opt"))
+    f2 = srv.submit(Request(graph=name, theta=th2, samples=50, burn_in=0, seed=9, session="opt"))
+    r1, r2 = f1.result(timeout=60), f2.result(timeout=60)
+    assert ex.resident_bytes() == 2 * 50 * g.info["n_words"] * 8
+    srv.close_session(name, "opt")
+    srv.stop()
+    assert ex.resident_bytes() == 0
+    p1 = g.sample(th1, 50, 1, 5, 1, 9, cost_edges=circ.edges, want_cost=True, want_states=True)
+    p2 = g.sample(th2, 50, 1, 0, 1, 9, cost_edges=circ.edges, want_cost=True,
+                  init_states=p1["states"].reshape(100, -1), first_sweep=6)
+    assert np.array_equal(r1["samples"], p1["samples"].cpu().numpy())
+    assert np.array_equal(r2["samples"], p2["samples"].cpu().numpy())
+    assert np.array_equal(r2["cost"], p2["cost"].cpu().numpy())

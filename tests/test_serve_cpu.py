@@ -68,8 +68,8 @@ class FakeExecutor:
         return [float(r.theta[0, 2]) * 2 for r in h["batch"]]
 
 
-def req(fp, lat, val=1.0, graph="g", samples=1, grad=False):
-    return Request(graph=graph, theta=np.array([[fp, lat, val]]), samples=samples, grad=grad)
+def req(fp, lat, val=1.0, graph="g", samples=1, grad=False, session=None):
+    return Request(graph=graph, theta=np.array([[fp, lat, val]]), samples=samples, grad=grad, session=session)
 
 
 def ev_req(fp, lat, val=1.0, graph="g", grad=False):
@@ -172,6 +172,42 @@ def test_eval_requests_of_one_graph_merge_others_do_not():
     assert fb.result() == 18.0 and fg.result() == 14.0 and fs.result() == 16.0
     assert sorted(sum((x[0] for x in ex.launched), [])) == list(range(8))
     assert srv.merged == 3
+
+
+def test_requests_of_one_session_run_one_at_a_time():
+    clock = Clock()
+    ex = FakeExecutor(clock, n_streams=4)
+    srv = Server(ex, mem_budget=1000, clock=clock)
+    a1 = srv.submit(req(10, 2.0, val=1, session="s"))
+    a2 = srv.submit(req(10, 1.0, val=2, session="s"))
+    b = srv.submit(req(10, 1.0, val=3, session="t"))
+    c = srv.submit(req(10, 1.0, val=4))
+    srv.step()
+    assert [x[0] for x in ex.launched] == [[0], [2], [3]]        # a2 waits for a1, others go ahead
+    clock.t = 1.0
+    srv.step()
+    assert len(ex.launched) == 3
+    clock.t = 2.0
+    srv.step()
+    assert [x[0] for x in ex.launched][-1] == [1]
+    run_until_idle(srv, clock)
+    assert [f.result() for f in (a1, a2, b, c)] == [2.0, 4.0, 6.0, 8.0]
+    assert not srv.busy_sessions
+
+
+def test_resident_session_bytes_count_against_the_budget():
+    clock = Clock()
+    ex = FakeExecutor(clock, n_streams=4)
+    ex.resident = 50
+    ex.resident_bytes = lambda: ex.resident
+    srv = Server(ex, mem_budget=100, clock=clock)
+    f1 = srv.submit(req(40, 1.0))
+    f2 = srv.submit(req(40, 1.0))
+    srv.step()
+    assert len(ex.launched) == 1                 # 50 resident + 40 + 40 > 100
+    ex.resident = 0
+    run_until_idle(srv, clock)
+    assert f1.done() and f2.done()
 
 
 def test_cancel_waiting_but_not_running():
