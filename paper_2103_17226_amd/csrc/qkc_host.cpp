@@ -334,6 +334,8 @@ extern "C" ac_status ac_load(const void *blob, size_t nbytes, int device, ac_gra
         return fail(AC_ERR_FORMAT, "ac_load: bad angle-slot count %u", n_angle_slots);
     if (N < 1 || L < 1 || L > N || E < N || root >= N)
         return fail(AC_ERR_FORMAT, "ac_load: bad DAG sizes (N=%u E=%u L=%u root=%u)", N, E, L, root);
+    if (N > REF_MASK || n_slots > REF_MASK || n_sel >= (MULTI_SIBLING & REF_MASK))
+        return fail(AC_ERR_FORMAT, "ac_load: too many nodes, slots or selectors for 30-bit references");
 
     const uint8_t *var_dom = rd.take<uint8_t>(n_vars);
     const uint8_t *var_kind = rd.take_packed<uint8_t>(n_vars);
@@ -462,6 +464,21 @@ extern "C" ac_status ac_load(const void *blob, size_t nbytes, int device, ac_gra
         }
     }
 
+    // parent-edge records in the order of par_edge / leaf_edge: parent | sibling << 32,
+    // the sibling being the other child of a two-child product (device
+    // encoding), NO_SIBLING for a sum parent, MULTI_SIBLING for a product
+    // with three or more children
+    auto edge_record = [&](uint32_t e) -> uint64_t {
+        const uint32_t p = edge_parent[e];
+        const uint32_t r0 = row_ptr[p], r1 = row_ptr[p + 1];
+        uint32_t sib = NO_SIBLING;
+        if (op[p] != 0) sib = r1 - r0 == 2 ? dcol[e == r0 ? r0 + 1 : r0] : MULTI_SIBLING;
+        return static_cast<uint64_t>(p) | (static_cast<uint64_t>(sib) << 32);
+    };
+    std::vector<uint64_t> par_rec(par_edge.size()), leaf_rec(leaf_edge.size());
+    for (size_t q = 0; q < par_edge.size(); ++q) par_rec[q] = edge_record(par_edge[q]);
+    for (size_t q = 0; q < leaf_edge.size(); ++q) leaf_rec[q] = edge_record(leaf_edge[q]);
+
     HostPlan hp = build_plan(N, op, row_ptr, col, root, ind_base, var_field, n_ind, n_sel, n_slots, sel_dev,
                              vsel_ptr, vsel);
 
@@ -495,6 +512,8 @@ extern "C" ac_status ac_load(const void *blob, size_t nbytes, int device, ac_gra
         {hp.edg_u.data(), hp.edg_u.size() * sizeof(uint64_t), 0},
         {hp.dstart.data(), hp.dstart.size() * sizeof(uint32_t), 0},
         {hp.dterm.data(), hp.dterm.size() * sizeof(uint64_t), 0},
+        {par_rec.data(), par_rec.size() * sizeof(uint64_t), 0},
+        {leaf_rec.data(), leaf_rec.size() * sizeof(uint64_t), 0},
     };
     size_t total = 0;
     for (auto &s : secs) {
@@ -552,6 +571,8 @@ extern "C" ac_status ac_load(const void *blob, size_t nbytes, int device, ac_gra
     d.sel = reinterpret_cast<const uint32_t *>(at(13));
     d.vsel_ptr = reinterpret_cast<const uint32_t *>(at(14));
     d.vsel = reinterpret_cast<const uint32_t *>(at(15));
+    d.par_rec = reinterpret_cast<const uint64_t *>(at(27));
+    d.leaf_rec = reinterpret_cast<const uint64_t *>(at(28));
     d.n_sel = static_cast<int32_t>(n_sel);
     if (hp.ok) {
         LdsPlan &lp = g->plan;

@@ -67,6 +67,8 @@ struct DevGraph {
     const uint32_t *sel;        // [SEL_REC * n_sel] field (word<<8|shift<<2|width-1), slot[4], pad
     const uint32_t *vsel_ptr;   // [n_vars+1] selectors of each variable
     const uint32_t *vsel;       // [n_sel]
+    const uint64_t *par_rec;    // [E_node] parent | sibling << 32 of each par_edge entry
+    const uint64_t *leaf_rec;   // [E_leaf] the same for each leaf_edge entry
     int32_t N, L, root, S, S_ang, n_vars, W, n_ind, K, n_noise, n_qubits, n_sel;
     int64_t E;
 };
@@ -85,6 +87,9 @@ struct DevGraph {
 //   orec[q]       further parent edges: parent | sibling << 32
 constexpr uint32_t NO_SIBLING = 0xFFFFFFFFu;
 constexpr uint32_t IDENT_REF = 0xFFFFFFFFu;
+// sibling field of a parent-edge record whose parent is a product of three or
+// more children (the other children's product is formed on the fly)
+constexpr uint32_t MULTI_SIBLING = 0xFFFFFFFEu;
 
 //   estart[t]     the same parent edges as one CSR sorted by target t:
 //   edg[e]        edges [estart[t], estart[t+1]) of target t, parent | sibling << 32;

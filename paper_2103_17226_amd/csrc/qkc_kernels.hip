@@ -148,51 +148,83 @@ struct Tile {
         return slot(r & REF_MASK);
     }
 
-    // Sum nodes accumulate in FP64 (for the complex64 path too: wide sums
-    // would otherwise lose ~k * 2^-24 relative accuracy); products run in T.
-    __device__ __forceinline__ cplx<T> eval_node(uint32_t i) const {
-        const uint32_t e0 = g.row_ptr[i], e1 = g.row_ptr[i + 1];
-        if (g.op[i] == 0) {
-            double sr = 0.0, si = 0.0;
-            for (uint32_t e = e0; e < e1; ++e) {
-                const uint32_t r = g.col[e];
-                const uint32_t tag = r >> 30;
-                if (tag == TAG_IND) {
-                    sr += ind_hit(r) ? 1.0 : 0.0;
-                    continue;
-                }
-                const cplx<T> v = child(r);
-                sr += static_cast<double>(v.re);
-                si += static_cast<double>(v.im);
-            }
-            return {static_cast<T>(sr), static_cast<T>(si)};
-        }
-        cplx<T> acc{T(1), T(0)};
-        for (uint32_t e = e0; e < e1; ++e) {
-            const uint32_t r = g.col[e];
-            const uint32_t tag = r >> 30;
-            if (tag == TAG_IND) {
-                if (!ind_hit(r)) acc = {T(0), T(0)};
-                continue;
-            }
-            acc = cmul(acc, child(r));
-        }
-        return acc;
+    // Row of a node child, or row 0 (always present) for a leaf, so that a
+    // group of child loads can be issued before any branch on their kind.
+    __device__ __forceinline__ cplx<T> node_row(uint32_t r) const {
+        const uint32_t x = (r >> 30) == TAG_NODE ? (r & REF_MASK) : 0u;
+        return val[static_cast<size_t>(x) * WAVE + lane];
+    }
+    // node row only for node children (the reference is uniform: a scalar branch;
+    // the sentinels NO_SIBLING / MULTI_SIBLING carry tag 3 and load nothing)
+    __device__ __forceinline__ cplx<T> eb_guard(uint32_t r) const {
+        return (r >> 30) == TAG_NODE ? val[static_cast<size_t>(r & REF_MASK) * WAVE + lane] : cplx<T>{T(0), T(0)};
     }
 
-    // product of the siblings of edge e inside parent p (1 for a sum parent)
+    // Sum nodes accumulate in FP64 (for the complex64 path too: wide sums
+    // would otherwise lose ~k * 2^-24 relative accuracy); products run in T.
+    // Children are taken in groups of KC whose row loads are issued together;
+    // the terms are still added (multiplied) one by one in child order.
+    __device__ __forceinline__ cplx<T> eval_node(uint32_t i) const {
+        constexpr int KC = 4;
+        const uint32_t e0 = g.row_ptr[i], e1 = g.row_ptr[i + 1];
+        const bool sum = g.op[i] == 0;
+        double sr = 0.0, si = 0.0;
+        cplx<T> acc{T(1), T(0)};
+        for (uint32_t eb = e0; eb < e1; eb += KC) {
+            uint32_t r[KC];
+            cplx<T> v[KC];
+#pragma unroll
+            for (int j = 0; j < KC; ++j) r[j] = eb + j < e1 ? g.col[eb + j] : IDENT_REF;
+#pragma unroll
+            for (int j = 0; j < KC; ++j) v[j] = eb_guard(r[j]);
+#pragma unroll
+            for (int j = 0; j < KC; ++j) {
+                if (eb + j >= e1) break;
+                const uint32_t tag = r[j] >> 30;
+                if (tag == TAG_IND) {
+                    const bool hit = ind_hit(r[j]);
+                    if (sum) sr += hit ? 1.0 : 0.0;
+                    else if (!hit) acc = {T(0), T(0)};
+                    continue;
+                }
+                const cplx<T> c = tag == TAG_NODE ? v[j] : child(r[j]);
+                if (sum) {
+                    sr += static_cast<double>(c.re);
+                    si += static_cast<double>(c.im);
+                } else {
+                    acc = cmul(acc, c);
+                }
+            }
+        }
+        return sum ? cplx<T>{static_cast<T>(sr), static_cast<T>(si)} : acc;
+    }
+
+    // product of the siblings of edge e inside parent p (1 for a sum parent),
+    // children loaded in groups like eval_node
     __device__ __forceinline__ cplx<T> sibling_product(uint32_t p, uint32_t e) const {
+        constexpr int KC = 4;
         cplx<T> acc{T(1), T(0)};
         if (g.op[p] == 0) return acc;
         const uint32_t e0 = g.row_ptr[p], e1 = g.row_ptr[p + 1];
-        for (uint32_t f = e0; f < e1; ++f) {
-            if (f == e) continue;
-            const uint32_t r = g.col[f];
-            if ((r >> 30) == TAG_IND) {
-                if (!ind_hit(r)) acc = {T(0), T(0)};
-                continue;
+        for (uint32_t fb = e0; fb < e1; fb += KC) {
+            uint32_t r[KC];
+            cplx<T> v[KC];
+#pragma unroll
+            for (int j = 0; j < KC; ++j) r[j] = fb + j < e1 ? g.col[fb + j] : IDENT_REF;
+#pragma unroll
+            for (int j = 0; j < KC; ++j) v[j] = eb_guard(r[j]);
+#pragma unroll
+            for (int j = 0; j < KC; ++j) {
+                const uint32_t f = fb + static_cast<uint32_t>(j);
+                if (f >= e1) break;
+                if (f == e) continue;
+                const uint32_t tag = r[j] >> 30;
+                if (tag == TAG_IND) {
+                    if (!ind_hit(r[j])) acc = {T(0), T(0)};
+                    continue;
+                }
+                acc = cmul(acc, tag == TAG_NODE ? v[j] : child(r[j]));
             }
-            acc = cmul(acc, child(r));
         }
         return acc;
     }
@@ -208,25 +240,60 @@ struct Tile {
         }
     }
 
+    // adj[parent] * (product of the other children) summed in FP64 over the
+    // parent edges q0..q1 of a node or leaf.  recs holds one record per edge
+    // (parent | sibling << 32, see DevGraph), so a group of KQ edges needs one
+    // round of scalar loads before the parents' adjoint rows and the sibling
+    // rows of the whole group are loaded together.  Edges whose parent has
+    // three or more children take the general sibling product after the
+    // group.  The order of the terms is fixed, so the result is reproducible.
+    __device__ __forceinline__ cplx<T> pull_parents(const cplx<T> *adj, const uint64_t *recs, const uint32_t *edges,
+                                                   uint32_t q0, uint32_t q1) const {
+        constexpr int KQ = 4;
+        double ar = 0.0, ai = 0.0;
+        for (uint32_t qb = q0; qb < q1; qb += KQ) {
+            uint64_t rr[KQ];
+            cplx<T> a[KQ], sv[KQ];
+#pragma unroll
+            for (int j = 0; j < KQ; ++j)
+                rr[j] = qb + j < q1 ? recs[qb + j] : (static_cast<uint64_t>(NO_SIBLING) << 32);
+#pragma unroll
+            for (int j = 0; j < KQ; ++j) {
+                a[j] = adj[static_cast<size_t>(static_cast<uint32_t>(rr[j])) * WAVE + lane];
+                sv[j] = eb_guard(static_cast<uint32_t>(rr[j] >> 32));
+            }
+#pragma unroll
+            for (int j = 0; j < KQ; ++j) {
+                const uint32_t sib = static_cast<uint32_t>(rr[j] >> 32);
+                if (qb + j >= q1 || sib == MULTI_SIBLING) continue;
+                cplx<T> t = a[j];
+                if (sib != NO_SIBLING) t = cmul(t, (sib >> 30) == TAG_NODE ? sv[j] : child(sib));
+                ar += static_cast<double>(t.re);
+                ai += static_cast<double>(t.im);
+            }
+            const uint32_t qe = qb + KQ < q1 ? qb + KQ : q1;
+#pragma unroll 1
+            for (uint32_t q = qb; q < qe; ++q) {       // parents with three or more children
+                const uint64_t r = recs[q];
+                if (static_cast<uint32_t>(r >> 32) != MULTI_SIBLING) continue;
+                const uint32_t pq = static_cast<uint32_t>(r);
+                const cplx<T> t = cmul(adj[static_cast<size_t>(pq) * WAVE + lane], sibling_product(pq, edges[q]));
+                ar += static_cast<double>(t.re);
+                ai += static_cast<double>(t.im);
+            }
+        }
+        return {static_cast<T>(ar), static_cast<T>(ai)};
+    }
+
     // downward pass: adj[c] = d root / d c, pull form over parent edges
     __device__ void backward(cplx<T> *adj, int wave, int nwaves) const {
         for (int l = g.L - 1; l >= 0; --l) {
             const uint32_t n0 = g.level_ptr[l], n1 = g.level_ptr[l + 1];
             for (uint32_t c = n0 + wave; c < n1; c += nwaves) {
-                double ar = 0.0, ai = 0.0;
-                if (c == static_cast<uint32_t>(g.root)) {
-                    ar = 1.0;
-                } else {
-                    const uint32_t q0 = g.par_ptr[c], q1 = g.par_ptr[c + 1];
-                    for (uint32_t q = q0; q < q1; ++q) {
-                        const uint32_t e = g.par_edge[q];
-                        const uint32_t p = g.edge_parent[e];
-                        const cplx<T> t = cmul(adj[p * WAVE + lane], sibling_product(p, e));
-                        ar += static_cast<double>(t.re);
-                        ai += static_cast<double>(t.im);
-                    }
-                }
-                adj[c * WAVE + lane] = {static_cast<T>(ar), static_cast<T>(ai)};
+                cplx<T> a;
+                if (c == static_cast<uint32_t>(g.root)) a = {T(1), T(0)};
+                else a = pull_parents(adj, g.par_rec, g.par_edge, g.par_ptr[c], g.par_ptr[c + 1]);
+                adj[c * WAVE + lane] = a;
             }
             __syncthreads();
         }
@@ -254,16 +321,7 @@ struct Tile {
 
     // d root / d leaf (leaf index: indicators first, then slots)
     __device__ __forceinline__ cplx<T> leaf_adjoint(const cplx<T> *adj, uint32_t li) const {
-        double ar = 0.0, ai = 0.0;
-        const uint32_t q0 = g.leaf_ptr[li], q1 = g.leaf_ptr[li + 1];
-        for (uint32_t q = q0; q < q1; ++q) {
-            const uint32_t e = g.leaf_edge[q];
-            const uint32_t p = g.edge_parent[e];
-            const cplx<T> t = cmul(adj[p * WAVE + lane], sibling_product(p, e));
-            ar += static_cast<double>(t.re);
-            ai += static_cast<double>(t.im);
-        }
-        return {static_cast<T>(ar), static_cast<T>(ai)};
+        return pull_parents(adj, g.leaf_rec, g.leaf_edge, g.leaf_ptr[li], g.leaf_ptr[li + 1]);
     }
 };
 
