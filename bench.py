@@ -48,9 +48,9 @@ KERNELS = os.path.join(ROOT, "paper_2103_17226_amd", "csrc", "qkc_kernels.hip")
 # the copy-kernel calibration, FETCH x 2.0, WRITE x 1.0), valid only for the
 # kernel source they were taken on and the default workload of each leg.
 PROFILED_TRAFFIC = {
-    "k_sample_stream": {"kernel_sha256_16": "9ee6f5c7cd0b4bf4", "bytes": 4447483641856,
+    "k_sample_stream": {"kernel_sha256_16": "9721beba56827546", "bytes": 4445035351040,
                         "profile": "profiles/k_sample_stream_qaoa_n8_p1_dep.md"},
-    "k_eval": {"kernel_sha256_16": "9ee6f5c7cd0b4bf4", "bytes": 341074879488,
+    "k_eval": {"kernel_sha256_16": "9721beba56827546", "bytes": 343793851392,
                "profile": "profiles/k_eval_qaoa_n16_p2_dep_ad.md"},
 }
 
@@ -92,8 +92,8 @@ def parse():
     ap.add_argument("--serve-streams", type=int, default=8)
     ap.add_argument("--serve-queue", type=int, default=16)
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
-    ap.add_argument("--serve-max-work", type=float, default=1e11,
-                    help="reject requests estimated above this many node evaluations")
+    ap.add_argument("--serve-max-seconds", type=float, default=2.0,
+                    help="reject requests estimated to hold the device longer than this")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device-to-device three times (calibrates the HBM "
                          "byte counters of a profiler run) and exit")
@@ -138,7 +138,7 @@ def serve_run(graphs, pool, rate, args):
     edges = {c.name: c.edges for c in pool}
     ex = GraphExecutor(graphs, edges, n_streams=args.serve_streams)
     srv = Server(ex, mem_budget=int(args.serve_budget_gib * (1 << 30)), max_queue=args.serve_queue,
-                 max_work=args.serve_max_work)
+                 max_seconds=args.serve_max_seconds)
     total = args.serve_warmup + args.serve_seconds
     reqs = W.serving_requests(pool, rate, total, seed=W.sub_seed("arrivals", 5) + int(rate))
     srv.start()
@@ -170,13 +170,13 @@ def serve_run(graphs, pool, rate, args):
         msg = str(e)
         if "queue full" in msg:
             return "rejected_queue"
-        if "node evaluations" in msg:
-            return "rejected_work"
+        if "hold the device" in msg:
+            return "rejected_cost"
         if "device memory" in msg:
             return "rejected_memory"
         return "failed"
 
-    counts = {k: 0 for k in ("completed", "rejected_queue", "rejected_work", "rejected_memory", "failed",
+    counts = {k: 0 for k in ("completed", "rejected_queue", "rejected_cost", "rejected_memory", "failed",
                              "unfinished")}
     for q in window:
         counts[outcome(q)] += 1
@@ -444,7 +444,7 @@ def main():
             "pool_circuits": len(pool), "pool_compile_s": t_pool,
             "pool_ac_nodes_max": max(gr.info["n_internal"] for gr in graphs.values()),
             "streams": args.serve_streams, "queue_limit": args.serve_queue,
-            "budget_gib": args.serve_budget_gib, "max_work_node_evals": args.serve_max_work,
+            "budget_gib": args.serve_budget_gib, "max_request_seconds": args.serve_max_seconds,
             "warmup_s": args.serve_warmup, "measured_s": args.serve_seconds,
             "runs": runs,
         }

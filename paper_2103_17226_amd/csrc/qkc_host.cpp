@@ -667,7 +667,7 @@ extern "C" ac_status ac_info(const ac_graph *g, ac_info_t *info) {
 
 namespace {
 
-constexpr size_t WS_CAP = static_cast<size_t>(48) << 30;   // cap on per-call tile buffers
+constexpr size_t WS_CAP = static_cast<size_t>(96) << 30;   // cap on per-call tile buffers (HBM is 288 GB)
 constexpr size_t LDS_LIMIT = 64 * 1024;                     // dynamic LDS per workgroup
 
 constexpr size_t CU_LDS = 160 * 1024;                      // LDS per compute unit (gfx950)
@@ -779,7 +779,12 @@ bool make_layout(const ac_graph *g, ac_dtype dt, int64_t batch, int op, Layout &
     if (const char *env = std::getenv("QKC_WG_PER_CU")) wg_per_cu = std::max(1, std::min(16, std::atoi(env)));
     int64_t grid = std::min<int64_t>(tiles, static_cast<int64_t>(g->n_cu) * wg_per_cu);
     if (per_wg > 0) {
-        const int64_t cap = std::max<int64_t>(1, static_cast<int64_t>(WS_CAP / (per_wg * cs)));
+        size_t ws_cap = WS_CAP;
+        if (const char *env = std::getenv("QKC_WS_CAP_GIB")) {
+            const long v = std::atol(env);
+            if (v >= 1 && v <= 256) ws_cap = static_cast<size_t>(v) << 30;
+        }
+        const int64_t cap = std::max<int64_t>(1, static_cast<int64_t>(ws_cap / (per_wg * cs)));
         grid = std::min(grid, cap);
     }
     if (batch > 0 && grid < 1) grid = 1;

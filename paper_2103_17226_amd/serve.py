@@ -30,8 +30,8 @@ resident on the device and a scheduler thread that, on every tick,
 Requests that arrive while others are on the device therefore start as soon
 as a stream and memory free up, and their kernels overlap on the device.
 Submissions beyond ``max_queue`` waiting requests, larger than the whole
-budget, or (with ``max_work``) estimated above that many node evaluations,
-are rejected at once.
+budget, or (with ``max_seconds``) estimated to occupy the device longer than
+that, are rejected at once.
 
 The device work is done by an executor (``GraphExecutor`` for libqkc); the
 scheduler only sees its footprint / launch / done / results calls, so tests
@@ -106,12 +106,12 @@ class Server:
     The executor provides ``n_streams``, ``footprint(req) -> bytes``,
     ``can_merge(a, b) -> bool``, ``launch(batch, stream) -> handle``,
     ``done(handle) -> bool`` and ``results(handle) -> list`` (one result per
-    request of the batch, in order), and ``work(req) -> node evaluations``
-    if ``max_work`` is used.  ``launch``, ``done`` and ``results`` may raise;
+    request of the batch, in order), and ``cost(req) -> estimated device
+    seconds`` if ``max_seconds`` is used.  ``launch``, ``done`` and ``results`` may raise;
     the requests of that batch then fail with the exception."""
 
     def __init__(self, executor, mem_budget: int, clock: Callable[[], float] = time.perf_counter,
-                 max_queue: int = 1 << 30, max_merge: int = 64, max_work: Optional[float] = None,
+                 max_queue: int = 1 << 30, max_merge: int = 64, max_seconds: Optional[float] = None,
                  tick: float = 1e-4):
         if mem_budget <= 0:
             raise ValueError("mem_budget must be positive")
@@ -120,7 +120,7 @@ class Server:
         self.clock = clock
         self.max_queue = int(max_queue)
         self.max_merge = max(1, int(max_merge))
-        self.max_work = max_work
+        self.max_seconds = max_seconds
         self.tick = tick
         self.queue: collections.deque = collections.deque()
         self.inflight: List[tuple] = []            # (handle, [requests], stream, bytes)
@@ -135,7 +135,7 @@ class Server:
         self.failed = 0
         self.rejected_memory = 0
         self.rejected_queue = 0
-        self.rejected_work = 0
+        self.rejected_cost = 0
         self.cancelled = 0
         self.launches = 0
         self.merged = 0
@@ -154,11 +154,13 @@ class Server:
             req.future.set_exception(AdmissionError(
                 f"request needs {req.footprint} bytes of device memory, the budget is {self.budget}"))
             return req.future
-        if self.max_work is not None and self.ex.work(req) > self.max_work:
-            self.rejected_work += 1
-            req.future.set_exception(AdmissionError(
-                f"request needs ~{self.ex.work(req):.3g} node evaluations, the limit is {self.max_work:.3g}"))
-            return req.future
+        if self.max_seconds is not None:
+            est = float(self.ex.cost(req))
+            if est > self.max_seconds:
+                self.rejected_cost += 1
+                req.future.set_exception(AdmissionError(
+                    f"request would hold the device ~{est:.3g} s, the limit is {self.max_seconds:.3g} s"))
+                return req.future
         with self.lock:
             if len(self.queue) >= self.max_queue:
                 self.rejected_queue += 1
@@ -335,7 +337,7 @@ class Server:
         lat = np.array([r.t_done - r.t_arrive for r in done])
         out: Dict[str, Any] = {"completed": len(done), "failed": self.failed,
                                "rejected_memory": self.rejected_memory,
-                               "rejected_queue": self.rejected_queue, "rejected_work": self.rejected_work,
+                               "rejected_queue": self.rejected_queue, "rejected_cost": self.rejected_cost,
                                "cancelled": self.cancelled,
                                "launches": self.launches, "merged": self.merged,
                                "max_inflight": self.max_inflight, "peak_bytes": self.peak_used}
@@ -452,18 +454,31 @@ class GraphExecutor:
         ws = g.workspace_size(req.dtype, B, op)
         return ws + B * (8 * W + 4 + 8 + cs) + (P + 1) * K * 16
 
-    def work(self, req: Request) -> float:
-        """Estimated node evaluations of a request (for ``max_work``): one
-        upward pass per amplitude, three passes (up, down, leaves) per
-        gradient element or Gibbs round, and about n/2 + 1 rounds per sweep
-        (a round ends at the first changed variable)."""
-        info = self.graphs[req.graph].info
+    # device-time model for admission: a lone tile of 64 elements walks the DAG
+    # level by level (latency per node step), a full chip streams node steps
+    # at a measured rate; a request takes the larger of the two
+    NODE_STEP_LATENCY = {"stream": 2.0e-7, "lds": 2.0e-8, "eval": 1.4e-7}
+    NODE_STEP_RATE = {"sample": 1.0e11, "eval": 1.7e11}
+
+    def cost(self, req: Request) -> float:
+        """Estimated device seconds of a request (for ``max_seconds``).
+        Sampling: about n/2 + 1 rounds per sweep (a round ends at the first
+        change) of three passes (up, down, leaves) over the DAG per chain;
+        amplitudes: one pass per row, three with a gradient."""
+        g = self.graphs[req.graph]
+        info = g.info
         N = float(info["n_internal"])
         if req.kind == "sample":
             chains = req.n_params * int(req.samples)
-            rounds = (req.burn_in + 1) * (info["n_qubits"] // 2 + 1)
-            return chains * 3.0 * N * (rounds + (1 if req.grad else 0))
-        return req.n_rows * N * (3.0 if req.grad else 1.0)
+            steps = 3.0 * N * (req.burn_in + 1) * (info["n_qubits"] // 2 + 1)
+            if req.grad:
+                steps += 3.0 * N
+            small = N <= 6000 and chains <= 4096
+            lat = steps * self.NODE_STEP_LATENCY["lds" if small else "stream"]
+            return max(lat, chains * steps / self.NODE_STEP_RATE["sample"])
+        passes = 3.0 if req.grad else 1.0
+        lat = passes * N * self.NODE_STEP_LATENCY["eval"]
+        return max(lat, req.n_rows * passes * N / self.NODE_STEP_RATE["eval"])
 
     def resident_bytes(self) -> int:
         """Device bytes of the resident session chains."""

@@ -39,8 +39,8 @@ class FakeExecutor:
     def footprint(self, req):
         return int(req.theta[0, 0])
 
-    def work(self, req):
-        return float(req.theta[0, 1]) * 1000
+    def cost(self, req):
+        return float(req.theta[0, 1])
 
     def can_merge(self, a, b):
         return a.kind == b.kind == "eval" and a.graph == b.graph and a.grad == b.grad and a.dtype == b.dtype
@@ -132,15 +132,15 @@ def test_oversized_and_queue_full_are_rejected():
     assert srv.latency_stats()["completed"] == 2
 
 
-def test_work_limit_rejects_long_requests():
+def test_time_limit_rejects_long_requests():
     clock = Clock()
-    srv = Server(FakeExecutor(clock), mem_budget=100, clock=clock, max_work=5000)
+    srv = Server(FakeExecutor(clock), mem_budget=100, clock=clock, max_seconds=5.0)
     f = srv.submit(req(10, 6.0))
     ok = srv.submit(req(10, 4.0, val=3))
-    with pytest.raises(AdmissionError, match="node evaluations"):
+    with pytest.raises(AdmissionError, match="hold the device"):
         f.result(timeout=0)
     run_until_idle(srv, clock)
-    assert ok.result() == 6.0 and srv.latency_stats()["rejected_work"] == 1
+    assert ok.result() == 6.0 and srv.latency_stats()["rejected_cost"] == 1
 
 
 def test_streams_bound_the_launches_in_flight():
