@@ -131,6 +131,7 @@ def compile_pool(full: bool):
 def serve_run(graphs, pool, rate, args):
     """One serving run at an offered rate; returns its summary (requests
     that arrive in the warm-up window are served but not counted)."""
+    import numpy as np
     import torch
 
     import workloads as W
@@ -182,13 +183,22 @@ def serve_run(graphs, pool, rate, args):
         counts[outcome(q)] += 1
     ok = [q for q in window if outcome(q) == "completed"]
     span = max([q.t_done for q in ok] + [t_end]) - since
+    # how the admission estimate compares with the time each request held a stream
+    ratio = [(q.t_done - q.t_start) / max(ex.cost(q), 1e-6) for q in ok]
+    stuck = [{"graph": q.graph, "kind": q.kind, "P": q.n_params, "S": q.samples, "rows": q.n_rows,
+              "grad": q.grad, "est_s": ex.cost(q)} for q in window if outcome(q) == "unfinished"]
     out = {"offered_rps": rate, "arrivals": len(window), **counts,
            "p50_ms": st.get("p50_ms"), "p99_ms": st.get("p99_ms"), "mean_ms": st.get("mean_ms"),
            "throughput_rps": len(ok) / span,
            "samples_per_s": sum(q.n_params * q.samples for q in ok) / span,
            "amplitudes_per_s": sum(q.n_rows for q in ok) / span,
            "launches": st["launches"], "merged": st["merged"], "max_inflight": st["max_inflight"],
-           "peak_gib": st["peak_bytes"] / (1 << 30)}
+           "peak_gib": st["peak_bytes"] / (1 << 30),
+           "launch_host_ms_p50": float(np.median([(q.t_launched - q.t_start) * 1e3 for q in ok])) if ok else None,
+           "queue_wait_ms_p50": float(np.median([(q.t_start - q.t_arrive) * 1e3 for q in ok])) if ok else None,
+           "service_over_estimate_p50": float(np.median(ratio)) if ratio else None,
+           "service_over_estimate_max": float(max(ratio)) if ratio else None,
+           "unfinished_requests": stuck[:5]}
     return out
 
 
@@ -266,6 +276,51 @@ def eval_leg(args, circ_cfg):
     g.close()
     del ws_e
     torch.cuda.empty_cache()
+    return out
+
+
+def small_configs_leg(steps: int):
+    """The two remaining workloads: the 4-qubit ring (64 angle pairs x all 16
+    outputs, complex128, launch-bound) and the noise-free 32-qubit circuit
+    (256 angle pairs x 3907 Gibbs chains = 1,000,192 samples, complex64)."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2103_17226_amd.api import ACGraph
+
+    def timed(fn, n):
+        fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(n):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / n / 1e3
+
+    c1 = W.config(1)
+    g1 = ACGraph(c1["circuit"], device=0)
+    dev = g1.torch_device
+    th1 = torch.as_tensor(c1["theta"], device=dev)
+    ev1 = torch.as_tensor(c1["evidence"].view(np.int64), device=dev)
+    po1 = torch.as_tensor(c1["param_of"], device=dev)
+    t1 = timed(lambda: g1.eval(th1, ev1, po1, dtype="c128", validate=False), 50)
+    c4 = W.config(4)
+    g4 = ACGraph(c4["circuit"], device=0)
+    th4 = torch.as_tensor(c4["theta"], device=dev)
+    C = c4["chains_per_param"]
+    t4 = timed(lambda: g4.sample(th4, C, 1, 10, 1, 7, dtype="c64", validate=False), steps)
+    out = {
+        "ring4_eval_us_per_call": t1 * 1e6, "ring4_amplitudes_per_s": ev1.shape[0] / t1,
+        "ring4_batch": int(ev1.shape[0]),
+        "qaoa_n32_samples_per_s": th4.shape[0] * C / t4, "qaoa_n32_sample_ms": t4 * 1e3,
+        "qaoa_n32_chains": int(th4.shape[0] * C), "qaoa_n32_ac_nodes": g4.info["n_internal"],
+    }
+    g1.close()
+    g4.close()
     return out
 
 
@@ -431,6 +486,9 @@ def main():
     if not args.no_eval:
         print("# amplitude/gradient leg (16 qubits, p=2)", file=sys.stderr, flush=True)
         res["eval"] = eval_leg(args, W.config(3))
+        print("# 4-qubit ring and 32-qubit sampling", file=sys.stderr, flush=True)
+        res["other_configs"] = small_configs_leg(args.eval_steps)
+        torch.cuda.empty_cache()
     if pool is not None:
         graphs = {c.name: ACGraph(b, device=0) for c, b in zip(pool, blobs)}
         runs = []

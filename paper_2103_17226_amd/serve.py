@@ -79,6 +79,7 @@ class Request:
     rid: int = -1
     t_arrive: float = 0.0
     t_start: float = 0.0
+    t_launched: float = 0.0
     t_done: float = 0.0
     footprint: int = 0
     future: Future = field(default_factory=Future, repr=False)
@@ -141,6 +142,7 @@ class Server:
         self.merged = 0
         self.max_inflight = 0
         self.busy_sessions = set()
+        self.launching = 0                          # batches taken from the queue, not yet in flight
 
     # ------------------------------------------------------------------ API
     def submit(self, req: Request, t_arrive: Optional[float] = None) -> Future:
@@ -190,7 +192,7 @@ class Server:
 
     def idle(self) -> bool:
         with self.lock:
-            return not self.queue and not self.inflight
+            return not self.queue and not self.inflight and not self.launching
 
     def stop(self, drain: bool = True, timeout: float = 600.0):
         """Stop the scheduler thread, after the queue and the device drain if
@@ -203,6 +205,11 @@ class Server:
         if self.thread is not None:
             self.thread.join(timeout)
             self.thread = None
+        # with drain, launches still on the device complete here (the thread has exited)
+        t0 = time.perf_counter()
+        while drain and self.inflight and time.perf_counter() - t0 < timeout:
+            if not self._complete():
+                time.sleep(self.tick)
         with self.lock:
             while self.queue:
                 r = self.queue.popleft()
@@ -287,6 +294,7 @@ class Server:
             self.queue = keep
         if head.session is not None:
             self.busy_sessions.add((head.graph, head.session))
+        self.launching += 1
         stream = self.free_streams.pop(0)
         self.used += total
         self.peak_used = max(self.peak_used, self.used)
@@ -317,10 +325,16 @@ class Server:
                     self.used -= total
                     self.free_streams.append(stream)
                     self._release(batch)
+                    self.launching -= 1
                 continue
+            now = self.clock()
+            for r in batch:
+                r.t_launched = now
             self.launches += 1
             self.merged += len(batch) - 1
-            self.inflight.append((handle, batch, stream, total))
+            with self.lock:
+                self.inflight.append((handle, batch, stream, total))
+                self.launching -= 1
             self.max_inflight = max(self.max_inflight, len(self.inflight))
         return finished
 
@@ -457,7 +471,7 @@ class GraphExecutor:
     # device-time model for admission: a lone tile of 64 elements walks the DAG
     # level by level (latency per node step), a full chip streams node steps
     # at a measured rate; a request takes the larger of the two
-    NODE_STEP_LATENCY = {"stream": 2.0e-7, "lds": 2.0e-8, "eval": 1.4e-7}
+    NODE_STEP_LATENCY = {"stream": 2.0e-7, "lds": 2.0e-8, "eval": 2.5e-7}
     NODE_STEP_RATE = {"sample": 1.0e11, "eval": 1.7e11}
 
     def cost(self, req: Request) -> float:

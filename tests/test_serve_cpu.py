@@ -282,6 +282,27 @@ def test_threaded_loop_serves_concurrent_clients():
     assert st["completed"] == 200 and st["failed"] == 0 and srv.used == 0
 
 
+def test_stop_waits_for_a_launch_in_progress():
+    # a batch taken from the queue but still inside launch() keeps the loop busy
+    started, release = threading.Event(), threading.Event()
+
+    class SlowLaunch(FakeExecutor):
+        def launch(self, batch, stream):
+            started.set()
+            release.wait(5)
+            return super().launch(batch, stream)
+
+    ex = SlowLaunch(time.perf_counter, n_streams=1)
+    srv = Server(ex, mem_budget=100, clock=time.perf_counter)
+    srv.start()
+    f = srv.submit(req(10, 1e-3, val=4))
+    assert started.wait(5)
+    assert not srv.idle()
+    threading.Timer(0.05, release.set).start()
+    srv.stop(drain=True, timeout=10)
+    assert f.result(timeout=0) == 8.0
+
+
 def test_stop_without_drain_cancels_waiting():
     clock = Clock()
     srv = Server(FakeExecutor(clock, n_streams=1), mem_budget=100, clock=clock)
