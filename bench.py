@@ -324,6 +324,46 @@ def small_configs_leg(steps: int):
     return out
 
 
+def vqe_leg(steps: int):
+    """The 2D Ising VQE workload on the same kernels: a noise-free 5x5 grid
+    with one iteration (25 qubits) and a 3x3 grid with two iterations under
+    depolarizing noise 0.005 after every gate; 256 parameter sets x 1000
+    Gibbs samples each, complex64, 10 burn-in sweeps; Ising energy of every
+    sample from the output bits."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2103_17226_amd.api import ACGraph
+    out = {}
+    for tag, (rows, cols, p, dep) in {"ideal_5x5_p1": (5, 5, 1, None), "noisy_3x3_p2": (3, 3, 2, 0.005)}.items():
+        _, J, h = W.ising_instance(rows, cols, W.sub_seed("graph", 6))
+        circ = W.vqe_ising(rows, cols, p, J, h, dep=dep)
+        g = ACGraph(circ, device=0)
+        theta = torch.as_tensor(W.uniform_angles(256, circ.n_angles, W.sub_seed("angles", 6)), device=g.torch_device)
+        C = 1000
+        g.sample(theta, C, 1, 10, 1, 3, dtype="c64", validate=False)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for k in range(steps):
+            res = g.sample(theta, C, 1, 10, 1, 4 + k, dtype="c64", want_rounds=True, validate=False)
+        b.record()
+        torch.cuda.synchronize()
+        t = a.elapsed_time(b) / steps / 1e3
+        x = res["samples"].cpu().numpy().reshape(-1).view(np.uint64)
+        bits = ((x[:, None] >> np.arange(circ.n, dtype=np.uint64)) & np.uint64(1)).astype(np.int64)
+        e = W.ising_energy(circ.edges, J, h, bits).reshape(256, C).mean(axis=1)
+        out[tag] = {"qubits": circ.n, "iterations": p, "gates": circ.n_gates(),
+                    "ac_internal_nodes": g.info["n_internal"], "ac_edges": g.info["n_edges"],
+                    "samples_per_s": 256 * C / t, "ms_per_256k_samples": t * 1e3,
+                    "gibbs_rounds_per_sample": float(res["rounds"].double().mean().item()),
+                    "best_mean_energy": float(e.min())}
+        g.close()
+    return out
+
+
 def cpu_baseline(circ, theta, chains, budget_s):
     """The oracle on the host cores, on a bounded sample of the same job:
     per parameter set, the density-matrix diagonal, `chains` exact samples by
@@ -488,6 +528,8 @@ def main():
         res["eval"] = eval_leg(args, W.config(3))
         print("# 4-qubit ring and 32-qubit sampling", file=sys.stderr, flush=True)
         res["other_configs"] = small_configs_leg(args.eval_steps)
+        print("# 2D Ising VQE", file=sys.stderr, flush=True)
+        res["vqe"] = vqe_leg(args.eval_steps)
         torch.cuda.empty_cache()
     if pool is not None:
         graphs = {c.name: ACGraph(b, device=0) for c, b in zip(pool, blobs)}

@@ -28,6 +28,8 @@ CIRCUITS = {
     "tiny": tiny_noisy,
     "ring4": lambda: W.config(1, small=True)["circuit"],
     "ring3_dep_ad": lambda: W.qaoa_maxcut(3, W.ring_graph(3), 1, dep=0.05, ad=0.02),
+    "vqe2x2_dep_ad": lambda: W.vqe_ising(2, 2, 1, [1.0, -1.0, -1.0, 1.0], [1.0, -1.0, 1.0, 1.0], dep=0.03, ad=0.02),
+    "vqe2x3_p2": lambda: W.vqe_ising(2, 3, 2, *W.ising_instance(2, 3, 3)[1:]),
     "ring3_dep": lambda: W.Circuit(n=2, ops=[("H", 0), ("DEP", 0, 0), ("H", 1), ("CNOT", 0, 1), ("DEP", 1, 0), ("RZ", 1, 0, 2.0), ("DEP", 1, 0), ("CNOT", 0, 1), ("RX", 0, 1, 2.0), ("RX", 1, 1, 2.0), ("DEP", 0, 0)], n_angles=2, noise=[0.04], edges=[(0, 1)]),
 }
 

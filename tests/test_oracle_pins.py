@@ -362,6 +362,33 @@ def test_lightcone_zz_equals_full_state_vector():
     assert abs(sim.qaoa_p1_zz_lightcone(edges, 0.0, 0.7, *edges[0])) < 1e-12
 
 
+def test_vqe_ising_single_site_closed_form():
+    # one site: H, RZ(2 h beta), RX(2 alpha) |0> gives P(1) = (1 - sin 2alpha sin 2h beta) / 2
+    rng = np.random.default_rng(13)
+    for hval in (1.0, -1.0):
+        circ = W.vqe_ising(1, 1, 1, [], [hval])
+        for _ in range(4):
+            g, b, a = rng.uniform(0, 2 * np.pi, size=3)
+            psi = sim.statevector(circ, [g, b, a])
+            want = (1 - np.sin(2 * a) * np.sin(2 * hval * b)) / 2
+            assert abs(abs(psi[1]) ** 2 - want) < 1e-14
+
+
+def test_vqe_ising_closed_forms_on_a_grid():
+    edges, J, h = W.ising_instance(2, 3, 5)
+    circ = W.vqe_ising(2, 3, 2, J, h, dep=0.02)
+    n = circ.n
+    # no coupling and no field phase: |+>^n is an X eigenstate, P(x) = 2^-n under depolarizing noise too
+    for th in ([0.0, 0.0, 0.7, 0.0, 0.0, 1.9], [0.0, 0.0, 2.3, 0.0, 0.0, 0.4]):
+        assert np.allclose(sim.probabilities(circ, th), 1.0 / 2 ** n, atol=1e-14)
+    # the energy function: all spins up (x = 0) gives sum J + sum h
+    assert W.ising_energy(edges, J, h, np.zeros((1, n), dtype=int))[0] == sum(J) + sum(h)
+    bits = np.array([[1, 0, 1, 1, 0, 0]])
+    s = 1 - 2 * bits[0]
+    want = sum(Jij * s[i] * s[j] for (i, j), Jij in zip(edges, J)) + sum(hi * s[i] for i, hi in enumerate(h))
+    assert W.ising_energy(edges, J, h, bits)[0] == want
+
+
 def test_chi2_detects_bias_and_accepts_truth():
     rng = np.random.default_rng(0)
     p = rng.dirichlet(np.ones(20))

@@ -58,6 +58,8 @@ class Circuit:
     noise: List[float]
     edges: List[Tuple[int, int]] = field(default_factory=list)
     name: str = ""
+    couplings: List[float] = field(default_factory=list)   # Ising J per edge (VQE circuits)
+    fields: List[float] = field(default_factory=list)      # Ising h per qubit (VQE circuits)
 
     # ---- evidence-variable bookkeeping (format only, no arithmetic) ----
     def channels(self) -> List[tuple]:
@@ -237,6 +239,92 @@ def qaoa_maxcut(n: int, edges: Sequence[Tuple[int, int]], p: int,
         raise ValueError("need exactly one depolarizing strength per channel: "
                          f"got {len(dep_list)}, circuit has {dep_count[0]}")
     return Circuit(n=n, ops=ops, n_angles=2 * p, noise=noise, edges=list(edges), name=name)
+
+
+def grid_graph(rows: int, cols: int) -> List[Tuple[int, int]]:
+    """Nearest-neighbour edges of a rows x cols grid, qubit q = r * cols + c."""
+    edges = []
+    for r in range(rows):
+        for c in range(cols):
+            q = r * cols + c
+            if c + 1 < cols:
+                edges.append((q, q + 1))
+            if r + 1 < rows:
+                edges.append((q, q + cols))
+    return sorted(edges)
+
+
+def ising_instance(rows: int, cols: int, seed: int):
+    """Random 2D Ising instance: grid edges with couplings J = +-1 and a
+    field h = +-1 on every site, uniform from the seed."""
+    rng = np.random.default_rng(seed)
+    edges = grid_graph(rows, cols)
+    J = [float(v) for v in rng.choice([-1.0, 1.0], size=len(edges))]
+    h = [float(v) for v in rng.choice([-1.0, 1.0], size=rows * cols)]
+    return edges, J, h
+
+
+def ising_energy(edges, J, h, bits: np.ndarray) -> np.ndarray:
+    """E(x) = sum_(i,j) J_ij s_i s_j + sum_i h_i s_i with s = 1 - 2x, for bits [B, n]."""
+    spins = 1 - 2 * np.asarray(bits, dtype=np.int64)
+    e = np.zeros(spins.shape[0])
+    for (i, j), Jij in zip(edges, J):
+        e += Jij * spins[:, i] * spins[:, j]
+    for i, hi in enumerate(h):
+        e += hi * spins[:, i]
+    return e
+
+
+def vqe_ising(rows: int, cols: int, p: int, J: Sequence[float], h: Sequence[float],
+              dep=None, ad=None, name: str = "") -> Circuit:
+    """Variational circuit for the 2D Ising model: one qubit per grid site,
+    two-qubit gates on the grid couplings.  H on every qubit, then per
+    iteration l: for each edge (i<j) CNOT(i->j) RZ(2 J_ij gamma_l) on j
+    CNOT(i->j) (the coupling phase exp(-i gamma_l J_ij Z_i Z_j)), RZ(2 h_i
+    beta_l) on every qubit (the field), RX(2 alpha_l) on every qubit.
+    theta[3l] = gamma_l, theta[3l+1] = beta_l, theta[3l+2] = alpha_l.
+    Noise as in ``qaoa_maxcut`` (dep / ad after every gate on the qubits it
+    touches; one shared strength each)."""
+    n = rows * cols
+    edges = grid_graph(rows, cols)
+    if len(J) != len(edges) or len(h) != n:
+        raise ValueError("need one coupling per grid edge and one field per site")
+    ops: List[tuple] = []
+    noise: List[float] = []
+    if dep is not None:
+        noise.append(float(dep))
+    ad_idx = None
+    if ad is not None:
+        ad_idx = len(noise)
+        noise.append(float(ad))
+
+    def after(qs):
+        for q in qs:
+            if dep is not None:
+                ops.append(("DEP", q, 0))
+            if ad is not None:
+                ops.append(("AD", q, ad_idx))
+
+    for q in range(n):
+        ops.append(("H", q))
+        after([q])
+    for l in range(p):
+        for (i, j), Jij in zip(edges, J):
+            ops.append(("CNOT", i, j))
+            after([i, j])
+            ops.append(("RZ", j, 3 * l, 2.0 * float(Jij)))
+            after([j])
+            ops.append(("CNOT", i, j))
+            after([i, j])
+        for q in range(n):
+            ops.append(("RZ", q, 3 * l + 1, 2.0 * float(h[q])))
+            after([q])
+        for q in range(n):
+            ops.append(("RX", q, 3 * l + 2, 2.0))
+            after([q])
+    return Circuit(n=n, ops=ops, n_angles=3 * p, noise=noise, edges=list(edges),
+                   name=name or f"vqe_ising_{rows}x{cols}_p{p}", couplings=[float(v) for v in J],
+                   fields=[float(v) for v in h])
 
 
 def qaoa_channel_count(n: int, n_edges: int, p: int) -> int:
