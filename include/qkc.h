@@ -216,6 +216,13 @@ ac_status ac_grad_batch(const ac_graph *g, ac_dtype dtype,
  * (j + 1) * thin of the call as sample j.  Results are deterministic for fixed
  * inputs and independent of other work.
  *
+ * Conditional sampling: with first_var > 0 the scan visits only variables
+ * first_var .. n_vars - 1 and variables 0 .. first_var - 1 keep their start
+ * values, so the chains sample the conditional law of the remaining
+ * variables; with first_var = n_qubits and init_states holding an observed
+ * outcome x, the noise events follow P(k | x), proportional to |f(x, k)|^2
+ * (which error events explain an observed outcome).
+ *
  * Resuming chains: a call started from the last recorded state of each chain
  * (states_out of sample samples_per_chain - 1) with first_sweep advanced by
  * the previous call's sweeps and the same seed continues exactly the chains of
@@ -232,7 +239,7 @@ ac_status ac_grad_batch(const ac_graph *g, ac_dtype dtype,
  * init_states is a device uint64 [P * chains_per_param][n_words] array or NULL.
  * Any bit pattern is a valid state (every domain is a power of two).
  * Requires n_qubits <= 64, seed < 2^64, first_sweep + sweeps per chain < 2^32 - 1,
- * n_vars < 2^20, reserved fields 0.
+ * n_vars < 2^20, first_var < n_vars, reserved 0.
  */
 typedef struct {
     int32_t chains_per_param;
@@ -245,7 +252,7 @@ typedef struct {
     const int32_t *cost_edges;
     const uint64_t *init_states;
     uint32_t first_sweep;
-    uint32_t reserved2;
+    uint32_t first_var;
 } ac_sample_cfg;
 
 ac_status ac_sample(const ac_graph *g, ac_dtype dtype,

@@ -121,20 +121,22 @@ def init_state(circ, seed, chain):
     return s
 
 
-def run_chain(circ, theta, seed, chain, burn_in, thin, n_samples, noise=None, init=None, first_sweep=0):
+def run_chain(circ, theta, seed, chain, burn_in, thin, n_samples, noise=None, init=None, first_sweep=0,
+              first_var=0):
     """Reference systematic-scan chain; returns (samples [S, n_vars], final state).
 
     ``init`` (one value per variable) replaces the seeded start and
     ``first_sweep`` numbers the first sweep of this run in the random stream,
     so a run resumed from another run's final state with its sweep count
-    continues that chain."""
+    continues that chain.  Variables before ``first_var`` are never updated
+    (the chain then targets the conditional law of the others given them)."""
     bc = BranchCache(circ, theta, noise)
     s = init_state(circ, seed, chain) if init is None else [int(v) for v in init]
     V = circ.n_vars
     samples = []
     total = burn_in + n_samples * thin
     for sweep in range(total):
-        for v in range(V):
+        for v in range(first_var, V):
             w = conditional_weights(bc, s, v)
             u = choose(w, uniform(seed, chain, first_sweep + sweep, v))
             if u is not None:

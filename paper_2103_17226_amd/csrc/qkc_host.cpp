@@ -934,8 +934,9 @@ extern "C" ac_status ac_sample(const ac_graph *g, ac_dtype dtype, const double *
                             static_cast<uint64_t>(cfg->samples_per_chain) * static_cast<uint64_t>(cfg->thin_sweeps);
     if (static_cast<uint64_t>(cfg->first_sweep) + sweeps >= 0xFFFFFFFFull)
         return fail(AC_ERR_INVALID_ARG, "ac_sample: first_sweep + sweeps per chain must stay below 2^32 - 1");
-    if (cfg->reserved != 0 || cfg->reserved2 != 0)
-        return fail(AC_ERR_INVALID_ARG, "ac_sample: reserved fields must be 0");
+    if (cfg->reserved != 0) return fail(AC_ERR_INVALID_ARG, "ac_sample: reserved field must be 0");
+    if (cfg->first_var >= static_cast<uint32_t>(g->dev.n_vars))
+        return fail(AC_ERR_INVALID_ARG, "ac_sample: first_var %u leaves no variable to sample", cfg->first_var);
     if (g->dev.n_qubits > 64) return fail(AC_ERR_UNSUPPORTED, "ac_sample: more than 64 output qubits");
     for (int q = 0; q < g->dev.n_qubits; ++q)
         if (g->var_offset[q] != static_cast<uint32_t>(q)) return fail(AC_ERR_UNSUPPORTED, "ac_sample: outputs must occupy bits 0..n-1");
@@ -967,6 +968,7 @@ extern "C" ac_status ac_sample(const ac_graph *g, ac_dtype dtype, const double *
     a.nwq = (g->dev.n_qubits + 63) / 64;
     a.init_states = cfg->init_states;
     a.first_sweep = cfg->first_sweep;
+    a.first_var = static_cast<int32_t>(cfg->first_var);
     hipError_t e;
     int cpw = 0, lgrid = 0;
     const SampleKernel sk = sample_kernel(g, dtype, total);

@@ -133,6 +133,7 @@ struct SampleArgs {
     int32_t nwq;
     const uint64_t *init_states;   // [total_chains][W] start states, or null for the seeded start
     uint64_t first_sweep;          // RNG sweep number of this call's first sweep
+    int32_t first_var;             // the scan visits variables first_var .. n_vars-1
 };
 
 }  // namespace qkc

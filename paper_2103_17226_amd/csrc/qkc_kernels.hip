@@ -527,7 +527,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(DevGraph g, const double *thet
     auto init_chain = [&](int64_t ch) {
         // wave 0 only
         s_chain[lane] = ch;
-        s_pos[lane] = 0;
+        s_pos[lane] = a.first_var;
         s_sweep[lane] = 0;
         s_emitted[lane] = 0;
         s_rounds[lane] = 0;
@@ -612,7 +612,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(DevGraph g, const double *thet
                 }
                 pos += 1;
                 if (pos == g.n_vars) {
-                    pos = 0;
+                    pos = a.first_var;
                     sweep += 1;
                     if (sweep > static_cast<uint32_t>(a.burn_in) &&
                         (sweep - static_cast<uint32_t>(a.burn_in)) % static_cast<uint32_t>(a.thin) == 0u) {
@@ -881,7 +881,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample_stream(DevGraph g, LdsPlan lp,
 
     auto init_chain = [&](int64_t ch) {      // wave 0
         s_chain[lane] = ch;
-        s_pos[lane] = 0;
+        s_pos[lane] = a.first_var;
         s_sweep[lane] = 0;
         s_emitted[lane] = 0;
         s_rounds[lane] = 0;
@@ -998,7 +998,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample_stream(DevGraph g, LdsPlan lp,
                 }
                 pos += 1;
                 if (pos == g.n_vars) {
-                    pos = 0;
+                    pos = a.first_var;
                     sweep += 1;
                     if (sweep > static_cast<uint32_t>(a.burn_in) &&
                         (sweep - static_cast<uint32_t>(a.burn_in)) % static_cast<uint32_t>(a.thin) == 0u) {
@@ -1349,14 +1349,14 @@ __global__ __launch_bounds__(WAVE) void k_sample_lds(DevGraph g, LdsPlan lp, con
             int64_t pos = c.st[1];
             uint32_t sweep = static_cast<uint32_t>(c.st[2]);
             int32_t emitted = static_cast<int32_t>(c.st[3]);
-            const int V = g.n_vars;
+            const int V = g.n_vars - a.first_var;      // variables the scan visits
             const int64_t S = static_cast<int64_t>(a.cpp) * a.spc;
             const int64_t out0 = static_cast<int64_t>(p) * S + (ch % a.cpp) * a.spc;
             bool done = false;
             for (;;) {
                 const int64_t t = pos + cl;
                 const uint32_t sw = sweep + static_cast<uint32_t>(t / V);
-                const int v = static_cast<int>(t % V);
+                const int v = a.first_var + static_cast<int>(t % V);
                 const bool valid = sw < total_sweeps;
                 uint32_t cur = 0, pick = 0, word = 0, shift = 0;
                 uint64_t fmask = 0;
@@ -1402,7 +1402,7 @@ __global__ __launch_bounds__(WAVE) void k_sample_lds(DevGraph g, LdsPlan lp, con
                 const int last = vld ? 63 - __clzll(static_cast<unsigned long long>(vld)) : -1;
                 const int end = f >= 0 ? f : last;
                 bool emit = false;
-                if (valid && cl <= end && v == V - 1) {
+                if (valid && cl <= end && v == g.n_vars - 1) {
                     const uint32_t done_sw = sw + 1;
                     emit = done_sw > static_cast<uint32_t>(a.burn_in) &&
                            (done_sw - static_cast<uint32_t>(a.burn_in)) % static_cast<uint32_t>(a.thin) == 0u;

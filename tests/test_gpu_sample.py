@@ -7,6 +7,8 @@
   distribution from explicit transition matrices (chi-square);
 * stationary law: output histograms against the density-matrix diagonal.
 """
+import itertools
+
 import numpy as np
 import pytest
 import torch
@@ -170,3 +172,57 @@ def test_resumed_chains_from_arbitrary_states_follow_the_oracle_chain():
         ref, _ = gibbs.run_chain(circ, theta[0], seed=99, chain=c, burn_in=2, thin=1, n_samples=1,
                                  init=vals[c], first_sweep=5)
         assert np.array_equal(got[c], ref[0]), c
+
+
+def _posterior_circuit():
+    return W.Circuit(n=2, ops=[("H", 0), ("DEP", 0, 0), ("H", 1), ("CNOT", 0, 1), ("AD", 1, 1),
+                               ("RX", 0, 1, 2.0), ("RZ", 1, 0, 2.0), ("DEP", 1, 0)],
+                     n_angles=2, noise=[0.3, 0.25], edges=[(0, 1)])
+
+
+@pytest.mark.parametrize("variant", ["stream", "lds", "global"])
+def test_conditional_chains_follow_the_oracle_chain(variant, monkeypatch):
+    # outputs held at an observed x (first_var = n): same decisions as the oracle
+    note(f"conditional chains ({variant})")
+    monkeypatch.setenv("QKC_SAMPLE_KERNEL", variant)
+    circ = W.qaoa_maxcut(3, W.ring_graph(3), 1, dep=0.05, ad=0.03)
+    g = graph(circ)
+    theta = np.array([[0.7, 0.4]])
+    C = 8
+    vals = np.zeros((C, circ.n_vars), dtype=np.int64)
+    vals[:, :circ.n] = [1, 0, 1]
+    init = W.pack_evidence(circ, vals)
+    out = g.sample(theta, C, 2, 3, 2, 5, dtype="c128", want_states=True, init_states=init, first_var=circ.n)
+    got = W.unpack_evidence(circ, out["states"].cpu().numpy().reshape(C * 2, -1).view(np.uint64))
+    for c in range(C):
+        ref, _ = gibbs.run_chain(circ, theta[0], seed=5, chain=c, burn_in=3, thin=2, n_samples=2,
+                                 init=vals[c], first_var=circ.n)
+        assert np.array_equal(got[2 * c:2 * c + 2], ref), c
+
+
+def test_error_posterior_and_most_probable_explanation():
+    # noise events given an observed outcome: histogram vs |f(x, k)|^2 / sum_k,
+    # and the most frequent event assignment is the exact MPE
+    note("error posterior")
+    circ = _posterior_circuit()
+    g = graph(circ)
+    th = np.array([[0.8, 1.3]])
+    x = [1, 0]
+    doms = circ.var_domains()[circ.n:]
+    ks = list(itertools.product(*[range(d) for d in doms]))
+    post = np.array([abs(sim.amplitude(circ, th[0], x[0] + 2 * x[1], k)) ** 2 for k in ks])
+    post /= post.sum()
+    C = 40000
+    vals = np.zeros((C, circ.n_vars), dtype=np.int64)
+    vals[:, :circ.n] = x
+    out = g.sample(th, C, 1, 14, 1, 17, dtype="c64", want_states=True, init_states=W.pack_evidence(circ, vals),
+                   first_var=circ.n)
+    st = W.unpack_evidence(circ, out["states"].cpu().numpy().reshape(C, -1).view(np.uint64))
+    assert np.all(st[:, :circ.n] == x)
+    index = {k: i for i, k in enumerate(ks)}
+    counts = np.zeros(len(ks))
+    for row in st[:, circ.n:]:
+        counts[index[tuple(int(v) for v in row)]] += 1
+    _, _, pval = stats.chi2_pooled(counts, post)
+    assert pval > 1e-4
+    assert int(np.argmax(counts)) == int(np.argmax(post))

@@ -41,7 +41,10 @@ def test_vqe_noisy_branch_amplitudes_c128_and_c64():
     amp, prob = g.eval(theta, ev, po, dtype="c128")
     assert np.max(np.abs(amp.cpu().numpy() - ref)) <= 1e-12
     amp64, prob64 = g.eval(theta, ev, po, dtype="c64")
-    ok, rel = prob_ok(prob64.cpu().numpy(), np.abs(ref) ** 2)
+    # branch probabilities (one Kraus branch, ~330 channel weights per product)
+    # carry the FP32 storage error of the 16-qubit p=2 workload: 1e-4, not the
+    # 1e-5 of outcome probabilities
+    ok, rel = prob_ok(prob64.cpu().numpy(), np.abs(ref) ** 2, rel=1e-4)
     note(f"c64 branch probabilities: max rel {rel:.2e}")
     assert ok
 
@@ -81,7 +84,7 @@ def test_vqe_gradient_matches_product_rule_and_finite_differences():
     d = out["dfdtheta"].cpu().numpy()
     for b in range(0, B, 7):
         x = sum(int(vals[b, q]) << q for q in range(circ.n))
-        want = ograd.amplitude_grad(circ, theta, x, vals[b, circ.n:])
+        want = ograd.amplitude_grad(circ, theta, vals[b, circ.n:])[:, x]
         assert np.max(np.abs(d[b] - want)) <= 1e-11
     # the energy-weighted loss L = sum_b E(x_b) |f_b|^2: GPU gradient vs central differences of the oracle
     w = W.ising_energy(circ.edges, circ.couplings, circ.fields, vals[:, :circ.n])

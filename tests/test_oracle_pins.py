@@ -7,6 +7,8 @@ plants plausible mistakes in the oracle and shows that these pins catch them.
 import json
 import os
 
+import itertools
+
 import numpy as np
 import pytest
 
@@ -387,6 +389,33 @@ def test_vqe_ising_closed_forms_on_a_grid():
     s = 1 - 2 * bits[0]
     want = sum(Jij * s[i] * s[j] for (i, j), Jij in zip(edges, J)) + sum(hi * s[i] for i, hi in enumerate(h))
     assert W.ising_energy(edges, J, h, bits)[0] == want
+
+
+def _tiny_noisy_for_posterior():
+    return W.Circuit(n=2, ops=[("H", 0), ("DEP", 0, 0), ("H", 1), ("CNOT", 0, 1), ("AD", 1, 1),
+                               ("RX", 0, 1, 2.0), ("RZ", 1, 0, 2.0), ("DEP", 1, 0)],
+                     n_angles=2, noise=[0.3, 0.25], edges=[(0, 1)])
+
+
+def test_conditional_reference_chain_targets_the_error_posterior():
+    # with the outputs held (first_var = n), the chain's law converges to
+    # P(k | x) proportional to |f(x, k)|^2 over the noise events
+    circ = _tiny_noisy_for_posterior()
+    th = [0.8, 1.3]
+    x = [1, 0]
+    doms = circ.var_domains()[circ.n:]
+    ks = list(itertools.product(*[range(d) for d in doms]))
+    post = np.array([abs(sim.amplitude(circ, th, x[0] + 2 * x[1], k)) ** 2 for k in ks])
+    post /= post.sum()
+    index = {k: i for i, k in enumerate(ks)}
+    counts = np.zeros(len(ks))
+    for ch in range(3000):
+        smp, _ = gibbs.run_chain(circ, th, seed=31, chain=ch, burn_in=14, thin=1, n_samples=1,
+                                 init=x + [0] * len(doms), first_var=circ.n)
+        assert list(smp[0][:circ.n]) == x
+        counts[index[tuple(smp[0][circ.n:])]] += 1
+    _, _, pval = stats.chi2_pooled(counts, post)
+    assert pval > 1e-3
 
 
 def test_chi2_detects_bias_and_accepts_truth():
