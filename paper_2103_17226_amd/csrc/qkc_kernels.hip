@@ -104,6 +104,13 @@ __global__ void k_fixed_slots(DevGraph g, const double *noise, cplx<T> *wfix) {
 // tile context
 // ---------------------------------------------------------------------------
 
+// Nodes a wave takes at a time in a level of the tile kernels: up to four,
+// fewer when the level is too narrow to give every wave a full batch.
+__device__ __forceinline__ uint32_t batch_nodes(uint32_t width, int nwaves) {
+    const uint32_t per_wave = (width + static_cast<uint32_t>(nwaves) - 1) / static_cast<uint32_t>(nwaves);
+    return per_wave < 4u ? (per_wave > 0u ? per_wave : 1u) : 4u;
+}
+
 template <typename T>
 struct Tile {
     DevGraph g;
@@ -229,12 +236,62 @@ struct Tile {
         return acc;
     }
 
-    // upward pass over all levels (all waves of the block)
+    // upward pass over all levels (all waves of the block).  A wave takes KB
+    // consecutive nodes of a level at a time and walks their children
+    // (contiguous in col) in groups of KC whose rows are loaded together;
+    // each node is summed (FP64) or multiplied in child order exactly as in
+    // eval_node, and stored when its last child is in.
     __device__ void forward(int wave, int nwaves) {
+        constexpr int KC = 4;
         for (int l = 0; l < g.L; ++l) {
             const uint32_t n0 = g.level_ptr[l], n1 = g.level_ptr[l + 1];
-            for (uint32_t i = n0 + wave; i < n1; i += nwaves) {
-                val[i * WAVE + lane] = eval_node(i);
+            const uint32_t kb = batch_nodes(n1 - n0, nwaves);
+            for (uint32_t b0 = n0 + static_cast<uint32_t>(wave) * kb; b0 < n1;
+                 b0 += static_cast<uint32_t>(nwaves) * kb) {
+                const uint32_t b1 = b0 + kb < n1 ? b0 + kb : n1;
+                const uint32_t e_end = g.row_ptr[b1];
+                uint32_t t = b0, t_next = g.row_ptr[b0 + 1];
+                bool sum = g.op[b0] == 0;
+                double sr = 0.0, si = 0.0;
+                cplx<T> acc{T(1), T(0)};
+                for (uint32_t e = g.row_ptr[b0]; e < e_end; e += KC) {
+                    uint32_t r[KC];
+                    cplx<T> v[KC];
+#pragma unroll
+                    for (int j = 0; j < KC; ++j) r[j] = e + j < e_end ? g.col[e + j] : IDENT_REF;
+#pragma unroll
+                    for (int j = 0; j < KC; ++j) v[j] = eb_guard(r[j]);
+#pragma unroll
+                    for (int j = 0; j < KC; ++j) {
+                        const uint32_t ee = e + static_cast<uint32_t>(j);
+                        if (ee >= e_end) break;
+                        while (ee >= t_next) {          // node t has all its children
+                            val[static_cast<size_t>(t) * WAVE + lane] =
+                                sum ? cplx<T>{static_cast<T>(sr), static_cast<T>(si)} : acc;
+                            sr = 0.0;
+                            si = 0.0;
+                            acc = {T(1), T(0)};
+                            ++t;
+                            t_next = g.row_ptr[t + 1];
+                            sum = g.op[t] == 0;
+                        }
+                        const uint32_t tag = r[j] >> 30;
+                        if (tag == TAG_IND) {
+                            const bool hit = ind_hit(r[j]);
+                            if (sum) sr += hit ? 1.0 : 0.0;
+                            else if (!hit) acc = {T(0), T(0)};
+                            continue;
+                        }
+                        const cplx<T> c = tag == TAG_NODE ? v[j] : child(r[j]);
+                        if (sum) {
+                            sr += static_cast<double>(c.re);
+                            si += static_cast<double>(c.im);
+                        } else {
+                            acc = cmul(acc, c);
+                        }
+                    }
+                }
+                val[static_cast<size_t>(t) * WAVE + lane] = sum ? cplx<T>{static_cast<T>(sr), static_cast<T>(si)} : acc;
             }
             __syncthreads();
         }
@@ -285,15 +342,88 @@ struct Tile {
         return {static_cast<T>(ar), static_cast<T>(ai)};
     }
 
-    // downward pass: adj[c] = d root / d c, pull form over parent edges
+    // downward pass: adj[c] = d root / d c, pull form over parent edges.  A
+    // wave takes KB consecutive nodes of a level at a time and walks their
+    // parent edges (contiguous in par_rec) in groups of KE whose adjoint and
+    // sibling rows are loaded together; each node's terms are added in FP64
+    // in edge order and its adjoint is stored once its last edge is in.
+    // Edges from products of three or more children (rare) are added to the
+    // stored adjoints afterwards by the same wave.
     __device__ void backward(cplx<T> *adj, int wave, int nwaves) const {
+        constexpr int KE = 4;
+        const uint32_t root = static_cast<uint32_t>(g.root);
         for (int l = g.L - 1; l >= 0; --l) {
             const uint32_t n0 = g.level_ptr[l], n1 = g.level_ptr[l + 1];
-            for (uint32_t c = n0 + wave; c < n1; c += nwaves) {
-                cplx<T> a;
-                if (c == static_cast<uint32_t>(g.root)) a = {T(1), T(0)};
-                else a = pull_parents(adj, g.par_rec, g.par_edge, g.par_ptr[c], g.par_ptr[c + 1]);
-                adj[c * WAVE + lane] = a;
+            const uint32_t kb = batch_nodes(n1 - n0, nwaves);
+            for (uint32_t b0 = n0 + static_cast<uint32_t>(wave) * kb; b0 < n1;
+                 b0 += static_cast<uint32_t>(nwaves) * kb) {
+                const uint32_t b1 = b0 + kb < n1 ? b0 + kb : n1;
+                const uint32_t e_begin = g.par_ptr[b0], e_end = g.par_ptr[b1];
+                uint32_t t = b0, t_next = g.par_ptr[b0 + 1];
+                double ar = 0.0, ai = 0.0;
+                bool multi = false;
+                for (uint32_t e = e_begin; e < e_end; e += KE) {
+                    uint64_t rr[KE];
+                    cplx<T> a[KE], sv[KE];
+#pragma unroll
+                    for (int j = 0; j < KE; ++j)
+                        rr[j] = e + j < e_end ? g.par_rec[e + j] : (static_cast<uint64_t>(NO_SIBLING) << 32);
+#pragma unroll
+                    for (int j = 0; j < KE; ++j) {
+                        a[j] = adj[static_cast<size_t>(static_cast<uint32_t>(rr[j])) * WAVE + lane];
+                        sv[j] = eb_guard(static_cast<uint32_t>(rr[j] >> 32));
+                    }
+#pragma unroll
+                    for (int j = 0; j < KE; ++j) {
+                        const uint32_t ee = e + static_cast<uint32_t>(j);
+                        if (ee >= e_end) break;
+                        while (ee >= t_next) {
+                            adj[static_cast<size_t>(t) * WAVE + lane] =
+                                t == root ? cplx<T>{T(1), T(0)} : cplx<T>{static_cast<T>(ar), static_cast<T>(ai)};
+                            ar = 0.0;
+                            ai = 0.0;
+                            ++t;
+                            t_next = g.par_ptr[t + 1];
+                        }
+                        const uint32_t sib = static_cast<uint32_t>(rr[j] >> 32);
+                        if (sib == MULTI_SIBLING) {
+                            multi = true;
+                            continue;
+                        }
+                        cplx<T> term = a[j];
+                        if (sib != NO_SIBLING) term = cmul(term, (sib >> 30) == TAG_NODE ? sv[j] : child(sib));
+                        ar += static_cast<double>(term.re);
+                        ai += static_cast<double>(term.im);
+                    }
+                }
+                for (; t < b1; ++t) {
+                    adj[static_cast<size_t>(t) * WAVE + lane] =
+                        t == root ? cplx<T>{T(1), T(0)} : cplx<T>{static_cast<T>(ar), static_cast<T>(ai)};
+                    ar = 0.0;
+                    ai = 0.0;
+                }
+                if (multi) {
+#pragma unroll 1
+                    for (uint32_t c = b0; c < b1; ++c) {
+                        const uint32_t q1 = g.par_ptr[c + 1];
+                        double mr = 0.0, mi = 0.0;
+                        bool any = false;
+#pragma unroll 1
+                        for (uint32_t q = g.par_ptr[c]; q < q1; ++q) {
+                            const uint64_t r = g.par_rec[q];
+                            if (static_cast<uint32_t>(r >> 32) != MULTI_SIBLING) continue;
+                            const uint32_t pq = static_cast<uint32_t>(r);
+                            const cplx<T> tm = cmul(adj[static_cast<size_t>(pq) * WAVE + lane], sibling_product(pq, g.par_edge[q]));
+                            mr += static_cast<double>(tm.re);
+                            mi += static_cast<double>(tm.im);
+                            any = true;
+                        }
+                        if (any) {
+                            cplx<T> &o = adj[static_cast<size_t>(c) * WAVE + lane];
+                            o = {static_cast<T>(static_cast<double>(o.re) + mr), static_cast<T>(static_cast<double>(o.im) + mi)};
+                        }
+                    }
+                }
             }
             __syncthreads();
         }
