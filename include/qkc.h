@@ -163,7 +163,10 @@ size_t ac_workspace_size(const ac_graph *g, ac_dtype dtype, int64_t batch, int o
  * Upward pass (Sec. 3.3.1) for a batch: amp_out[b] = f(evidence[b]; theta[param_of[b]], noise)
  * for b in [0, B).  prob_out (optional, may be NULL) receives |amp|^2 in
  * FP64.  amp_out is complex64 or complex128 [B] as selected by dtype.
- * B = 0 enqueues nothing and returns AC_OK.
+ * B = 0 enqueues nothing and returns AC_OK.  param_of lives on the device and
+ * is not checked on the host: an entry outside [0, P) reads no parameters and
+ * yields a NaN amplitude (and, in ac_grad_batch, NaN raw derivatives and no
+ * gradient contribution).
  */
 ac_status ac_eval_batch(const ac_graph *g, ac_dtype dtype,
                         const double *theta, int32_t P, const double *noise,

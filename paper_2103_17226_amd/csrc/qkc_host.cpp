@@ -21,7 +21,7 @@ namespace qkc {
 template <typename T>
 hipError_t launch_fixed_slots(const DevGraph &g, const double *noise, void *wfix, hipStream_t st);
 template <typename T>
-hipError_t launch_eval(const DevGraph &g, int grid, const double *theta, const int32_t *param_of,
+hipError_t launch_eval(const DevGraph &g, int grid, const double *theta, const int32_t *param_of, int P,
                        const uint64_t *evidence, int64_t B, const void *wfix, void *vals, size_t per_wg_elems,
                        void *amp_out, double *prob_out, hipStream_t st);
 template <typename T>
@@ -857,12 +857,12 @@ extern "C" ac_status ac_eval_batch(const ac_graph *g, ac_dtype dtype, const doub
     if (dtype == AC_C64) {
         e = launch_fixed_slots<float>(g->dev, noise, w + L.wfix_off, st);
         if (e == hipSuccess)
-            e = launch_eval<float>(g->dev, L.grid, theta, param_of, evidence, B, w + L.wfix_off, w + L.tiles_off,
+            e = launch_eval<float>(g->dev, L.grid, theta, param_of, P, evidence, B, w + L.wfix_off, w + L.tiles_off,
                                    L.per_wg_elems, amp_out, prob_out, st);
     } else {
         e = launch_fixed_slots<double>(g->dev, noise, w + L.wfix_off, st);
         if (e == hipSuccess)
-            e = launch_eval<double>(g->dev, L.grid, theta, param_of, evidence, B, w + L.wfix_off, w + L.tiles_off,
+            e = launch_eval<double>(g->dev, L.grid, theta, param_of, P, evidence, B, w + L.wfix_off, w + L.tiles_off,
                                     L.per_wg_elems, amp_out, prob_out, st);
     }
     if (e != hipSuccess) return fail_hip(e, "ac_eval_batch: launch");

@@ -457,17 +457,20 @@ struct Tile {
 
 // Stage one tile's evidence and angle weights into LDS.
 template <typename T>
-__device__ void stage_tile(const DevGraph &g, uint64_t *ev_s, cplx<T> *ang_s, const uint64_t *evidence,
-                           const int32_t *param_of, const double *theta, int64_t b, bool valid,
+__device__ bool stage_tile(const DevGraph &g, uint64_t *ev_s, cplx<T> *ang_s, const uint64_t *evidence,
+                           const int32_t *param_of, int P, const double *theta, int64_t b, bool valid,
                            int lane, int wave, int nwaves) {
     for (int w = wave; w < g.W; w += nwaves) ev_s[w * WAVE + lane] = valid ? evidence[b * g.W + w] : 0ull;
-    const int p = valid ? param_of[b] : 0;
+    int p = valid ? param_of[b] : 0;
+    const bool in_range = p >= 0 && p < P;       // an index outside [0, P) reads no parameters
+    if (!in_range) p = 0;
     const double *trow = theta + static_cast<int64_t>(p) * g.K;
     for (int s = wave; s < g.S_ang; s += nwaves) {
         double re, im;
         slot_value(g.slots[s], trow, nullptr, re, im);
         ang_s[s * WAVE + lane] = {static_cast<T>(re), static_cast<T>(im)};
     }
+    return in_range;
 }
 
 // ---------------------------------------------------------------------------
@@ -475,7 +478,7 @@ __device__ void stage_tile(const DevGraph &g, uint64_t *ev_s, cplx<T> *ang_s, co
 // ---------------------------------------------------------------------------
 
 template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_eval(DevGraph g, const double *theta, const int32_t *param_of,
+__global__ __launch_bounds__(BLOCK) void k_eval(DevGraph g, const double *theta, const int32_t *param_of, int P,
                                                 const uint64_t *evidence, int64_t B, const cplx<T> *wfix,
                                                 cplx<T> *vals, size_t per_wg, cplx<T> *amp_out,
                                                 double *prob_out) {
@@ -491,11 +494,12 @@ __global__ __launch_bounds__(BLOCK) void k_eval(DevGraph g, const double *theta,
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const int64_t b = tile * WAVE + lane;
         const bool valid = b < B;
-        stage_tile(g, ev_s, ang_s, evidence, param_of, theta, b, valid, lane, wave, nwaves);
+        const bool in_range = stage_tile(g, ev_s, ang_s, evidence, param_of, P, theta, b, valid, lane, wave, nwaves);
         __syncthreads();
         t.forward(wave, nwaves);
         if (wave == 0 && valid) {
             cplx<T> f = val[static_cast<uint32_t>(g.root) * WAVE + lane];
+            if (!in_range) f = {T(NAN), T(NAN)};
             amp_out[b] = f;
             if (prob_out) {
                 double re = static_cast<double>(f.re), im = static_cast<double>(f.im);
@@ -511,7 +515,7 @@ __global__ __launch_bounds__(BLOCK) void k_eval(DevGraph g, const double *theta,
 // ---------------------------------------------------------------------------
 
 template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_grad(DevGraph g, const double *theta, const int32_t *param_of,
+__global__ __launch_bounds__(BLOCK) void k_grad(DevGraph g, const double *theta, const int32_t *param_of, int P,
                                                 const uint64_t *evidence, int64_t B, const cplx<T> *wfix,
                                                 cplx<T> *vals, size_t per_wg, int mode,
                                                 const cplx<T> *cotangent, const double *weight,
@@ -530,8 +534,9 @@ __global__ __launch_bounds__(BLOCK) void k_grad(DevGraph g, const double *theta,
     Tile<T> t{g, val, ev_s, ang_s, wfix, lane};
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const int64_t b = tile * WAVE + lane;
-        const bool valid = b < B;
-        stage_tile(g, ev_s, ang_s, evidence, param_of, theta, b, valid, lane, wave, nwaves);
+        const bool in_batch = b < B;
+        const bool in_range = stage_tile(g, ev_s, ang_s, evidence, param_of, P, theta, b, in_batch, lane, wave, nwaves);
+        const bool valid = in_batch && in_range;
         __syncthreads();
         t.forward(wave, nwaves);
         t.backward(adj, wave, nwaves);
@@ -582,9 +587,11 @@ __global__ __launch_bounds__(BLOCK) void k_grad(DevGraph g, const double *theta,
                 // Re(g * conj(df/dtheta_j))
                 contrib[b * g.K + j] = gre * sre + gim * sim;
                 if (dfdtheta_out) dfdtheta_out[b * g.K + j] = {static_cast<T>(sre), static_cast<T>(sim)};
+            } else if (in_batch && dfdtheta_out) {
+                dfdtheta_out[b * g.K + j] = {T(NAN), T(NAN)};
             }
         }
-        if (wave == 0 && valid && amp_out) amp_out[b] = f;
+        if (wave == 0 && in_batch && amp_out) amp_out[b] = valid ? f : cplx<T>{T(NAN), T(NAN)};
         __syncthreads();
     }
 }
@@ -1614,11 +1621,11 @@ size_t lds_bytes(const DevGraph &g, size_t csize) {
 }
 
 template <typename T>
-hipError_t launch_eval(const DevGraph &g, int grid, const double *theta, const int32_t *param_of,
+hipError_t launch_eval(const DevGraph &g, int grid, const double *theta, const int32_t *param_of, int P,
                        const uint64_t *evidence, int64_t B, const void *wfix, void *vals, size_t per_wg_elems,
                        void *amp_out, double *prob_out, hipStream_t st) {
     size_t lds = lds_bytes(g, sizeof(cplx<T>));
-    hipLaunchKernelGGL(k_eval<T>, dim3(grid), dim3(BLOCK), lds, st, g, theta, param_of, evidence, B,
+    hipLaunchKernelGGL(k_eval<T>, dim3(grid), dim3(BLOCK), lds, st, g, theta, param_of, P, evidence, B,
                        reinterpret_cast<const cplx<T> *>(wfix), reinterpret_cast<cplx<T> *>(vals),
                        per_wg_elems, reinterpret_cast<cplx<T> *>(amp_out), prob_out);
     return hipGetLastError();
@@ -1630,7 +1637,7 @@ hipError_t launch_grad(const DevGraph &g, int grid, const double *theta, const i
                        int mode, const void *cotangent, const double *weight, double *contrib, int P,
                        double *grad, void *amp_out, void *dfdtheta_out, void *dind_out, hipStream_t st) {
     size_t lds = lds_bytes(g, sizeof(cplx<T>));
-    hipLaunchKernelGGL(k_grad<T>, dim3(grid), dim3(BLOCK), lds, st, g, theta, param_of, evidence, B,
+    hipLaunchKernelGGL(k_grad<T>, dim3(grid), dim3(BLOCK), lds, st, g, theta, param_of, P, evidence, B,
                        reinterpret_cast<const cplx<T> *>(wfix), reinterpret_cast<cplx<T> *>(vals),
                        per_wg_elems, mode, reinterpret_cast<const cplx<T> *>(cotangent), weight, contrib,
                        reinterpret_cast<cplx<T> *>(amp_out), reinterpret_cast<cplx<T> *>(dfdtheta_out),
@@ -1736,9 +1743,9 @@ template hipError_t launch_sample_stream<double>(const DevGraph &, const LdsPlan
 
 template hipError_t launch_fixed_slots<float>(const DevGraph &, const double *, void *, hipStream_t);
 template hipError_t launch_fixed_slots<double>(const DevGraph &, const double *, void *, hipStream_t);
-template hipError_t launch_eval<float>(const DevGraph &, int, const double *, const int32_t *, const uint64_t *,
+template hipError_t launch_eval<float>(const DevGraph &, int, const double *, const int32_t *, int, const uint64_t *,
                                        int64_t, const void *, void *, size_t, void *, double *, hipStream_t);
-template hipError_t launch_eval<double>(const DevGraph &, int, const double *, const int32_t *, const uint64_t *,
+template hipError_t launch_eval<double>(const DevGraph &, int, const double *, const int32_t *, int, const uint64_t *,
                                         int64_t, const void *, void *, size_t, void *, double *, hipStream_t);
 template hipError_t launch_grad<float>(const DevGraph &, int, const double *, const int32_t *, const uint64_t *,
                                        int64_t, const void *, void *, size_t, int, const void *, const double *,

@@ -232,3 +232,23 @@ def test_selector_and_indicator_forms_agree(cfg_id):
     a1, _ = ACGraph(C.compile_circuit(circ, selectors=True)).eval(theta, ev, po, dtype="c128")
     a2, _ = ACGraph(C.compile_circuit(circ, selectors=False)).eval(theta, ev, po, dtype="c128")
     assert np.max(np.abs(a1.cpu().numpy() - a2.cpu().numpy())) <= 1e-12
+
+
+def test_param_rows_outside_range_give_nan_not_reads():
+    # an index outside [0, P) must not read past theta: NaN amplitude, no gradient term
+    circ = W.config(1, small=True)["circuit"]
+    note("param_of outside [0, P)")
+    g = graph(circ)
+    theta = np.array([[0.3, 0.8], [1.1, 0.2]])
+    ev = W.pack_evidence(circ, np.array([[1, 0, 1, 0]] * 4))
+    po = np.array([0, 7, 1, -3], dtype=np.int32)
+    amp, prob = g.eval(theta, ev, po, dtype="c128", validate=False)
+    a = amp.cpu().numpy()
+    assert np.isfinite(a[[0, 2]]).all() and np.isnan(a[[1, 3]]).all()
+    ok = np.array([0, 0, 1, 1], dtype=np.int32)
+    ref, _ = g.eval(theta, ev, ok, dtype="c128")
+    assert np.array_equal(a[[0, 2]], ref.cpu().numpy()[[0, 2]])
+    out = g.grad(theta, ev, po, mode="prob", weight=np.ones(4), dtype="c128", validate=False, want_amp=True)
+    good = g.grad(theta, ev[[0, 2]], np.array([0, 1], np.int32), mode="prob", weight=np.ones(2), dtype="c128")
+    assert np.array_equal(out["grad"].cpu().numpy(), good["grad"].cpu().numpy())
+    assert np.isnan(out["amp"].cpu().numpy()[[1, 3]]).all()
