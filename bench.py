@@ -258,6 +258,13 @@ def eval_leg(args, circ_cfg):
     up, down, E_ii = byte_model(comp, info["n_words"], 8)
     N = info["n_internal"]
     achieved = up * B / t_eval / 1e9
+    # complex64 against complex128 per result, on the first 32768 elements
+    sub = slice(0, 32768)
+    _, p64 = g.eval(theta, ev[sub], po[sub], dtype="c64", validate=False)
+    _, p128 = g.eval(theta, ev[sub], po[sub], dtype="c128", validate=False)
+    p64, p128 = p64.cpu().numpy(), p128.cpu().numpy()
+    rel = np.abs(p64 - p128) / np.maximum(p128, 1e-300)
+    big = p128 >= 1e-3 * p128.max()
     out = {
         "workload": "noisy QAOA p=2 MaxCut, seeded random 3-regular graph, 16 qubits, depolarizing "
                     "p_c~U[1e-3,1e-2] + amplitude damping 5e-3 after every gate; 4096 angle sets x 64 "
@@ -272,6 +279,8 @@ def eval_leg(args, circ_cfg):
                      "traffic": profiled_traffic("k_eval", circ_cfg["evidence"].shape[0] == 262144),
                      "traffic_unit": "HBM bytes per dispatch (rocprofv3)"},
         "grad_model_GBps": (up + down) * B / t_grad / 1e9,
+        "c64_vs_c128_branch_prob_rel_err": {"max": float(rel[big].max()), "p99": float(np.percentile(rel[big], 99)),
+                                            "median": float(np.median(rel[big])), "results": int(big.sum())},
     }
     g.close()
     del ws_e
@@ -386,7 +395,12 @@ def cpu_baseline(circ, theta, chains, budget_s):
         if time.perf_counter() - t0 > budget_s:
             break
     dt = time.perf_counter() - t0
-    return {"value": done * chains / dt, "unit": "samples/s", "cores": torch.get_num_threads(),
+    try:                                   # threads of the BLAS the oracle's matrix products use
+        from threadpoolctl import threadpool_info
+        cores = max([int(i.get("num_threads", 1)) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
+    except Exception:
+        cores = torch.get_num_threads()
+    return {"value": done * chains / dt, "unit": "samples/s", "cores": cores,
             "kind": "oracle",
             "sample": f"{done} of {theta.shape[0]} parameter sets: density-matrix diagonal, {chains} "
                       f"exact samples each, parameter-shift gradient of <C> ({dt:.1f} s, numpy complex128)"}

@@ -108,12 +108,14 @@ class Server:
     ``can_merge(a, b) -> bool``, ``launch(batch, stream) -> handle``,
     ``done(handle) -> bool`` and ``results(handle) -> list`` (one result per
     request of the batch, in order), and ``cost(req) -> estimated device
-    seconds`` if ``max_seconds`` is used.  ``launch``, ``done`` and ``results`` may raise;
+    seconds`` if ``max_seconds`` is used.  With ``request_timeout`` a launch
+    still running that long after it started fails its requests with
+    TimeoutError; its memory and stream return when the device finishes.  ``launch``, ``done`` and ``results`` may raise;
     the requests of that batch then fail with the exception."""
 
     def __init__(self, executor, mem_budget: int, clock: Callable[[], float] = time.perf_counter,
                  max_queue: int = 1 << 30, max_merge: int = 64, max_seconds: Optional[float] = None,
-                 tick: float = 1e-4):
+                 request_timeout: Optional[float] = None, tick: float = 1e-4):
         if mem_budget <= 0:
             raise ValueError("mem_budget must be positive")
         self.ex = executor
@@ -122,6 +124,7 @@ class Server:
         self.max_queue = int(max_queue)
         self.max_merge = max(1, int(max_merge))
         self.max_seconds = max_seconds
+        self.request_timeout = request_timeout
         self.tick = tick
         self.queue: collections.deque = collections.deque()
         self.inflight: List[tuple] = []            # (handle, [requests], stream, bytes)
@@ -137,6 +140,7 @@ class Server:
         self.rejected_memory = 0
         self.rejected_queue = 0
         self.rejected_cost = 0
+        self.timed_out = 0
         self.cancelled = 0
         self.launches = 0
         self.merged = 0
@@ -240,13 +244,23 @@ class Server:
                     except Exception as exc:
                         outs = exc
             if not ready:
+                if self.request_timeout is not None and self.clock() - reqs[0].t_launched > self.request_timeout:
+                    # the kernels cannot be stopped: the callers get an error now and
+                    # the memory and stream are released when the launch completes
+                    pending = [r for r in reqs if not r.future.done()]
+                    if pending:
+                        self.timed_out += len(pending)
+                        self._fail(pending, TimeoutError(
+                            f"request still on the device after {self.request_timeout:.3g} s"))
                 still.append((h, reqs, stream, nbytes))
                 continue
             if isinstance(outs, Exception):
-                self._fail(reqs, outs)
+                self._fail([r for r in reqs if not r.future.done()], outs)
             else:
                 now = self.clock()
                 for r, o in zip(reqs, outs):
+                    if r.future.done():            # timed out earlier
+                        continue
                     r.t_done = now
                     self.completed.append(r)
                     r.future.set_result(o)
@@ -351,7 +365,7 @@ class Server:
         lat = np.array([r.t_done - r.t_arrive for r in done])
         out: Dict[str, Any] = {"completed": len(done), "failed": self.failed,
                                "rejected_memory": self.rejected_memory,
-                               "rejected_queue": self.rejected_queue, "rejected_cost": self.rejected_cost,
+                               "rejected_queue": self.rejected_queue, "rejected_cost": self.rejected_cost, "timed_out": self.timed_out,
                                "cancelled": self.cancelled,
                                "launches": self.launches, "merged": self.merged,
                                "max_inflight": self.max_inflight, "peak_bytes": self.peak_used}

@@ -210,6 +210,25 @@ def test_resident_session_bytes_count_against_the_budget():
     assert f1.done() and f2.done()
 
 
+def test_request_timeout_fails_the_caller_but_holds_resources_until_done():
+    clock = Clock()
+    ex = FakeExecutor(clock, n_streams=1)
+    srv = Server(ex, mem_budget=100, clock=clock, request_timeout=5.0)
+    slow = srv.submit(req(60, 10.0, val=1))
+    nxt = srv.submit(req(60, 1.0, val=2))
+    srv.step()
+    clock.t = 6.0
+    srv.step()
+    with pytest.raises(TimeoutError):
+        slow.result(timeout=0)
+    assert srv.used == 60 and not nxt.done()      # the kernel still holds its memory and stream
+    clock.t = 10.0
+    srv.step()
+    assert srv.used == 60 and not nxt.done()      # the next one started
+    run_until_idle(srv, clock)
+    assert nxt.result() == 4.0 and srv.latency_stats()["timed_out"] == 1
+
+
 def test_cancel_waiting_but_not_running():
     clock = Clock()
     srv = Server(FakeExecutor(clock, n_streams=1), mem_budget=100, clock=clock)
