@@ -62,6 +62,11 @@ class ACGraph:
             self._h = ctypes.c_void_p()
         self._ws = {}
 
+    def release_workspaces(self):
+        """Drop the cached per-(dtype, op) workspaces (they can be tens of GB
+        for large batches); later calls allocate again as needed."""
+        self._ws = {}
+
     def __del__(self):
         try:
             self.close()

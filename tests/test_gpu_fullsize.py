@@ -1,0 +1,146 @@
+"""Parity at the full workload sizes, in the launch configuration the bench
+times: the whole batch runs on the GPU and the oracle checks a seeded sample
+of the results one by one, or properties that hold at any size.
+
+* 8-qubit noisy QAOA, 1024 parameter sets x 1000 chains, 10 burn-in sweeps:
+  chi-square of sampled parameter sets against the density-matrix diagonal
+  (and uniform p-values across them), the MaxCut cost of every sample, and
+  the score-function gradient over the sampled states against the oracle's
+  product rule for sampled parameter sets;
+* 16-qubit p=2 noisy QAOA, 262,144 amplitudes: sampled rows against the
+  oracle's branch amplitudes, every row's complex64 probability against
+  complex128, the complex64 gradient against complex128;
+* 32-qubit noise-free QAOA, 256 x 3907 chains: per-edge <Z_i Z_j> of sampled
+  parameter sets against the light cone, and every sample's cost.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import grad as ograd
+from oracle import sim, stats
+from tests.gpu_common import graph, note, oracle_amplitudes, prob_ok, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _bits(x, n):
+    x = np.asarray(x).reshape(-1).view(np.uint64)
+    return ((x[:, None] >> np.arange(n, dtype=np.uint64)) & np.uint64(1)).astype(np.int64)
+
+
+def test_config2_full_batch_samples_costs_and_gradient():
+    cfg = W.config(2)
+    circ = cfg["circuit"]
+    theta = cfg["theta"]
+    P, C = theta.shape[0], cfg["chains_per_param"]
+    note(f"config 2 full batch: {P} x {C} chains")
+    g = graph(circ)
+    out = g.sample(theta, C, 1, 10, 1, 2024, cost_edges=circ.edges, dtype="c64", want_states=True,
+                   want_cost=True, validate=False)
+    x = out["samples"].cpu().numpy().reshape(P, C)
+    cost = out["cost"].cpu().numpy().reshape(P, C)
+    bits = _bits(x, circ.n)
+    assert np.array_equal(cost.reshape(-1), W.maxcut_cost(circ.edges, bits).astype(np.float64))
+    rng = np.random.default_rng(3)
+    pick = np.sort(rng.choice(P, size=24, replace=False))
+    pvals = []
+    for p in pick:
+        probs = sim.probabilities(circ, theta[p])
+        _, _, pv = stats.chi2_pooled(np.bincount(x[p].astype(np.int64), minlength=1 << circ.n), probs)
+        pvals.append(pv)
+    note(f"  chi2 p-values: min {min(pvals):.3g}, KS {stats.uniformity_pvalue(pvals):.3g}")
+    assert min(pvals) > 1e-5
+    assert stats.uniformity_pvalue(pvals) > 1e-3
+    # the bench's gradient: LOGPROB over the sampled states, weight = cost
+    states = out["states"].reshape(P * C, -1)
+    po = torch.arange(P, dtype=torch.int32, device=states.device).repeat_interleave(C)
+    grad = g.grad(theta, states, po, mode="logprob", weight=out["cost"].reshape(-1), dtype="c64",
+                  validate=False)["grad"].cpu().numpy()
+    vals = W.unpack_evidence(circ, states.cpu().numpy().view(np.uint64))
+    for p in pick[:2]:
+        want = np.zeros(circ.n_angles)
+        mass = np.zeros(circ.n_angles)          # sum of |terms|: the score terms cancel
+        cache = {}
+        for c in range(C):
+            v = vals[p * C + c]
+            k = tuple(int(z) for z in v[circ.n:])
+            if k not in cache:
+                kk = np.array(k)
+                cache[k] = (sim.branch_state(circ, theta[p], kk), ograd.amplitude_grad(circ, theta[p], kk))
+            psi, dpsi = cache[k]
+            xi = sum(int(v[q]) << q for q in range(circ.n))
+            f, df = psi[xi], dpsi[:, xi]
+            if abs(f) > 0:
+                term = cost[p, c] * 2.0 * np.real(np.conj(f) * df) / abs(f) ** 2
+                want += term
+                mass += np.abs(term)
+        note(f"  param {p}: gradient {grad[p]} vs oracle {want} (term mass {mass})")
+        assert np.all(np.abs(grad[p] - want) <= 1e-5 * mass)
+
+
+def test_config3_full_batch_amplitudes_and_gradient():
+    cfg = W.config(3)
+    circ = cfg["circuit"]
+    theta, ev, po = cfg["theta"], cfg["evidence"], cfg["param_of"]
+    B = ev.shape[0]
+    note(f"config 3 full batch: {B} amplitudes")
+    g = graph(circ)
+
+    def free():
+        g.release_workspaces()
+        torch.cuda.empty_cache()
+
+    a64, p64 = g.eval(theta, ev, po, dtype="c64", validate=False)
+    free()
+    a128, p128 = g.eval(theta, ev, po, dtype="c128", validate=False)
+    free()
+    a128 = a128.cpu().numpy()
+    p64, p128 = p64.cpu().numpy(), p128.cpu().numpy()
+    # every result: complex64 against complex128 (branch probabilities, 1e-4)
+    ok, worst = prob_ok(p64, p128, rel=1e-4)
+    note(f"  c64 vs c128 worst rel err {worst:.2e}")
+    assert ok
+    # sampled rows against the oracle's branch amplitudes
+    vals = W.unpack_evidence(circ, ev)
+    rng = np.random.default_rng(11)
+    rows = np.sort(rng.choice(B, size=16, replace=False))
+    ref = np.array([oracle_amplitudes(circ, theta[po[b]], vals[b:b + 1])[0] for b in rows])
+    assert np.max(np.abs(a128[rows] - ref)) <= 1e-12
+    # gradient of sum_b |f_b|^2 at full size: complex64 against complex128
+    w = np.ones(B)
+    g64 = g.grad(theta, ev, po, mode="prob", weight=w, dtype="c64", validate=False)["grad"].cpu().numpy()
+    free()
+    g128 = g.grad(theta, ev, po, mode="prob", weight=w, dtype="c128", validate=False)["grad"].cpu().numpy()
+    free()
+    scale = np.max(np.abs(g128))
+    note(f"  gradient c64 vs c128: max |diff| / max |g| = {np.max(np.abs(g64 - g128)) / scale:.2e}")
+    assert np.max(np.abs(g64 - g128)) <= 1e-4 * scale
+
+
+def test_config4_full_batch_lightcone_and_costs():
+    cfg = W.config(4)
+    circ = cfg["circuit"]
+    theta = cfg["theta"]
+    P, C = theta.shape[0], cfg["chains_per_param"]
+    note(f"config 4 full batch: {P} x {C} chains")
+    g = graph(circ)
+    out = g.sample(theta, C, 1, 10, 1, 77, cost_edges=circ.edges, dtype="c64", want_cost=True, validate=False)
+    x = out["samples"].cpu().numpy().reshape(P, C)
+    cost = out["cost"].cpu().numpy().reshape(P, C)
+    assert np.array_equal(cost.reshape(-1), W.maxcut_cost(circ.edges, _bits(x, circ.n)).astype(np.float64))
+    rng = np.random.default_rng(5)
+    n_e = len(circ.edges)
+    for p in rng.choice(P, size=4, replace=False):
+        spins = 1 - 2 * _bits(x[p], circ.n)
+        for (i, j) in circ.edges:
+            est = float(np.mean(spins[:, i] * spins[:, j]))
+            ref = sim.qaoa_p1_zz_lightcone(circ.edges, theta[p, 0], theta[p, 1], i, j)
+            sd = np.sqrt(max(1.0 - ref * ref, 1e-3) / C)
+            assert abs(est - ref) <= 5.0 * sd, (p, i, j, est, ref, n_e)
