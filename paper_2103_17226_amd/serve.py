@@ -108,10 +108,11 @@ class Server:
     ``can_merge(a, b) -> bool``, ``launch(batch, stream) -> handle``,
     ``done(handle) -> bool`` and ``results(handle) -> list`` (one result per
     request of the batch, in order), and ``cost(req) -> estimated device
-    seconds`` if ``max_seconds`` is used.  With ``request_timeout`` a launch
-    still running that long after it started fails its requests with
-    TimeoutError; its memory and stream return when the device finishes.  ``launch``, ``done`` and ``results`` may raise;
-    the requests of that batch then fail with the exception."""
+    seconds`` if ``max_seconds`` is used.  ``launch``, ``done`` and
+    ``results`` may raise; the requests of that batch then fail with the
+    exception.  With ``request_timeout`` a launch still running that long
+    after it started fails its requests with TimeoutError at once; its memory
+    and stream return when the device finishes."""
 
     def __init__(self, executor, mem_budget: int, clock: Callable[[], float] = time.perf_counter,
                  max_queue: int = 1 << 30, max_merge: int = 64, max_seconds: Optional[float] = None,

@@ -6,7 +6,6 @@ import numpy as np
 import pytest
 import torch
 
-import workloads as W
 from oracle import sim
 
 

@@ -5,7 +5,6 @@ overlapping streams, what the same request gets from the plain binding calls
 on its own.  Amplitudes and samples are compared bit for bit, gradients to
 1e-12 relative (the merged reduction is arranged to add the same terms in the
 same order, so they are expected to agree bit for bit too)."""
-import threading
 import time
 
 import numpy as np

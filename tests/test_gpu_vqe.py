@@ -2,7 +2,6 @@
 samples against the oracle."""
 import numpy as np
 import pytest
-import torch
 
 import workloads as W
 from oracle import grad as ograd
