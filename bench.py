@@ -255,6 +255,12 @@ def eval_leg(args, circ_cfg):
     t_eval = timed(lambda: g.eval(theta, ev, po, dtype="c64", validate=False, ws=ws_e), args.eval_steps)
     t_grad = timed(lambda: g.grad(theta, ev, po, mode="prob", weight=wgt, dtype="c64", validate=False),
                    args.eval_steps)
+    # the differentiated form against the plain batched evaluation (same amplitudes expected)
+    a_eval, _ = g.eval(theta, ev, po, dtype="c64", validate=False, ws=ws_e)
+    a_grad = g.grad(theta, ev, po, mode="prob", weight=wgt, dtype="c64", validate=False, want_amp=True)["amp"]
+    diff = (a_grad - a_eval).abs() / a_eval.abs().clamp_min(1e-30)
+    grad_vs_eval = float(diff.max().item())
+    del a_eval, a_grad, diff
     up, down, E_ii = byte_model(comp, info["n_words"], 8)
     N = info["n_internal"]
     achieved = up * B / t_eval / 1e9
@@ -279,6 +285,7 @@ def eval_leg(args, circ_cfg):
                      "traffic": profiled_traffic("k_eval", circ_cfg["evidence"].shape[0] == 262144),
                      "traffic_unit": "HBM bytes per dispatch (rocprofv3)"},
         "grad_model_GBps": (up + down) * B / t_grad / 1e9,
+        "grad_vs_eval_amplitude_max_rel_diff": grad_vs_eval,
         "c64_vs_c128_branch_prob_rel_err": {"max": float(rel[big].max()), "p99": float(np.percentile(rel[big], 99)),
                                             "median": float(np.median(rel[big])), "results": int(big.sum())},
     }

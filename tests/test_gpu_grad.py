@@ -180,3 +180,24 @@ def test_autograd_gradcheck_c128():
     def fn(t):
         return amplitudes(g, t, ev, po, dtype="c128")
     assert torch.autograd.gradcheck(fn, (theta,), eps=1e-6, atol=1e-8)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_differentiated_pass_reproduces_the_plain_amplitudes(dtype):
+    # the gradient kernel's upward pass gives the plain batched evaluation's amplitudes bit for bit
+    note(f"grad amplitudes vs eval ({dtype})")
+    for i in (2, 3):
+        cfg = W.config(i, small=True)
+        circ = cfg["circuit"]
+        g = graph(circ)
+        if "evidence" in cfg:
+            theta, ev, po = cfg["theta"], cfg["evidence"], cfg["param_of"]
+        else:
+            rng = np.random.default_rng(i)
+            theta = cfg["theta"][:4]
+            vals = np.zeros((300, circ.n_vars), dtype=np.int64)
+            vals[:, :circ.n] = rng.integers(0, 2, size=(300, circ.n))
+            ev, po = W.pack_evidence(circ, vals), rng.integers(0, 4, size=300).astype(np.int32)
+        amp, _ = g.eval(theta, ev, po, dtype=dtype)
+        out = g.grad(theta, ev, po, mode="prob", weight=np.ones(len(po)), dtype=dtype, want_amp=True)
+        assert torch.equal(amp, out["amp"])
