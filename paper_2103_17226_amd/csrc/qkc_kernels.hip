@@ -971,14 +971,24 @@ struct StreamTile {
 #pragma unroll
             for (int u = 0; u < SEL_DOM; ++u)
                 acc[u] = static_cast<uint32_t>(u) < dom ? D[static_cast<size_t>(base + u) * WAVE + lane] : cplx<T>{T(0), T(0)};
-            for (uint32_t qq = q0; qq < q1; ++qq) {
-                const uint32_t q = g.vsel[qq];
-                const cplx<T> Aq = A[static_cast<size_t>(q) * WAVE + lane];
-                const uint32_t *rec = g.sel + static_cast<size_t>(q) * SEL_REC;
+            // the selectors of v in groups of SEL_DOM: their A rows load together
+            for (uint32_t qb = q0; qb < q1; qb += SEL_DOM) {
+                uint32_t qs[SEL_DOM];
+                cplx<T> Aq[SEL_DOM];
 #pragma unroll
-                for (int u = 0; u < SEL_DOM; ++u) {
-                    const uint32_t sl = rec[1 + u];
-                    if (sl != NO_SLOT) acc[u] = cadd(acc[u], cmul(Aq, wfix[sl]));
+                for (int j = 0; j < SEL_DOM; ++j) qs[j] = qb + j < q1 ? g.vsel[qb + j] : 0u;
+#pragma unroll
+                for (int j = 0; j < SEL_DOM; ++j)
+                    Aq[j] = qb + j < q1 ? A[static_cast<size_t>(qs[j]) * WAVE + lane] : cplx<T>{T(0), T(0)};
+#pragma unroll
+                for (int j = 0; j < SEL_DOM; ++j) {
+                    if (qb + j >= q1) break;
+                    const uint32_t *rec = g.sel + static_cast<size_t>(qs[j]) * SEL_REC;
+#pragma unroll
+                    for (int u = 0; u < SEL_DOM; ++u) {
+                        const uint32_t sl = rec[1 + u];
+                        if (sl != NO_SLOT) acc[u] = cadd(acc[u], cmul(Aq[j], wfix[sl]));
+                    }
                 }
             }
 #pragma unroll
