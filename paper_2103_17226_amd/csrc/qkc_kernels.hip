@@ -1073,7 +1073,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample_stream(DevGraph g, LdsPlan lp,
             bool done = false;
             // Gibbs weights of the next PF variables, loaded together (the
             // derivatives do not change until the state does)
-            constexpr int PF = 4;
+            constexpr int PF = sizeof(T) == 4 ? 3 : 2;
             double wpf[PF][SEL_DOM];
             int pf_pos = -1;
             for (;;) {
