@@ -48,9 +48,9 @@ KERNELS = os.path.join(ROOT, "paper_2103_17226_amd", "csrc", "qkc_kernels.hip")
 # the copy-kernel calibration, FETCH x 2.0, WRITE x 1.0), valid only for the
 # kernel source they were taken on and the default workload of each leg.
 PROFILED_TRAFFIC = {
-    "k_sample_stream": {"kernel_sha256_16": "82d404b165e9b9d4", "bytes": 4446783819776,
+    "k_sample_stream": {"kernel_sha256_16": "be05412a23cc49ea", "bytes": 4829788303360,
                         "profile": "profiles/k_sample_stream_qaoa_n8_p1_dep.md"},
-    "k_eval": {"kernel_sha256_16": "82d404b165e9b9d4", "bytes": 346177918976,
+    "k_eval": {"kernel_sha256_16": "be05412a23cc49ea", "bytes": 346192068608,
                "profile": "profiles/k_eval_qaoa_n16_p2_dep_ad.md"},
 }
 

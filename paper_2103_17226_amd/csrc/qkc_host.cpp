@@ -687,16 +687,20 @@ bool lds_capacity(const ac_graph *g, ac_dtype dt, int &cpw, int64_t &per_cu);
 
 SampleKernel sample_kernel(const ac_graph *g, ac_dtype dt, int64_t chains) {
     if (!g->has_plan) return SK_GLOBAL;
+    // the streaming sampler addresses a workgroup's rows through a buffer
+    // resource with 32-bit offsets: its region must stay below 2 GiB
+    const size_t stream_rows = 2 * static_cast<size_t>(g->plan.N) + g->dev.n_ind + g->dev.n_sel;
+    const bool stream_ok = stream_rows * WAVE * (dt == AC_C64 ? 8 : 16) < (size_t{1} << 31);
     const char *kern = std::getenv("QKC_SAMPLE_KERNEL");
     if (kern && std::strcmp(kern, "global") == 0) return SK_GLOBAL;
     if (kern && std::strcmp(kern, "lds") == 0) return SK_LDS;
-    if (kern && std::strcmp(kern, "stream") == 0) return SK_STREAM;
+    if (kern && std::strcmp(kern, "stream") == 0) return stream_ok ? SK_STREAM : SK_GLOBAL;
     int cpw = 0;
     int64_t per_cu = 0;
     if (lds_capacity(g, dt, cpw, per_cu) &&
         chains <= LDS_BATCH_FACTOR * per_cu * cpw * static_cast<int64_t>(g->n_cu))
         return SK_LDS;
-    return SK_STREAM;
+    return stream_ok ? SK_STREAM : SK_GLOBAL;
 }
 
 // Launch shape of the LDS-resident sampler, or false if a chain does not fit.

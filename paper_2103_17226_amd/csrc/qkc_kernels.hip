@@ -811,20 +811,55 @@ __device__ __forceinline__ void level_sync(int nwaves) {
     if (nwaves > 1) __syncthreads();
 }
 
+// Rows of a workgroup's [rows][64] region through a buffer resource: the row
+// offset (row x 64 x element bytes) is wave-uniform and goes in the scalar
+// offset, the lane offset is one VGPR shared by every access, so a batch of
+// row loads holds no 64-bit addresses in VGPRs.  The region is below 2 GiB
+// (checked at launch).
+template <typename T>
+struct RowBuf {
+    __amdgpu_buffer_rsrc_t rs;
+    uint32_t lane_off;
+
+    static constexpr uint32_t ROW_BYTES = WAVE * sizeof(cplx<T>);
+
+    __device__ __forceinline__ RowBuf(cplx<T> *region, size_t rows, int lane)
+        : rs(__builtin_amdgcn_make_buffer_rsrc(region, 0, static_cast<int>(rows * ROW_BYTES), 0x00020000)),
+          lane_off(static_cast<uint32_t>(lane) * static_cast<uint32_t>(sizeof(cplx<T>))) {}
+
+    __device__ __forceinline__ cplx<T> ld(uint32_t row) const {
+        if constexpr (sizeof(T) == 4)
+            return __builtin_bit_cast(cplx<T>, __builtin_amdgcn_raw_buffer_load_b64(rs, lane_off, row * ROW_BYTES, 0));
+        else
+            return __builtin_bit_cast(cplx<T>, __builtin_amdgcn_raw_buffer_load_b128(rs, lane_off, row * ROW_BYTES, 0));
+    }
+    __device__ __forceinline__ void st(uint32_t row, cplx<T> v) const {
+        if constexpr (sizeof(T) == 4)
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) uint32_t, v), rs,
+                                                  lane_off, row * ROW_BYTES, 0);
+        else
+            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(__attribute__((ext_vector_type(4))) uint32_t, v), rs,
+                                                   lane_off, row * ROW_BYTES, 0);
+    }
+};
+
+// Rows of the region: node values [0, N), node adjoints [N, 2N), indicator
+// derivatives [2N, 2N + n_ind), selector adjoints after them.
 template <typename T>
 struct StreamTile {
     DevGraph g;
-    cplx<T> *val, *adj;
+    RowBuf<T> rb;
+    uint32_t adj0, d0, a0;   // first row of the adjoints, indicator derivatives, selector adjoints
     const uint64_t *ev;      // [W][64] (LDS)
     const cplx<T> *ang;      // [S_ang][64] (LDS)
     const cplx<T> *wfix;     // [S] (LDS copy of the fixed weights)
     int lane;
 
-    // row of a node reference, or row 0 (always cached) for a leaf: lets a
-    // batch issue every row load before any branch on the reference kind
-    __device__ __forceinline__ cplx<T> row(const cplx<T> *base, uint32_t r) const {
+    // value row of a node reference, or row 0 (always cached) for a leaf:
+    // lets a batch issue every row load before any branch on the reference kind
+    __device__ __forceinline__ cplx<T> row(uint32_t r) const {
         const uint32_t x = (r != IDENT_REF && (r >> 30) == TAG_NODE) ? (r & REF_MASK) : 0u;
-        return base[static_cast<size_t>(x) * WAVE + lane];
+        return rb.ld(x);
     }
     __device__ __forceinline__ cplx<T> pick(uint32_t r, const cplx<T> &rowval) const {
         return (r >> 30) == TAG_NODE ? rowval : value(r);
@@ -832,7 +867,7 @@ struct StreamTile {
 
     __device__ __forceinline__ cplx<T> value(uint32_t r) const {
         const uint32_t tag = r >> 30, x = r & REF_MASK;
-        if (tag == TAG_NODE) return val[static_cast<size_t>(x) * WAVE + lane];
+        if (tag == TAG_NODE) return rb.ld(x);
         if (tag == TAG_IND) {
             const uint32_t u = (r >> 26) & 15u, width = ((r >> 24) & 3u) + 1u;
             const uint32_t word = (r >> 6) & 0x3ffffu, shift = r & 63u;
@@ -860,8 +895,8 @@ struct StreamTile {
                 for (int j = 0; j < KB; ++j) rec[j] = b0 + j < n1 ? lp.fwd[b0 + j] : ~0ull;
 #pragma unroll
                 for (int j = 0; j < KB; ++j) {
-                    va[j] = row(val, static_cast<uint32_t>(rec[j]));
-                    vb[j] = row(val, static_cast<uint32_t>(rec[j] >> 32));
+                    va[j] = row(static_cast<uint32_t>(rec[j]));
+                    vb[j] = row(static_cast<uint32_t>(rec[j] >> 32));
                 }
 #pragma unroll
                 for (int j = 0; j < KB; ++j) {
@@ -873,7 +908,7 @@ struct StreamTile {
 #pragma unroll
                 for (int j = 0; j < KB; ++j) {
                     if (b0 + j < n1)
-                        val[static_cast<size_t>(b0 + j) * WAVE + lane] = b0 + j >= np ? cmul(va[j], vb[j]) : cadd(va[j], vb[j]);
+                        rb.st(b0 + j, b0 + j >= np ? cmul(va[j], vb[j]) : cadd(va[j], vb[j]));
                 }
             }
             level_sync(nwaves);
@@ -901,8 +936,8 @@ struct StreamTile {
                 rr[j] = e + j < e_end ? lp.edg[e + j] : (static_cast<uint64_t>(NO_SIBLING) << 32);
 #pragma unroll
             for (int j = 0; j < KE; ++j) {
-                ap[j] = adj[static_cast<size_t>(static_cast<uint32_t>(rr[j])) * WAVE + lane];
-                sv[j] = row(val, static_cast<uint32_t>(rr[j] >> 32));
+                ap[j] = rb.ld(adj0 + static_cast<uint32_t>(rr[j]));
+                sv[j] = row(static_cast<uint32_t>(rr[j] >> 32));
             }
 #pragma unroll
             for (int j = 0; j < KE; ++j) {
@@ -931,14 +966,12 @@ struct StreamTile {
     __device__ void backward(const LdsPlan &lp, int wave, int nwaves) {
         constexpr int KB = sizeof(T) == 4 ? 8 : 4;
         const uint32_t root = static_cast<uint32_t>(lp.root);
-        cplx<T> *a = adj;
-        const int ln = lane;
         for (int l = lp.L - 1; l >= 0; --l) {
             const uint32_t n0 = lp.level_ptr[l], n1 = lp.level_ptr[l + 1];
             for (uint32_t b0 = n0 + static_cast<uint32_t>(wave) * KB; b0 < n1; b0 += static_cast<uint32_t>(nwaves) * KB) {
                 const uint32_t b1 = b0 + KB < n1 ? b0 + KB : n1;
                 pull_targets(lp, b0, b1, [&](uint32_t i, cplx<T> v) {
-                    a[static_cast<size_t>(i) * WAVE + ln] = i == root ? cplx<T>{T(1), T(0)} : v;
+                    rb.st(adj0 + i, i == root ? cplx<T>{T(1), T(0)} : v);
                 });
             }
             level_sync(nwaves);
@@ -948,19 +981,14 @@ struct StreamTile {
     // adjoints of every indicator leaf (into D rows) and selector leaf (into
     // A rows), batched like the downward pass; then the selector terms of
     // d root / d lambda_{v=u} (A_q * W[slot_q(u)]) are added per variable
-    __device__ void leaf_derivatives(const LdsPlan &lp, int wave, int nwaves, cplx<T> *D, cplx<T> *A) {
+    __device__ void leaf_derivatives(const LdsPlan &lp, int wave, int nwaves) {
         constexpr int KB = sizeof(T) == 4 ? 8 : 4;
         const uint32_t M = static_cast<uint32_t>(lp.N);
         const uint32_t nt = static_cast<uint32_t>(g.n_ind + g.n_sel);
-        const uint32_t n_ind = static_cast<uint32_t>(g.n_ind);
-        const int ln = lane;
         for (uint32_t b0 = static_cast<uint32_t>(wave) * KB; b0 < nt; b0 += static_cast<uint32_t>(nwaves) * KB) {
             const uint32_t b1 = b0 + KB < nt ? b0 + KB : nt;
-            pull_targets(lp, M + b0, M + b1, [&](uint32_t i, cplx<T> v) {
-                const uint32_t t = i - M;
-                if (t < n_ind) D[static_cast<size_t>(t) * WAVE + ln] = v;
-                else A[static_cast<size_t>(t - n_ind) * WAVE + ln] = v;
-            });
+            // indicator and selector rows are contiguous: target M + t -> row d0 + t
+            pull_targets(lp, M + b0, M + b1, [&](uint32_t i, cplx<T> v) { rb.st(d0 + (i - M), v); });
         }
         level_sync(nwaves);
         for (int v = wave; v < g.n_vars; v += nwaves) {
@@ -970,7 +998,7 @@ struct StreamTile {
             cplx<T> acc[SEL_DOM];
 #pragma unroll
             for (int u = 0; u < SEL_DOM; ++u)
-                acc[u] = static_cast<uint32_t>(u) < dom ? D[static_cast<size_t>(base + u) * WAVE + lane] : cplx<T>{T(0), T(0)};
+                acc[u] = static_cast<uint32_t>(u) < dom ? rb.ld(d0 + base + u) : cplx<T>{T(0), T(0)};
             // the selectors of v in groups of SEL_DOM: their A rows load together
             for (uint32_t qb = q0; qb < q1; qb += SEL_DOM) {
                 uint32_t qs[SEL_DOM];
@@ -979,7 +1007,7 @@ struct StreamTile {
                 for (int j = 0; j < SEL_DOM; ++j) qs[j] = qb + j < q1 ? g.vsel[qb + j] : 0u;
 #pragma unroll
                 for (int j = 0; j < SEL_DOM; ++j)
-                    Aq[j] = qb + j < q1 ? A[static_cast<size_t>(qs[j]) * WAVE + lane] : cplx<T>{T(0), T(0)};
+                    Aq[j] = qb + j < q1 ? rb.ld(a0 + qs[j]) : cplx<T>{T(0), T(0)};
 #pragma unroll
                 for (int j = 0; j < SEL_DOM; ++j) {
                     if (qb + j >= q1) break;
@@ -993,13 +1021,17 @@ struct StreamTile {
             }
 #pragma unroll
             for (int u = 0; u < SEL_DOM; ++u)
-                if (static_cast<uint32_t>(u) < dom) D[static_cast<size_t>(base + u) * WAVE + lane] = acc[u];
+                if (static_cast<uint32_t>(u) < dom) rb.st(d0 + base + u, acc[u]);
         }
     }
 };
 
+// complex64: 6 waves per SIMD (80 VGPRs, a few spilled to scratch) -- the
+// kernel waits on dependent row loads and more resident waves hide more of it
+// (measured: 4 waves 1.49 s, 5 waves 1.44 s, 6-8 waves 1.41 s per 1,024,000
+// 8-qubit samples)
 template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_sample_stream(DevGraph g, LdsPlan lp, const double *theta,
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 1, 8))) void k_sample_stream(DevGraph g, LdsPlan lp, const double *theta,
                                                          const cplx<T> *wfix, cplx<T> *vals, size_t per_wg,
                                                          SampleArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1016,11 +1048,11 @@ __global__ __launch_bounds__(BLOCK) void k_sample_stream(DevGraph g, LdsPlan lp,
     const int wave = static_cast<int>(uniform_u32(threadIdx.x / WAVE));
     const int nwaves = blockDim.x / WAVE;
     cplx<T> *val = vals + per_wg * blockIdx.x;
-    cplx<T> *adj = val + static_cast<size_t>(lp.N) * WAVE;
-    cplx<T> *D = adj + static_cast<size_t>(lp.N) * WAVE;    // [n_ind][64]
-    cplx<T> *Asel = D + static_cast<size_t>(g.n_ind) * WAVE;  // [n_sel][64]
+    cplx<T> *D = val + 2 * static_cast<size_t>(lp.N) * WAVE;    // [n_ind][64]
     for (int s2 = threadIdx.x; s2 < g.S; s2 += blockDim.x) fix_s[s2] = wfix[s2];
-    StreamTile<T> t{g, val, adj, ev_s, ang_s, fix_s, lane};
+    const uint32_t N = static_cast<uint32_t>(lp.N);
+    StreamTile<T> t{g, RowBuf<T>(val, per_wg / WAVE, lane), N, 2 * N, 2 * N + static_cast<uint32_t>(g.n_ind),
+                    ev_s, ang_s, fix_s, lane};
     const int64_t stride = static_cast<int64_t>(gridDim.x) * WAVE;
     const uint32_t total_sweeps = static_cast<uint32_t>(a.burn_in) +
                                   static_cast<uint32_t>(a.spc) * static_cast<uint32_t>(a.thin);
@@ -1062,7 +1094,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample_stream(DevGraph g, LdsPlan lp,
         __syncthreads();
         t.forward(lp, wave, nwaves);
         t.backward(lp, wave, nwaves);
-        t.leaf_derivatives(lp, wave, nwaves, D, Asel);
+        t.leaf_derivatives(lp, wave, nwaves);
         __syncthreads();
 
         if (wave == 0 && ch >= 0) {
