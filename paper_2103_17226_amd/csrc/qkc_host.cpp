@@ -133,7 +133,7 @@ int cdiv64(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) / b); }
 // Node-parallel plan (see LdsPlan in qkc_internal.h), built on the host.
 struct HostPlan {
     std::vector<uint64_t> fwd, orec, edg, fwd_u, edg_u, dterm;
-    std::vector<uint32_t> level_ptr, level_prod, brec, estart, dstart;
+    std::vector<uint32_t> level_ptr, level_prod, brec, estart, dstart, esel;
     uint32_t N = 0, L = 0, root = 0, max_edges = 0;
     bool ok = false;
 };
@@ -221,8 +221,12 @@ HostPlan build_plan(uint32_t N, const uint8_t *op, const uint32_t *row_ptr, cons
     }
     for (uint32_t l = 1; l <= Lmax; ++l) P.level_ptr[l] += P.level_ptr[l - 1];
     for (uint32_t l = 0; l < Lmax; ++l) P.level_prod[l] = P.level_ptr[l] + n_sum[l + 1];
-    // parent edges of nodes, indicator leaves and selectors, in increasing parent order
+    // parent edges of nodes, indicator leaves and selectors, in increasing
+    // parent order; selector targets follow the per-variable selector lists
+    // (vsel), so the selectors of one variable are contiguous targets
     const size_t T = static_cast<size_t>(M) + n_ind + n_sel;
+    std::vector<uint32_t> selpos(n_sel, 0);
+    for (uint32_t k = 0; k < n_sel; ++k) selpos[vsel[k]] = k;
     std::vector<std::vector<uint64_t>> edges(T);
     auto target_of = [&](uint32_t r) -> int64_t {
         if (r == IDENT_REF) return -1;
@@ -232,7 +236,7 @@ HostPlan build_plan(uint32_t N, const uint8_t *op, const uint32_t *row_ptr, cons
             const uint32_t x = r & REF_MASK;
             return static_cast<int64_t>(M) + ind_base[x & 0xffffffu] + (x >> 24);
         }
-        if (tag == TAG_SEL) return static_cast<int64_t>(M) + n_ind + (r & REF_MASK);
+        if (tag == TAG_SEL) return static_cast<int64_t>(M) + n_ind + selpos[r & REF_MASK];
         return -1;
     };
     for (uint32_t j = 0; j < M; ++j) {
@@ -251,6 +255,8 @@ HostPlan build_plan(uint32_t N, const uint8_t *op, const uint32_t *row_ptr, cons
         P.estart[t + 1] = P.estart[t] + static_cast<uint32_t>(edges[t].size());
         P.edg.insert(P.edg.end(), edges[t].begin(), edges[t].end());
     }
+    for (uint32_t k = 0; k < n_sel; ++k)
+        P.esel.insert(P.esel.end(), edges[static_cast<size_t>(M) + n_ind + k].size(), vsel[k]);
     for (uint32_t l = 0; l < Lmax; ++l)
         P.max_edges = std::max(P.max_edges, P.estart[P.level_ptr[l + 1]] - P.estart[P.level_ptr[l]]);
     P.max_edges = std::max(P.max_edges, P.estart[T] - P.estart[M]);
@@ -296,7 +302,7 @@ HostPlan build_plan(uint32_t N, const uint8_t *op, const uint32_t *row_ptr, cons
                 const uint32_t sl = u < static_cast<uint32_t>(SEL_DOM) ? sel_dev[static_cast<size_t>(q) * SEL_REC + 1 + u]
                                                                        : NO_SLOT;
                 if (sl == NO_SLOT) continue;
-                for (uint32_t e = P.estart[M + n_ind + q]; e < P.estart[M + n_ind + q + 1]; ++e)
+                for (uint32_t e = P.estart[M + n_ind + qq]; e < P.estart[M + n_ind + qq + 1]; ++e)
                     P.dterm.push_back(static_cast<uint64_t>(e - leaf0) | (static_cast<uint64_t>(sl) << 32));
             }
             P.dstart[t + 1] = static_cast<uint32_t>(P.dterm.size());
@@ -514,6 +520,7 @@ extern "C" ac_status ac_load(const void *blob, size_t nbytes, int device, ac_gra
         {hp.dterm.data(), hp.dterm.size() * sizeof(uint64_t), 0},
         {par_rec.data(), par_rec.size() * sizeof(uint64_t), 0},
         {leaf_rec.data(), leaf_rec.size() * sizeof(uint64_t), 0},
+        {hp.esel.data(), hp.esel.size() * sizeof(uint32_t), 0},
     };
     size_t total = 0;
     for (auto &s : secs) {
@@ -587,6 +594,7 @@ extern "C" ac_status ac_load(const void *blob, size_t nbytes, int device, ac_gra
         lp.edg_u = reinterpret_cast<const uint64_t *>(at(24));
         lp.dstart = reinterpret_cast<const uint32_t *>(at(25));
         lp.dterm = reinterpret_cast<const uint64_t *>(at(26));
+        lp.esel = reinterpret_cast<const uint32_t *>(at(29));
         lp.max_edges = static_cast<int32_t>(hp.max_edges);
         lp.N = static_cast<int32_t>(hp.N);
         lp.L = static_cast<int32_t>(hp.L);
@@ -689,7 +697,7 @@ SampleKernel sample_kernel(const ac_graph *g, ac_dtype dt, int64_t chains) {
     if (!g->has_plan) return SK_GLOBAL;
     // the streaming sampler addresses a workgroup's rows through a buffer
     // resource with 32-bit offsets: its region must stay below 2 GiB
-    const size_t stream_rows = 2 * static_cast<size_t>(g->plan.N) + g->dev.n_ind + g->dev.n_sel;
+    const size_t stream_rows = 2 * static_cast<size_t>(g->plan.N) + g->dev.n_ind;
     const bool stream_ok = stream_rows * WAVE * (dt == AC_C64 ? 8 : 16) < (size_t{1} << 31);
     const char *kern = std::getenv("QKC_SAMPLE_KERNEL");
     if (kern && std::strcmp(kern, "global") == 0) return SK_GLOBAL;
@@ -769,7 +777,7 @@ bool make_layout(const ac_graph *g, ac_dtype dt, int64_t batch, int op, Layout &
         const SampleKernel sk = sample_kernel(g, dt, batch);
         if (sk == SK_LDS && sample_lds_shape(g, dt, batch, cpw, lgrid)) rows = 0;
         else if (sk == SK_STREAM) {
-            rows = 2 * static_cast<size_t>(g->plan.N) + d.n_ind + d.n_sel;
+            rows = 2 * static_cast<size_t>(g->plan.N) + d.n_ind;
             kid = 3;
         } else {
             rows = 2 * static_cast<size_t>(d.N) + d.n_ind;

@@ -80,7 +80,8 @@ struct DevGraph {
 //   fwd[i]        children refs a | b << 32 (b = IDENT_REF for a single child)
 //   level_prod[l] first product of level l (sums are [level_ptr[l], level_prod[l]))
 //   brec[t]       for node t < N, indicator leaf t - N < n_ind or selector
-//                 t - N - n_ind: {number of parent
+//                 vsel[t - N - n_ind] (selector targets follow the
+//                 per-variable selector lists): {number of parent
 //                 edges, offset of the 2nd.. in orec, first parent, first
 //                 sibling}; a parent edge contributes adj[parent] * value(sibling),
 //                 sibling = NO_SIBLING for a sum parent
@@ -114,6 +115,7 @@ struct LdsPlan {
     const uint64_t *edg_u;      // [estart[N + n_ind + n_sel]]
     const uint32_t *dstart;     // [n_ind + 1]
     const uint64_t *dterm;      // [dstart[n_ind]]
+    const uint32_t *esel;       // [estart[N + n_ind + n_sel] - estart[N + n_ind]] selector of each selector parent edge
     int32_t N, L, root;
     int32_t max_edges;          // most parent edges of one level, or of all leaves
     int64_t R;

@@ -844,22 +844,23 @@ struct RowBuf {
 };
 
 // Rows of the region: node values [0, N), node adjoints [N, 2N), indicator
-// derivatives [2N, 2N + n_ind), selector adjoints after them.
+// derivatives d root / d lambda_{v=u} [2N, 2N + n_ind).
 template <typename T>
 struct StreamTile {
     DevGraph g;
     RowBuf<T> rb;
-    uint32_t adj0, d0, a0;   // first row of the adjoints, indicator derivatives, selector adjoints
+    uint32_t adj0, d0;       // first row of the adjoints and of the indicator derivatives
     const uint64_t *ev;      // [W][64] (LDS)
     const cplx<T> *ang;      // [S_ang][64] (LDS)
     const cplx<T> *wfix;     // [S] (LDS copy of the fixed weights)
     int lane;
 
-    // value row of a node reference, or row 0 (always cached) for a leaf:
-    // lets a batch issue every row load before any branch on the reference kind
+    // value row of a node reference, zero for a leaf (decoded later by
+    // pick): the reference is wave-uniform, so the test is a scalar branch
+    // and a batch still issues all of its row loads before the first wait
     __device__ __forceinline__ cplx<T> row(uint32_t r) const {
-        const uint32_t x = (r != IDENT_REF && (r >> 30) == TAG_NODE) ? (r & REF_MASK) : 0u;
-        return rb.ld(x);
+        if (r != IDENT_REF && (r >> 30) == TAG_NODE) return rb.ld(r & REF_MASK);
+        return cplx<T>{T(0), T(0)};
     }
     __device__ __forceinline__ cplx<T> pick(uint32_t r, const cplx<T> &rowval) const {
         return (r >> 30) == TAG_NODE ? rowval : value(r);
@@ -978,44 +979,52 @@ struct StreamTile {
         }
     }
 
-    // adjoints of every indicator leaf (into D rows) and selector leaf (into
-    // A rows), batched like the downward pass; then the selector terms of
-    // d root / d lambda_{v=u} (A_q * W[slot_q(u)]) are added per variable
+    // d root / d lambda_{v=u}, one wave per variable: the adjoint sums of v's
+    // indicator leaves into its D rows, then every parent edge of v's
+    // selector leaves (contiguous in the plan, in batches of KE whose row
+    // loads issue together) adds its term times the edge's selector weight for
+    // each value u.  Only D rows are stored; no barrier inside.
     __device__ void leaf_derivatives(const LdsPlan &lp, int wave, int nwaves) {
-        constexpr int KB = sizeof(T) == 4 ? 8 : 4;
+        constexpr int KE = sizeof(T) == 4 ? 4 : 2;
         const uint32_t M = static_cast<uint32_t>(lp.N);
-        const uint32_t nt = static_cast<uint32_t>(g.n_ind + g.n_sel);
-        for (uint32_t b0 = static_cast<uint32_t>(wave) * KB; b0 < nt; b0 += static_cast<uint32_t>(nwaves) * KB) {
-            const uint32_t b1 = b0 + KB < nt ? b0 + KB : nt;
-            // indicator and selector rows are contiguous: target M + t -> row d0 + t
-            pull_targets(lp, M + b0, M + b1, [&](uint32_t i, cplx<T> v) { rb.st(d0 + (i - M), v); });
-        }
-        level_sync(nwaves);
+        const uint32_t s0 = M + static_cast<uint32_t>(g.n_ind);    // first selector target
+        const uint32_t sel_e0 = lp.estart[s0];                        // first selector edge
         for (int v = wave; v < g.n_vars; v += nwaves) {
             const uint32_t base = g.ind_base[v], dom = g.ind_base[v + 1] - base;
+            if (dom > 0)
+                pull_targets(lp, M + base, M + base + dom, [&](uint32_t i, cplx<T> val) { rb.st(d0 + (i - M), val); });
             const uint32_t q0 = g.vsel_ptr[v], q1 = g.vsel_ptr[v + 1];
             if (q0 == q1) continue;
             cplx<T> acc[SEL_DOM];
 #pragma unroll
-            for (int u = 0; u < SEL_DOM; ++u)
+            for (int u = 0; u < SEL_DOM; ++u)       // this wave's own stores, read back in program order
                 acc[u] = static_cast<uint32_t>(u) < dom ? rb.ld(d0 + base + u) : cplx<T>{T(0), T(0)};
-            // the selectors of v in groups of SEL_DOM: their A rows load together
-            for (uint32_t qb = q0; qb < q1; qb += SEL_DOM) {
-                uint32_t qs[SEL_DOM];
-                cplx<T> Aq[SEL_DOM];
+            const uint32_t e1 = lp.estart[s0 + q1];
+            for (uint32_t e = lp.estart[s0 + q0]; e < e1; e += KE) {
+                uint64_t rr[KE];
+                uint32_t qe[KE];
+                cplx<T> ap[KE], sv[KE];
 #pragma unroll
-                for (int j = 0; j < SEL_DOM; ++j) qs[j] = qb + j < q1 ? g.vsel[qb + j] : 0u;
+                for (int j = 0; j < KE; ++j) {
+                    const bool in = e + j < e1;
+                    rr[j] = in ? lp.edg[e + j] : (static_cast<uint64_t>(NO_SIBLING) << 32);
+                    qe[j] = in ? lp.esel[e + j - sel_e0] : 0u;
+                }
 #pragma unroll
-                for (int j = 0; j < SEL_DOM; ++j)
-                    Aq[j] = qb + j < q1 ? rb.ld(a0 + qs[j]) : cplx<T>{T(0), T(0)};
+                for (int j = 0; j < KE; ++j) {
+                    ap[j] = e + j < e1 ? rb.ld(adj0 + static_cast<uint32_t>(rr[j])) : cplx<T>{T(0), T(0)};
+                    sv[j] = row(static_cast<uint32_t>(rr[j] >> 32));
+                }
 #pragma unroll
-                for (int j = 0; j < SEL_DOM; ++j) {
-                    if (qb + j >= q1) break;
-                    const uint32_t *rec = g.sel + static_cast<size_t>(qs[j]) * SEL_REC;
+                for (int j = 0; j < KE; ++j) {
+                    if (e + j >= e1) break;
+                    const uint32_t sb = static_cast<uint32_t>(rr[j] >> 32);
+                    const cplx<T> term = sb != NO_SIBLING ? cmul(ap[j], pick(sb, sv[j])) : ap[j];
+                    const uint32_t *rec = g.sel + static_cast<size_t>(qe[j]) * SEL_REC;
 #pragma unroll
                     for (int u = 0; u < SEL_DOM; ++u) {
                         const uint32_t sl = rec[1 + u];
-                        if (sl != NO_SLOT) acc[u] = cadd(acc[u], cmul(Aq[j], wfix[sl]));
+                        if (sl != NO_SLOT) acc[u] = cadd(acc[u], cmul(term, wfix[sl]));
                     }
                 }
             }
@@ -1051,8 +1060,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T)
     cplx<T> *D = val + 2 * static_cast<size_t>(lp.N) * WAVE;    // [n_ind][64]
     for (int s2 = threadIdx.x; s2 < g.S; s2 += blockDim.x) fix_s[s2] = wfix[s2];
     const uint32_t N = static_cast<uint32_t>(lp.N);
-    StreamTile<T> t{g, RowBuf<T>(val, per_wg / WAVE, lane), N, 2 * N, 2 * N + static_cast<uint32_t>(g.n_ind),
-                    ev_s, ang_s, fix_s, lane};
+    StreamTile<T> t{g, RowBuf<T>(val, per_wg / WAVE, lane), N, 2 * N, ev_s, ang_s, fix_s, lane};
     const int64_t stride = static_cast<int64_t>(gridDim.x) * WAVE;
     const uint32_t total_sweeps = static_cast<uint32_t>(a.burn_in) +
                                   static_cast<uint32_t>(a.spc) * static_cast<uint32_t>(a.thin);
