@@ -991,14 +991,18 @@ struct StreamTile {
         const uint32_t sel_e0 = lp.estart[s0];                        // first selector edge
         for (int v = wave; v < g.n_vars; v += nwaves) {
             const uint32_t base = g.ind_base[v], dom = g.ind_base[v + 1] - base;
-            if (dom > 0)
-                pull_targets(lp, M + base, M + base + dom, [&](uint32_t i, cplx<T> val) { rb.st(d0 + (i - M), val); });
             const uint32_t q0 = g.vsel_ptr[v], q1 = g.vsel_ptr[v + 1];
+            // indicator leaves: walked unless v has none with a parent and
+            // all of its values are covered by the selector accumulators
+            const bool ind_edges = lp.estart[M + base] != lp.estart[M + base + dom];
+            const bool walk_ind = dom > 0 && (ind_edges || q0 == q1 || dom > static_cast<uint32_t>(SEL_DOM));
+            if (walk_ind)
+                pull_targets(lp, M + base, M + base + dom, [&](uint32_t i, cplx<T> val) { rb.st(d0 + (i - M), val); });
             if (q0 == q1) continue;
             cplx<T> acc[SEL_DOM];
 #pragma unroll
             for (int u = 0; u < SEL_DOM; ++u)       // this wave's own stores, read back in program order
-                acc[u] = static_cast<uint32_t>(u) < dom ? rb.ld(d0 + base + u) : cplx<T>{T(0), T(0)};
+                acc[u] = walk_ind && static_cast<uint32_t>(u) < dom ? rb.ld(d0 + base + u) : cplx<T>{T(0), T(0)};
             const uint32_t e1 = lp.estart[s0 + q1];
             for (uint32_t e = lp.estart[s0 + q0]; e < e1; e += KE) {
                 uint64_t rr[KE];
