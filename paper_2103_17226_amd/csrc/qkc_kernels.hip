@@ -477,8 +477,11 @@ __device__ bool stage_tile(const DevGraph &g, uint64_t *ev_s, cplx<T> *ang_s, co
 // upward pass for a batch (amplitude queries)
 // ---------------------------------------------------------------------------
 
+// complex64: 8 waves per SIMD (64 VGPRs, a few spilled): rows wait on HBM and
+// more resident waves hide it (16-qubit noisy QAOA, 262,144 amplitudes:
+// 6 waves 74 ms, 8 waves 66 ms)
 template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_eval(DevGraph g, const double *theta, const int32_t *param_of, int P,
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 1, 8))) void k_eval(DevGraph g, const double *theta, const int32_t *param_of, int P,
                                                 const uint64_t *evidence, int64_t B, const cplx<T> *wfix,
                                                 cplx<T> *vals, size_t per_wg, cplx<T> *amp_out,
                                                 double *prob_out) {
@@ -514,8 +517,10 @@ __global__ __launch_bounds__(BLOCK) void k_eval(DevGraph g, const double *theta,
 // upward + downward pass + chain rule (gradients)
 // ---------------------------------------------------------------------------
 
+// complex64: 6 waves per SIMD (80 VGPRs, a few spilled; 5 waves unbounded):
+// 16-qubit noisy QAOA gradients over 262,144 elements 283 -> 255 ms
 template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_grad(DevGraph g, const double *theta, const int32_t *param_of, int P,
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 1, 8))) void k_grad(DevGraph g, const double *theta, const int32_t *param_of, int P,
                                                 const uint64_t *evidence, int64_t B, const cplx<T> *wfix,
                                                 cplx<T> *vals, size_t per_wg, int mode,
                                                 const cplx<T> *cotangent, const double *weight,
