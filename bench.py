@@ -48,9 +48,9 @@ KERNELS = os.path.join(ROOT, "paper_2103_17226_amd", "csrc", "qkc_kernels.hip")
 # the copy-kernel calibration, FETCH x 2.0, WRITE x 1.0), valid only for the
 # kernel source they were taken on and the default workload of each leg.
 PROFILED_TRAFFIC = {
-    "k_sample_stream": {"kernel_sha256_16": "be05412a23cc49ea", "bytes": 4829788303360,
+    "k_sample_stream": {"kernel_sha256_16": "17b9837fbaa91d0a", "bytes": 4203551689728,
                         "profile": "profiles/k_sample_stream_qaoa_n8_p1_dep.md"},
-    "k_eval": {"kernel_sha256_16": "be05412a23cc49ea", "bytes": 346192068608,
+    "k_eval": {"kernel_sha256_16": "17b9837fbaa91d0a", "bytes": 360739991552,
                "profile": "profiles/k_eval_qaoa_n16_p2_dep_ad.md"},
 }
 
@@ -199,6 +199,12 @@ def serve_run(graphs, pool, rate, args):
            "service_over_estimate_p50": float(np.median(ratio)) if ratio else None,
            "service_over_estimate_max": float(max(ratio)) if ratio else None,
            "unfinished_requests": stuck[:5]}
+    if len(ok) <= 16:       # light load: every request's estimate and timeline
+        out["requests"] = [{"graph": q.graph, "ac_nodes": graphs[q.graph].info["n_internal"], "kind": q.kind,
+                            "P": q.n_params, "S": q.samples, "rows": q.n_rows, "grad": q.grad,
+                            "est_ms": ex.cost(q) * 1e3, "queue_ms": (q.t_start - q.t_arrive) * 1e3,
+                            "host_ms": (q.t_launched - q.t_start) * 1e3, "device_ms": (q.t_done - q.t_launched) * 1e3}
+                           for q in ok]
     return out
 
 
