@@ -159,6 +159,19 @@ const char *ac_last_error(void);
  */
 size_t ac_workspace_size(const ac_graph *g, ac_dtype dtype, int64_t batch, int op);
 
+/* Sampler kernels, as reported by ac_sample_shape. */
+typedef enum { AC_SAMPLER_STREAM = 0, AC_SAMPLER_LDS = 1, AC_SAMPLER_GLOBAL = 2 } ac_sampler_kind;
+
+/*
+ * Which Gibbs-sampler kernel ac_sample runs for `chains` chains
+ * (P * chains_per_param) in `dtype` on this graph's device, and how many
+ * chains it advances at once (the rest wait for a free slot), so a scheduler
+ * can estimate a call's device time before making it.  Host-only; writes
+ * *kind (an ac_sampler_kind) and *concurrent.  AC_ERR_INVALID_ARG for a null
+ * graph or output, a bad dtype or chains < 1.
+ */
+ac_status ac_sample_shape(const ac_graph *g, ac_dtype dtype, int64_t chains, int32_t *kind, int64_t *concurrent);
+
 /*
  * Upward pass (Sec. 3.3.1) for a batch: amp_out[b] = f(evidence[b]; theta[param_of[b]], noise)
  * for b in [0, B).  prob_out (optional, may be NULL) receives |amp|^2 in

@@ -80,6 +80,14 @@ class ACGraph:
     def workspace_size(self, dtype: str, batch: int, op: int) -> int:
         return int(L.lib().ac_workspace_size(self._h, _CDTYPE[dtype][0], int(batch), int(op)))
 
+    def sample_shape(self, dtype: str, chains: int):
+        """(kernel, chains advanced at once) that ``sample`` uses for this many
+        chains: kernel is "stream", "lds" or "global"."""
+        kind, conc = ctypes.c_int32(), ctypes.c_int64()
+        L.check(L.lib().ac_sample_shape(self._h, _CDTYPE[dtype][0], int(chains), ctypes.byref(kind),
+                                        ctypes.byref(conc)))
+        return ("stream", "lds", "global")[kind.value], int(conc.value)
+
     def workspace(self, dtype: str, batch: int, op: int, ws: Optional[torch.Tensor] = None) -> torch.Tensor:
         """The workspace for one call: ``ws`` if given (checked for size), else
         a buffer cached per (dtype, op) on this graph.  The cached buffer is

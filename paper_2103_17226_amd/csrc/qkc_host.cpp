@@ -685,11 +685,14 @@ constexpr size_t CU_LDS = 160 * 1024;                      // LDS per compute un
 // blob's own DAG (used when no plan exists).  The streaming kernel has the
 // higher throughput once the batch fills the chip; the LDS-resident one has a
 // much shorter time per chain (its node values never leave the CU), so it
-// wins for batches up to a few times the number of chains it holds at once.
-// QKC_SAMPLE_KERNEL = stream | lds | global forces one (comparisons, tests).
+// wins for batches up to a couple of dozen times the number of chains it
+// holds at once (complex64, 10 sweeps, noisy QAOA ACs of 937 to 3577 nodes:
+// the crossover lies between 21 and 43 such groups).
+// QKC_SAMPLE_KERNEL = stream | lds | global forces one (comparisons, tests);
+// QKC_LDS_BATCH_FACTOR replaces the factor below (measurements).
 enum SampleKernel { SK_STREAM, SK_LDS, SK_GLOBAL };
 
-constexpr int64_t LDS_BATCH_FACTOR = 6;   // LDS kernel up to this many rounds of resident chains
+constexpr int64_t LDS_BATCH_FACTOR = 24;  // LDS kernel up to this many groups of resident chains
 
 bool lds_capacity(const ac_graph *g, ac_dtype dt, int &cpw, int64_t &per_cu);
 
@@ -705,8 +708,9 @@ SampleKernel sample_kernel(const ac_graph *g, ac_dtype dt, int64_t chains) {
     if (kern && std::strcmp(kern, "stream") == 0) return stream_ok ? SK_STREAM : SK_GLOBAL;
     int cpw = 0;
     int64_t per_cu = 0;
-    if (lds_capacity(g, dt, cpw, per_cu) &&
-        chains <= LDS_BATCH_FACTOR * per_cu * cpw * static_cast<int64_t>(g->n_cu))
+    int64_t factor = LDS_BATCH_FACTOR;
+    if (const char *env = std::getenv("QKC_LDS_BATCH_FACTOR")) factor = std::max(0, std::min(1 << 20, std::atoi(env)));
+    if (lds_capacity(g, dt, cpw, per_cu) && chains <= factor * per_cu * cpw * static_cast<int64_t>(g->n_cu))
         return SK_LDS;
     return stream_ok ? SK_STREAM : SK_GLOBAL;
 }
@@ -844,6 +848,26 @@ extern "C" size_t ac_workspace_size(const ac_graph *g, ac_dtype dtype, int64_t b
         return 0;
     }
     return L.total;
+}
+
+extern "C" ac_status ac_sample_shape(const ac_graph *g, ac_dtype dtype, int64_t chains, int32_t *kind,
+                                     int64_t *concurrent) {
+    if (!g || !kind || !concurrent || (dtype != AC_C64 && dtype != AC_C128) || chains < 1)
+        return fail(AC_ERR_INVALID_ARG, "ac_sample_shape: invalid arguments");
+    const SampleKernel sk = sample_kernel(g, dtype, chains);
+    int cpw = 0, lgrid = 0;
+    if (sk == SK_LDS && sample_lds_shape(g, dtype, chains, cpw, lgrid)) {
+        int64_t per_cu = 0;
+        lds_capacity(g, dtype, cpw, per_cu);
+        *kind = AC_SAMPLER_LDS;
+        *concurrent = std::min<int64_t>(chains, per_cu * cpw * static_cast<int64_t>(g->n_cu));
+        return AC_OK;
+    }
+    Layout L;
+    if (!make_layout(g, dtype, chains, AC_OP_SAMPLE, L)) return fail(AC_ERR_INVALID_ARG, "ac_sample_shape: no layout");
+    *kind = sk == SK_STREAM ? AC_SAMPLER_STREAM : AC_SAMPLER_GLOBAL;
+    *concurrent = std::min<int64_t>(chains, static_cast<int64_t>(L.grid) * WAVE);
+    return AC_OK;
 }
 
 extern "C" ac_status ac_eval_batch(const ac_graph *g, ac_dtype dtype, const double *theta, int32_t P,

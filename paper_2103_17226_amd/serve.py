@@ -486,14 +486,17 @@ class GraphExecutor:
     # device-time model for admission: a lone tile of 64 elements walks the DAG
     # level by level (latency per node step), a full chip streams node steps
     # at a measured rate; a request takes the larger of the two
-    NODE_STEP_LATENCY = {"stream": 2.0e-7, "lds": 2.0e-8, "eval": 2.5e-7}
+    NODE_STEP_LATENCY = {"stream": 2.0e-7, "global": 3.0e-7, "lds": 2.0e-8, "eval": 2.5e-7}
     NODE_STEP_RATE = {"sample": 1.0e11, "eval": 1.7e11}
 
     def cost(self, req: Request) -> float:
         """Estimated device seconds of a request (for ``max_seconds``).
         Sampling: about n/2 + 1 rounds per sweep (a round ends at the first
-        change) of three passes (up, down, leaves) over the DAG per chain;
-        amplitudes: one pass per row, three with a gradient."""
+        change) of three passes (up, down, leaves) over the DAG per chain, at
+        the per-step latency of the kernel the library picks for this many
+        chains, once per group of chains it runs at once, or at the chip's
+        node-step rate when that is slower; amplitudes: one pass per row,
+        three with a gradient."""
         g = self.graphs[req.graph]
         info = g.info
         N = float(info["n_internal"])
@@ -502,8 +505,9 @@ class GraphExecutor:
             steps = 3.0 * N * (req.burn_in + 1) * (info["n_qubits"] // 2 + 1)
             if req.grad:
                 steps += 3.0 * N
-            small = N <= 6000 and chains <= 4096
-            lat = steps * self.NODE_STEP_LATENCY["lds" if small else "stream"]
+            kind, conc = g.sample_shape(req.dtype, chains)
+            groups = -(-chains // max(conc, 1))
+            lat = groups * steps * self.NODE_STEP_LATENCY[kind]
             return max(lat, chains * steps / self.NODE_STEP_RATE["sample"])
         passes = 3.0 if req.grad else 1.0
         lat = passes * N * self.NODE_STEP_LATENCY["eval"]

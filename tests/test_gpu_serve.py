@@ -192,3 +192,21 @@ def test_session_resumes_its_resident_chains():
     assert np.array_equal(r1["samples"], p1["samples"].cpu().numpy())
     assert np.array_equal(r2["samples"], p2["samples"].cpu().numpy())
     assert np.array_equal(r2["cost"], p2["cost"].cpu().numpy())
+
+
+def test_sample_shape_reports_the_kernel_sample_runs(monkeypatch):
+    """ac_sample_shape (used by the serving cost model) names the kernel
+    ac_sample picks and how many chains it advances at once."""
+    note("sampler shape query")
+    g = graph(W.config(2, small=True)["circuit"])
+    kind, conc = g.sample_shape("c64", 64)
+    assert kind == "lds" and 1 <= conc <= 64
+    kind, conc = g.sample_shape("c64", 1_024_000)
+    assert kind == "stream" and conc % 64 == 0 and 64 <= conc < 1_024_000
+    assert g.sample_shape("c128", 1_024_000)[0] == "stream"
+    for forced in ("global", "stream", "lds"):
+        monkeypatch.setenv("QKC_SAMPLE_KERNEL", forced)
+        assert g.sample_shape("c64", 4096)[0] == forced
+    monkeypatch.delenv("QKC_SAMPLE_KERNEL")
+    with pytest.raises(Exception):
+        g.sample_shape("c64", 0)
