@@ -32,7 +32,7 @@ hipError_t launch_grad(const DevGraph &g, int grid, const double *theta, const i
 template <typename T>
 hipError_t launch_sample(const DevGraph &g, int grid, const double *theta, const void *wfix, void *vals,
                          size_t per_wg_elems, const SampleArgs &a, hipStream_t st);
-size_t lds_bytes(const DevGraph &g, size_t csize);
+size_t lds_bytes(const DevGraph &g);
 template <typename T>
 size_t sample_lds_chain_bytes(const DevGraph &g, const LdsPlan &lp);
 size_t sample_lds_meta_bytes(const LdsPlan &lp);
@@ -806,8 +806,8 @@ bool make_layout(const ac_graph *g, ac_dtype dt, int64_t batch, int op, Layout &
     if (batch > 0 && grid < 1) grid = 1;
     Layout L;
     size_t off = 0;
-    L.wfix_off = off;
-    off += align256(static_cast<size_t>(std::max(d.S, 1)) * cs);
+    L.wfix_off = off;                                    // fixed weights, 16 bytes each for both dtypes
+    off += align256(static_cast<size_t>(std::max(d.S, 1)) * 16);
     L.contrib_off = off;
     if (op == AC_OP_GRAD) off += align256(static_cast<size_t>(std::max<int64_t>(batch, 1)) * std::max(d.K, 1) * 8);
     L.tiles_off = off;
@@ -876,7 +876,7 @@ extern "C" ac_status ac_eval_batch(const ac_graph *g, ac_dtype dtype, const doub
                                    void *stream) {
     ac_status s = check_common(g, dtype, theta, P, "ac_eval_batch");
     if (s != AC_OK) return s;
-    if (lds_bytes(g->dev, dtype == AC_C64 ? 8 : 16) > LDS_LIMIT)
+    if (lds_bytes(g->dev) > LDS_LIMIT)
         return fail(AC_ERR_UNSUPPORTED, "ac_eval_batch: evidence and angle tables exceed LDS");
     if (B < 0) return fail(AC_ERR_INVALID_ARG, "ac_eval_batch: B < 0");
     if (B == 0) return AC_OK;
@@ -912,7 +912,7 @@ extern "C" ac_status ac_grad_batch(const ac_graph *g, ac_dtype dtype, const doub
                                    void *ws, size_t ws_bytes, void *stream) {
     ac_status s = check_common(g, dtype, theta, P, "ac_grad_batch");
     if (s != AC_OK) return s;
-    if (lds_bytes(g->dev, dtype == AC_C64 ? 8 : 16) > LDS_LIMIT)
+    if (lds_bytes(g->dev) > LDS_LIMIT)
         return fail(AC_ERR_UNSUPPORTED, "ac_grad_batch: evidence and angle tables exceed LDS");
     if (B < 0) return fail(AC_ERR_INVALID_ARG, "ac_grad_batch: B < 0");
     if (mode < 0 || mode > 2) return fail(AC_ERR_INVALID_ARG, "ac_grad_batch: bad mode %d", mode);
@@ -960,7 +960,7 @@ extern "C" ac_status ac_sample(const ac_graph *g, ac_dtype dtype, const double *
                                size_t ws_bytes, void *stream) {
     ac_status s = check_common(g, dtype, theta, P, "ac_sample");
     if (s != AC_OK) return s;
-    if (lds_bytes(g->dev, dtype == AC_C64 ? 8 : 16) + static_cast<size_t>(g->dev.S) * (dtype == AC_C64 ? 8 : 16) >
+    if (lds_bytes(g->dev) + static_cast<size_t>(g->dev.S) * (dtype == AC_C64 ? 8 : 16) >
         LDS_LIMIT)
         return fail(AC_ERR_UNSUPPORTED, "ac_sample: evidence and weight tables exceed LDS");
     if (!cfg) return fail(AC_ERR_INVALID_ARG, "ac_sample: null cfg");

@@ -30,6 +30,46 @@ __device__ __forceinline__ cplx<T> cadd(cplx<T> a, cplx<T> b) {
     return {a.re + b.re, a.im + b.im};
 }
 
+// A leaf weight as the passes use it, 16 bytes for both dtypes.  complex128
+// keeps it exact; complex64 keeps the FP64 weight as hi + lo, two FP32
+// parts, and the upward pass multiplies by both: a weight rounded to FP32
+// once and shared by hundreds of channels (one damping strength, one angle)
+// would otherwise put the same relative error into every factor of a path.
+template <typename T>
+struct Weight;
+template <>
+struct Weight<double> {
+    cplx<double> w;
+};
+template <>
+struct Weight<float> {
+    cplx<float> hi, lo;
+};
+
+__device__ inline void make_weight(double re, double im, Weight<double> &w) { w.w = {re, im}; }
+__device__ inline void make_weight(double re, double im, Weight<float> &w) {
+    const float hr = static_cast<float>(re), hi = static_cast<float>(im);
+    w.hi = {hr, hi};
+    w.lo = {static_cast<float>(re - static_cast<double>(hr)), static_cast<float>(im - static_cast<double>(hi))};
+}
+// the weight rounded to the pass dtype (what every pass but the upward one uses)
+__device__ __forceinline__ cplx<double> wval(const Weight<double> &w) { return w.w; }
+__device__ __forceinline__ cplx<float> wval(const Weight<float> &w) { return w.hi; }
+// a * weight: exact weight, one rounding per product in the pass dtype
+__device__ __forceinline__ cplx<double> wmul(cplx<double> a, const Weight<double> &w) { return cmul(a, w.w); }
+__device__ __forceinline__ cplx<float> wmul(cplx<float> a, const Weight<float> &w) {
+    const float re = __builtin_fmaf(a.re, w.lo.re, -a.im * w.lo.im);
+    const float im = __builtin_fmaf(a.re, w.lo.im, a.im * w.lo.re);
+    return {__builtin_fmaf(a.re, w.hi.re, __builtin_fmaf(-a.im, w.hi.im, re)),
+            __builtin_fmaf(a.re, w.hi.im, __builtin_fmaf(a.im, w.hi.re, im))};
+}
+// the weight in FP64 (sum nodes accumulate in FP64)
+__device__ __forceinline__ cplx<double> wsum(const Weight<double> &w) { return w.w; }
+__device__ __forceinline__ cplx<double> wsum(const Weight<float> &w) {
+    return {static_cast<double>(w.hi.re) + static_cast<double>(w.lo.re),
+            static_cast<double>(w.hi.im) + static_cast<double>(w.lo.im)};
+}
+
 __device__ __forceinline__ uint32_t uniform_u32(uint32_t v) {
     return __builtin_amdgcn_readfirstlane(v);
 }
@@ -91,13 +131,15 @@ __device__ inline void slot_dvalue(const SlotDesc &s, const double *theta_row, d
 
 // One thread per slot: weights that do not depend on theta.
 template <typename T>
-__global__ void k_fixed_slots(DevGraph g, const double *noise, cplx<T> *wfix) {
+__global__ void k_fixed_slots(DevGraph g, const double *noise, Weight<T> *wfix) {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= g.S) return;
     const double *nz = noise ? noise : g.noise_default;
     double re = 0.0, im = 0.0;
     if (s >= g.S_ang) slot_value(g.slots[s], nullptr, nz, re, im);
-    wfix[s] = {static_cast<T>(re), static_cast<T>(im)};
+    Weight<T> w;
+    make_weight(re, im, w);
+    wfix[s] = w;
 }
 
 // ---------------------------------------------------------------------------
@@ -114,10 +156,10 @@ __device__ __forceinline__ uint32_t batch_nodes(uint32_t width, int nwaves) {
 template <typename T>
 struct Tile {
     DevGraph g;
-    cplx<T> *val;            // [N][64] node values of this tile (global)
-    const uint64_t *ev;      // [W][64] evidence words (LDS)
-    const cplx<T> *ang;      // [S_ang][64] angle weights (LDS)
-    const cplx<T> *wfix;     // [S] fixed weights (global, uniform reads)
+    cplx<T> *val;                // [N][64] node values of this tile (global)
+    const uint64_t *ev;          // [W][64] evidence words (LDS)
+    const Weight<T> *ang;        // [S_ang][64] angle weights (LDS)
+    const Weight<T> *wfix;       // [S] fixed weights (global, uniform reads)
     int lane;
 
     __device__ __forceinline__ bool ind_hit(uint32_t r) const {
@@ -129,30 +171,34 @@ struct Tile {
         return x == static_cast<uint64_t>(u);
     }
 
-    __device__ __forceinline__ cplx<T> slot(uint32_t s) const {
+    __device__ __forceinline__ Weight<T> slot(uint32_t s) const {
         if (s < static_cast<uint32_t>(g.S_ang)) return ang[s * WAVE + lane];
         return wfix[s];
     }
 
     // selector leaf: the weight of its variable's current value
-    __device__ __forceinline__ cplx<T> sel(uint32_t q) const {
+    __device__ __forceinline__ Weight<T> sel(uint32_t q) const {
         const uint32_t *rec = g.sel + static_cast<size_t>(q) * SEL_REC;
         const uint32_t fld = rec[0];
         const uint32_t word = fld >> 8, shift = (fld >> 2) & 63u, width = (fld & 3u) + 1u;
         const uint32_t k = static_cast<uint32_t>((ev[word * WAVE + lane] >> shift) & ((1ull << width) - 1ull));
         const uint32_t s0 = rec[1], s1 = rec[2], s2 = rec[3], s3 = rec[4];
         const uint32_t s = k == 0 ? s0 : k == 1 ? s1 : k == 2 ? s2 : k == 3 ? s3 : NO_SLOT;
-        if (s == NO_SLOT) return {T(0), T(0)};
+        if (s == NO_SLOT) return Weight<T>{};
         return wfix[s];
     }
 
-    // value of a child reference (leaves computed on the fly)
+    // weight of a slot or selector leaf reference
+    __device__ __forceinline__ Weight<T> weight(uint32_t r) const {
+        return (r >> 30) == TAG_SEL ? sel(r & REF_MASK) : slot(r & REF_MASK);
+    }
+
+    // value of a child reference in the pass dtype (leaves computed on the fly)
     __device__ __forceinline__ cplx<T> child(uint32_t r) const {
-        uint32_t tag = r >> 30;
+        const uint32_t tag = r >> 30;
         if (tag == TAG_NODE) return val[(r & REF_MASK) * WAVE + lane];
         if (tag == TAG_IND) return {ind_hit(r) ? T(1) : T(0), T(0)};
-        if (tag == TAG_SEL) return sel(r & REF_MASK);
-        return slot(r & REF_MASK);
+        return wval(weight(r));
     }
 
     // Row of a node child, or row 0 (always present) for a leaf, so that a
@@ -167,47 +213,8 @@ struct Tile {
         return (r >> 30) == TAG_NODE ? val[static_cast<size_t>(r & REF_MASK) * WAVE + lane] : cplx<T>{T(0), T(0)};
     }
 
-    // Sum nodes accumulate in FP64 (for the complex64 path too: wide sums
-    // would otherwise lose ~k * 2^-24 relative accuracy); products run in T.
-    // Children are taken in groups of KC whose row loads are issued together;
-    // the terms are still added (multiplied) one by one in child order.
-    __device__ __forceinline__ cplx<T> eval_node(uint32_t i) const {
-        constexpr int KC = 4;
-        const uint32_t e0 = g.row_ptr[i], e1 = g.row_ptr[i + 1];
-        const bool sum = g.op[i] == 0;
-        double sr = 0.0, si = 0.0;
-        cplx<T> acc{T(1), T(0)};
-        for (uint32_t eb = e0; eb < e1; eb += KC) {
-            uint32_t r[KC];
-            cplx<T> v[KC];
-#pragma unroll
-            for (int j = 0; j < KC; ++j) r[j] = eb + j < e1 ? g.col[eb + j] : IDENT_REF;
-#pragma unroll
-            for (int j = 0; j < KC; ++j) v[j] = eb_guard(r[j]);
-#pragma unroll
-            for (int j = 0; j < KC; ++j) {
-                if (eb + j >= e1) break;
-                const uint32_t tag = r[j] >> 30;
-                if (tag == TAG_IND) {
-                    const bool hit = ind_hit(r[j]);
-                    if (sum) sr += hit ? 1.0 : 0.0;
-                    else if (!hit) acc = {T(0), T(0)};
-                    continue;
-                }
-                const cplx<T> c = tag == TAG_NODE ? v[j] : child(r[j]);
-                if (sum) {
-                    sr += static_cast<double>(c.re);
-                    si += static_cast<double>(c.im);
-                } else {
-                    acc = cmul(acc, c);
-                }
-            }
-        }
-        return sum ? cplx<T>{static_cast<T>(sr), static_cast<T>(si)} : acc;
-    }
-
     // product of the siblings of edge e inside parent p (1 for a sum parent),
-    // children loaded in groups like eval_node
+    // children loaded in groups like the upward pass
     __device__ __forceinline__ cplx<T> sibling_product(uint32_t p, uint32_t e) const {
         constexpr int KC = 4;
         cplx<T> acc{T(1), T(0)};
@@ -239,8 +246,9 @@ struct Tile {
     // upward pass over all levels (all waves of the block).  A wave takes KB
     // consecutive nodes of a level at a time and walks their children
     // (contiguous in col) in groups of KC whose rows are loaded together;
-    // each node is summed (FP64) or multiplied in child order exactly as in
-    // eval_node, and stored when its last child is in.
+    // each node is summed (FP64) or multiplied (pass dtype, leaf weights
+    // applied at full precision by wmul) in child order and stored when its
+    // last child is in.
     __device__ void forward(int wave, int nwaves) {
         constexpr int KC = 4;
         for (int l = 0; l < g.L; ++l) {
@@ -282,12 +290,22 @@ struct Tile {
                             else if (!hit) acc = {T(0), T(0)};
                             continue;
                         }
-                        const cplx<T> c = tag == TAG_NODE ? v[j] : child(r[j]);
-                        if (sum) {
-                            sr += static_cast<double>(c.re);
-                            si += static_cast<double>(c.im);
+                        if (tag == TAG_NODE) {
+                            if (sum) {
+                                sr += static_cast<double>(v[j].re);
+                                si += static_cast<double>(v[j].im);
+                            } else {
+                                acc = cmul(acc, v[j]);
+                            }
                         } else {
-                            acc = cmul(acc, c);
+                            const Weight<T> w = weight(r[j]);
+                            if (sum) {
+                                const cplx<double> d = wsum(w);
+                                sr += d.re;
+                                si += d.im;
+                            } else {
+                                acc = wmul(acc, w);
+                            }
                         }
                     }
                 }
@@ -442,7 +460,7 @@ struct Tile {
             for (uint32_t u = 0; u < dom && u < static_cast<uint32_t>(SEL_DOM); ++u) {
                 const uint32_t sl = rec[1 + u];
                 if (sl == NO_SLOT) continue;
-                const cplx<T> t = cmul(A, wfix[sl]);
+                const cplx<T> t = cmul(A, wval(wfix[sl]));
                 cplx<T> &o = out[(base + u) * ostride];
                 o = cadd(o, t);
             }
@@ -457,7 +475,7 @@ struct Tile {
 
 // Stage one tile's evidence and angle weights into LDS.
 template <typename T>
-__device__ bool stage_tile(const DevGraph &g, uint64_t *ev_s, cplx<T> *ang_s, const uint64_t *evidence,
+__device__ bool stage_tile(const DevGraph &g, uint64_t *ev_s, Weight<T> *ang_s, const uint64_t *evidence,
                            const int32_t *param_of, int P, const double *theta, int64_t b, bool valid,
                            int lane, int wave, int nwaves) {
     for (int w = wave; w < g.W; w += nwaves) ev_s[w * WAVE + lane] = valid ? evidence[b * g.W + w] : 0ull;
@@ -468,7 +486,7 @@ __device__ bool stage_tile(const DevGraph &g, uint64_t *ev_s, cplx<T> *ang_s, co
     for (int s = wave; s < g.S_ang; s += nwaves) {
         double re, im;
         slot_value(g.slots[s], trow, nullptr, re, im);
-        ang_s[s * WAVE + lane] = {static_cast<T>(re), static_cast<T>(im)};
+        make_weight(re, im, ang_s[s * WAVE + lane]);
     }
     return in_range;
 }
@@ -482,12 +500,12 @@ __device__ bool stage_tile(const DevGraph &g, uint64_t *ev_s, cplx<T> *ang_s, co
 // 6 waves 74 ms, 8 waves 66 ms)
 template <typename T>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 1, 8))) void k_eval(DevGraph g, const double *theta, const int32_t *param_of, int P,
-                                                const uint64_t *evidence, int64_t B, const cplx<T> *wfix,
+                                                const uint64_t *evidence, int64_t B, const Weight<T> *wfix,
                                                 cplx<T> *vals, size_t per_wg, cplx<T> *amp_out,
                                                 double *prob_out) {
     extern __shared__ __align__(16) unsigned char smem[];
     uint64_t *ev_s = reinterpret_cast<uint64_t *>(smem);
-    cplx<T> *ang_s = reinterpret_cast<cplx<T> *>(smem + static_cast<size_t>(g.W) * WAVE * 8);
+    Weight<T> *ang_s = reinterpret_cast<Weight<T> *>(smem + static_cast<size_t>(g.W) * WAVE * 8);
     const int lane = threadIdx.x & (WAVE - 1);
     const int wave = static_cast<int>(uniform_u32(threadIdx.x / WAVE));
     const int nwaves = blockDim.x / WAVE;
@@ -521,14 +539,14 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T)
 // 16-qubit noisy QAOA gradients over 262,144 elements 283 -> 255 ms
 template <typename T>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 1, 8))) void k_grad(DevGraph g, const double *theta, const int32_t *param_of, int P,
-                                                const uint64_t *evidence, int64_t B, const cplx<T> *wfix,
+                                                const uint64_t *evidence, int64_t B, const Weight<T> *wfix,
                                                 cplx<T> *vals, size_t per_wg, int mode,
                                                 const cplx<T> *cotangent, const double *weight,
                                                 double *contrib, cplx<T> *amp_out,
                                                 cplx<T> *dfdtheta_out, cplx<T> *dind_out) {
     extern __shared__ __align__(16) unsigned char smem[];
     uint64_t *ev_s = reinterpret_cast<uint64_t *>(smem);
-    cplx<T> *ang_s = reinterpret_cast<cplx<T> *>(smem + static_cast<size_t>(g.W) * WAVE * 8);
+    Weight<T> *ang_s = reinterpret_cast<Weight<T> *>(smem + static_cast<size_t>(g.W) * WAVE * 8);
     const int lane = threadIdx.x & (WAVE - 1);
     const int wave = static_cast<int>(uniform_u32(threadIdx.x / WAVE));
     const int nwaves = blockDim.x / WAVE;
@@ -643,11 +661,11 @@ constexpr uint64_t INIT_SWEEP = 0xFFFFFFFFull;
 
 
 template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_sample(DevGraph g, const double *theta, const cplx<T> *wfix,
+__global__ __launch_bounds__(BLOCK) void k_sample(DevGraph g, const double *theta, const Weight<T> *wfix,
                                                   cplx<T> *vals, size_t per_wg, SampleArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     uint64_t *ev_s = reinterpret_cast<uint64_t *>(smem);
-    cplx<T> *ang_s = reinterpret_cast<cplx<T> *>(smem + static_cast<size_t>(g.W) * WAVE * 8);
+    Weight<T> *ang_s = reinterpret_cast<Weight<T> *>(smem + static_cast<size_t>(g.W) * WAVE * 8);
     __shared__ int64_t s_chain[WAVE];
     __shared__ int32_t s_pos[WAVE];
     __shared__ uint32_t s_sweep[WAVE];
@@ -701,7 +719,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(DevGraph g, const double *thet
         for (int s = wave; s < g.S_ang; s += nwaves) {
             double re, im;
             slot_value(g.slots[s], trow, nullptr, re, im);
-            ang_s[s * WAVE + lane] = {static_cast<T>(re), static_cast<T>(im)};
+            make_weight(re, im, ang_s[s * WAVE + lane]);
         }
         __syncthreads();
         t.forward(wave, nwaves);
@@ -1050,7 +1068,7 @@ struct StreamTile {
 // 8-qubit samples)
 template <typename T>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 1, 8))) void k_sample_stream(DevGraph g, LdsPlan lp, const double *theta,
-                                                         const cplx<T> *wfix, cplx<T> *vals, size_t per_wg,
+                                                         const Weight<T> *wfix, cplx<T> *vals, size_t per_wg,
                                                          SampleArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     uint64_t *ev_s = reinterpret_cast<uint64_t *>(smem);
@@ -1067,7 +1085,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T)
     const int nwaves = blockDim.x / WAVE;
     cplx<T> *val = vals + per_wg * blockIdx.x;
     cplx<T> *D = val + 2 * static_cast<size_t>(lp.N) * WAVE;    // [n_ind][64]
-    for (int s2 = threadIdx.x; s2 < g.S; s2 += blockDim.x) fix_s[s2] = wfix[s2];
+    for (int s2 = threadIdx.x; s2 < g.S; s2 += blockDim.x) fix_s[s2] = wval(wfix[s2]);
     const uint32_t N = static_cast<uint32_t>(lp.N);
     StreamTile<T> t{g, RowBuf<T>(val, per_wg / WAVE, lane), N, 2 * N, ev_s, ang_s, fix_s, lane};
     const int64_t stride = static_cast<int64_t>(gridDim.x) * WAVE;
@@ -1671,21 +1689,32 @@ hipError_t launch_fixed_slots(const DevGraph &g, const double *noise, void *wfix
     int blocks = (g.S + threads - 1) / threads;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_fixed_slots<T>, dim3(blocks), dim3(threads), 0, st, g, noise,
-                       reinterpret_cast<cplx<T> *>(wfix));
+                       reinterpret_cast<Weight<T> *>(wfix));
     return hipGetLastError();
 }
 
-size_t lds_bytes(const DevGraph &g, size_t csize) {
-    return static_cast<size_t>(g.W) * WAVE * 8 + static_cast<size_t>(g.S_ang) * WAVE * csize;
+static_assert(sizeof(Weight<float>) == 16 && sizeof(Weight<double>) == 16, "weights are 16 bytes");
+
+// dynamic LDS of the tile kernels: evidence words and angle weights of a tile
+size_t lds_bytes(const DevGraph &g) {
+    return static_cast<size_t>(g.W) * WAVE * 8 + static_cast<size_t>(g.S_ang) * WAVE * sizeof(Weight<float>);
+}
+
+// dynamic LDS of the streaming sampler: evidence words, angle weights and the
+// fixed weights, in the pass dtype
+template <typename T>
+size_t stream_lds_bytes(const DevGraph &g) {
+    return static_cast<size_t>(g.W) * WAVE * 8 + static_cast<size_t>(g.S_ang) * WAVE * sizeof(cplx<T>) +
+           static_cast<size_t>(g.S) * sizeof(cplx<T>);
 }
 
 template <typename T>
 hipError_t launch_eval(const DevGraph &g, int grid, const double *theta, const int32_t *param_of, int P,
                        const uint64_t *evidence, int64_t B, const void *wfix, void *vals, size_t per_wg_elems,
                        void *amp_out, double *prob_out, hipStream_t st) {
-    size_t lds = lds_bytes(g, sizeof(cplx<T>));
+    size_t lds = lds_bytes(g);
     hipLaunchKernelGGL(k_eval<T>, dim3(grid), dim3(BLOCK), lds, st, g, theta, param_of, P, evidence, B,
-                       reinterpret_cast<const cplx<T> *>(wfix), reinterpret_cast<cplx<T> *>(vals),
+                       reinterpret_cast<const Weight<T> *>(wfix), reinterpret_cast<cplx<T> *>(vals),
                        per_wg_elems, reinterpret_cast<cplx<T> *>(amp_out), prob_out);
     return hipGetLastError();
 }
@@ -1695,9 +1724,9 @@ hipError_t launch_grad(const DevGraph &g, int grid, const double *theta, const i
                        const uint64_t *evidence, int64_t B, const void *wfix, void *vals, size_t per_wg_elems,
                        int mode, const void *cotangent, const double *weight, double *contrib, int P,
                        double *grad, void *amp_out, void *dfdtheta_out, void *dind_out, hipStream_t st) {
-    size_t lds = lds_bytes(g, sizeof(cplx<T>));
+    size_t lds = lds_bytes(g);
     hipLaunchKernelGGL(k_grad<T>, dim3(grid), dim3(BLOCK), lds, st, g, theta, param_of, P, evidence, B,
-                       reinterpret_cast<const cplx<T> *>(wfix), reinterpret_cast<cplx<T> *>(vals),
+                       reinterpret_cast<const Weight<T> *>(wfix), reinterpret_cast<cplx<T> *>(vals),
                        per_wg_elems, mode, reinterpret_cast<const cplx<T> *>(cotangent), weight, contrib,
                        reinterpret_cast<cplx<T> *>(amp_out), reinterpret_cast<cplx<T> *>(dfdtheta_out),
                        reinterpret_cast<cplx<T> *>(dind_out));
@@ -1713,9 +1742,9 @@ hipError_t launch_grad(const DevGraph &g, int grid, const double *theta, const i
 template <typename T>
 hipError_t launch_sample(const DevGraph &g, int grid, const double *theta, const void *wfix, void *vals,
                          size_t per_wg_elems, const SampleArgs &a, hipStream_t st) {
-    size_t lds = lds_bytes(g, sizeof(cplx<T>));
+    size_t lds = lds_bytes(g);
     hipLaunchKernelGGL(k_sample<T>, dim3(grid), dim3(BLOCK), lds, st, g, theta,
-                       reinterpret_cast<const cplx<T> *>(wfix), reinterpret_cast<cplx<T> *>(vals),
+                       reinterpret_cast<const Weight<T> *>(wfix), reinterpret_cast<cplx<T> *>(vals),
                        per_wg_elems, a);
     return hipGetLastError();
 }
@@ -1757,16 +1786,15 @@ hipError_t launch_sample_lds(const DevGraph &g, const LdsPlan &lp, int cpw, int 
 // threads per workgroup.
 template <typename T>
 int resident_blocks(const DevGraph &g, int which, int block) {
-    const size_t base = lds_bytes(g, sizeof(cplx<T>));
     const void *fn = nullptr;
-    size_t lds = base;
+    size_t lds = lds_bytes(g);
     switch (which) {
         case 0: fn = reinterpret_cast<const void *>(&k_eval<T>); break;
         case 1: fn = reinterpret_cast<const void *>(&k_grad<T>); break;
         case 2: fn = reinterpret_cast<const void *>(&k_sample<T>); break;
         case 3:
             fn = reinterpret_cast<const void *>(&k_sample_stream<T>);
-            lds = base + static_cast<size_t>(g.S) * sizeof(cplx<T>);
+            lds = stream_lds_bytes<T>(g);
             break;
         default: return 1;
     }
@@ -1790,18 +1818,18 @@ hipError_t launch_sample_stream(const DevGraph &g, const LdsPlan &lp, int grid, 
                                 const void *wfix, void *vals, size_t per_wg_elems, const SampleArgs &a,
                                 hipStream_t st) {
     if (block < WAVE || block > BLOCK || block % WAVE != 0) return hipErrorInvalidValue;
-    size_t lds = lds_bytes(g, sizeof(cplx<T>)) + static_cast<size_t>(g.S) * sizeof(cplx<T>);
+    size_t lds = stream_lds_bytes<T>(g);
     hipLaunchKernelGGL(k_sample_stream<T>, dim3(grid), dim3(block), lds, st, g, lp, theta,
-                       reinterpret_cast<const cplx<T> *>(wfix), reinterpret_cast<cplx<T> *>(vals), per_wg_elems, a);
+                       reinterpret_cast<const Weight<T> *>(wfix), reinterpret_cast<cplx<T> *>(vals), per_wg_elems, a);
     return hipGetLastError();
 }
+template hipError_t launch_fixed_slots<float>(const DevGraph &, const double *, void *, hipStream_t);
+template hipError_t launch_fixed_slots<double>(const DevGraph &, const double *, void *, hipStream_t);
 template hipError_t launch_sample_stream<float>(const DevGraph &, const LdsPlan &, int, int, const double *,
                                                 const void *, void *, size_t, const SampleArgs &, hipStream_t);
 template hipError_t launch_sample_stream<double>(const DevGraph &, const LdsPlan &, int, int, const double *,
                                                  const void *, void *, size_t, const SampleArgs &, hipStream_t);
 
-template hipError_t launch_fixed_slots<float>(const DevGraph &, const double *, void *, hipStream_t);
-template hipError_t launch_fixed_slots<double>(const DevGraph &, const double *, void *, hipStream_t);
 template hipError_t launch_eval<float>(const DevGraph &, int, const double *, const int32_t *, int, const uint64_t *,
                                        int64_t, const void *, void *, size_t, void *, double *, hipStream_t);
 template hipError_t launch_eval<double>(const DevGraph &, int, const double *, const int32_t *, int, const uint64_t *,

@@ -135,15 +135,16 @@ def test_config3_amplitudes_seeded_subset():
     pick = np.sort(rng.choice(B, size=12, replace=False))
     ref = np.array([oracle_amplitudes(circ, cfg["theta"][cfg["param_of"][b]], vals[b:b + 1])[0] for b in pick])
     assert np.max(np.abs(a128[pick] - ref)) <= 1e-12
-    # complex64 vs complex128 on the whole batch, per result.  These are
-    # branch probabilities |f(x,k)|^2 of random noisy branches, not outcome
-    # probabilities: a branch is a product of ~600 channel weights through a
-    # 51-level DAG, and FP32 storage of node values plus the fixed rounding of
-    # weights shared by ~300 channels bound the relative error by about
-    # 2 * (300 + 51) * 2^-24 ~ 4e-5; the test uses 1e-4.
+    # complex64 vs complex128 on the whole batch, per result, at the 1e-5 of
+    # the probability rule.  These are branch probabilities |f(x,k)|^2: a
+    # branch is a product of ~600 channel weights through a 51-level DAG.
+    # The upward pass applies every weight at full precision (FP32 hi + lo),
+    # so only the per-node FP32 roundings remain, which do not add up
+    # coherently (a weight rounded once and shared by ~300 channels would
+    # give ~2e-5).
     p128 = np.abs(a128) ** 2
-    ok, worst = prob_ok(p64, p128, rel=1e-4)
-    note(f"  c64 vs c128 worst rel err {worst:.2e} (bound 1e-4)")
+    ok, worst = prob_ok(p64, p128, rel=1e-5)
+    note(f"  c64 vs c128 worst rel err {worst:.2e} (bound 1e-5)")
     assert ok
 
 
