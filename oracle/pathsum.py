@@ -69,3 +69,25 @@ def amplitudes_from_histogram(hist, n, n_edges, gammas, betas):
 def qaoa_p1_amplitude(n, edges, x_index, gammas, betas):
     hist = path_histogram(n, edges, x_index)
     return amplitudes_from_histogram(hist, n, len(edges), gammas, betas)
+
+
+def ring_amplitude(n, x_index, gamma, beta):
+    """f(x) of noise-free QAOA p=1 on the n-ring (edges (i, i+1 mod n), n >= 3)
+    at any n: the same closed path sum as above,
+    f(x) = 2^{-n/2} sum_z prod_edges exp(-i g (1 - 2 [z_a != z_b])) prod_i R(x_i, z_i)
+    with R(a, a) = cos b and R(a, not a) = -i sin b, summed over the paths z
+    of the ring by transfer matrices: M_i[a][c] = R(x_i, a) exp(-i g (1 - 2 [a != c]))
+    links z_i = a to z_{i+1} = c, and the sum is the trace of M_0 ... M_{n-1}.
+    Exact in complex128 up to rounding; x_index holds bit i = x_i (n <= 64)."""
+    if n < 3:
+        raise ValueError("the ring needs n >= 3")
+    x = int(x_index)
+    cb, sb = np.cos(beta), -1j * np.sin(beta)
+    bond = np.array([[np.exp(-1j * gamma), np.exp(1j * gamma)],
+                     [np.exp(1j * gamma), np.exp(-1j * gamma)]])
+    prod = np.eye(2, dtype=np.complex128)
+    for i in range(n):
+        xi = (x >> i) & 1
+        r = np.array([cb if xi == 0 else sb, sb if xi == 0 else cb])   # R(x_i, z_i = 0 / 1)
+        prod = prod @ (r[:, None] * bond)
+    return complex(2.0 ** (-n / 2.0) * np.trace(prod))

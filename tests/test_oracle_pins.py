@@ -190,6 +190,27 @@ def test_pathsum_matches_statevector(n, seed):
             assert abs(f[t] - sim.statevector(c, th)[x]) < 1e-14
 
 
+def test_ring_transfer_matrix_amplitude_matches_path_sum_and_state_vector():
+    """The ring transfer-matrix form against the brute-force path histogram
+    (n <= 12) and the state vector (n <= 10); and its gamma = 0 closed form
+    (a product state: |f|^2 = 2^-n) at n = 64."""
+    rng = np.random.default_rng(17)
+    for n in (3, 4, 7, 10, 12):
+        edges = W.ring_graph(n)
+        circ = W.qaoa_maxcut(n, edges, 1)
+        g, b = rng.uniform(0, 2 * np.pi, size=2)
+        psi = sim.statevector(circ, np.array([g, b])) if n <= 10 else None
+        for x in rng.integers(0, 1 << n, size=4):
+            f = pathsum.ring_amplitude(n, int(x), g, b)
+            ref = pathsum.qaoa_p1_amplitude(n, edges, int(x), [g], [b])[0]
+            assert abs(f - ref) <= 1e-13
+            if psi is not None:
+                assert abs(f - psi[int(x)]) <= 1e-13
+    for x in (0, (1 << 64) - 1, 0x5A5A5A5A5A5A5A5A):
+        f = pathsum.ring_amplitude(64, x, 0.0, 0.3)
+        assert abs(abs(f) ** 2 - 2.0 ** -64) <= 1e-30
+
+
 def test_pathsum_closed_forms_large_n():
     n = 24
     edges = W.random_regular_graph(n, 3, 5)
