@@ -2,9 +2,9 @@
 evidence word an output.  Noise-free QAOA p=1 on the 64-ring (1140 internal
 nodes, 130 levels): amplitudes of random 64-bit outcomes against the ring's
 transfer-matrix path sum (complex128 within 1e-12, complex64 probabilities
-within a bound derived from the DAG depth), and Gibbs samples against the exact p=1 light cone (<Z_i Z_j>
-of every edge), bit-flip symmetry (<Z_i> = 0) and the MaxCut cost of every
-sample, on each sampler kernel."""
+within a bound derived from the DAG depth), and Gibbs samples against the
+exact p=1 light cone (<Z_i Z_j> of every edge), bit-flip symmetry (<Z_i> = 0)
+and the MaxCut cost of every sample, on each sampler kernel."""
 import numpy as np
 import pytest
 
