@@ -368,7 +368,7 @@ struct Tile {
     // Edges from products of three or more children (rare) are added to the
     // stored adjoints afterwards by the same wave.
     __device__ void backward(cplx<T> *adj, int wave, int nwaves) const {
-        constexpr int KE = 4;
+        constexpr int KE = sizeof(T) == 4 ? 8 : 4;
         const uint32_t root = static_cast<uint32_t>(g.root);
         for (int l = g.L - 1; l >= 0; --l) {
             const uint32_t n0 = g.level_ptr[l], n1 = g.level_ptr[l + 1];
