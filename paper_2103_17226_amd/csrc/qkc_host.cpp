@@ -715,7 +715,6 @@ SampleKernel sample_kernel(const ac_graph *g, ac_dtype dt, int64_t chains) {
     return stream_ok ? SK_STREAM : SK_GLOBAL;
 }
 
-// Launch shape of the LDS-resident sampler, or false if a chain does not fit.
 // Chains per wave and workgroups per CU of the LDS-resident sampler, or false
 // if one chain's state does not fit in a CU's LDS.
 bool lds_capacity(const ac_graph *g, ac_dtype dt, int &cpw, int64_t &per_cu) {

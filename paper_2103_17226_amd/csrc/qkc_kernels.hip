@@ -536,7 +536,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T)
 // ---------------------------------------------------------------------------
 
 // complex64: 6 waves per SIMD (80 VGPRs, a few spilled; 5 waves unbounded):
-// 16-qubit noisy QAOA gradients over 262,144 elements 283 -> 255 ms
+// 16-qubit noisy QAOA gradients over 262,144 elements 283 -> 255 ms (4 waves
+// per workgroup as everywhere; the downward pass's edge groups of eight took
+// it to 252 ms)
 template <typename T>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 1, 8))) void k_grad(DevGraph g, const double *theta, const int32_t *param_of, int P,
                                                 const uint64_t *evidence, int64_t B, const Weight<T> *wfix,
