@@ -279,3 +279,37 @@ def qaoa_p1_zz_lightcone(edges, gamma, beta, i, j):
     ops += [("RX", q, 1, 2.0) for q in range(m)]
     psi = branch_state(_Ops(m, ops), [gamma, beta])
     return zz_expectation(psi, pos[i], pos[j], m)
+
+
+def qaoa_zz_lightcone(edges, theta, i, j):
+    """<Z_i Z_j> after p QAOA layers (theta = [gamma_1, beta_1, ..., gamma_p,
+    beta_p], the circuit of qaoa_p1_zz_lightcone repeated per layer) from the
+    reverse light cone.
+
+    Pulled back through the last layer, Z_i Z_j acts on i, j and their
+    neighbours; through each earlier layer its support grows by one more ring
+    of neighbours, so after p layers it lies in the qubits within graph
+    distance p of {i, j}.  A gate on an edge with an endpoint farther away
+    never meets the operator, and gates inside that set that do not meet it
+    commute with it and cancel, so the value is that of the circuit restricted
+    to that set with every edge inside it (textbook locality of QAOA)."""
+    p = len(theta) // 2
+    und = {tuple(sorted(e)) for e in edges}
+    nbr = {}
+    for a, b in und:
+        nbr.setdefault(a, set()).add(b)
+        nbr.setdefault(b, set()).add(a)
+    cone = {i, j}
+    for _ in range(p):
+        cone |= {b for a in cone for b in nbr.get(a, ())}
+    cone = sorted(cone)
+    pos = {q: k for k, q in enumerate(cone)}
+    inner = sorted(e for e in und if e[0] in pos and e[1] in pos)
+    m = len(cone)
+    ops = [("H", q) for q in range(m)]
+    for layer in range(p):
+        for a, b in inner:
+            ops += [("CNOT", pos[a], pos[b]), ("RZ", pos[b], 2 * layer, 2.0), ("CNOT", pos[a], pos[b])]
+        ops += [("RX", q, 2 * layer + 1, 2.0) for q in range(m)]
+    psi = branch_state(_Ops(m, ops), list(theta))
+    return zz_expectation(psi, pos[i], pos[j], m)

@@ -190,6 +190,24 @@ def test_pathsum_matches_statevector(n, seed):
             assert abs(f[t] - sim.statevector(c, th)[x]) < 1e-14
 
 
+def test_p_layer_light_cone_matches_the_full_state_vector():
+    """<Z_i Z_j> of QAOA with p = 1, 2, 3 from the restricted light-cone
+    circuit against the full state vector, for every edge of 3-regular graphs
+    and rings (on 16 qubits the cones are strict subsets), and against the
+    p = 1 light cone."""
+    rng = np.random.default_rng(23)
+    for n, p, seed in ((10, 1, 1), (10, 2, 2), (16, 2, 3), (16, 2, -1), (14, 3, -1)):
+        edges = W.random_regular_graph(n, 3, seed) if seed >= 0 else W.ring_graph(n)
+        circ = W.qaoa_maxcut(n, edges, p)
+        th = rng.uniform(0, 2 * np.pi, size=2 * p)
+        psi = sim.statevector(circ, th)
+        for (a, b) in edges:
+            full = sim.zz_expectation(psi, a, b, n)
+            assert abs(sim.qaoa_zz_lightcone(edges, th, a, b) - full) <= 1e-12
+            if p == 1:
+                assert abs(sim.qaoa_p1_zz_lightcone(edges, th[0], th[1], a, b) - full) <= 1e-12
+
+
 def test_ring_transfer_matrix_amplitude_matches_path_sum_and_state_vector():
     """The ring transfer-matrix form against the brute-force path histogram
     (n <= 12) and the state vector (n <= 10); and its gamma = 0 closed form
