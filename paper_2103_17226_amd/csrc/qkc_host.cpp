@@ -86,7 +86,8 @@ struct ac_graph {
     int device = 0;
     int n_cu = 0;
     int resident[2][4] = {{1, 1, 1, 1}, {1, 1, 1, 1}};   // [dtype][eval, grad, sample, stream] per CU
-    int stream_block = BLOCK;                             // threads per workgroup of the streaming sampler
+    int stream_waves = 0;                                 // forced waves per streaming workgroup (0: per call)
+    int stream_resident[2][3] = {{1, 1, 1}, {1, 1, 1}};  // [dtype][4, 8, 16 waves] workgroups per CU
     ac_info_t info{};
     std::vector<uint8_t> var_dom;
     std::vector<uint32_t> var_offset;
@@ -620,12 +621,16 @@ extern "C" ac_status ac_load(const void *blob, size_t nbytes, int device, ac_gra
     g->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;
     if (const char *env = std::getenv("QKC_STREAM_WAVES")) {
         const int nw = std::atoi(env);
-        if (nw >= 1 && nw <= BLOCK / WAVE) g->stream_block = nw * WAVE;
+        if (nw >= 1 && nw <= STREAM_MAX_BLOCK / WAVE) g->stream_waves = nw;
     }
     for (int k = 0; k < 4; ++k) {
-        const int blk = k == 3 ? g->stream_block : BLOCK;
+        const int blk = k == 3 && g->stream_waves ? g->stream_waves * WAVE : BLOCK;
         g->resident[AC_C64][k] = resident_blocks<float>(d, k, blk);
         g->resident[AC_C128][k] = resident_blocks<double>(d, k, blk);
+    }
+    for (int j = 0; j < 3; ++j) {
+        g->stream_resident[AC_C64][j] = resident_blocks<float>(d, 3, BLOCK << j);
+        g->stream_resident[AC_C128][j] = resident_blocks<double>(d, 3, BLOCK << j);
     }
     g->var_dom.assign(var_dom, var_dom + n_vars);
     g->var_offset.assign(var_off, var_off + n_vars);
@@ -759,10 +764,28 @@ bool sample_lds_shape(const ac_graph *g, ac_dtype dt, int64_t chains, int &cpw, 
     return true;
 }
 
+// Threads per workgroup of the streaming sampler for a batch of `chains`:
+// four waves per 64-chain tile while the tiles fill the co-resident
+// workgroup slots; with fewer tiles, 8 or 16 waves split each tile's levels
+// (a small batch on a large AC is otherwise latency-bound on one tile's
+// level chain while most of the chip idles).  QKC_STREAM_WAVES forces it.
+int stream_block_for(const ac_graph *g, ac_dtype dt, int64_t chains, int &wg_per_cu) {
+    if (g->stream_waves) {
+        wg_per_cu = g->resident[dt][3];
+        return g->stream_waves * WAVE;
+    }
+    const int64_t tiles = std::max<int64_t>(1, (chains + WAVE - 1) / WAVE);
+    int j = 0;   // 4 << j waves: the most for which every tile still has a co-resident workgroup
+    while (j < 2 && static_cast<int64_t>(g->n_cu) * g->stream_resident[dt][j + 1] >= tiles) ++j;
+    wg_per_cu = g->stream_resident[dt][j];
+    return BLOCK << j;
+}
+
 struct Layout {
     size_t wfix_off = 0, contrib_off = 0, tiles_off = 0, total = 0;
     size_t per_wg_elems = 0;   // complex elements per workgroup buffer
     int grid = 0;
+    int block = BLOCK;         // threads per workgroup
 };
 
 bool make_layout(const ac_graph *g, ac_dtype dt, int64_t batch, int op, Layout &out) {
@@ -791,6 +814,8 @@ bool make_layout(const ac_graph *g, ac_dtype dt, int64_t batch, int op, Layout &
     int64_t tiles = (batch + WAVE - 1) / WAVE;
     // persistent grids: exactly the workgroups that are resident together
     int wg_per_cu = g->resident[dt][kid];
+    int block = BLOCK;
+    if (kid == 3) block = stream_block_for(g, dt, batch, wg_per_cu);
     if (const char *env = std::getenv("QKC_WG_PER_CU")) wg_per_cu = std::max(1, std::min(16, std::atoi(env)));
     int64_t grid = std::min<int64_t>(tiles, static_cast<int64_t>(g->n_cu) * wg_per_cu);
     if (per_wg > 0) {
@@ -814,6 +839,7 @@ bool make_layout(const ac_graph *g, ac_dtype dt, int64_t batch, int op, Layout &
     L.total = off;
     L.per_wg_elems = per_wg;
     L.grid = static_cast<int>(grid);
+    L.block = block;
     out = L;
     return true;
 }
@@ -1014,13 +1040,13 @@ extern "C" ac_status ac_sample(const ac_graph *g, ac_dtype dtype, const double *
         if (dtype == AC_C64) {
             e = launch_fixed_slots<float>(g->dev, noise, w + L.wfix_off, st);
             if (e == hipSuccess)
-                e = launch_sample_stream<float>(g->dev, g->plan, L.grid, g->stream_block, theta, w + L.wfix_off,
+                e = launch_sample_stream<float>(g->dev, g->plan, L.grid, L.block, theta, w + L.wfix_off,
                                                 w + L.tiles_off,
                                                 L.per_wg_elems, a, st);
         } else {
             e = launch_fixed_slots<double>(g->dev, noise, w + L.wfix_off, st);
             if (e == hipSuccess)
-                e = launch_sample_stream<double>(g->dev, g->plan, L.grid, g->stream_block, theta, w + L.wfix_off,
+                e = launch_sample_stream<double>(g->dev, g->plan, L.grid, L.block, theta, w + L.wfix_off,
                                                  w + L.tiles_off,
                                                  L.per_wg_elems, a, st);
         }

@@ -1069,7 +1069,7 @@ struct StreamTile {
 // (measured: 4 waves 1.49 s, 5 waves 1.44 s, 6-8 waves 1.41 s per 1,024,000
 // 8-qubit samples)
 template <typename T>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 1, 8))) void k_sample_stream(DevGraph g, LdsPlan lp, const double *theta,
+__global__ __launch_bounds__(STREAM_MAX_BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 1, 8))) void k_sample_stream(DevGraph g, LdsPlan lp, const double *theta,
                                                          const Weight<T> *wfix, cplx<T> *vals, size_t per_wg,
                                                          SampleArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1819,7 +1819,7 @@ template <typename T>
 hipError_t launch_sample_stream(const DevGraph &g, const LdsPlan &lp, int grid, int block, const double *theta,
                                 const void *wfix, void *vals, size_t per_wg_elems, const SampleArgs &a,
                                 hipStream_t st) {
-    if (block < WAVE || block > BLOCK || block % WAVE != 0) return hipErrorInvalidValue;
+    if (block < WAVE || block > STREAM_MAX_BLOCK || block % WAVE != 0) return hipErrorInvalidValue;
     size_t lds = stream_lds_bytes<T>(g);
     hipLaunchKernelGGL(k_sample_stream<T>, dim3(grid), dim3(block), lds, st, g, lp, theta,
                        reinterpret_cast<const Weight<T> *>(wfix), reinterpret_cast<cplx<T> *>(vals), per_wg_elems, a);
