@@ -302,9 +302,10 @@ def eval_leg(args, circ_cfg):
 
 
 def small_configs_leg(steps: int):
-    """The two remaining workloads: the 4-qubit ring (64 angle pairs x all 16
-    outputs, complex128, launch-bound) and the noise-free 32-qubit circuit
-    (256 angle pairs x 3907 Gibbs chains = 1,000,192 samples, complex64)."""
+    """The remaining workloads: the 4-qubit ring (64 angle pairs x all 16
+    outputs, complex128, launch-bound), the noise-free 32-qubit circuit
+    (256 angle pairs x 3907 Gibbs chains = 1,000,192 samples, complex64) and,
+    beyond the configurations, its p=2 version (8,192 chains, 10 sweeps)."""
     import numpy as np
     import torch
 
@@ -343,6 +344,29 @@ def small_configs_leg(steps: int):
     }
     g1.close()
     g4.close()
+    # the paper's largest QAOA setting, noise-free p=2 on 32 qubits: a small
+    # batch (2 angle sets x 4096 chains) on a large AC, one timed call
+    from paper_2103_17226_amd.compiler import compile_circuit
+    circ = W.qaoa_maxcut(32, W.random_regular_graph(32, 3, W.sub_seed("graph", 4)), 2)
+    t0 = time.perf_counter()
+    ac = compile_circuit(circ, order_trials=8)
+    t_compile = time.perf_counter() - t0
+    g5 = ACGraph(ac, device=0)
+    th5 = torch.tensor([[0.30, 0.25, 0.50, 0.20], [1.20, 0.90, 0.40, 0.60]], dtype=torch.float64, device=dev)
+    g5.sample(th5, 4096, 1, 1, 1, 1, dtype="c64", validate=False)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    g5.sample(th5, 4096, 1, 10, 1, 2, dtype="c64", validate=False)
+    b.record()
+    torch.cuda.synchronize()
+    t5 = a.elapsed_time(b) / 1e3
+    out.update({"qaoa_n32_p2_ac_nodes": g5.info["n_internal"], "qaoa_n32_p2_compile_s": t_compile,
+                "qaoa_n32_p2_chains": 8192, "qaoa_n32_p2_sample_ms": t5 * 1e3,
+                "qaoa_n32_p2_samples_per_s": 8192 / t5})
+    g5.release_workspaces()
+    g5.close()
     return out
 
 
