@@ -48,9 +48,9 @@ KERNELS = os.path.join(ROOT, "paper_2103_17226_amd", "csrc", "qkc_kernels.hip")
 # the copy-kernel calibration, FETCH x 2.0, WRITE x 1.0), valid only for the
 # kernel source they were taken on and the default workload of each leg.
 PROFILED_TRAFFIC = {
-    "k_sample_stream": {"kernel_sha256_16": "15d2873d13f0c58e", "bytes": 4203461859328,
+    "k_sample_stream": {"kernel_sha256_16": "7f8e54cd8fc0c8b3", "bytes": 4203521042432,
                         "profile": "profiles/k_sample_stream_qaoa_n8_p1_dep.md"},
-    "k_eval": {"kernel_sha256_16": "15d2873d13f0c58e", "bytes": 360657231872,
+    "k_eval": {"kernel_sha256_16": "7f8e54cd8fc0c8b3", "bytes": 360690504362,
                "profile": "profiles/k_eval_qaoa_n16_p2_dep_ad.md"},
 }
 
