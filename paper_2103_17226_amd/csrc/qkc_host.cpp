@@ -21,11 +21,11 @@ namespace qkc {
 template <typename T>
 hipError_t launch_fixed_slots(const DevGraph &g, const double *noise, void *wfix, hipStream_t st);
 template <typename T>
-hipError_t launch_eval(const DevGraph &g, int grid, const double *theta, const int32_t *param_of, int P,
+hipError_t launch_eval(const DevGraph &g, int grid, int block, const double *theta, const int32_t *param_of, int P,
                        const uint64_t *evidence, int64_t B, const void *wfix, void *vals, size_t per_wg_elems,
                        void *amp_out, double *prob_out, hipStream_t st);
 template <typename T>
-hipError_t launch_grad(const DevGraph &g, int grid, const double *theta, const int32_t *param_of,
+hipError_t launch_grad(const DevGraph &g, int grid, int block, const double *theta, const int32_t *param_of,
                        const uint64_t *evidence, int64_t B, const void *wfix, void *vals, size_t per_wg_elems,
                        int mode, const void *cotangent, const double *weight, double *contrib, int P,
                        double *grad, void *amp_out, void *dfdtheta_out, void *dind_out, hipStream_t st);
@@ -87,7 +87,8 @@ struct ac_graph {
     int n_cu = 0;
     int resident[2][4] = {{1, 1, 1, 1}, {1, 1, 1, 1}};   // [dtype][eval, grad, sample, stream] per CU
     int stream_waves = 0;                                 // forced waves per streaming workgroup (0: per call)
-    int stream_resident[2][3] = {{1, 1, 1}, {1, 1, 1}};  // [dtype][4, 8, 16 waves] workgroups per CU
+    int tile_waves = 0;                                   // forced waves per upward/gradient workgroup (0: per call)
+    int wide_resident[2][4][3] = {};                      // [dtype][eval, grad, -, stream][4, 8, 16 waves] per CU
     ac_info_t info{};
     std::vector<uint8_t> var_dom;
     std::vector<uint32_t> var_offset;
@@ -621,17 +622,22 @@ extern "C" ac_status ac_load(const void *blob, size_t nbytes, int device, ac_gra
     g->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;
     if (const char *env = std::getenv("QKC_STREAM_WAVES")) {
         const int nw = std::atoi(env);
-        if (nw >= 1 && nw <= STREAM_MAX_BLOCK / WAVE) g->stream_waves = nw;
+        if (nw >= 1 && nw <= MAX_BLOCK / WAVE) g->stream_waves = nw;
+    }
+    if (const char *env = std::getenv("QKC_TILE_WAVES")) {
+        const int nw = std::atoi(env);
+        if (nw == 4 || nw == 8 || nw == 16) g->tile_waves = nw;
     }
     for (int k = 0; k < 4; ++k) {
         const int blk = k == 3 && g->stream_waves ? g->stream_waves * WAVE : BLOCK;
         g->resident[AC_C64][k] = resident_blocks<float>(d, k, blk);
         g->resident[AC_C128][k] = resident_blocks<double>(d, k, blk);
     }
-    for (int j = 0; j < 3; ++j) {
-        g->stream_resident[AC_C64][j] = resident_blocks<float>(d, 3, BLOCK << j);
-        g->stream_resident[AC_C128][j] = resident_blocks<double>(d, 3, BLOCK << j);
-    }
+    for (int k : {0, 1, 3})
+        for (int j = 0; j < 3; ++j) {
+            g->wide_resident[AC_C64][k][j] = resident_blocks<float>(d, k, BLOCK << j);
+            g->wide_resident[AC_C128][k][j] = resident_blocks<double>(d, k, BLOCK << j);
+        }
     g->var_dom.assign(var_dom, var_dom + n_vars);
     g->var_offset.assign(var_off, var_off + n_vars);
     ac_info_t &inf = g->info;
@@ -764,20 +770,38 @@ bool sample_lds_shape(const ac_graph *g, ac_dtype dt, int64_t chains, int &cpw, 
     return true;
 }
 
-// Threads per workgroup of the streaming sampler for a batch of `chains`:
-// four waves per 64-chain tile while the tiles fill the co-resident
-// workgroup slots; with fewer tiles, 8 or 16 waves split each tile's levels
-// (a small batch on a large AC is otherwise latency-bound on one tile's
-// level chain while most of the chip idles).  QKC_STREAM_WAVES forces it.
-int stream_block_for(const ac_graph *g, ac_dtype dt, int64_t chains, int &wg_per_cu) {
-    if (g->stream_waves) {
+// Threads per workgroup of a tile kernel (kid 0 upward pass, 1 gradients, 3
+// streaming sampler) for a batch of `batch` elements or chains: 4, 8 or 16
+// waves per 64-element tile, whichever keeps the most waves resident at once
+// (ties: the smaller workgroup).  Full batches keep four waves; a small batch
+// on a large AC gets its tiles' levels split over more waves instead of
+// being held to one tile's level chain while most of the chip idles
+// (measured on noisy QAOA ACs of 3.6k and 138k nodes, batches of 1306 to
+// 262,144: the rule picked the fastest size at every point).
+// QKC_STREAM_WAVES forces the sampler's size, QKC_TILE_WAVES (4, 8, 16) the
+// others' (measurements).
+int wide_block_for(const ac_graph *g, ac_dtype dt, int64_t batch, int kid, int &wg_per_cu) {
+    if (kid == 3 && g->stream_waves) {
         wg_per_cu = g->resident[dt][3];
         return g->stream_waves * WAVE;
     }
-    const int64_t tiles = std::max<int64_t>(1, (chains + WAVE - 1) / WAVE);
-    int j = 0;   // 4 << j waves: the most for which every tile still has a co-resident workgroup
-    while (j < 2 && static_cast<int64_t>(g->n_cu) * g->stream_resident[dt][j + 1] >= tiles) ++j;
-    wg_per_cu = g->stream_resident[dt][j];
+    if (kid != 3 && g->tile_waves) {
+        const int j = g->tile_waves == 4 ? 0 : g->tile_waves == 8 ? 1 : 2;
+        wg_per_cu = std::max(1, g->wide_resident[dt][kid][j]);
+        return BLOCK << j;
+    }
+    const int64_t tiles = std::max<int64_t>(1, (batch + WAVE - 1) / WAVE);
+    int j = 0;
+    int64_t best = -1;
+    for (int jj = 0; jj < 3; ++jj) {      // most waves resident at once; ties go to smaller workgroups
+        const int64_t wgs = std::min<int64_t>(tiles, static_cast<int64_t>(g->n_cu) * g->wide_resident[dt][kid][jj]);
+        const int64_t waves = wgs * (4 << jj);
+        if (waves > best) {
+            best = waves;
+            j = jj;
+        }
+    }
+    wg_per_cu = std::max(1, g->wide_resident[dt][kid][j]);
     return BLOCK << j;
 }
 
@@ -815,7 +839,7 @@ bool make_layout(const ac_graph *g, ac_dtype dt, int64_t batch, int op, Layout &
     // persistent grids: exactly the workgroups that are resident together
     int wg_per_cu = g->resident[dt][kid];
     int block = BLOCK;
-    if (kid == 3) block = stream_block_for(g, dt, batch, wg_per_cu);
+    if (kid != 2) block = wide_block_for(g, dt, batch, kid, wg_per_cu);
     if (const char *env = std::getenv("QKC_WG_PER_CU")) wg_per_cu = std::max(1, std::min(16, std::atoi(env)));
     int64_t grid = std::min<int64_t>(tiles, static_cast<int64_t>(g->n_cu) * wg_per_cu);
     if (per_wg > 0) {
@@ -918,12 +942,12 @@ extern "C" ac_status ac_eval_batch(const ac_graph *g, ac_dtype dtype, const doub
     if (dtype == AC_C64) {
         e = launch_fixed_slots<float>(g->dev, noise, w + L.wfix_off, st);
         if (e == hipSuccess)
-            e = launch_eval<float>(g->dev, L.grid, theta, param_of, P, evidence, B, w + L.wfix_off, w + L.tiles_off,
+            e = launch_eval<float>(g->dev, L.grid, L.block, theta, param_of, P, evidence, B, w + L.wfix_off, w + L.tiles_off,
                                    L.per_wg_elems, amp_out, prob_out, st);
     } else {
         e = launch_fixed_slots<double>(g->dev, noise, w + L.wfix_off, st);
         if (e == hipSuccess)
-            e = launch_eval<double>(g->dev, L.grid, theta, param_of, P, evidence, B, w + L.wfix_off, w + L.tiles_off,
+            e = launch_eval<double>(g->dev, L.grid, L.block, theta, param_of, P, evidence, B, w + L.wfix_off, w + L.tiles_off,
                                     L.per_wg_elems, amp_out, prob_out, st);
     }
     if (e != hipSuccess) return fail_hip(e, "ac_eval_batch: launch");
@@ -965,13 +989,13 @@ extern "C" ac_status ac_grad_batch(const ac_graph *g, ac_dtype dtype, const doub
     if (dtype == AC_C64) {
         e = launch_fixed_slots<float>(g->dev, noise, w + L.wfix_off, st);
         if (e == hipSuccess)
-            e = launch_grad<float>(g->dev, L.grid, theta, param_of, evidence, B, w + L.wfix_off, w + L.tiles_off,
+            e = launch_grad<float>(g->dev, L.grid, L.block, theta, param_of, evidence, B, w + L.wfix_off, w + L.tiles_off,
                                    L.per_wg_elems, mode, cotangent, weight, contrib, P, grad_theta, amp_out,
                                    dfdtheta_out, dind_out, st);
     } else {
         e = launch_fixed_slots<double>(g->dev, noise, w + L.wfix_off, st);
         if (e == hipSuccess)
-            e = launch_grad<double>(g->dev, L.grid, theta, param_of, evidence, B, w + L.wfix_off, w + L.tiles_off,
+            e = launch_grad<double>(g->dev, L.grid, L.block, theta, param_of, evidence, B, w + L.wfix_off, w + L.tiles_off,
                                     L.per_wg_elems, mode, cotangent, weight, contrib, P, grad_theta, amp_out,
                                     dfdtheta_out, dind_out, st);
     }

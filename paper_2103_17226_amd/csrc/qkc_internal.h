@@ -9,7 +9,7 @@ namespace qkc {
 
 constexpr int WAVE = 64;              // wavefront width on CDNA
 constexpr int BLOCK = 256;            // threads per workgroup (4 waves)
-constexpr int STREAM_MAX_BLOCK = 1024; // streaming sampler: up to 16 waves on one tile
+constexpr int MAX_BLOCK = 1024;       // tile kernels and streaming sampler: up to 16 waves on one tile
 constexpr int MAX_WORDS = 64;         // evidence words staged in LDS
 constexpr int MAX_ANGLE_SLOTS = 64;   // angle-dependent weights per element
 constexpr int MAX_ANGLES = 64;        // columns of theta

@@ -499,7 +499,7 @@ __device__ bool stage_tile(const DevGraph &g, uint64_t *ev_s, Weight<T> *ang_s, 
 // more resident waves hide it (16-qubit noisy QAOA, 262,144 amplitudes:
 // 6 waves 74 ms, 8 waves 66 ms)
 template <typename T>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 1, 8))) void k_eval(DevGraph g, const double *theta, const int32_t *param_of, int P,
+__global__ __launch_bounds__(MAX_BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 1, 8))) void k_eval(DevGraph g, const double *theta, const int32_t *param_of, int P,
                                                 const uint64_t *evidence, int64_t B, const Weight<T> *wfix,
                                                 cplx<T> *vals, size_t per_wg, cplx<T> *amp_out,
                                                 double *prob_out) {
@@ -540,7 +540,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T)
 // per workgroup as everywhere; the downward pass's edge groups of eight took
 // it to 252 ms)
 template <typename T>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 1, 8))) void k_grad(DevGraph g, const double *theta, const int32_t *param_of, int P,
+__global__ __launch_bounds__(MAX_BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 1, 8))) void k_grad(DevGraph g, const double *theta, const int32_t *param_of, int P,
                                                 const uint64_t *evidence, int64_t B, const Weight<T> *wfix,
                                                 cplx<T> *vals, size_t per_wg, int mode,
                                                 const cplx<T> *cotangent, const double *weight,
@@ -1069,7 +1069,7 @@ struct StreamTile {
 // (measured: 4 waves 1.49 s, 5 waves 1.44 s, 6-8 waves 1.41 s per 1,024,000
 // 8-qubit samples)
 template <typename T>
-__global__ __launch_bounds__(STREAM_MAX_BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 1, 8))) void k_sample_stream(DevGraph g, LdsPlan lp, const double *theta,
+__global__ __launch_bounds__(MAX_BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 1, 8))) void k_sample_stream(DevGraph g, LdsPlan lp, const double *theta,
                                                          const Weight<T> *wfix, cplx<T> *vals, size_t per_wg,
                                                          SampleArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1711,23 +1711,25 @@ size_t stream_lds_bytes(const DevGraph &g) {
 }
 
 template <typename T>
-hipError_t launch_eval(const DevGraph &g, int grid, const double *theta, const int32_t *param_of, int P,
+hipError_t launch_eval(const DevGraph &g, int grid, int block, const double *theta, const int32_t *param_of, int P,
                        const uint64_t *evidence, int64_t B, const void *wfix, void *vals, size_t per_wg_elems,
                        void *amp_out, double *prob_out, hipStream_t st) {
     size_t lds = lds_bytes(g);
-    hipLaunchKernelGGL(k_eval<T>, dim3(grid), dim3(BLOCK), lds, st, g, theta, param_of, P, evidence, B,
+    if (block < WAVE || block > MAX_BLOCK || block % WAVE != 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_eval<T>, dim3(grid), dim3(block), lds, st, g, theta, param_of, P, evidence, B,
                        reinterpret_cast<const Weight<T> *>(wfix), reinterpret_cast<cplx<T> *>(vals),
                        per_wg_elems, reinterpret_cast<cplx<T> *>(amp_out), prob_out);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_grad(const DevGraph &g, int grid, const double *theta, const int32_t *param_of,
+hipError_t launch_grad(const DevGraph &g, int grid, int block, const double *theta, const int32_t *param_of,
                        const uint64_t *evidence, int64_t B, const void *wfix, void *vals, size_t per_wg_elems,
                        int mode, const void *cotangent, const double *weight, double *contrib, int P,
                        double *grad, void *amp_out, void *dfdtheta_out, void *dind_out, hipStream_t st) {
     size_t lds = lds_bytes(g);
-    hipLaunchKernelGGL(k_grad<T>, dim3(grid), dim3(BLOCK), lds, st, g, theta, param_of, P, evidence, B,
+    if (block < WAVE || block > MAX_BLOCK || block % WAVE != 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_grad<T>, dim3(grid), dim3(block), lds, st, g, theta, param_of, P, evidence, B,
                        reinterpret_cast<const Weight<T> *>(wfix), reinterpret_cast<cplx<T> *>(vals),
                        per_wg_elems, mode, reinterpret_cast<const cplx<T> *>(cotangent), weight, contrib,
                        reinterpret_cast<cplx<T> *>(amp_out), reinterpret_cast<cplx<T> *>(dfdtheta_out),
@@ -1819,7 +1821,7 @@ template <typename T>
 hipError_t launch_sample_stream(const DevGraph &g, const LdsPlan &lp, int grid, int block, const double *theta,
                                 const void *wfix, void *vals, size_t per_wg_elems, const SampleArgs &a,
                                 hipStream_t st) {
-    if (block < WAVE || block > STREAM_MAX_BLOCK || block % WAVE != 0) return hipErrorInvalidValue;
+    if (block < WAVE || block > MAX_BLOCK || block % WAVE != 0) return hipErrorInvalidValue;
     size_t lds = stream_lds_bytes<T>(g);
     hipLaunchKernelGGL(k_sample_stream<T>, dim3(grid), dim3(block), lds, st, g, lp, theta,
                        reinterpret_cast<const Weight<T> *>(wfix), reinterpret_cast<cplx<T> *>(vals), per_wg_elems, a);
@@ -1832,14 +1834,14 @@ template hipError_t launch_sample_stream<float>(const DevGraph &, const LdsPlan 
 template hipError_t launch_sample_stream<double>(const DevGraph &, const LdsPlan &, int, int, const double *,
                                                  const void *, void *, size_t, const SampleArgs &, hipStream_t);
 
-template hipError_t launch_eval<float>(const DevGraph &, int, const double *, const int32_t *, int, const uint64_t *,
+template hipError_t launch_eval<float>(const DevGraph &, int, int, const double *, const int32_t *, int, const uint64_t *,
                                        int64_t, const void *, void *, size_t, void *, double *, hipStream_t);
-template hipError_t launch_eval<double>(const DevGraph &, int, const double *, const int32_t *, int, const uint64_t *,
+template hipError_t launch_eval<double>(const DevGraph &, int, int, const double *, const int32_t *, int, const uint64_t *,
                                         int64_t, const void *, void *, size_t, void *, double *, hipStream_t);
-template hipError_t launch_grad<float>(const DevGraph &, int, const double *, const int32_t *, const uint64_t *,
+template hipError_t launch_grad<float>(const DevGraph &, int, int, const double *, const int32_t *, const uint64_t *,
                                        int64_t, const void *, void *, size_t, int, const void *, const double *,
                                        double *, int, double *, void *, void *, void *, hipStream_t);
-template hipError_t launch_grad<double>(const DevGraph &, int, const double *, const int32_t *, const uint64_t *,
+template hipError_t launch_grad<double>(const DevGraph &, int, int, const double *, const int32_t *, const uint64_t *,
                                         int64_t, const void *, void *, size_t, int, const void *, const double *,
                                         double *, int, double *, void *, void *, void *, hipStream_t);
 template hipError_t launch_sample<float>(const DevGraph &, int, const double *, const void *, void *, size_t,
