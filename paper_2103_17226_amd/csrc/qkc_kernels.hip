@@ -1345,19 +1345,31 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
-template <typename T, int CPW>
-__global__ __launch_bounds__(WAVE) void k_sample_lds(DevGraph g, LdsPlan lp, const double *theta,
+// the lanes working on one chain meet: one wavefront, or the workgroup
+template <int WPC>
+__device__ __forceinline__ void chain_sync() {
+    if constexpr (WPC == 1) wave_sync();
+    else __syncthreads();
+}
+
+template <typename T, int CPW, int WPC>
+__global__ __launch_bounds__(WAVE * WPC) void k_sample_lds(DevGraph g, LdsPlan lp, const double *theta,
                                                      const double *noise, SampleArgs a, uint32_t chain_bytes) {
     extern __shared__ __align__(16) unsigned char smem[];
-    constexpr int LPC = WAVE / CPW;
+    static_assert(WPC == 1 || CPW == 1, "several waves work on one chain, or one wave on several");
+    constexpr int LPC = WAVE * WPC / CPW;     // lanes per chain in the node passes
+    constexpr int DPC = WAVE / CPW;           // lanes per chain in the Gibbs decisions (wave 0 only)
     const int lane = threadIdx.x;
     const int sub = lane / LPC;
     const int cl = lane - sub * LPC;
+    const int wl = lane & (WAVE - 1);
+    const int dsub = wl / DPC;
+    const int dcl = wl - dsub * DPC;
     const int L = lp.L;
     uint32_t *lv_ptr = reinterpret_cast<uint32_t *>(smem);
     uint32_t *lv_prod = lv_ptr + (L + 1);
     uint32_t *lv_edge = lv_prod + (L + 1);
-    for (int l = lane; l <= L; l += WAVE) {
+    for (int l = lane; l <= L; l += WAVE * WPC) {
         lv_ptr[l] = lp.level_ptr[l];
         lv_prod[l] = l < L ? lp.level_prod[l] : lp.level_ptr[L];
         lv_edge[l] = lp.estart[lp.level_ptr[l]];
@@ -1378,8 +1390,8 @@ __global__ __launch_bounds__(WAVE) void k_sample_lds(DevGraph g, LdsPlan lp, con
     const uint32_t total_sweeps = static_cast<uint32_t>(a.burn_in) +
                                   static_cast<uint32_t>(a.spc) * static_cast<uint32_t>(a.thin);
     const uint64_t xmask = g.n_qubits >= 64 ? ~0ull : ((1ull << g.n_qubits) - 1ull);
-    const int shift_sub = sub * LPC;
-    const uint64_t gmask = LPC == WAVE ? ~0ull : (((1ull << LPC) - 1ull) << shift_sub);
+    const int shift_sub = dsub * DPC;
+    const uint64_t gmask = DPC == WAVE ? ~0ull : (((1ull << DPC) - 1ull) << shift_sub);
     const uint32_t T_all = static_cast<uint32_t>(lp.N + g.n_ind + g.n_sel);
     const uint32_t leaf_e0 = lp.estart[lp.N], leaf_e1 = lp.estart[T_all];
 
@@ -1437,7 +1449,7 @@ __global__ __launch_bounds__(WAVE) void k_sample_lds(DevGraph g, LdsPlan lp, con
         const int64_t ch = static_cast<int64_t>(blockIdx.x) * CPW + sub;
         init_chain(ch < a.total_chains ? ch : -1);
     }
-    wave_sync();
+    chain_sync<WPC>();
 
     for (;;) {
         if (c.st[6] != 0) {                  // weights of a chain that just started
@@ -1448,7 +1460,7 @@ __global__ __launch_bounds__(WAVE) void k_sample_lds(DevGraph g, LdsPlan lp, con
                 c.sv[s] = {static_cast<T>(re), static_cast<T>(im)};
             }
         }
-        wave_sync();
+        chain_sync<WPC>();
         if (cl == 0) c.st[6] = 0;
         const bool active = c.st[0] >= 0;
         if (__ballot(active) == 0ull) break;
@@ -1464,7 +1476,7 @@ __global__ __launch_bounds__(WAVE) void k_sample_lds(DevGraph g, LdsPlan lp, con
                 c.selv[q] = sl == NO_SLOT ? cplx<T>{T(0), T(0)} : c.sv[sl];
             }
         }
-        wave_sync();
+        chain_sync<WPC>();
 
         // ---- upward pass; the first record of a level is loaded two levels ahead
         {
@@ -1489,7 +1501,7 @@ __global__ __launch_bounds__(WAVE) void k_sample_lds(DevGraph g, LdsPlan lp, con
                 }
                 r0 = r1;
                 r1 = r2;
-                wave_sync();
+                chain_sync<WPC>();
             }
         }
         // ---- downward pass, level by level: every parent edge of the level's
@@ -1510,7 +1522,7 @@ __global__ __launch_bounds__(WAVE) void k_sample_lds(DevGraph g, LdsPlan lp, con
                         rr = rnext;
                     }
                 }
-                wave_sync();
+                chain_sync<WPC>();
                 if (active) {
                     const uint32_t n1 = lv_ptr[l + 1];
                     uint64_t bb = b0r;
@@ -1530,14 +1542,14 @@ __global__ __launch_bounds__(WAVE) void k_sample_lds(DevGraph g, LdsPlan lp, con
                 e1r = e2r;
                 b0r = b1r;
                 b1r = b2r;
-                wave_sync();
+                chain_sync<WPC>();
             }
             // leaves: every parent edge of indicator and selector leaves, then
             // d root / d lambda_{v=u} per variable
             if (active) {
                 for (uint32_t e = leaf_e0 + cl; e < leaf_e1; e += LPC) c.tmp[e - leaf_e0] = edge_term(lp.edg_u[e]);
             }
-            wave_sync();
+            chain_sync<WPC>();
             if (active) {
                 for (int t0 = cl; t0 < g.n_ind; t0 += LPC) {
                     double ar = 0.0, ai = 0.0;
@@ -1554,12 +1566,13 @@ __global__ __launch_bounds__(WAVE) void k_sample_lds(DevGraph g, LdsPlan lp, con
                     c.D[t0] = {static_cast<T>(ar), static_cast<T>(ai)};
                 }
             }
-            wave_sync();
+            chain_sync<WPC>();
         }
 
         // ---- Gibbs decisions: lane k decides the k-th next variable of the
         // scan; the first lane whose decision changes the state ends the round.
-        if (active) {
+        // With several waves on one chain, wave 0 alone decides.
+        if (active && (WPC == 1 || lane < WAVE)) {
             const int64_t ch = c.st[0];
             const int p = static_cast<int>(c.st[5]);
             int64_t pos = c.st[1];
@@ -1570,7 +1583,7 @@ __global__ __launch_bounds__(WAVE) void k_sample_lds(DevGraph g, LdsPlan lp, con
             const int64_t out0 = static_cast<int64_t>(p) * S + (ch % a.cpp) * a.spc;
             bool done = false;
             for (;;) {
-                const int64_t t = pos + cl;
+                const int64_t t = pos + dcl;
                 const uint32_t sw = sweep + static_cast<uint32_t>(t / V);
                 const int v = a.first_var + static_cast<int>(t % V);
                 const bool valid = sw < total_sweeps;
@@ -1618,17 +1631,17 @@ __global__ __launch_bounds__(WAVE) void k_sample_lds(DevGraph g, LdsPlan lp, con
                 const int last = vld ? 63 - __clzll(static_cast<unsigned long long>(vld)) : -1;
                 const int end = f >= 0 ? f : last;
                 bool emit = false;
-                if (valid && cl <= end && v == g.n_vars - 1) {
+                if (valid && dcl <= end && v == g.n_vars - 1) {
                     const uint32_t done_sw = sw + 1;
                     emit = done_sw > static_cast<uint32_t>(a.burn_in) &&
                            (done_sw - static_cast<uint32_t>(a.burn_in)) % static_cast<uint32_t>(a.thin) == 0u;
                 }
                 const uint64_t em = (__ballot(emit) & gmask) >> shift_sub;
-                const uint64_t newword = (cl == f) ? ((c.ev[word] & ~(fmask << shift)) |
+                const uint64_t newword = (dcl == f) ? ((c.ev[word] & ~(fmask << shift)) |
                                                       (static_cast<uint64_t>(pick) << shift)) : 0ull;
                 if (emit) {
-                    const int rank = __popcll(static_cast<unsigned long long>(em & ((1ull << cl) - 1ull)));
-                    emit_sample(g, a, out0 + emitted + rank, c.ev, cl == f ? static_cast<int>(word) : g.W,
+                    const int rank = __popcll(static_cast<unsigned long long>(em & ((1ull << dcl) - 1ull)));
+                    emit_sample(g, a, out0 + emitted + rank, c.ev, dcl == f ? static_cast<int>(word) : g.W,
                                 newword, xmask);
                 }
                 emitted += __popcll(static_cast<unsigned long long>(em));
@@ -1636,7 +1649,7 @@ __global__ __launch_bounds__(WAVE) void k_sample_lds(DevGraph g, LdsPlan lp, con
                 // order; the fences keep the compiler from reordering them and wait
                 // for completion (every emission reads the old state first)
                 __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
-                if (cl == f) c.ev[word] = newword;
+                if (dcl == f) c.ev[word] = newword;
                 __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
                 if (end < 0) {                   // nothing left to decide
                     done = true;
@@ -1651,7 +1664,7 @@ __global__ __launch_bounds__(WAVE) void k_sample_lds(DevGraph g, LdsPlan lp, con
                 }
                 if (f >= 0) break;
             }
-            if (cl == 0) {
+            if (dcl == 0) {
                 c.st[4] += 1;
                 if (done) {
                     if (a.rounds_out) a.rounds_out[ch] = c.st[4];
@@ -1664,7 +1677,7 @@ __global__ __launch_bounds__(WAVE) void k_sample_lds(DevGraph g, LdsPlan lp, con
                 }
             }
         }
-        wave_sync();
+        chain_sync<WPC>();
     }
 }
 
@@ -1761,25 +1774,28 @@ size_t sample_lds_chain_bytes(const DevGraph &g, const LdsPlan &lp) {
 
 size_t sample_lds_meta_bytes(const LdsPlan &lp) { return level_meta_bytes(lp.L); }
 
-template <typename T, int CPW>
+template <typename T, int CPW, int WPC>
 hipError_t launch_sample_lds_cpw(const DevGraph &g, const LdsPlan &lp, int grid, const double *theta,
                                  const double *noise, const SampleArgs &a, hipStream_t st) {
     const uint32_t cb = static_cast<uint32_t>(chain_lds_bytes<T>(lp.N, g.n_ind, g.S, g.n_sel, lp.max_edges, g.W));
     const size_t lds = static_cast<size_t>(cb) * CPW + level_meta_bytes(lp.L);
-    hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sample_lds<T, CPW>),
+    hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sample_lds<T, CPW, WPC>),
                                          hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL((k_sample_lds<T, CPW>), dim3(grid), dim3(WAVE), lds, st, g, lp, theta, noise, a, cb);
+    hipLaunchKernelGGL((k_sample_lds<T, CPW, WPC>), dim3(grid), dim3(WAVE * WPC), lds, st, g, lp, theta, noise, a,
+                       cb);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_sample_lds(const DevGraph &g, const LdsPlan &lp, int cpw, int grid, const double *theta,
+hipError_t launch_sample_lds(const DevGraph &g, const LdsPlan &lp, int cpw, int wpc, int grid, const double *theta,
                              const double *noise, const SampleArgs &a, hipStream_t st) {
+    if (wpc == 4 && cpw == 1) return launch_sample_lds_cpw<T, 1, 4>(g, lp, grid, theta, noise, a, st);
+    if (wpc != 1) return hipErrorInvalidValue;
     switch (cpw) {
-        case 1: return launch_sample_lds_cpw<T, 1>(g, lp, grid, theta, noise, a, st);
-        case 2: return launch_sample_lds_cpw<T, 2>(g, lp, grid, theta, noise, a, st);
-        case 4: return launch_sample_lds_cpw<T, 4>(g, lp, grid, theta, noise, a, st);
+        case 1: return launch_sample_lds_cpw<T, 1, 1>(g, lp, grid, theta, noise, a, st);
+        case 2: return launch_sample_lds_cpw<T, 2, 1>(g, lp, grid, theta, noise, a, st);
+        case 4: return launch_sample_lds_cpw<T, 4, 1>(g, lp, grid, theta, noise, a, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1811,9 +1827,9 @@ template int resident_blocks<double>(const DevGraph &, int, int);
 
 template size_t sample_lds_chain_bytes<float>(const DevGraph &, const LdsPlan &);
 template size_t sample_lds_chain_bytes<double>(const DevGraph &, const LdsPlan &);
-template hipError_t launch_sample_lds<float>(const DevGraph &, const LdsPlan &, int, int, const double *,
+template hipError_t launch_sample_lds<float>(const DevGraph &, const LdsPlan &, int, int, int, const double *,
                                              const double *, const SampleArgs &, hipStream_t);
-template hipError_t launch_sample_lds<double>(const DevGraph &, const LdsPlan &, int, int, const double *,
+template hipError_t launch_sample_lds<double>(const DevGraph &, const LdsPlan &, int, int, int, const double *,
                                               const double *, const SampleArgs &, hipStream_t);
 
 

@@ -25,14 +25,19 @@ def _gpu():
     require_gpu()
 
 
-@pytest.mark.parametrize("variant", ["auto", "stream", "lds-cpw1", "lds-cpw2", "lds-cpw4", "global"])
+@pytest.mark.parametrize("variant", ["auto", "stream", "lds-cpw1", "lds-cpw2", "lds-cpw4", "lds-wpc4", "global"])
 def test_same_chain_bitwise_c128(variant, monkeypatch):
     note(f"same-chain bitwise ({variant})")
     if variant in ("global", "stream"):
         monkeypatch.setenv("QKC_SAMPLE_KERNEL", variant)
+    elif variant == "lds-wpc4":                      # four waves on each chain
+        monkeypatch.setenv("QKC_SAMPLE_KERNEL", "lds")
+        monkeypatch.setenv("QKC_SAMPLE_CPW", "1")
+        monkeypatch.setenv("QKC_SAMPLE_WPC", "4")
     elif variant != "auto":
         monkeypatch.setenv("QKC_SAMPLE_KERNEL", "lds")
         monkeypatch.setenv("QKC_SAMPLE_CPW", variant[-1])
+        monkeypatch.setenv("QKC_SAMPLE_WPC", "1")
     circ = W.qaoa_maxcut(3, W.ring_graph(3), 1, dep=0.05, ad=0.03)
     g = graph(circ)
     theta = np.array([[0.7, 0.4], [2.2, 1.3]])
@@ -94,7 +99,7 @@ def test_stationary_distribution_noisy_qaoa_n8():
     assert min(pvals) > 1e-4
 
 
-@pytest.mark.parametrize("other", ["lds", "global", "auto"])
+@pytest.mark.parametrize("other", ["lds", "lds-wpc4", "global", "auto"])
 def test_sampler_kernels_agree_c128(other, monkeypatch):
     note(f"streaming sampler kernel vs {other}")
     cfg = W.config(2, small=True)
@@ -106,6 +111,10 @@ def test_sampler_kernels_agree_c128(other, monkeypatch):
     a = g.sample(theta, **kw)
     if other == "auto":
         monkeypatch.delenv("QKC_SAMPLE_KERNEL")
+    elif other == "lds-wpc4":
+        monkeypatch.setenv("QKC_SAMPLE_KERNEL", "lds")
+        monkeypatch.setenv("QKC_SAMPLE_CPW", "1")
+        monkeypatch.setenv("QKC_SAMPLE_WPC", "4")
     else:
         monkeypatch.setenv("QKC_SAMPLE_KERNEL", other)
     b = g.sample(theta, **kw)
@@ -180,11 +189,14 @@ def _posterior_circuit():
                      n_angles=2, noise=[0.3, 0.25], edges=[(0, 1)])
 
 
-@pytest.mark.parametrize("variant", ["stream", "lds", "global"])
+@pytest.mark.parametrize("variant", ["stream", "lds", "lds-wpc4", "global"])
 def test_conditional_chains_follow_the_oracle_chain(variant, monkeypatch):
     # outputs held at an observed x (first_var = n): same decisions as the oracle
     note(f"conditional chains ({variant})")
-    monkeypatch.setenv("QKC_SAMPLE_KERNEL", variant)
+    monkeypatch.setenv("QKC_SAMPLE_KERNEL", variant.split("-")[0])
+    if variant == "lds-wpc4":
+        monkeypatch.setenv("QKC_SAMPLE_CPW", "1")
+        monkeypatch.setenv("QKC_SAMPLE_WPC", "4")
     circ = W.qaoa_maxcut(3, W.ring_graph(3), 1, dep=0.05, ad=0.03)
     g = graph(circ)
     theta = np.array([[0.7, 0.4]])
