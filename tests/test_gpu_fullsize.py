@@ -6,7 +6,9 @@ of the results one by one, or properties that hold at any size.
   chi-square of sampled parameter sets against the density-matrix diagonal
   (and uniform p-values across them), the MaxCut cost of every sample, and
   the score-function gradient over the sampled states against the oracle's
-  product rule for sampled parameter sets;
+  product rule for sampled parameter sets, and sampled chains against the
+  oracle's chain with the same random stream (the same final state wherever
+  no decision is a near tie);
 * 16-qubit p=2 noisy QAOA, 262,144 amplitudes: sampled rows against the
   oracle's branch amplitudes, every row's complex64 probability against
   complex128 (1e-5 relative), the complex64 gradient against complex128;
@@ -18,6 +20,7 @@ import pytest
 import torch
 
 import workloads as W
+from oracle import gibbs
 from oracle import grad as ograd
 from oracle import sim, stats
 from tests.gpu_common import graph, note, oracle_amplitudes, prob_ok, require_gpu
@@ -83,6 +86,59 @@ def test_config2_full_batch_samples_costs_and_gradient():
                 mass += np.abs(term)
         note(f"  param {p}: gradient {grad[p]} vs oracle {want} (term mass {mass})")
         assert np.all(np.abs(grad[p] - want) <= 1e-5 * mass)
+
+
+def _oracle_chain_with_margin(circ, theta, seed, ch, sweeps):
+    """The oracle's systematic-scan chain, and the smallest distance of any of
+    its decisions' targets r * total from a cumulative-weight boundary,
+    relative to the total."""
+    bc = gibbs.BranchCache(circ, theta)
+    s = gibbs.init_state(circ, seed, ch)
+    margin = 1.0
+    for sweep in range(sweeps):
+        for v in range(circ.n_vars):
+            w = gibbs.conditional_weights(bc, s, v)
+            r = gibbs.uniform(seed, ch, sweep, v)
+            u = gibbs.choose(w, r)
+            if u is not None:
+                s[v] = u
+            tot = sum(w)
+            if tot > 0:
+                margin = min(margin, float(np.min(np.abs(r * tot - np.cumsum(w)))) / tot)
+    return s, margin
+
+
+def test_config2_full_batch_chains_follow_the_oracle_chain():
+    """Sampled chains of the full batch, in complex64, against the oracle's
+    complex128 chain with the same random stream.  A complex64 decision can
+    differ from the oracle's only if the target r * total lies within the
+    weights' rounding error of a cumulative boundary: |d|^2 from complex64
+    derivatives is within ~6e-6 relative of complex128 (the measured
+    branch-probability error), so a boundary and the target each move by at
+    most ~6e-6 of the total.  Chains whose every decision is farther than
+    5e-5 of the total from a boundary must end in the oracle's state
+    exactly."""
+    cfg = W.config(2)
+    circ = cfg["circuit"]
+    theta = cfg["theta"]
+    P, C = theta.shape[0], cfg["chains_per_param"]
+    seed, burn = 777, 10
+    note(f"config 2 full batch, complex64 chains against the oracle chain: {P} x {C} chains")
+    g = graph(circ)
+    out = g.sample(theta, C, 1, burn, 1, seed, dtype="c64", want_states=True, validate=False)
+    states = out["states"].reshape(P * C, -1).cpu().numpy().view(np.uint64)
+    rng = np.random.default_rng(11)
+    chains = np.sort(rng.choice(P * C, size=6, replace=False))
+    exact = 0
+    for ch in chains:
+        ref, margin = _oracle_chain_with_margin(circ, theta[ch // C], seed, int(ch), burn + 1)
+        got = W.unpack_evidence(circ, states[ch])[0]
+        same = np.array_equal(got, np.array(ref))
+        note(f"  chain {ch}: {'same state' if same else 'differs'}, smallest decision margin {margin:.2e}")
+        if margin > 5e-5:
+            assert same, (int(ch), margin)
+            exact += 1
+    assert exact >= 3
 
 
 def test_config3_full_batch_amplitudes_and_gradient():
