@@ -83,7 +83,7 @@ def parse():
     ap.add_argument("--no-eval", action="store_true")
     ap.add_argument("--eval-steps", type=int, default=5)
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-rates", default="0.5,2000",
+    ap.add_argument("--serve-rates", default="0.5,5,2000",
                     help="offered request rates (req/s), one serving run each")
     ap.add_argument("--serve-seconds", type=float, default=12.0)
     ap.add_argument("--serve-warmup", type=float, default=2.0)
