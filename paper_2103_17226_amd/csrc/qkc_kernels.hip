@@ -74,6 +74,15 @@ __device__ __forceinline__ uint32_t uniform_u32(uint32_t v) {
     return __builtin_amdgcn_readfirstlane(v);
 }
 
+// Load of read-only graph data through the constant address space: the
+// plan and graph arrays are written once at load time and never during a
+// kernel, so a wave-uniform index becomes a scalar load (scalar cache, no
+// VGPRs) instead of a vector load that every lane repeats.
+template <typename U>
+__device__ __forceinline__ U cld(const U *p) {
+    return *(const __attribute__((address_space(4))) U *)(p);
+}
+
 // ---------------------------------------------------------------------------
 // weights (FP64, then rounded to the pass dtype)
 // ---------------------------------------------------------------------------
@@ -902,10 +911,10 @@ struct StreamTile {
         }
         if (tag == TAG_SLOT) return x < static_cast<uint32_t>(g.S_ang) ? ang[x * WAVE + lane] : wfix[x];
         const uint32_t *rec = g.sel + static_cast<size_t>(x) * SEL_REC;
-        const uint32_t fld = rec[0];
+        const uint32_t fld = cld(rec);
         const uint32_t word = fld >> 8, shift = (fld >> 2) & 63u, width = (fld & 3u) + 1u;
         const uint32_t k = static_cast<uint32_t>((ev[word * WAVE + lane] >> shift) & ((1ull << width) - 1ull));
-        const uint32_t s0 = rec[1], s1 = rec[2], s2 = rec[3], s3 = rec[4];
+        const uint32_t s0 = cld(rec + 1), s1 = cld(rec + 2), s2 = cld(rec + 3), s3 = cld(rec + 4);
         const uint32_t sl = k == 0 ? s0 : k == 1 ? s1 : k == 2 ? s2 : k == 3 ? s3 : NO_SLOT;
         return sl == NO_SLOT ? cplx<T>{T(0), T(0)} : wfix[sl];
     }
@@ -913,12 +922,12 @@ struct StreamTile {
     __device__ void forward(const LdsPlan &lp, int wave, int nwaves) {
         constexpr int KB = sizeof(T) == 4 ? 8 : 4;
         for (int l = 0; l < lp.L; ++l) {
-            const uint32_t n0 = lp.level_ptr[l], n1 = lp.level_ptr[l + 1], np = lp.level_prod[l];
+            const uint32_t n0 = cld(lp.level_ptr + l), n1 = cld(lp.level_ptr + l + 1), np = cld(lp.level_prod + l);
             for (uint32_t b0 = n0 + static_cast<uint32_t>(wave) * KB; b0 < n1; b0 += static_cast<uint32_t>(nwaves) * KB) {
                 uint64_t rec[KB];
                 cplx<T> va[KB], vb[KB];
 #pragma unroll
-                for (int j = 0; j < KB; ++j) rec[j] = b0 + j < n1 ? lp.fwd[b0 + j] : ~0ull;
+                for (int j = 0; j < KB; ++j) rec[j] = b0 + j < n1 ? cld(lp.fwd + b0 + j) : ~0ull;
 #pragma unroll
                 for (int j = 0; j < KB; ++j) {
                     va[j] = row(static_cast<uint32_t>(rec[j]));
@@ -950,16 +959,16 @@ struct StreamTile {
     template <typename Out>
     __device__ __forceinline__ void pull_targets(const LdsPlan &lp, uint32_t t0, uint32_t t1, Out out) const {
         constexpr int KE = sizeof(T) == 4 ? 8 : 4;
-        const uint32_t e_end = lp.estart[t1];
+        const uint32_t e_end = cld(lp.estart + t1);
         uint32_t t = t0;
-        uint32_t t_next = lp.estart[t0 + 1];      // first edge past target t
+        uint32_t t_next = cld(lp.estart + t0 + 1);      // first edge past target t
         double ar = 0.0, ai = 0.0;
-        for (uint32_t e = lp.estart[t0]; e < e_end; e += KE) {
+        for (uint32_t e = cld(lp.estart + t0); e < e_end; e += KE) {
             uint64_t rr[KE];
             cplx<T> ap[KE], sv[KE];
 #pragma unroll
             for (int j = 0; j < KE; ++j)
-                rr[j] = e + j < e_end ? lp.edg[e + j] : (static_cast<uint64_t>(NO_SIBLING) << 32);
+                rr[j] = e + j < e_end ? cld(lp.edg + e + j) : (static_cast<uint64_t>(NO_SIBLING) << 32);
 #pragma unroll
             for (int j = 0; j < KE; ++j) {
                 ap[j] = rb.ld(adj0 + static_cast<uint32_t>(rr[j]));
@@ -974,7 +983,7 @@ struct StreamTile {
                     ar = 0.0;
                     ai = 0.0;
                     ++t;
-                    t_next = lp.estart[t + 1];
+                    t_next = cld(lp.estart + t + 1);
                 }
                 const uint32_t sb = static_cast<uint32_t>(rr[j] >> 32);
                 const cplx<T> term = sb != NO_SIBLING ? cmul(ap[j], pick(sb, sv[j])) : ap[j];
@@ -993,7 +1002,7 @@ struct StreamTile {
         constexpr int KB = sizeof(T) == 4 ? 8 : 4;
         const uint32_t root = static_cast<uint32_t>(lp.root);
         for (int l = lp.L - 1; l >= 0; --l) {
-            const uint32_t n0 = lp.level_ptr[l], n1 = lp.level_ptr[l + 1];
+            const uint32_t n0 = cld(lp.level_ptr + l), n1 = cld(lp.level_ptr + l + 1);
             for (uint32_t b0 = n0 + static_cast<uint32_t>(wave) * KB; b0 < n1; b0 += static_cast<uint32_t>(nwaves) * KB) {
                 const uint32_t b1 = b0 + KB < n1 ? b0 + KB : n1;
                 pull_targets(lp, b0, b1, [&](uint32_t i, cplx<T> v) {
@@ -1013,13 +1022,13 @@ struct StreamTile {
         constexpr int KE = sizeof(T) == 4 ? 4 : 2;
         const uint32_t M = static_cast<uint32_t>(lp.N);
         const uint32_t s0 = M + static_cast<uint32_t>(g.n_ind);    // first selector target
-        const uint32_t sel_e0 = lp.estart[s0];                        // first selector edge
+        const uint32_t sel_e0 = cld(lp.estart + s0);                  // first selector edge
         for (int v = wave; v < g.n_vars; v += nwaves) {
-            const uint32_t base = g.ind_base[v], dom = g.ind_base[v + 1] - base;
-            const uint32_t q0 = g.vsel_ptr[v], q1 = g.vsel_ptr[v + 1];
+            const uint32_t base = cld(g.ind_base + v), dom = cld(g.ind_base + v + 1) - base;
+            const uint32_t q0 = cld(g.vsel_ptr + v), q1 = cld(g.vsel_ptr + v + 1);
             // indicator leaves: walked unless v has none with a parent and
             // all of its values are covered by the selector accumulators
-            const bool ind_edges = lp.estart[M + base] != lp.estart[M + base + dom];
+            const bool ind_edges = cld(lp.estart + M + base) != cld(lp.estart + M + base + dom);
             const bool walk_ind = dom > 0 && (ind_edges || q0 == q1 || dom > static_cast<uint32_t>(SEL_DOM));
             if (walk_ind)
                 pull_targets(lp, M + base, M + base + dom, [&](uint32_t i, cplx<T> val) { rb.st(d0 + (i - M), val); });
@@ -1028,16 +1037,16 @@ struct StreamTile {
 #pragma unroll
             for (int u = 0; u < SEL_DOM; ++u)       // this wave's own stores, read back in program order
                 acc[u] = walk_ind && static_cast<uint32_t>(u) < dom ? rb.ld(d0 + base + u) : cplx<T>{T(0), T(0)};
-            const uint32_t e1 = lp.estart[s0 + q1];
-            for (uint32_t e = lp.estart[s0 + q0]; e < e1; e += KE) {
+            const uint32_t e1 = cld(lp.estart + s0 + q1);
+            for (uint32_t e = cld(lp.estart + s0 + q0); e < e1; e += KE) {
                 uint64_t rr[KE];
                 uint32_t qe[KE];
                 cplx<T> ap[KE], sv[KE];
 #pragma unroll
                 for (int j = 0; j < KE; ++j) {
                     const bool in = e + j < e1;
-                    rr[j] = in ? lp.edg[e + j] : (static_cast<uint64_t>(NO_SIBLING) << 32);
-                    qe[j] = in ? lp.esel[e + j - sel_e0] : 0u;
+                    rr[j] = in ? cld(lp.edg + e + j) : (static_cast<uint64_t>(NO_SIBLING) << 32);
+                    qe[j] = in ? cld(lp.esel + e + j - sel_e0) : 0u;
                 }
 #pragma unroll
                 for (int j = 0; j < KE; ++j) {
@@ -1052,7 +1061,7 @@ struct StreamTile {
                     const uint32_t *rec = g.sel + static_cast<size_t>(qe[j]) * SEL_REC;
 #pragma unroll
                     for (int u = 0; u < SEL_DOM; ++u) {
-                        const uint32_t sl = rec[1 + u];
+                        const uint32_t sl = cld(rec + 1 + u);
                         if (sl != NO_SLOT) acc[u] = cadd(acc[u], cmul(term, wfix[sl]));
                     }
                 }
