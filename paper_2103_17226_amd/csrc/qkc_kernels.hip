@@ -80,7 +80,18 @@ __device__ __forceinline__ uint32_t uniform_u32(uint32_t v) {
 // VGPRs) instead of a vector load that every lane repeats.
 template <typename U>
 __device__ __forceinline__ U cld(const U *p) {
-    return *(const __attribute__((address_space(4))) U *)(p);
+    if constexpr (__is_arithmetic(U)) {
+        return *(const __attribute__((address_space(4))) U *)(p);
+    } else {                                   // a small struct: its dwords, then a bit cast
+        static_assert(sizeof(U) % 4 == 0, "cld: struct size must be a multiple of 4 bytes");
+        struct Words {
+            uint32_t w[sizeof(U) / 4];
+        } x;
+        const __attribute__((address_space(4))) uint32_t *q = (const __attribute__((address_space(4))) uint32_t *)(p);
+#pragma unroll
+        for (size_t i = 0; i < sizeof(U) / 4; ++i) x.w[i] = q[i];
+        return __builtin_bit_cast(U, x);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -171,6 +182,12 @@ struct Tile {
     const Weight<T> *wfix;       // [S] fixed weights (global, uniform reads)
     int lane;
 
+    // op of node i from the dword that holds it (a scalar load; the op
+    // section is padded to 256 bytes, so the dword is inside it)
+    __device__ __forceinline__ uint32_t op_at(uint32_t i) const {
+        return (cld(reinterpret_cast<const uint32_t *>(g.op) + (i >> 2)) >> ((i & 3u) * 8u)) & 0xffu;
+    }
+
     __device__ __forceinline__ bool ind_hit(uint32_t r) const {
         uint32_t u = (r >> 26) & 15u;
         uint32_t width = ((r >> 24) & 3u) + 1u;
@@ -182,19 +199,19 @@ struct Tile {
 
     __device__ __forceinline__ Weight<T> slot(uint32_t s) const {
         if (s < static_cast<uint32_t>(g.S_ang)) return ang[s * WAVE + lane];
-        return wfix[s];
+        return cld(wfix + s);
     }
 
     // selector leaf: the weight of its variable's current value
     __device__ __forceinline__ Weight<T> sel(uint32_t q) const {
         const uint32_t *rec = g.sel + static_cast<size_t>(q) * SEL_REC;
-        const uint32_t fld = rec[0];
+        const uint32_t fld = cld(rec);
         const uint32_t word = fld >> 8, shift = (fld >> 2) & 63u, width = (fld & 3u) + 1u;
         const uint32_t k = static_cast<uint32_t>((ev[word * WAVE + lane] >> shift) & ((1ull << width) - 1ull));
-        const uint32_t s0 = rec[1], s1 = rec[2], s2 = rec[3], s3 = rec[4];
+        const uint32_t s0 = cld(rec + 1), s1 = cld(rec + 2), s2 = cld(rec + 3), s3 = cld(rec + 4);
         const uint32_t s = k == 0 ? s0 : k == 1 ? s1 : k == 2 ? s2 : k == 3 ? s3 : NO_SLOT;
         if (s == NO_SLOT) return Weight<T>{};
-        return wfix[s];
+        return cld(wfix + s);
     }
 
     // weight of a slot or selector leaf reference
@@ -227,13 +244,13 @@ struct Tile {
     __device__ __forceinline__ cplx<T> sibling_product(uint32_t p, uint32_t e) const {
         constexpr int KC = 4;
         cplx<T> acc{T(1), T(0)};
-        if (g.op[p] == 0) return acc;
-        const uint32_t e0 = g.row_ptr[p], e1 = g.row_ptr[p + 1];
+        if (op_at(p) == 0) return acc;
+        const uint32_t e0 = cld(g.row_ptr + (p)), e1 = cld(g.row_ptr + (p + 1));
         for (uint32_t fb = e0; fb < e1; fb += KC) {
             uint32_t r[KC];
             cplx<T> v[KC];
 #pragma unroll
-            for (int j = 0; j < KC; ++j) r[j] = fb + j < e1 ? g.col[fb + j] : IDENT_REF;
+            for (int j = 0; j < KC; ++j) r[j] = fb + j < e1 ? cld(g.col + (fb + j)) : IDENT_REF;
 #pragma unroll
             for (int j = 0; j < KC; ++j) v[j] = eb_guard(r[j]);
 #pragma unroll
@@ -261,21 +278,21 @@ struct Tile {
     __device__ void forward(int wave, int nwaves) {
         constexpr int KC = 4;
         for (int l = 0; l < g.L; ++l) {
-            const uint32_t n0 = g.level_ptr[l], n1 = g.level_ptr[l + 1];
+            const uint32_t n0 = cld(g.level_ptr + (l)), n1 = cld(g.level_ptr + (l + 1));
             const uint32_t kb = batch_nodes(n1 - n0, nwaves);
             for (uint32_t b0 = n0 + static_cast<uint32_t>(wave) * kb; b0 < n1;
                  b0 += static_cast<uint32_t>(nwaves) * kb) {
                 const uint32_t b1 = b0 + kb < n1 ? b0 + kb : n1;
-                const uint32_t e_end = g.row_ptr[b1];
-                uint32_t t = b0, t_next = g.row_ptr[b0 + 1];
-                bool sum = g.op[b0] == 0;
+                const uint32_t e_end = cld(g.row_ptr + (b1));
+                uint32_t t = b0, t_next = cld(g.row_ptr + (b0 + 1));
+                bool sum = op_at(b0) == 0;
                 double sr = 0.0, si = 0.0;
                 cplx<T> acc{T(1), T(0)};
-                for (uint32_t e = g.row_ptr[b0]; e < e_end; e += KC) {
+                for (uint32_t e = cld(g.row_ptr + (b0)); e < e_end; e += KC) {
                     uint32_t r[KC];
                     cplx<T> v[KC];
 #pragma unroll
-                    for (int j = 0; j < KC; ++j) r[j] = e + j < e_end ? g.col[e + j] : IDENT_REF;
+                    for (int j = 0; j < KC; ++j) r[j] = e + j < e_end ? cld(g.col + (e + j)) : IDENT_REF;
 #pragma unroll
                     for (int j = 0; j < KC; ++j) v[j] = eb_guard(r[j]);
 #pragma unroll
@@ -289,8 +306,8 @@ struct Tile {
                             si = 0.0;
                             acc = {T(1), T(0)};
                             ++t;
-                            t_next = g.row_ptr[t + 1];
-                            sum = g.op[t] == 0;
+                            t_next = cld(g.row_ptr + (t + 1));
+                            sum = op_at(t) == 0;
                         }
                         const uint32_t tag = r[j] >> 30;
                         if (tag == TAG_IND) {
@@ -340,7 +357,7 @@ struct Tile {
             cplx<T> a[KQ], sv[KQ];
 #pragma unroll
             for (int j = 0; j < KQ; ++j)
-                rr[j] = qb + j < q1 ? recs[qb + j] : (static_cast<uint64_t>(NO_SIBLING) << 32);
+                rr[j] = qb + j < q1 ? cld(recs + qb + j) : (static_cast<uint64_t>(NO_SIBLING) << 32);
 #pragma unroll
             for (int j = 0; j < KQ; ++j) {
                 a[j] = adj[static_cast<size_t>(static_cast<uint32_t>(rr[j])) * WAVE + lane];
@@ -358,10 +375,10 @@ struct Tile {
             const uint32_t qe = qb + KQ < q1 ? qb + KQ : q1;
 #pragma unroll 1
             for (uint32_t q = qb; q < qe; ++q) {       // parents with three or more children
-                const uint64_t r = recs[q];
+                const uint64_t r = cld(recs + q);
                 if (static_cast<uint32_t>(r >> 32) != MULTI_SIBLING) continue;
                 const uint32_t pq = static_cast<uint32_t>(r);
-                const cplx<T> t = cmul(adj[static_cast<size_t>(pq) * WAVE + lane], sibling_product(pq, edges[q]));
+                const cplx<T> t = cmul(adj[static_cast<size_t>(pq) * WAVE + lane], sibling_product(pq, cld(edges + q)));
                 ar += static_cast<double>(t.re);
                 ai += static_cast<double>(t.im);
             }
@@ -380,13 +397,13 @@ struct Tile {
         constexpr int KE = sizeof(T) == 4 ? 8 : 4;
         const uint32_t root = static_cast<uint32_t>(g.root);
         for (int l = g.L - 1; l >= 0; --l) {
-            const uint32_t n0 = g.level_ptr[l], n1 = g.level_ptr[l + 1];
+            const uint32_t n0 = cld(g.level_ptr + (l)), n1 = cld(g.level_ptr + (l + 1));
             const uint32_t kb = batch_nodes(n1 - n0, nwaves);
             for (uint32_t b0 = n0 + static_cast<uint32_t>(wave) * kb; b0 < n1;
                  b0 += static_cast<uint32_t>(nwaves) * kb) {
                 const uint32_t b1 = b0 + kb < n1 ? b0 + kb : n1;
-                const uint32_t e_begin = g.par_ptr[b0], e_end = g.par_ptr[b1];
-                uint32_t t = b0, t_next = g.par_ptr[b0 + 1];
+                const uint32_t e_begin = cld(g.par_ptr + (b0)), e_end = cld(g.par_ptr + (b1));
+                uint32_t t = b0, t_next = cld(g.par_ptr + (b0 + 1));
                 double ar = 0.0, ai = 0.0;
                 bool multi = false;
                 for (uint32_t e = e_begin; e < e_end; e += KE) {
@@ -394,7 +411,7 @@ struct Tile {
                     cplx<T> a[KE], sv[KE];
 #pragma unroll
                     for (int j = 0; j < KE; ++j)
-                        rr[j] = e + j < e_end ? g.par_rec[e + j] : (static_cast<uint64_t>(NO_SIBLING) << 32);
+                        rr[j] = e + j < e_end ? cld(g.par_rec + (e + j)) : (static_cast<uint64_t>(NO_SIBLING) << 32);
 #pragma unroll
                     for (int j = 0; j < KE; ++j) {
                         a[j] = adj[static_cast<size_t>(static_cast<uint32_t>(rr[j])) * WAVE + lane];
@@ -410,7 +427,7 @@ struct Tile {
                             ar = 0.0;
                             ai = 0.0;
                             ++t;
-                            t_next = g.par_ptr[t + 1];
+                            t_next = cld(g.par_ptr + (t + 1));
                         }
                         const uint32_t sib = static_cast<uint32_t>(rr[j] >> 32);
                         if (sib == MULTI_SIBLING) {
@@ -432,15 +449,15 @@ struct Tile {
                 if (multi) {
 #pragma unroll 1
                     for (uint32_t c = b0; c < b1; ++c) {
-                        const uint32_t q1 = g.par_ptr[c + 1];
+                        const uint32_t q1 = cld(g.par_ptr + (c + 1));
                         double mr = 0.0, mi = 0.0;
                         bool any = false;
 #pragma unroll 1
-                        for (uint32_t q = g.par_ptr[c]; q < q1; ++q) {
-                            const uint64_t r = g.par_rec[q];
+                        for (uint32_t q = cld(g.par_ptr + (c)); q < q1; ++q) {
+                            const uint64_t r = cld(g.par_rec + (q));
                             if (static_cast<uint32_t>(r >> 32) != MULTI_SIBLING) continue;
                             const uint32_t pq = static_cast<uint32_t>(r);
-                            const cplx<T> tm = cmul(adj[static_cast<size_t>(pq) * WAVE + lane], sibling_product(pq, g.par_edge[q]));
+                            const cplx<T> tm = cmul(adj[static_cast<size_t>(pq) * WAVE + lane], sibling_product(pq, cld(g.par_edge + (q))));
                             mr += static_cast<double>(tm.re);
                             mi += static_cast<double>(tm.im);
                             any = true;
@@ -459,17 +476,17 @@ struct Tile {
     // d root / d lambda_{v=u} for every value u of variable v, written to
     // out[(base + u) * ostride] (indicator leaves plus selector leaves)
     __device__ void ind_derivatives(const cplx<T> *adj, int v, cplx<T> *out, size_t ostride) const {
-        const uint32_t base = g.ind_base[v], dom = g.ind_base[v + 1] - base;
+        const uint32_t base = cld(g.ind_base + (v)), dom = cld(g.ind_base + (v + 1)) - base;
         for (uint32_t u = 0; u < dom; ++u) out[(base + u) * ostride] = leaf_adjoint(adj, base + u);
-        const uint32_t q1 = g.vsel_ptr[v + 1];
-        for (uint32_t qq = g.vsel_ptr[v]; qq < q1; ++qq) {
-            const uint32_t q = g.vsel[qq];
+        const uint32_t q1 = cld(g.vsel_ptr + (v + 1));
+        for (uint32_t qq = cld(g.vsel_ptr + (v)); qq < q1; ++qq) {
+            const uint32_t q = cld(g.vsel + (qq));
             const cplx<T> A = leaf_adjoint(adj, static_cast<uint32_t>(g.n_ind + g.S) + q);
             const uint32_t *rec = g.sel + static_cast<size_t>(q) * SEL_REC;
             for (uint32_t u = 0; u < dom && u < static_cast<uint32_t>(SEL_DOM); ++u) {
-                const uint32_t sl = rec[1 + u];
+                const uint32_t sl = cld(rec + 1 + u);
                 if (sl == NO_SLOT) continue;
-                const cplx<T> t = cmul(A, wval(wfix[sl]));
+                const cplx<T> t = cmul(A, wval(cld(wfix + sl)));
                 cplx<T> &o = out[(base + u) * ostride];
                 o = cadd(o, t);
             }
@@ -478,7 +495,7 @@ struct Tile {
 
     // d root / d leaf (leaf index: indicators first, then slots)
     __device__ __forceinline__ cplx<T> leaf_adjoint(const cplx<T> *adj, uint32_t li) const {
-        return pull_parents(adj, g.leaf_rec, g.leaf_edge, g.leaf_ptr[li], g.leaf_ptr[li + 1]);
+        return pull_parents(adj, g.leaf_rec, g.leaf_edge, cld(g.leaf_ptr + (li)), cld(g.leaf_ptr + (li + 1)));
     }
 };
 
