@@ -48,9 +48,9 @@ KERNELS = os.path.join(ROOT, "paper_2103_17226_amd", "csrc", "qkc_kernels.hip")
 # the copy-kernel calibration, FETCH x 2.0, WRITE x 1.0), valid only for the
 # kernel source they were taken on and the default workload of each leg.
 PROFILED_TRAFFIC = {
-    "k_sample_stream": {"kernel_sha256_16": "411af6b4d036cf36", "bytes": 4203448788992,
+    "k_sample_stream": {"kernel_sha256_16": "b5628148f98f97a1", "bytes": 4169501327360,
                         "profile": "profiles/k_sample_stream_qaoa_n8_p1_dep.md"},
-    "k_eval": {"kernel_sha256_16": "411af6b4d036cf36", "bytes": 360695616853,
+    "k_eval": {"kernel_sha256_16": "b5628148f98f97a1", "bytes": 363483498496,
                "profile": "profiles/k_eval_qaoa_n16_p2_dep_ad.md"},
 }
 

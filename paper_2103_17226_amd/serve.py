@@ -487,8 +487,8 @@ class GraphExecutor:
     # level by level (latency per node step, with the 8- or 16-wave
     # workgroups the library gives small batches), a full chip streams node
     # steps at a measured rate; a request takes the larger of the two
-    NODE_STEP_LATENCY = {"stream": 1.2e-7, "global": 3.0e-7, "lds": 1.0e-8, "eval": 1.0e-7}
-    NODE_STEP_RATE = {"sample": 1.0e11, "eval": 1.7e11}
+    NODE_STEP_LATENCY = {"stream": 7.0e-8, "global": 3.0e-7, "lds": 1.0e-8, "eval": 1.0e-7}
+    NODE_STEP_RATE = {"sample": 1.7e11, "eval": 1.7e11}
 
     def cost(self, req: Request) -> float:
         """Estimated device seconds of a request (for ``max_seconds``).
