@@ -696,16 +696,16 @@ constexpr size_t CU_LDS = 160 * 1024;                      // LDS per compute un
 // blob's own DAG (used when no plan exists).  The streaming kernel has the
 // higher throughput once the batch fills the chip; the LDS-resident one has a
 // much shorter time per chain (its node values never leave the CU), so it
-// wins for batches up to a couple of dozen times the number of chains it
-// holds at once (complex64, 10 sweeps, noisy QAOA ACs of 937 to 3577 nodes,
-// both kernels with their per-call workgroup shapes: the LDS kernel is
-// faster at 16 such groups on every AC and slower at 32 on all but the
-// smallest, whose crossover lies between 21 and 43).
+// wins for batches up to about ten times the number of chains it holds at
+// once (complex64, 10 sweeps, noisy QAOA ACs of 937 to 3577 nodes, both
+// kernels with their per-call workgroup shapes: the LDS kernel is faster at
+// 8 such groups on every AC, slower at 16 on all but one where the two tie,
+// and slower at 10.7 on the smallest).
 // QKC_SAMPLE_KERNEL = stream | lds | global forces one (comparisons, tests);
 // QKC_LDS_BATCH_FACTOR replaces the factor below (measurements).
 enum SampleKernel { SK_STREAM, SK_LDS, SK_GLOBAL };
 
-constexpr int64_t LDS_BATCH_FACTOR = 24;  // LDS kernel up to this many groups of resident chains
+constexpr int64_t LDS_BATCH_FACTOR = 10;  // LDS kernel up to this many groups of resident chains
 
 bool lds_capacity(const ac_graph *g, ac_dtype dt, int &cpw, int64_t &per_cu);
 
