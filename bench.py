@@ -92,7 +92,7 @@ def parse():
     ap.add_argument("--serve-streams", type=int, default=8)
     ap.add_argument("--serve-queue", type=int, default=16)
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
-    ap.add_argument("--serve-max-seconds", type=float, default=1.0,
+    ap.add_argument("--serve-max-seconds", type=float, default=0.5,
                     help="reject requests estimated to hold the device longer than this")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device-to-device three times (calibrates the HBM "
