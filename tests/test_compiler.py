@@ -236,3 +236,17 @@ def test_blob_header_and_layout():
     offs, widths, W_ = circ.var_layout()
     assert ac.var_offset == offs and ac.n_words == W_
     assert len(b) % 8 == 0
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_circuits_match_oracle(seed):
+    # every op kind, CNOTs in both directions, negative and non-unit angle
+    # scales, channels anywhere: the compiled AC against the branch state
+    circ = W.random_circuit(seed)
+    ac = C.compile_circuit(circ)
+    rng = np.random.default_rng(seed)
+    theta = rng.uniform(0, 2 * np.pi, size=circ.n_angles)
+    states = list(all_assignments(circ))
+    for i in rng.choice(len(states), size=min(120, len(states)), replace=False):
+        vals = list(states[i])
+        assert abs(H.evaluate_assignment(ac, theta, vals) - oracle_amp(circ, theta, vals)) < 1e-13, vals

@@ -332,6 +332,33 @@ def qaoa_channel_count(n: int, n_edges: int, p: int) -> int:
     return n + p * (5 * n_edges + n)
 
 
+def random_circuit(seed: int, n: int = None, n_ops: int = None, n_angles: int = 3, n_noise: int = 3) -> Circuit:
+    """A seeded random op list over every op kind: H, CNOT in either
+    direction, RZ/RX with random angle indices and scales (negative and
+    non-unit included), and DEP/AD/PD channels at random places with
+    strengths ~ U[0.02, 0.3]."""
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(2, 6)) if n is None else n
+    n_ops = int(rng.integers(12, 31)) if n_ops is None else n_ops
+    kinds = ["H", "CNOT", "RZ", "RX", "DEP", "AD", "PD"]
+    weights = np.array([2, 3, 3, 3, 1, 1, 1], dtype=float)
+    ops = [("H", q) for q in range(n) if rng.uniform() < 0.5]
+    for _ in range(n_ops):
+        k = kinds[int(rng.choice(len(kinds), p=weights / weights.sum()))]
+        q = int(rng.integers(0, n))
+        if k == "H":
+            ops.append(("H", q))
+        elif k == "CNOT":
+            t = int(rng.integers(0, n - 1))
+            ops.append(("CNOT", q, t if t < q else t + 1))
+        elif k in ("RZ", "RX"):
+            ops.append((k, q, int(rng.integers(0, n_angles)), float(rng.choice([-2.0, -1.0, 0.5, 1.0, 2.0, 3.0]))))
+        else:
+            ops.append((k, q, int(rng.integers(0, n_noise))))
+    noise = [float(x) for x in rng.uniform(0.02, 0.3, size=n_noise)]
+    return Circuit(n=n, ops=ops, n_angles=n_angles, noise=noise, name=f"random_{seed}")
+
+
 def noisy_bell(gamma: float = 0.36) -> Circuit:
     """The paper's running example (Sec. 3.1): H on q0, phase damping on q0,
     CNOT q0 -> q1."""
