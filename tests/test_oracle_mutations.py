@@ -97,3 +97,19 @@ def test_amplitude_instead_of_probability_weights_is_caught(monkeypatch):
         return out
     monkeypatch.setattr(gibbs, "conditional_weights", bad)
     _fails(pins.test_reference_chain_matches_exact_sweep_distribution)
+
+
+def test_amplitude_damping_toward_the_excited_state_is_caught(monkeypatch):
+    good = sim.kraus
+
+    def bad(kind, p):
+        if kind == "AD":            # the mirrored channel: decays |0> -> |1>
+            return [np.array([[np.sqrt(1.0 - p), 0], [0, 1]], dtype=np.complex128),
+                    np.array([[0, 0], [np.sqrt(p), 0]], dtype=np.complex128)]
+        return good(kind, p)
+    monkeypatch.setattr(sim, "kraus", bad)
+    # still a complete channel that breaks bit-flip symmetry ...
+    pins.test_gate_unitarity_and_kraus_completeness()
+    pins.test_bitflip_symmetry_and_ad_breaks_it()
+    # ... but not the relaxation to |0>
+    _fails(pins.test_amplitude_damping_relaxes_toward_the_ground_state)

@@ -158,6 +158,34 @@ def test_bitflip_symmetry_and_ad_breaks_it():
     assert np.max(np.abs(p - p[idx ^ 63])) > 1e-4
 
 
+def test_amplitude_damping_relaxes_toward_the_ground_state():
+    """Amplitude damping is the T1 (energy-relaxation) channel of Sec. 2.2,
+    Table *noise models*: the excited state |1> decays to |0> with
+    probability gamma and |0> is left alone.  Closed forms from the Kraus
+    pair, checked through the density matrix and through the Kraus
+    branches: AD(g)|1> gives P(0) = g; AD(g)|+> gives rho_00 = (1 + g)/2 and
+    |rho_01| = sqrt(1 - g)/2; m rounds leave P(1) = (1 - g)^m."""
+    g = 0.37
+    one = W.Circuit(n=1, ops=[("RX", 0, 0, 1.0), ("AD", 0, 0)], n_angles=1, noise=[g])
+    rho = sim.density_matrix(one, [np.pi])
+    assert np.isclose(rho[0, 0].real, g, atol=1e-14)
+    assert np.isclose(rho[1, 1].real, 1.0 - g, atol=1e-14)
+    # branch amplitudes: k = 1 (the decay event) only lands on |0>
+    f1 = sim.branch_state(one, [np.pi], k=[1])
+    f0 = sim.branch_state(one, [np.pi], k=[0])
+    assert np.isclose(abs(f1[0]) ** 2, g, atol=1e-14) and abs(f1[1]) < 1e-15
+    assert np.isclose(abs(f0[1]) ** 2, 1.0 - g, atol=1e-14) and abs(f0[0]) < 1e-15
+    zero = W.Circuit(n=1, ops=[("AD", 0, 0)], n_angles=0, noise=[g])
+    assert np.allclose(sim.density_matrix(zero, []), [[1, 0], [0, 0]], atol=1e-15)
+    plus = W.Circuit(n=1, ops=[("H", 0), ("AD", 0, 0)], n_angles=0, noise=[g])
+    rho = sim.density_matrix(plus, [])
+    assert np.isclose(rho[0, 0].real, (1.0 + g) / 2.0, atol=1e-14)
+    assert np.isclose(abs(rho[0, 1]), np.sqrt(1.0 - g) / 2.0, atol=1e-14)
+    m = 5
+    rep = W.Circuit(n=1, ops=[("RX", 0, 0, 1.0)] + [("AD", 0, 0)] * m, n_angles=1, noise=[g])
+    assert np.isclose(sim.probabilities(rep, [np.pi])[1], (1.0 - g) ** m, atol=1e-14)
+
+
 def test_zero_noise_equivalence():
     edges = W.ring_graph(4)
     ideal = W.qaoa_maxcut(4, edges, 1)
