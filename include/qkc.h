@@ -188,6 +188,30 @@ ac_status ac_eval_batch(const ac_graph *g, ac_dtype dtype,
                         void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * Allocation-free upward pass, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, results and errors as ac_eval_batch
+ * (bit for bit the same amplitudes and probabilities), without the
+ * workspace: the fixed weights and the per-workgroup node rows live in a
+ * library-owned device array of AC_STATIC_SCRATCH_BYTES on each GPU, whose
+ * address ac_load resolves once per device and which the device holds until
+ * the process ends.  The call allocates nothing (no hipMalloc or allocating
+ * library routine) and launches as many workgroups as the array holds node
+ * rows for.  Returns AC_ERR_UNSUPPORTED, before enqueuing anything, when the
+ * fixed weights (16 bytes per slot) plus one 64-element tile's node rows
+ * (n_internal * 64 * 8 bytes in complex64, * 16 in complex128), each rounded
+ * up to 256 bytes, exceed AC_STATIC_SCRATCH_BYTES.  Every call on a GPU
+ * shares that GPU's array and leaves its last contents there (nothing in it
+ * needs clearing: each call writes what it reads), so calls that overlap in
+ * time on one GPU race: serialise them (one stream, or events).
+ */
+#define AC_STATIC_SCRATCH_BYTES ((size_t)256 << 20)
+ac_status ac_eval_batch_static(const ac_graph *g, ac_dtype dtype,
+                               const double *theta, int32_t P, const double *noise,
+                               const int32_t *param_of, const uint64_t *evidence, int64_t B,
+                               void *amp_out, double *prob_out, void *stream);
+
+/*
  * Upward + downward pass and chain rule (Sec. 3.3.2 downward pass; Sec. 5
  * gradients).  With g_b the cotangent of f_b chosen by `mode`:
  *

@@ -21,7 +21,8 @@ AC_GRAD_COTANGENT, AC_GRAD_PROB, AC_GRAD_LOGPROB = 0, 1, 2
 AC_SAMPLER_STREAM, AC_SAMPLER_LDS, AC_SAMPLER_GLOBAL = 0, 1, 2
 
 EXPORTED = ("ac_load", "ac_free", "ac_info", "ac_last_error", "ac_workspace_size", "ac_sample_shape",
-            "ac_eval_batch", "ac_grad_batch", "ac_sample")
+            "ac_eval_batch", "ac_eval_batch_static", "ac_grad_batch", "ac_sample")
+AC_STATIC_SCRATCH_BYTES = 256 << 20
 
 
 class ACInfo(ctypes.Structure):
@@ -80,6 +81,8 @@ def lib():
     L.ac_sample_shape.restype = ctypes.c_int
     L.ac_eval_batch.argtypes = [vp, ctypes.c_int, vp, i32, vp, vp, vp, i64, vp, vp, vp, sz, vp]
     L.ac_eval_batch.restype = ctypes.c_int
+    L.ac_eval_batch_static.argtypes = [vp, ctypes.c_int, vp, i32, vp, vp, vp, i64, vp, vp, vp]
+    L.ac_eval_batch_static.restype = ctypes.c_int
     L.ac_grad_batch.argtypes = [vp, ctypes.c_int, vp, i32, vp, vp, vp, i64, ctypes.c_int, vp, vp,
                                 vp, vp, vp, vp, vp, sz, vp]
     L.ac_grad_batch.restype = ctypes.c_int

@@ -160,6 +160,27 @@ class ACGraph:
                                       self._stream()))
         return amp, pr
 
+    def eval_static(self, theta, evidence, param_of=None, noise=None, dtype: str = "c64",
+                    prob: bool = True, validate: bool = True, out=None):
+        """``eval`` through ac_eval_batch_static: the library's own static
+        scratch instead of a workspace, so the C call allocates nothing.
+        ``out`` = (amp, prob) tensors to write into (the binding allocates
+        them otherwise).  Calls on one GPU share that scratch: do not run two
+        at once."""
+        code, cdt = _CDTYPE[dtype]
+        theta, evidence, param_of, noise, P, B = self._inputs(theta, evidence, param_of, noise, validate)
+        if out is not None:
+            amp, pr = out
+            if amp.dtype != cdt or amp.numel() < B or (prob and (pr is None or pr.numel() < B)):
+                raise ValueError("out: amplitudes of the dtype and probabilities of at least B entries")
+        else:
+            amp = torch.empty(B, dtype=cdt, device=self.torch_device)
+            pr = torch.empty(B, dtype=torch.float64, device=self.torch_device) if prob else None
+        L.check(L.lib().ac_eval_batch_static(self._h, code, _ptr(theta), P, _ptr(noise), _ptr(param_of),
+                                             _ptr(evidence), B, _ptr(amp), _ptr(pr if prob else None),
+                                             self._stream()))
+        return amp, pr
+
     def grad(self, theta, evidence, param_of=None, mode: str = "cotangent", cotangent=None,
              weight=None, noise=None, dtype: str = "c64", want_amp=False, want_dfdtheta=False,
              want_dind=False, validate: bool = True, ws: Optional[torch.Tensor] = None):

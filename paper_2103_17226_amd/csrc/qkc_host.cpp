@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -44,12 +45,15 @@ template <typename T>
 hipError_t launch_sample_lds(const DevGraph &g, const LdsPlan &lp, int cpw, int wpc, int grid, const double *theta,
                              const double *noise, const SampleArgs &a, hipStream_t st);
 hipError_t launch_zero_f64(double *p, int64_t n, hipStream_t st);
+hipError_t static_scratch_address(void **out);
 template <typename T>
 int resident_blocks(const DevGraph &g, int which, int block);
 
 }  // namespace qkc
 
 using namespace qkc;
+
+static_assert(AC_STATIC_SCRATCH_BYTES == STATIC_SCRATCH_BYTES, "static scratch size in qkc.h and the library agree");
 
 // ---------------------------------------------------------------------------
 // errors
@@ -72,6 +76,38 @@ static ac_status fail_hip(hipError_t e, const char *what) {
         return fail(AC_ERR_OOM, "%s: %s", what, hipGetErrorString(e));
     return fail(AC_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
+
+// ---------------------------------------------------------------------------
+// library-owned scratch of ac_eval_batch_static, one address per device
+// ---------------------------------------------------------------------------
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+
+// Resolve this device's copy of the scratch array once (the device must be
+// current).  Later calls return the stored address.
+hipError_t resolve_scratch(int device) {
+    if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    void *ptr = nullptr;
+    const hipError_t e = static_scratch_address(&ptr);
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = ptr;
+    return hipSuccess;
+}
+
+void *scratch_of(int device) {
+    if (device < 0 || device >= MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
+
+}  // namespace
 
 // ---------------------------------------------------------------------------
 // graph handle
@@ -545,6 +581,14 @@ extern "C" ac_status ac_load(const void *blob, size_t nbytes, int device, ac_gra
         (void)hipSetDevice(prev);
         return fail_hip(e, "ac_load: hipGetDeviceProperties");
     }
+    if (device >= MAX_DEVICES) {
+        (void)hipSetDevice(prev);
+        return fail(AC_ERR_UNSUPPORTED, "ac_load: device index %d above %d", device, MAX_DEVICES - 1);
+    }
+    if ((e = resolve_scratch(device)) != hipSuccess) {
+        (void)hipSetDevice(prev);
+        return fail_hip(e, "ac_load: address of the static scratch");
+    }
     void *dmem = nullptr;
     if ((e = hipMalloc(&dmem, total)) != hipSuccess) {
         (void)hipSetDevice(prev);
@@ -830,7 +874,7 @@ struct Layout {
     int block = BLOCK;         // threads per workgroup
 };
 
-bool make_layout(const ac_graph *g, ac_dtype dt, int64_t batch, int op, Layout &out) {
+bool make_layout(const ac_graph *g, ac_dtype dt, int64_t batch, int op, Layout &out, size_t tile_cap = 0) {
     if (!g || batch < 0 || (dt != AC_C64 && dt != AC_C128) || op < 0 || op > 2) return false;
     const DevGraph &d = g->dev;
     const size_t cs = dt == AC_C64 ? 8 : 16;
@@ -866,6 +910,7 @@ bool make_layout(const ac_graph *g, ac_dtype dt, int64_t batch, int op, Layout &
             const long v = std::atol(env);
             if (v >= 1 && v <= 256) ws_cap = static_cast<size_t>(v) << 30;
         }
+        if (tile_cap) ws_cap = tile_cap;   // a fixed region (the static scratch)
         const int64_t cap = std::max<int64_t>(1, static_cast<int64_t>(ws_cap / (per_wg * cs)));
         grid = std::min(grid, cap);
     }
@@ -969,6 +1014,52 @@ extern "C" ac_status ac_eval_batch(const ac_graph *g, ac_dtype dtype, const doub
                                     L.per_wg_elems, amp_out, prob_out, st);
     }
     if (e != hipSuccess) return fail_hip(e, "ac_eval_batch: launch");
+    return AC_OK;
+}
+
+extern "C" ac_status ac_eval_batch_static(const ac_graph *g, ac_dtype dtype, const double *theta, int32_t P,
+                                          const double *noise, const int32_t *param_of, const uint64_t *evidence,
+                                          int64_t B, void *amp_out, double *prob_out, void *stream) {
+    ac_status s = check_common(g, dtype, theta, P, "ac_eval_batch_static");
+    if (s != AC_OK) return s;
+    if (lds_bytes(g->dev) > LDS_LIMIT)
+        return fail(AC_ERR_UNSUPPORTED, "ac_eval_batch_static: evidence and angle tables exceed LDS");
+    if (B < 0) return fail(AC_ERR_INVALID_ARG, "ac_eval_batch_static: B < 0");
+    if (B == 0) return AC_OK;
+    if (P < 1) return fail(AC_ERR_INVALID_ARG, "ac_eval_batch_static: P must be >= 1 when B > 0");
+    if (!param_of || !evidence || !amp_out)
+        return fail(AC_ERR_INVALID_ARG, "ac_eval_batch_static: null param_of/evidence/amp_out");
+    // the fixed weights come first; the rest of the scratch holds as many
+    // workgroups' node rows as fit (the grid is capped to that number)
+    const size_t cs = dtype == AC_C64 ? 8 : 16;
+    const size_t wfix_bytes = align256(static_cast<size_t>(std::max(g->dev.S, 1)) * 16);
+    const size_t one_tile = align256(static_cast<size_t>(g->dev.N) * WAVE * cs);
+    if (wfix_bytes + one_tile > STATIC_SCRATCH_BYTES)
+        return fail(AC_ERR_UNSUPPORTED,
+                    "ac_eval_batch_static: one 64-element tile needs %zu bytes of scratch (%d nodes), above the "
+                    "%zu-byte static scratch; use ac_eval_batch with a workspace",
+                    wfix_bytes + one_tile, g->dev.N, STATIC_SCRATCH_BYTES);
+    Layout L;
+    make_layout(g, dtype, B, AC_OP_EVAL, L, STATIC_SCRATCH_BYTES - wfix_bytes);
+    if (L.total > STATIC_SCRATCH_BYTES)
+        return fail(AC_ERR_UNSUPPORTED, "ac_eval_batch_static: layout of %zu bytes exceeds the static scratch", L.total);
+    uint8_t *w = static_cast<uint8_t *>(scratch_of(g->device));
+    if (!w) return fail(AC_ERR_DEVICE, "ac_eval_batch_static: static scratch of device %d not resolved", g->device);
+    DeviceGuard dg(g->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e;
+    if (dtype == AC_C64) {
+        e = launch_fixed_slots<float>(g->dev, noise, w + L.wfix_off, st);
+        if (e == hipSuccess)
+            e = launch_eval<float>(g->dev, L.grid, L.block, theta, param_of, P, evidence, B, w + L.wfix_off, w + L.tiles_off,
+                                   L.per_wg_elems, amp_out, prob_out, st);
+    } else {
+        e = launch_fixed_slots<double>(g->dev, noise, w + L.wfix_off, st);
+        if (e == hipSuccess)
+            e = launch_eval<double>(g->dev, L.grid, L.block, theta, param_of, P, evidence, B, w + L.wfix_off, w + L.tiles_off,
+                                    L.per_wg_elems, amp_out, prob_out, st);
+    }
+    if (e != hipSuccess) return fail_hip(e, "ac_eval_batch_static: launch");
     return AC_OK;
 }
 

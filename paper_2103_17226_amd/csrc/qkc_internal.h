@@ -14,6 +14,7 @@ constexpr int MAX_WORDS = 64;         // evidence words staged in LDS
 constexpr int MAX_ANGLE_SLOTS = 64;   // angle-dependent weights per element
 constexpr int MAX_ANGLES = 64;        // columns of theta
 constexpr int MAX_DOM = 16;           // values per evidence variable
+constexpr size_t STATIC_SCRATCH_BYTES = size_t{256} << 20;   // scratch of ac_eval_batch_static per device
 
 // child-reference tags (bits 31..30)
 constexpr uint32_t TAG_NODE = 0u;

@@ -1711,6 +1711,18 @@ __global__ __launch_bounds__(WAVE * WPC) void k_sample_lds(DevGraph g, LdsPlan l
 // launch wrappers (called by the host runtime)
 // ---------------------------------------------------------------------------
 
+// Library-owned scratch of ac_eval_batch_static: the fixed weights and the
+// per-workgroup node rows that ac_eval_batch takes from the caller's
+// workspace.  One copy per device, alive until the process ends.  On the host
+// the name is only a stand-in for the symbol: host code uses the address that
+// static_scratch_address returns for the current device, never the name.
+static __device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+
+// Device address of this device's copy of `scratch` (call with the device current).
+hipError_t static_scratch_address(void **out) {
+    return hipGetSymbolAddress(out, HIP_SYMBOL(scratch));
+}
+
 __global__ void k_fill_zero_f64(double *p, int64_t n) {
     int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0.0;
