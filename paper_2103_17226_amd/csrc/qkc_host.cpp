@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -22,7 +23,7 @@ namespace qkc {
 template <typename T>
 hipError_t launch_fixed_slots(const DevGraph &g, const double *noise, void *wfix, hipStream_t st);
 template <typename T>
-hipError_t launch_eval(const DevGraph &g, int grid, int block, const double *theta, const int32_t *param_of, int P,
+hipError_t launch_eval(const DevGraph &g, const SopPlan &sp, int grid, int block, const double *theta, const int32_t *param_of, int P,
                        const uint64_t *evidence, int64_t B, const void *wfix, void *vals, size_t per_wg_elems,
                        void *amp_out, double *prob_out, hipStream_t st);
 template <typename T>
@@ -38,7 +39,7 @@ template <typename T>
 size_t sample_lds_chain_bytes(const DevGraph &g, const LdsPlan &lp);
 size_t sample_lds_meta_bytes(const LdsPlan &lp);
 template <typename T>
-hipError_t launch_sample_stream(const DevGraph &g, const LdsPlan &lp, int grid, int block, const double *theta,
+hipError_t launch_sample_stream(const DevGraph &g, const SopPlan &sp, int grid, int block, const double *theta,
                                 const void *wfix, void *vals, size_t per_wg_elems, const SampleArgs &a,
                                 hipStream_t st);
 template <typename T>
@@ -117,6 +118,8 @@ struct ac_graph {
     DevGraph dev;
     LdsPlan plan{};
     bool has_plan = false;
+    SopPlan sop{};
+    bool has_sop = false;
     std::vector<uint32_t> plan_level_ptr;   // host copy (launch heuristics)
     void *dmem = nullptr;
     int device = 0;
@@ -353,6 +356,176 @@ HostPlan build_plan(uint32_t N, const uint8_t *op, const uint32_t *row_ptr, cons
     return P;
 }
 
+// Sum-of-products plan (see SopPlan in qkc_internal.h), built on the host.
+struct HostSop {
+    std::vector<uint32_t> level_ptr, fptr, ostart, occ, osel;
+    std::vector<uint64_t> frec;
+    uint32_t S = 0, L = 0, root = 0, max_factors = 0;
+    bool ok = false;
+};
+
+HostSop build_sop(uint32_t N, const uint8_t *op, const uint32_t *row_ptr, const uint32_t *col, uint32_t root,
+                  const std::vector<uint32_t> &ind_base, const std::vector<uint32_t> &var_field, uint32_t n_ind,
+                  uint32_t n_sel, const std::vector<uint32_t> &vsel) {
+    HostSop P;
+    // parents of each node: a product with exactly one parent, a sum, is folded into it
+    std::vector<uint32_t> npar(N, 0), parent(N, 0);
+    for (uint32_t i = 0; i < N; ++i)
+        for (uint32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e)
+            if ((col[e] >> 30) == TAG_NODE) {
+                const uint32_t c = col[e] & REF_MASK;
+                npar[c]++;
+                parent[c] = i;
+            }
+    std::vector<uint8_t> folded(N, 0);
+    for (uint32_t i = 0; i < N; ++i)
+        folded[i] = op[i] == 1 && npar[i] == 1 && i != root && op[parent[i]] == 0;
+    // super-nodes (pre-sort ids): terms as factor lists; node refs hold pre-sort super ids (tag 0)
+    struct SN {
+        std::vector<std::vector<uint32_t>> terms;
+        std::vector<uint8_t> direct;           // per term: a sum's own (non-product) child
+    };
+    std::vector<SN> sn;
+    sn.reserve(N);
+    std::vector<uint32_t> sid(N, 0xFFFFFFFFu);
+    bool bad = false;
+    auto fref = [&](uint32_t r) -> uint32_t {
+        if ((r >> 30) != TAG_NODE) return r;
+        const uint32_t x = sid[r & REF_MASK];
+        if (x == 0xFFFFFFFFu) bad = true;                      // a folded or later node: no plan
+        return x & REF_MASK;
+    };
+    // a term of more than SOP_MAX_FACTORS factors: its leading factors become a
+    // product super-node (multiplied in the same order)
+    auto cap_term = [&](std::vector<uint32_t> t) {
+        while (t.size() > static_cast<size_t>(SOP_MAX_FACTORS)) {
+            SN x;
+            x.terms.emplace_back(t.begin(), t.begin() + SOP_MAX_FACTORS);
+            x.direct.push_back(0);
+            sn.push_back(std::move(x));
+            std::vector<uint32_t> rest;
+            rest.push_back(static_cast<uint32_t>(sn.size() - 1));
+            rest.insert(rest.end(), t.begin() + SOP_MAX_FACTORS, t.end());
+            t.swap(rest);
+        }
+        return t;
+    };
+    for (uint32_t i = 0; i < N; ++i) {
+        if (folded[i]) continue;
+        if (row_ptr[i + 1] <= row_ptr[i]) return P;               // a node without children
+        std::vector<std::vector<uint32_t>> terms;
+        std::vector<uint8_t> direct;
+        if (op[i] == 0) {
+            for (uint32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+                const uint32_t r = col[e];
+                if ((r >> 30) == TAG_NODE && folded[r & REF_MASK]) {
+                    const uint32_t c = r & REF_MASK;
+                    if (row_ptr[c + 1] <= row_ptr[c]) return P;
+                    std::vector<uint32_t> t;
+                    for (uint32_t f = row_ptr[c]; f < row_ptr[c + 1]; ++f) {
+                        if ((col[f] >> 30) == TAG_NODE && folded[col[f] & REF_MASK]) return P;   // not below a sum
+                        t.push_back(fref(col[f]));
+                    }
+                    terms.push_back(cap_term(std::move(t)));
+                    direct.push_back(0);
+                } else {
+                    terms.push_back({fref(r)});
+                    direct.push_back(1);
+                }
+            }
+        } else {
+            std::vector<uint32_t> t;
+            for (uint32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) t.push_back(fref(col[e]));
+            terms.push_back(cap_term(std::move(t)));
+            direct.push_back(0);
+        }
+        SN x;
+        x.terms = std::move(terms);
+        x.direct = std::move(direct);
+        sn.push_back(std::move(x));
+        sid[i] = static_cast<uint32_t>(sn.size() - 1);
+    }
+    if (bad) return P;
+    const uint32_t M = static_cast<uint32_t>(sn.size());
+    if (sid[root] == 0xFFFFFFFFu) return P;
+    // ASAP levels (children come first in sn, since DAG children precede parents)
+    std::vector<uint32_t> lev(M, 0);
+    uint32_t Lmax = 0;
+    for (uint32_t s = 0; s < M; ++s) {
+        uint32_t l = 0;
+        for (const auto &t : sn[s].terms)
+            for (uint32_t r : t)
+                if ((r >> 30) == TAG_NODE) {
+                    if (r >= s) return P;
+                    l = std::max(l, lev[r]);
+                }
+        lev[s] = l + 1;
+        Lmax = std::max(Lmax, lev[s]);
+    }
+    const uint32_t sroot = sid[root];
+    if (lev[sroot] != Lmax) return P;
+    for (uint32_t s = 0; s < M; ++s)
+        if (lev[s] == Lmax && s != sroot) return P;               // unreachable super-nodes
+    std::vector<uint32_t> order(M), newid(M);
+    for (uint32_t s = 0; s < M; ++s) order[s] = s;
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return lev[a] < lev[b]; });
+    for (uint32_t j = 0; j < M; ++j) newid[order[j]] = j;
+    auto pref = [&](uint32_t r) -> uint32_t {
+        return (r >> 30) == TAG_NODE ? newid[r] : encode_leaf(r, var_field);
+    };
+    P.level_ptr.assign(Lmax + 1, 0);
+    for (uint32_t s = 0; s < M; ++s) P.level_ptr[lev[s]]++;
+    for (uint32_t l = 1; l <= Lmax; ++l) P.level_ptr[l] += P.level_ptr[l - 1];
+    P.fptr.assign(M + 1, 0);
+    // occurrences per target
+    std::vector<uint32_t> selpos(n_sel, 0);
+    for (uint32_t k = 0; k < n_sel; ++k) selpos[vsel[k]] = k;
+    const size_t T = static_cast<size_t>(M) + n_ind + n_sel;
+    std::vector<std::vector<std::array<uint32_t, 4>>> occ(T);
+    for (uint32_t j = 0; j < M; ++j) {
+        const SN &x = sn[order[j]];
+        uint32_t nf = 0;
+        for (size_t ti = 0; ti < x.terms.size(); ++ti) {
+            const auto &t = x.terms[ti];
+            for (size_t f = 0; f < t.size(); ++f) {
+                P.frec.push_back(static_cast<uint64_t>(pref(t[f])) | (f + 1 == t.size() ? SOP_LAST_OF_TERM : 0ull) |
+                                 (x.direct[ti] ? SOP_DIRECT : 0ull));
+                ++nf;
+                // occurrence of t[f] as a factor
+                const uint32_t r = t[f], tag = r >> 30;
+                int64_t tg = -1;
+                if (tag == TAG_NODE) tg = newid[r];
+                else if (tag == TAG_IND) {
+                    const uint32_t xx = r & REF_MASK;
+                    tg = static_cast<int64_t>(M) + ind_base[xx & 0xffffffu] + (xx >> 24);
+                } else if (tag == TAG_SEL) {
+                    tg = static_cast<int64_t>(M) + n_ind + selpos[r & REF_MASK];
+                }
+                if (tg < 0) continue;                             // weights need no adjoint here
+                std::array<uint32_t, 4> rec = {j, NO_SIBLING, NO_SIBLING, NO_SIBLING};
+                int k = 1;
+                for (size_t g = 0; g < t.size(); ++g)
+                    if (g != f) rec[k++] = pref(t[g]);
+                occ[tg].push_back(rec);
+            }
+        }
+        P.fptr[j + 1] = P.fptr[j] + nf;
+        P.max_factors = std::max(P.max_factors, nf);
+    }
+    P.ostart.assign(T + 1, 0);
+    for (size_t t = 0; t < T; ++t) {
+        P.ostart[t + 1] = P.ostart[t] + static_cast<uint32_t>(occ[t].size());
+        for (const auto &rec : occ[t]) P.occ.insert(P.occ.end(), rec.begin(), rec.end());
+    }
+    for (uint32_t k = 0; k < n_sel; ++k)
+        P.osel.insert(P.osel.end(), occ[static_cast<size_t>(M) + n_ind + k].size(), vsel[k]);
+    P.S = M;
+    P.L = Lmax;
+    P.root = newid[sroot];
+    P.ok = true;
+    return P;
+}
+
 }  // namespace
 
 extern "C" const char *ac_last_error(void) { return g_last_error.c_str(); }
@@ -525,6 +698,7 @@ extern "C" ac_status ac_load(const void *blob, size_t nbytes, int device, ac_gra
 
     HostPlan hp = build_plan(N, op, row_ptr, col, root, ind_base, var_field, n_ind, n_sel, n_slots, sel_dev,
                              vsel_ptr, vsel);
+    HostSop hs = build_sop(N, op, row_ptr, col, root, ind_base, var_field, n_ind, n_sel, vsel);
 
     // ---- device copy: one allocation, 256-byte aligned sections
     struct Sec { const void *src; size_t bytes; size_t off; };
@@ -559,6 +733,12 @@ extern "C" ac_status ac_load(const void *blob, size_t nbytes, int device, ac_gra
         {par_rec.data(), par_rec.size() * sizeof(uint64_t), 0},
         {leaf_rec.data(), leaf_rec.size() * sizeof(uint64_t), 0},
         {hp.esel.data(), hp.esel.size() * sizeof(uint32_t), 0},
+        {hs.level_ptr.data(), hs.level_ptr.size() * sizeof(uint32_t), 0},
+        {hs.fptr.data(), hs.fptr.size() * sizeof(uint32_t), 0},
+        {hs.frec.data(), hs.frec.size() * sizeof(uint64_t), 0},
+        {hs.ostart.data(), hs.ostart.size() * sizeof(uint32_t), 0},
+        {hs.occ.data(), hs.occ.size() * sizeof(uint32_t), 0},
+        {hs.osel.data(), hs.osel.size() * sizeof(uint32_t), 0},
     };
     size_t total = 0;
     for (auto &s : secs) {
@@ -648,6 +828,20 @@ extern "C" ac_status ac_load(const void *blob, size_t nbytes, int device, ac_gra
         lp.R = static_cast<int64_t>(hp.orec.size());
         g->has_plan = true;
         g->plan_level_ptr = hp.level_ptr;
+    }
+    if (hs.ok) {
+        SopPlan &sp = g->sop;
+        sp.level_ptr = reinterpret_cast<const uint32_t *>(at(30));
+        sp.fptr = reinterpret_cast<const uint32_t *>(at(31));
+        sp.frec = reinterpret_cast<const uint64_t *>(at(32));
+        sp.ostart = reinterpret_cast<const uint32_t *>(at(33));
+        sp.occ = reinterpret_cast<const uint32_t *>(at(34));
+        sp.osel = reinterpret_cast<const uint32_t *>(at(35));
+        sp.S = static_cast<int32_t>(hs.S);
+        sp.L = static_cast<int32_t>(hs.L);
+        sp.root = static_cast<int32_t>(hs.root);
+        sp.max_factors = static_cast<int32_t>(hs.max_factors);
+        g->has_sop = true;
     }
     d.N = static_cast<int32_t>(N);
     d.E = E;
@@ -754,11 +948,12 @@ constexpr int64_t LDS_BATCH_FACTOR = 10;  // LDS kernel up to this many groups o
 bool lds_capacity(const ac_graph *g, ac_dtype dt, int &cpw, int64_t &per_cu);
 
 SampleKernel sample_kernel(const ac_graph *g, ac_dtype dt, int64_t chains) {
-    if (!g->has_plan) return SK_GLOBAL;
-    // the streaming sampler addresses a workgroup's rows through a buffer
-    // resource with 32-bit offsets: its region must stay below 2 GiB
-    const size_t stream_rows = 2 * static_cast<size_t>(g->plan.N) + g->dev.n_ind;
-    const bool stream_ok = stream_rows * WAVE * (dt == AC_C64 ? 8 : 16) < (size_t{1} << 31);
+    // the streaming sampler runs on the sum-of-products plan and addresses a
+    // workgroup's rows through a buffer resource with 32-bit offsets: its
+    // region must stay below 2 GiB
+    const size_t stream_rows = 2 * static_cast<size_t>(g->sop.S) + g->dev.n_ind;
+    const bool stream_ok = g->has_sop && stream_rows * WAVE * (dt == AC_C64 ? 8 : 16) < (size_t{1} << 31);
+    if (!g->has_plan) return stream_ok ? SK_STREAM : SK_GLOBAL;
     const char *kern = std::getenv("QKC_SAMPLE_KERNEL");
     if (kern && std::strcmp(kern, "global") == 0) return SK_GLOBAL;
     if (kern && std::strcmp(kern, "lds") == 0) return SK_LDS;
@@ -867,6 +1062,11 @@ int wide_block_for(const ac_graph *g, ac_dtype dt, int64_t batch, int kid, int &
     return BLOCK << j;
 }
 
+// The upward pass runs on the sum-of-products plan when there is one (rows
+// only for super-nodes), else on the DAG.
+SopPlan eval_plan(const ac_graph *g) { return g->has_sop ? g->sop : SopPlan{}; }
+size_t eval_rows(const ac_graph *g) { return g->has_sop ? static_cast<size_t>(g->sop.S) : static_cast<size_t>(g->dev.N); }
+
 struct Layout {
     size_t wfix_off = 0, contrib_off = 0, tiles_off = 0, total = 0;
     size_t per_wg_elems = 0;   // complex elements per workgroup buffer
@@ -880,7 +1080,7 @@ bool make_layout(const ac_graph *g, ac_dtype dt, int64_t batch, int op, Layout &
     const size_t cs = dt == AC_C64 ? 8 : 16;
     size_t rows = 0;
     int kid = 0;
-    if (op == AC_OP_EVAL) rows = d.N;
+    if (op == AC_OP_EVAL) rows = eval_rows(g);
     else if (op == AC_OP_GRAD) {
         rows = 2 * static_cast<size_t>(d.N) + d.S_ang + d.n_ind;
         kid = 1;
@@ -889,7 +1089,7 @@ bool make_layout(const ac_graph *g, ac_dtype dt, int64_t batch, int op, Layout &
         const SampleKernel sk = sample_kernel(g, dt, batch);
         if (sk == SK_LDS && sample_lds_shape(g, dt, batch, cpw, lgrid)) rows = 0;
         else if (sk == SK_STREAM) {
-            rows = 2 * static_cast<size_t>(g->plan.N) + d.n_ind;
+            rows = 2 * static_cast<size_t>(g->sop.S) + d.n_ind;
             kid = 3;
         } else {
             rows = 2 * static_cast<size_t>(d.N) + d.n_ind;
@@ -1005,12 +1205,12 @@ extern "C" ac_status ac_eval_batch(const ac_graph *g, ac_dtype dtype, const doub
     if (dtype == AC_C64) {
         e = launch_fixed_slots<float>(g->dev, noise, w + L.wfix_off, st);
         if (e == hipSuccess)
-            e = launch_eval<float>(g->dev, L.grid, L.block, theta, param_of, P, evidence, B, w + L.wfix_off, w + L.tiles_off,
+            e = launch_eval<float>(g->dev, eval_plan(g), L.grid, L.block, theta, param_of, P, evidence, B, w + L.wfix_off, w + L.tiles_off,
                                    L.per_wg_elems, amp_out, prob_out, st);
     } else {
         e = launch_fixed_slots<double>(g->dev, noise, w + L.wfix_off, st);
         if (e == hipSuccess)
-            e = launch_eval<double>(g->dev, L.grid, L.block, theta, param_of, P, evidence, B, w + L.wfix_off, w + L.tiles_off,
+            e = launch_eval<double>(g->dev, eval_plan(g), L.grid, L.block, theta, param_of, P, evidence, B, w + L.wfix_off, w + L.tiles_off,
                                     L.per_wg_elems, amp_out, prob_out, st);
     }
     if (e != hipSuccess) return fail_hip(e, "ac_eval_batch: launch");
@@ -1033,12 +1233,12 @@ extern "C" ac_status ac_eval_batch_static(const ac_graph *g, ac_dtype dtype, con
     // workgroups' node rows as fit (the grid is capped to that number)
     const size_t cs = dtype == AC_C64 ? 8 : 16;
     const size_t wfix_bytes = align256(static_cast<size_t>(std::max(g->dev.S, 1)) * 16);
-    const size_t one_tile = align256(static_cast<size_t>(g->dev.N) * WAVE * cs);
+    const size_t one_tile = align256(eval_rows(g) * WAVE * cs);
     if (wfix_bytes + one_tile > STATIC_SCRATCH_BYTES)
         return fail(AC_ERR_UNSUPPORTED,
-                    "ac_eval_batch_static: one 64-element tile needs %zu bytes of scratch (%d nodes), above the "
+                    "ac_eval_batch_static: one 64-element tile needs %zu bytes of scratch (%zu node rows), above the "
                     "%zu-byte static scratch; use ac_eval_batch with a workspace",
-                    wfix_bytes + one_tile, g->dev.N, STATIC_SCRATCH_BYTES);
+                    wfix_bytes + one_tile, eval_rows(g), STATIC_SCRATCH_BYTES);
     Layout L;
     make_layout(g, dtype, B, AC_OP_EVAL, L, STATIC_SCRATCH_BYTES - wfix_bytes);
     if (L.total > STATIC_SCRATCH_BYTES)
@@ -1051,12 +1251,12 @@ extern "C" ac_status ac_eval_batch_static(const ac_graph *g, ac_dtype dtype, con
     if (dtype == AC_C64) {
         e = launch_fixed_slots<float>(g->dev, noise, w + L.wfix_off, st);
         if (e == hipSuccess)
-            e = launch_eval<float>(g->dev, L.grid, L.block, theta, param_of, P, evidence, B, w + L.wfix_off, w + L.tiles_off,
+            e = launch_eval<float>(g->dev, eval_plan(g), L.grid, L.block, theta, param_of, P, evidence, B, w + L.wfix_off, w + L.tiles_off,
                                    L.per_wg_elems, amp_out, prob_out, st);
     } else {
         e = launch_fixed_slots<double>(g->dev, noise, w + L.wfix_off, st);
         if (e == hipSuccess)
-            e = launch_eval<double>(g->dev, L.grid, L.block, theta, param_of, P, evidence, B, w + L.wfix_off, w + L.tiles_off,
+            e = launch_eval<double>(g->dev, eval_plan(g), L.grid, L.block, theta, param_of, P, evidence, B, w + L.wfix_off, w + L.tiles_off,
                                     L.per_wg_elems, amp_out, prob_out, st);
     }
     if (e != hipSuccess) return fail_hip(e, "ac_eval_batch_static: launch");
@@ -1174,13 +1374,13 @@ extern "C" ac_status ac_sample(const ac_graph *g, ac_dtype dtype, const double *
         if (dtype == AC_C64) {
             e = launch_fixed_slots<float>(g->dev, noise, w + L.wfix_off, st);
             if (e == hipSuccess)
-                e = launch_sample_stream<float>(g->dev, g->plan, L.grid, L.block, theta, w + L.wfix_off,
+                e = launch_sample_stream<float>(g->dev, g->sop, L.grid, L.block, theta, w + L.wfix_off,
                                                 w + L.tiles_off,
                                                 L.per_wg_elems, a, st);
         } else {
             e = launch_fixed_slots<double>(g->dev, noise, w + L.wfix_off, st);
             if (e == hipSuccess)
-                e = launch_sample_stream<double>(g->dev, g->plan, L.grid, L.block, theta, w + L.wfix_off,
+                e = launch_sample_stream<double>(g->dev, g->sop, L.grid, L.block, theta, w + L.wfix_off,
                                                  w + L.tiles_off,
                                                  L.per_wg_elems, a, st);
         }

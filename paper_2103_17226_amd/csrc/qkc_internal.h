@@ -123,6 +123,43 @@ struct LdsPlan {
     int64_t R;
 };
 
+// Sum-of-products plan of the DAG, derived at load time for the streaming
+// sampler and the upward pass.  Every product node whose only parent is a sum
+// is folded into that sum as one of its terms, so a super-node is
+//   value = sum over its terms t of (product over the factors f of t)
+// where a factor is a leaf or another super-node; a term holds at most
+// SOP_MAX_FACTORS factors (a longer product is split into product
+// super-nodes, multiplied in the same order).  Folded products never get a
+// row of their own: their values stay in registers.  Super-nodes are levelled
+// as soon as possible and sorted by level.
+//   level_ptr[l]  super-nodes of level l are [level_ptr[l], level_ptr[l+1])
+//   fptr[s]       factors of super-node s are [fptr[s], fptr[s+1]), term by term
+//   frec[f]       factor reference (tag 0: super-node index; leaves as in the
+//                 device graph) | SOP_LAST_OF_TERM if it ends its term
+//                 | SOP_DIRECT if the term is a sum's child that is not a product
+//   ostart[t]     occurrences of target t as a factor: super-node t < S,
+//                 indicator leaf S + i, selector S + n_ind + k with the
+//                 selectors in per-variable order (vsel)
+//   occ[4 o ..]   {parent super-node, three sibling references}: the
+//                 occurrence contributes adj[parent] times the product of its
+//                 siblings (the other factors of its term; NO_SIBLING pads)
+//   osel[o - ostart[S + n_ind]]  selector of each selector occurrence
+constexpr int SOP_MAX_FACTORS = 4;
+constexpr uint64_t SOP_LAST_OF_TERM = 1ull << 32;
+// a term that is a sum's own child (not a folded product): its one factor is
+// added as it is rather than multiplied into a product
+constexpr uint64_t SOP_DIRECT = 1ull << 33;
+struct SopPlan {
+    const uint32_t *level_ptr;  // [L+1]
+    const uint32_t *fptr;       // [S+1]
+    const uint64_t *frec;       // [fptr[S]]
+    const uint32_t *ostart;     // [S + n_ind + n_sel + 1]
+    const uint32_t *occ;        // [4 * ostart[S + n_ind + n_sel]]
+    const uint32_t *osel;       // [selector occurrences]
+    int32_t S, L, root;
+    int32_t max_factors;        // most factors of one super-node
+};
+
 // Arguments of the Gibbs sampler kernel.
 struct SampleArgs {
     int64_t total_chains;

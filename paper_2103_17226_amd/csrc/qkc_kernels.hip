@@ -21,9 +21,14 @@ struct cplx {
     T re, im;
 };
 
-template <typename T>
-__device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
-    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+// Complex product with its fused multiply-adds written out, so that every
+// pass rounds it the same way wherever it is inlined (contraction left to
+// the compiler may pick a different fused form at different call sites).
+__device__ __forceinline__ cplx<float> cmul(cplx<float> a, cplx<float> b) {
+    return {__builtin_fmaf(a.re, b.re, -(a.im * b.im)), __builtin_fmaf(a.re, b.im, a.im * b.re)};
+}
+__device__ __forceinline__ cplx<double> cmul(cplx<double> a, cplx<double> b) {
+    return {__builtin_fma(a.re, b.re, -(a.im * b.im)), __builtin_fma(a.re, b.im, a.im * b.re)};
 }
 template <typename T>
 __device__ __forceinline__ cplx<T> cadd(cplx<T> a, cplx<T> b) {
@@ -341,6 +346,80 @@ struct Tile {
         }
     }
 
+    // Upward pass on the sum-of-products plan (rows only for super-nodes):
+    // the same arithmetic as forward() on the DAG -- a folded product's
+    // factors are multiplied in child order in the pass dtype (weights at
+    // full precision by wmul), a sum adds its terms in FP64 in child order,
+    // a child of a sum that is not a product is added as it is (a weight in
+    // FP64) -- so the root comes out bit for bit the same.  A wave takes up to four
+    // consecutive super-nodes of a level and walks their factors in groups of
+    // KC whose rows are loaded together.
+    __device__ void forward_sop(const SopPlan &sp, int wave, int nwaves) {
+        constexpr int KC = 8;
+        for (int l = 0; l < sp.L; ++l) {
+            const uint32_t n0 = cld(sp.level_ptr + l), n1 = cld(sp.level_ptr + l + 1);
+            const uint32_t kb = batch_nodes(n1 - n0, nwaves);
+            for (uint32_t b0 = n0 + static_cast<uint32_t>(wave) * kb; b0 < n1;
+                 b0 += static_cast<uint32_t>(nwaves) * kb) {
+                const uint32_t b1 = b0 + kb < n1 ? b0 + kb : n1;
+                const uint32_t f_end = cld(sp.fptr + b1);
+                uint32_t t = b0, t_next = cld(sp.fptr + b0 + 1);
+                double sr = 0.0, si = 0.0;
+                cplx<T> acc{T(1), T(0)};
+                for (uint32_t f = cld(sp.fptr + b0); f < f_end; f += KC) {
+                    uint64_t rec[KC];
+                    cplx<T> v[KC];
+#pragma unroll
+                    for (int j = 0; j < KC; ++j) rec[j] = f + j < f_end ? cld(sp.frec + f + j) : static_cast<uint64_t>(IDENT_REF);
+#pragma unroll
+                    for (int j = 0; j < KC; ++j) v[j] = eb_guard(static_cast<uint32_t>(rec[j]));
+#pragma unroll
+                    for (int j = 0; j < KC; ++j) {
+                        const uint32_t ff = f + static_cast<uint32_t>(j);
+                        if (ff >= f_end) break;
+                        while (ff >= t_next) {          // super-node t has all its terms
+                            val[static_cast<size_t>(t) * WAVE + lane] = cplx<T>{static_cast<T>(sr), static_cast<T>(si)};
+                            sr = 0.0;
+                            si = 0.0;
+                            ++t;
+                            t_next = cld(sp.fptr + (t + 1));
+                        }
+                        const uint32_t r = static_cast<uint32_t>(rec[j]);
+                        const bool last = (rec[j] & SOP_LAST_OF_TERM) != 0;
+                        const uint32_t tag = r >> 30;
+                        if (rec[j] & SOP_DIRECT) {      // a sum's own child: added as it is
+                            if (tag == TAG_IND) {
+                                sr += ind_hit(r) ? 1.0 : 0.0;
+                            } else if (tag == TAG_NODE) {
+                                sr += static_cast<double>(v[j].re);
+                                si += static_cast<double>(v[j].im);
+                            } else {
+                                const cplx<double> d = wsum(weight(r));
+                                sr += d.re;
+                                si += d.im;
+                            }
+                            continue;
+                        }
+                        if (tag == TAG_IND) {
+                            if (!ind_hit(r)) acc = {T(0), T(0)};
+                        } else if (tag == TAG_NODE) {
+                            acc = cmul(acc, v[j]);
+                        } else {
+                            acc = wmul(acc, weight(r));
+                        }
+                        if (last) {
+                            sr += static_cast<double>(acc.re);
+                            si += static_cast<double>(acc.im);
+                            acc = {T(1), T(0)};
+                        }
+                    }
+                }
+                val[static_cast<size_t>(t) * WAVE + lane] = cplx<T>{static_cast<T>(sr), static_cast<T>(si)};
+            }
+            __syncthreads();
+        }
+    }
+
     // adj[parent] * (product of the other children) summed in FP64 over the
     // parent edges q0..q1 of a node or leaf.  recs holds one record per edge
     // (parent | sibling << 32, see DevGraph), so a group of KQ edges needs one
@@ -525,7 +604,7 @@ __device__ bool stage_tile(const DevGraph &g, uint64_t *ev_s, Weight<T> *ang_s, 
 // more resident waves hide it (16-qubit noisy QAOA, 262,144 amplitudes:
 // 6 waves 74 ms, 8 waves 66 ms)
 template <typename T>
-__global__ __launch_bounds__(MAX_BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 1, 8))) void k_eval(DevGraph g, const double *theta, const int32_t *param_of, int P,
+__global__ __launch_bounds__(MAX_BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 1, 8))) void k_eval(DevGraph g, SopPlan sp, const double *theta, const int32_t *param_of, int P,
                                                 const uint64_t *evidence, int64_t B, const Weight<T> *wfix,
                                                 cplx<T> *vals, size_t per_wg, cplx<T> *amp_out,
                                                 double *prob_out) {
@@ -543,9 +622,10 @@ __global__ __launch_bounds__(MAX_BLOCK) __attribute__((amdgpu_waves_per_eu(sizeo
         const bool valid = b < B;
         const bool in_range = stage_tile(g, ev_s, ang_s, evidence, param_of, P, theta, b, valid, lane, wave, nwaves);
         __syncthreads();
-        t.forward(wave, nwaves);
+        if (sp.S > 0) t.forward_sop(sp, wave, nwaves);
+        else t.forward(wave, nwaves);
         if (wave == 0 && valid) {
-            cplx<T> f = val[static_cast<uint32_t>(g.root) * WAVE + lane];
+            cplx<T> f = val[static_cast<uint32_t>(sp.S > 0 ? sp.root : g.root) * WAVE + lane];
             if (!in_range) f = {T(NAN), T(NAN)};
             amp_out[b] = f;
             if (prob_out) {
@@ -894,8 +974,25 @@ struct RowBuf {
     }
 };
 
-// Rows of the region: node values [0, N), node adjoints [N, 2N), indicator
-// derivatives d root / d lambda_{v=u} [2N, 2N + n_ind).
+// Batch sizes of the streaming passes on the sum-of-products plan
+// (complex64; complex128 halves the factor and occurrence groups):
+// super-nodes per wave batch, factors per group of row loads (upward pass),
+// occurrences per group (downward pass, leaf step).
+#ifndef SOP_KB
+#define SOP_KB 4
+#endif
+#ifndef SOP_KF
+#define SOP_KF 8
+#endif
+#ifndef SOP_KE
+#define SOP_KE 4
+#endif
+#ifndef SOP_KE_LEAF
+#define SOP_KE_LEAF 2
+#endif
+
+// Rows of the region: super-node values [0, S), adjoints [S, 2S), indicator
+// derivatives d root / d lambda_{v=u} [2S, 2S + n_ind).
 template <typename T>
 struct StreamTile {
     DevGraph g;
@@ -936,93 +1033,130 @@ struct StreamTile {
         return sl == NO_SLOT ? cplx<T>{T(0), T(0)} : wfix[sl];
     }
 
-    __device__ void forward(const LdsPlan &lp, int wave, int nwaves) {
-        constexpr int KB = sizeof(T) == 4 ? 8 : 4;
-        for (int l = 0; l < lp.L; ++l) {
-            const uint32_t n0 = cld(lp.level_ptr + l), n1 = cld(lp.level_ptr + l + 1), np = cld(lp.level_prod + l);
+    // Upward pass on the sum-of-products plan.  A wave takes KB consecutive
+    // super-nodes of a level at a time and walks their factors (contiguous in
+    // frec) in groups of KF whose rows are all loaded before the first is
+    // used; a term's product is formed in registers in factor order, the
+    // terms are added in order and a super-node's row is stored once its
+    // last factor is in.
+    __device__ void forward(const SopPlan &sp, int wave, int nwaves) {
+        constexpr int KB = SOP_KB;
+        constexpr int KF = sizeof(T) == 4 ? SOP_KF : SOP_KF / 2;
+        for (int l = 0; l < sp.L; ++l) {
+            const uint32_t n0 = cld(sp.level_ptr + l), n1 = cld(sp.level_ptr + l + 1);
             for (uint32_t b0 = n0 + static_cast<uint32_t>(wave) * KB; b0 < n1; b0 += static_cast<uint32_t>(nwaves) * KB) {
-                uint64_t rec[KB];
-                cplx<T> va[KB], vb[KB];
+                const uint32_t b1 = b0 + KB < n1 ? b0 + KB : n1;
+                const uint32_t f_end = cld(sp.fptr + b1);
+                uint32_t t = b0, t_next = cld(sp.fptr + b0 + 1);
+                cplx<T> sum{T(0), T(0)}, term{T(1), T(0)};
+                for (uint32_t f = cld(sp.fptr + b0); f < f_end; f += KF) {
+                    uint64_t rec[KF];
+                    cplx<T> v[KF];
 #pragma unroll
-                for (int j = 0; j < KB; ++j) rec[j] = b0 + j < n1 ? cld(lp.fwd + b0 + j) : ~0ull;
+                    for (int j = 0; j < KF; ++j) rec[j] = f + j < f_end ? cld(sp.frec + f + j) : static_cast<uint64_t>(IDENT_REF);
 #pragma unroll
-                for (int j = 0; j < KB; ++j) {
-                    va[j] = row(static_cast<uint32_t>(rec[j]));
-                    vb[j] = row(static_cast<uint32_t>(rec[j] >> 32));
+                    for (int j = 0; j < KF; ++j) v[j] = row(static_cast<uint32_t>(rec[j]));
+#pragma unroll
+                    for (int j = 0; j < KF; ++j) {
+                        const uint32_t ff = f + static_cast<uint32_t>(j);
+                        if (ff >= f_end) break;
+                        while (ff >= t_next) {               // super-node t has all its terms
+                            rb.st(t, sum);
+                            sum = {T(0), T(0)};
+                            ++t;
+                            t_next = cld(sp.fptr + t + 1);
+                        }
+                        term = cmul(term, pick(static_cast<uint32_t>(rec[j]), v[j]));
+                        if (rec[j] & SOP_LAST_OF_TERM) {
+                            sum = cadd(sum, term);
+                            term = {T(1), T(0)};
+                        }
+                    }
                 }
-#pragma unroll
-                for (int j = 0; j < KB; ++j) {
-                    const uint32_t ra = static_cast<uint32_t>(rec[j]), rb = static_cast<uint32_t>(rec[j] >> 32);
-                    const bool prod = b0 + j >= np;
-                    va[j] = b0 + j < n1 ? pick(ra, va[j]) : cplx<T>{T(0), T(0)};
-                    vb[j] = rb != IDENT_REF ? pick(rb, vb[j]) : cplx<T>{prod ? T(1) : T(0), T(0)};
-                }
-#pragma unroll
-                for (int j = 0; j < KB; ++j) {
-                    if (b0 + j < n1)
-                        rb.st(b0 + j, b0 + j >= np ? cmul(va[j], vb[j]) : cadd(va[j], vb[j]));
-                }
+                rb.st(t, sum);                                // every super-node has a factor: t = b1 - 1
             }
             level_sync(nwaves);
         }
     }
 
-    // Adjoint sums of the targets [t0, t1) (plan nodes, then indicator and
-    // selector leaves): out(t, sum over the parent edges of t of
-    // adj[parent] * value(sibling)), the edges in increasing parent order.
-    // The edges of the whole range are walked in batches of KE whose row
-    // loads are all issued before any term is added, so a target with many
-    // parents costs batches, not one dependent load per parent.
+    // term of one occurrence: adj[parent] times its (up to three) siblings
+    __device__ __forceinline__ cplx<T> occ_term(const uint32_t (&r)[4], const cplx<T> &ap, const cplx<T> &s0,
+                                                const cplx<T> &s1, const cplx<T> &s2) const {
+        cplx<T> term = ap;
+        if (r[1] != NO_SIBLING) term = cmul(term, pick(r[1], s0));
+        if (r[2] != NO_SIBLING) term = cmul(term, pick(r[2], s1));
+        if (r[3] != NO_SIBLING) term = cmul(term, pick(r[3], s2));
+        return term;
+    }
+
+    __device__ __forceinline__ void load_occ(const SopPlan &sp, uint32_t o, bool in, uint32_t (&r)[4]) const {
+        if (in) {
+            const uint32_t *q = sp.occ + 4 * static_cast<size_t>(o);
+            r[0] = cld(q);
+            r[1] = cld(q + 1);
+            r[2] = cld(q + 2);
+            r[3] = cld(q + 3);
+        } else {
+            r[0] = 0u;
+            r[1] = r[2] = r[3] = NO_SIBLING;
+        }
+    }
+
+    // Adjoint sums of the targets [t0, t1) (super-nodes, then indicator and
+    // selector leaves): out(t, sum over the occurrences of t of adj[parent] *
+    // siblings), the occurrences in increasing parent order.  The occurrences
+    // of the whole range are walked in groups of KE whose row loads (adjoint
+    // and sibling rows) are all issued before any term is added.
     template <typename Out>
-    __device__ __forceinline__ void pull_targets(const LdsPlan &lp, uint32_t t0, uint32_t t1, Out out) const {
-        constexpr int KE = sizeof(T) == 4 ? 8 : 4;
-        const uint32_t e_end = cld(lp.estart + t1);
+    __device__ __forceinline__ void pull_targets(const SopPlan &sp, uint32_t t0, uint32_t t1, Out out) const {
+        constexpr int KE = sizeof(T) == 4 ? SOP_KE : SOP_KE / 2;
+        const uint32_t e_end = cld(sp.ostart + t1);
         uint32_t t = t0;
-        uint32_t t_next = cld(lp.estart + t0 + 1);      // first edge past target t
+        uint32_t t_next = cld(sp.ostart + t0 + 1);      // first occurrence past target t
         double ar = 0.0, ai = 0.0;
-        for (uint32_t e = cld(lp.estart + t0); e < e_end; e += KE) {
-            uint64_t rr[KE];
-            cplx<T> ap[KE], sv[KE];
+        for (uint32_t e = cld(sp.ostart + t0); e < e_end; e += KE) {
+            uint32_t rr[KE][4];
+            cplx<T> ap[KE], s0[KE], s1[KE], s2[KE];
 #pragma unroll
-            for (int j = 0; j < KE; ++j)
-                rr[j] = e + j < e_end ? cld(lp.edg + e + j) : (static_cast<uint64_t>(NO_SIBLING) << 32);
+            for (int j = 0; j < KE; ++j) load_occ(sp, e + j, e + j < e_end, rr[j]);
 #pragma unroll
             for (int j = 0; j < KE; ++j) {
-                ap[j] = rb.ld(adj0 + static_cast<uint32_t>(rr[j]));
-                sv[j] = row(static_cast<uint32_t>(rr[j] >> 32));
+                ap[j] = rb.ld(adj0 + rr[j][0]);
+                s0[j] = row(rr[j][1]);
+                s1[j] = row(rr[j][2]);
+                s2[j] = row(rr[j][3]);
             }
 #pragma unroll
             for (int j = 0; j < KE; ++j) {
                 const uint32_t ee = e + static_cast<uint32_t>(j);
                 if (ee >= e_end) break;
-                while (ee >= t_next) {            // every edge of target t is in
+                while (ee >= t_next) {            // every occurrence of target t is in
                     out(t, cplx<T>{static_cast<T>(ar), static_cast<T>(ai)});
                     ar = 0.0;
                     ai = 0.0;
                     ++t;
-                    t_next = cld(lp.estart + t + 1);
+                    t_next = cld(sp.ostart + t + 1);
                 }
-                const uint32_t sb = static_cast<uint32_t>(rr[j] >> 32);
-                const cplx<T> term = sb != NO_SIBLING ? cmul(ap[j], pick(sb, sv[j])) : ap[j];
+                const cplx<T> term = occ_term(rr[j], ap[j], s0[j], s1[j], s2[j]);
                 ar += static_cast<double>(term.re);
                 ai += static_cast<double>(term.im);
             }
         }
-        for (; t < t1; ++t) {                      // the last target with edges, and any without
+        for (; t < t1; ++t) {                      // the last target with occurrences, and any without
             out(t, cplx<T>{static_cast<T>(ar), static_cast<T>(ai)});
             ar = 0.0;
             ai = 0.0;
         }
     }
 
-    __device__ void backward(const LdsPlan &lp, int wave, int nwaves) {
-        constexpr int KB = sizeof(T) == 4 ? 8 : 4;
-        const uint32_t root = static_cast<uint32_t>(lp.root);
-        for (int l = lp.L - 1; l >= 0; --l) {
-            const uint32_t n0 = cld(lp.level_ptr + l), n1 = cld(lp.level_ptr + l + 1);
+    __device__ void backward(const SopPlan &sp, int wave, int nwaves) {
+        constexpr int KB = SOP_KB;
+        const uint32_t root = static_cast<uint32_t>(sp.root);
+        for (int l = sp.L - 1; l >= 0; --l) {
+            const uint32_t n0 = cld(sp.level_ptr + l), n1 = cld(sp.level_ptr + l + 1);
             for (uint32_t b0 = n0 + static_cast<uint32_t>(wave) * KB; b0 < n1; b0 += static_cast<uint32_t>(nwaves) * KB) {
                 const uint32_t b1 = b0 + KB < n1 ? b0 + KB : n1;
-                pull_targets(lp, b0, b1, [&](uint32_t i, cplx<T> v) {
+                pull_targets(sp, b0, b1, [&](uint32_t i, cplx<T> v) {
                     rb.st(adj0 + i, i == root ? cplx<T>{T(1), T(0)} : v);
                 });
             }
@@ -1031,50 +1165,51 @@ struct StreamTile {
     }
 
     // d root / d lambda_{v=u}, one wave per variable: the adjoint sums of v's
-    // indicator leaves into its D rows, then every parent edge of v's
-    // selector leaves (contiguous in the plan, in batches of KE whose row
-    // loads issue together) adds its term times the edge's selector weight for
-    // each value u.  Only D rows are stored; no barrier inside.
-    __device__ void leaf_derivatives(const LdsPlan &lp, int wave, int nwaves) {
-        constexpr int KE = sizeof(T) == 4 ? 4 : 2;
-        const uint32_t M = static_cast<uint32_t>(lp.N);
-        const uint32_t s0 = M + static_cast<uint32_t>(g.n_ind);    // first selector target
-        const uint32_t sel_e0 = cld(lp.estart + s0);                  // first selector edge
+    // indicator leaves into its D rows, then every occurrence of v's selector
+    // leaves (contiguous in the plan, in groups of KE whose row loads issue
+    // together) adds its term times the occurrence's selector weight for each
+    // value u.  Only D rows are stored; no barrier inside.
+    __device__ void leaf_derivatives(const SopPlan &sp, int wave, int nwaves) {
+        constexpr int KE = sizeof(T) == 4 ? SOP_KE_LEAF : SOP_KE_LEAF / 2 > 0 ? SOP_KE_LEAF / 2 : 1;
+        const uint32_t M = static_cast<uint32_t>(sp.S);
+        const uint32_t s0t = M + static_cast<uint32_t>(g.n_ind);   // first selector target
+        const uint32_t sel_e0 = cld(sp.ostart + s0t);               // first selector occurrence
         for (int v = wave; v < g.n_vars; v += nwaves) {
             const uint32_t base = cld(g.ind_base + v), dom = cld(g.ind_base + v + 1) - base;
             const uint32_t q0 = cld(g.vsel_ptr + v), q1 = cld(g.vsel_ptr + v + 1);
-            // indicator leaves: walked unless v has none with a parent and
+            // indicator leaves: walked unless v has none with an occurrence and
             // all of its values are covered by the selector accumulators
-            const bool ind_edges = cld(lp.estart + M + base) != cld(lp.estart + M + base + dom);
-            const bool walk_ind = dom > 0 && (ind_edges || q0 == q1 || dom > static_cast<uint32_t>(SEL_DOM));
+            const bool ind_occ = cld(sp.ostart + M + base) != cld(sp.ostart + M + base + dom);
+            const bool walk_ind = dom > 0 && (ind_occ || q0 == q1 || dom > static_cast<uint32_t>(SEL_DOM));
             if (walk_ind)
-                pull_targets(lp, M + base, M + base + dom, [&](uint32_t i, cplx<T> val) { rb.st(d0 + (i - M), val); });
+                pull_targets(sp, M + base, M + base + dom, [&](uint32_t i, cplx<T> val) { rb.st(d0 + (i - M), val); });
             if (q0 == q1) continue;
             cplx<T> acc[SEL_DOM];
 #pragma unroll
             for (int u = 0; u < SEL_DOM; ++u)       // this wave's own stores, read back in program order
                 acc[u] = walk_ind && static_cast<uint32_t>(u) < dom ? rb.ld(d0 + base + u) : cplx<T>{T(0), T(0)};
-            const uint32_t e1 = cld(lp.estart + s0 + q1);
-            for (uint32_t e = cld(lp.estart + s0 + q0); e < e1; e += KE) {
-                uint64_t rr[KE];
+            const uint32_t e1 = cld(sp.ostart + s0t + q1);
+            for (uint32_t e = cld(sp.ostart + s0t + q0); e < e1; e += KE) {
+                uint32_t rr[KE][4];
                 uint32_t qe[KE];
-                cplx<T> ap[KE], sv[KE];
+                cplx<T> ap[KE], sa[KE], sb[KE], sc[KE];
 #pragma unroll
                 for (int j = 0; j < KE; ++j) {
                     const bool in = e + j < e1;
-                    rr[j] = in ? cld(lp.edg + e + j) : (static_cast<uint64_t>(NO_SIBLING) << 32);
-                    qe[j] = in ? cld(lp.esel + e + j - sel_e0) : 0u;
+                    load_occ(sp, e + j, in, rr[j]);
+                    qe[j] = in ? cld(sp.osel + e + j - sel_e0) : 0u;
                 }
 #pragma unroll
                 for (int j = 0; j < KE; ++j) {
-                    ap[j] = e + j < e1 ? rb.ld(adj0 + static_cast<uint32_t>(rr[j])) : cplx<T>{T(0), T(0)};
-                    sv[j] = row(static_cast<uint32_t>(rr[j] >> 32));
+                    ap[j] = e + j < e1 ? rb.ld(adj0 + rr[j][0]) : cplx<T>{T(0), T(0)};
+                    sa[j] = row(rr[j][1]);
+                    sb[j] = row(rr[j][2]);
+                    sc[j] = row(rr[j][3]);
                 }
 #pragma unroll
                 for (int j = 0; j < KE; ++j) {
                     if (e + j >= e1) break;
-                    const uint32_t sb = static_cast<uint32_t>(rr[j] >> 32);
-                    const cplx<T> term = sb != NO_SIBLING ? cmul(ap[j], pick(sb, sv[j])) : ap[j];
+                    const cplx<T> term = occ_term(rr[j], ap[j], sa[j], sb[j], sc[j]);
                     const uint32_t *rec = g.sel + static_cast<size_t>(qe[j]) * SEL_REC;
 #pragma unroll
                     for (int u = 0; u < SEL_DOM; ++u) {
@@ -1095,7 +1230,7 @@ struct StreamTile {
 // (measured: 4 waves 1.49 s, 5 waves 1.44 s, 6-8 waves 1.41 s per 1,024,000
 // 8-qubit samples)
 template <typename T>
-__global__ __launch_bounds__(MAX_BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 1, 8))) void k_sample_stream(DevGraph g, LdsPlan lp, const double *theta,
+__global__ __launch_bounds__(MAX_BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 1, 8))) void k_sample_stream(DevGraph g, SopPlan sp, const double *theta,
                                                          const Weight<T> *wfix, cplx<T> *vals, size_t per_wg,
                                                          SampleArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1112,9 +1247,9 @@ __global__ __launch_bounds__(MAX_BLOCK) __attribute__((amdgpu_waves_per_eu(sizeo
     const int wave = static_cast<int>(uniform_u32(threadIdx.x / WAVE));
     const int nwaves = blockDim.x / WAVE;
     cplx<T> *val = vals + per_wg * blockIdx.x;
-    cplx<T> *D = val + 2 * static_cast<size_t>(lp.N) * WAVE;    // [n_ind][64]
+    cplx<T> *D = val + 2 * static_cast<size_t>(sp.S) * WAVE;    // [n_ind][64]
     for (int s2 = threadIdx.x; s2 < g.S; s2 += blockDim.x) fix_s[s2] = wval(wfix[s2]);
-    const uint32_t N = static_cast<uint32_t>(lp.N);
+    const uint32_t N = static_cast<uint32_t>(sp.S);
     StreamTile<T> t{g, RowBuf<T>(val, per_wg / WAVE, lane), N, 2 * N, ev_s, ang_s, fix_s, lane};
     const int64_t stride = static_cast<int64_t>(gridDim.x) * WAVE;
     const uint32_t total_sweeps = static_cast<uint32_t>(a.burn_in) +
@@ -1155,9 +1290,9 @@ __global__ __launch_bounds__(MAX_BLOCK) __attribute__((amdgpu_waves_per_eu(sizeo
             ang_s[s2 * WAVE + lane] = {static_cast<T>(re), static_cast<T>(im)};
         }
         __syncthreads();
-        t.forward(lp, wave, nwaves);
-        t.backward(lp, wave, nwaves);
-        t.leaf_derivatives(lp, wave, nwaves);
+        t.forward(sp, wave, nwaves);
+        t.backward(sp, wave, nwaves);
+        t.leaf_derivatives(sp, wave, nwaves);
         __syncthreads();
 
         if (wave == 0 && ch >= 0) {
@@ -1762,12 +1897,12 @@ size_t stream_lds_bytes(const DevGraph &g) {
 }
 
 template <typename T>
-hipError_t launch_eval(const DevGraph &g, int grid, int block, const double *theta, const int32_t *param_of, int P,
+hipError_t launch_eval(const DevGraph &g, const SopPlan &sp, int grid, int block, const double *theta, const int32_t *param_of, int P,
                        const uint64_t *evidence, int64_t B, const void *wfix, void *vals, size_t per_wg_elems,
                        void *amp_out, double *prob_out, hipStream_t st) {
     size_t lds = lds_bytes(g);
     if (block < WAVE || block > MAX_BLOCK || block % WAVE != 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_eval<T>, dim3(grid), dim3(block), lds, st, g, theta, param_of, P, evidence, B,
+    hipLaunchKernelGGL(k_eval<T>, dim3(grid), dim3(block), lds, st, g, sp, theta, param_of, P, evidence, B,
                        reinterpret_cast<const Weight<T> *>(wfix), reinterpret_cast<cplx<T> *>(vals),
                        per_wg_elems, reinterpret_cast<cplx<T> *>(amp_out), prob_out);
     return hipGetLastError();
@@ -1872,25 +2007,25 @@ template hipError_t launch_sample_lds<double>(const DevGraph &, const LdsPlan &,
 
 
 template <typename T>
-hipError_t launch_sample_stream(const DevGraph &g, const LdsPlan &lp, int grid, int block, const double *theta,
+hipError_t launch_sample_stream(const DevGraph &g, const SopPlan &sp, int grid, int block, const double *theta,
                                 const void *wfix, void *vals, size_t per_wg_elems, const SampleArgs &a,
                                 hipStream_t st) {
     if (block < WAVE || block > MAX_BLOCK || block % WAVE != 0) return hipErrorInvalidValue;
     size_t lds = stream_lds_bytes<T>(g);
-    hipLaunchKernelGGL(k_sample_stream<T>, dim3(grid), dim3(block), lds, st, g, lp, theta,
+    hipLaunchKernelGGL(k_sample_stream<T>, dim3(grid), dim3(block), lds, st, g, sp, theta,
                        reinterpret_cast<const Weight<T> *>(wfix), reinterpret_cast<cplx<T> *>(vals), per_wg_elems, a);
     return hipGetLastError();
 }
 template hipError_t launch_fixed_slots<float>(const DevGraph &, const double *, void *, hipStream_t);
 template hipError_t launch_fixed_slots<double>(const DevGraph &, const double *, void *, hipStream_t);
-template hipError_t launch_sample_stream<float>(const DevGraph &, const LdsPlan &, int, int, const double *,
+template hipError_t launch_sample_stream<float>(const DevGraph &, const SopPlan &, int, int, const double *,
                                                 const void *, void *, size_t, const SampleArgs &, hipStream_t);
-template hipError_t launch_sample_stream<double>(const DevGraph &, const LdsPlan &, int, int, const double *,
+template hipError_t launch_sample_stream<double>(const DevGraph &, const SopPlan &, int, int, const double *,
                                                  const void *, void *, size_t, const SampleArgs &, hipStream_t);
 
-template hipError_t launch_eval<float>(const DevGraph &, int, int, const double *, const int32_t *, int, const uint64_t *,
+template hipError_t launch_eval<float>(const DevGraph &, const SopPlan &, int, int, const double *, const int32_t *, int, const uint64_t *,
                                        int64_t, const void *, void *, size_t, void *, double *, hipStream_t);
-template hipError_t launch_eval<double>(const DevGraph &, int, int, const double *, const int32_t *, int, const uint64_t *,
+template hipError_t launch_eval<double>(const DevGraph &, const SopPlan &, int, int, const double *, const int32_t *, int, const uint64_t *,
                                         int64_t, const void *, void *, size_t, void *, double *, hipStream_t);
 template hipError_t launch_grad<float>(const DevGraph &, int, int, const double *, const int32_t *, const uint64_t *,
                                        int64_t, const void *, void *, size_t, int, const void *, const double *,
