@@ -209,17 +209,29 @@ def serve_run(graphs, pool, rate, args):
 
 
 def byte_model(comp, W: int, cs: int):
-    """Algorithmic bytes of the streaming model for one element: upward pass
-    (every node value written once, every internal child read once, the
-    evidence words read once, the amplitude written) and downward pass (node
-    values and parent adjoints read, every adjoint written, one derivative per
-    indicator value)."""
+    """Bytes of the streaming model on the compiled DAG for one element:
+    upward pass (every node value written once, every internal child read
+    once, the evidence words read once, the amplitude written) and downward
+    pass (node values and parent adjoints read, every adjoint written)."""
     tags = comp.col >> 30
     E_ii = int((tags == 0).sum())
     N = comp.n_internal
     up = cs * (E_ii + N) + 8 * W + cs
     down = cs * (N + 2 * E_ii)
     return up, down, E_ii
+
+
+def plan_byte_model(info, cs: int):
+    """The same streaming model on the sum-of-products plan the kernels run
+    (products folded into their sum parents never get a row): per element,
+    upward pass s*(super-nodes + super-node factors) + evidence words + the
+    amplitude; downward pass s*(super-nodes + adjoint and sibling rows read);
+    leaf step s*(adjoint and sibling rows read + one derivative per value)."""
+    S = info["n_super"]
+    up = cs * (S + info["n_super_node_factors"]) + 8 * info["n_words"] + cs
+    down = cs * (S + info["n_super_down_reads"])
+    leaf = cs * (info["n_super_leaf_reads"] + info["n_indicator_leaves"])
+    return up, down, leaf
 
 
 def eval_leg(args, circ_cfg):
@@ -267,7 +279,8 @@ def eval_leg(args, circ_cfg):
     diff = (a_grad - a_eval).abs() / a_eval.abs().clamp_min(1e-30)
     grad_vs_eval = float(diff.max().item())
     del a_eval, a_grad, diff
-    up, down, E_ii = byte_model(comp, info["n_words"], 8)
+    dag_up, dag_down, E_ii = byte_model(comp, info["n_words"], 8)
+    up, _, _ = plan_byte_model(info, 8)
     N = info["n_internal"]
     achieved = up * B / t_eval / 1e9
     # complex64 against complex128 per result, on the first 32768 elements
@@ -286,11 +299,13 @@ def eval_leg(args, circ_cfg):
         "eval_ms": t_eval * 1e3, "amplitudes_per_s": B / t_eval, "node_evals_per_s": N * B / t_eval,
         "grad_ms": t_grad * 1e3, "grad_elements_per_s": B / t_grad,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "kernel": "k_eval (upward pass)",
-                     "bytes_per_element": up,
+                     "frac": achieved / HBM_PEAK_GBS, "kernel": "k_eval (upward pass, sum-of-products plan)",
+                     "bytes_per_element": up, "ac_super_nodes": info["n_super"],
+                     "dag_model_bytes_per_element": dag_up,
+                     "dag_model_GBps": dag_up * B / t_eval / 1e9,
                      "traffic": profiled_traffic("k_eval", circ_cfg["evidence"].shape[0] == 262144),
                      "traffic_unit": "HBM bytes per dispatch (rocprofv3)"},
-        "grad_model_GBps": (up + down) * B / t_grad / 1e9,
+        "grad_model_GBps": (dag_up + dag_down) * B / t_grad / 1e9,
         "grad_vs_eval_amplitude_max_rel_diff": grad_vs_eval,
         "c64_vs_c128_branch_prob_rel_err": {"max": float(rel[big].max()), "p99": float(np.percentile(rel[big], 99)),
                                             "median": float(np.median(rel[big])), "results": int(big.sum())},
@@ -519,11 +534,17 @@ def main():
     E_ii = int((tags == 0).sum())
     n_ind = info["n_indicator_leaves"]
     cs = 8 if args.dtype == "c64" else 16
-    # algorithmic bytes per chain-round (streaming model: every node value
-    # written once and every internal child read once in the upward pass;
-    # the downward pass reads the node values and parent adjoints and writes
-    # each adjoint; one indicator derivative per variable value)
-    bytes_round = cs * (E_ii + N) + cs * (N + 2 * E_ii) + cs * n_ind + 8 * Wn
+    # algorithmic bytes per chain-round: the streaming model on the
+    # sum-of-products plan the sampler runs (every super-node value written
+    # once and every super-node factor read once in the upward pass; the
+    # downward pass reads the parent adjoint and sibling rows of every
+    # occurrence and writes each adjoint; the leaf step reads the same for
+    # indicator and selector occurrences and writes one derivative per
+    # variable value; the evidence words once)
+    p_up, p_down, p_leaf = plan_byte_model(info, cs)
+    bytes_round = (p_up - cs) + p_down + p_leaf
+    # the same model on the compiled DAG (every node a row), for comparison
+    dag_bytes_round = cs * (E_ii + N) + cs * (N + 2 * E_ii) + cs * n_ind + 8 * Wn
     samp_s = float(np.mean(samp_ms)) / 1e3
     achieved = bytes_round * rounds / samp_s / 1e9
     default_run = (P, chains, args.burn_in, args.dtype, args.order_trials) == (1024, 1000, 10, "c64", 64)
@@ -566,6 +587,9 @@ def main():
             "kernel": "k_sample_stream (Gibbs rounds: upward + downward pass + decisions; "
                       "timed with HIP events around ac_sample on its stream)",
             "bytes_per_chain_round": bytes_round,
+            "ac_super_nodes": info["n_super"],
+            "dag_model_bytes_per_chain_round": dag_bytes_round,
+            "dag_model_GBps": dag_bytes_round * rounds / samp_s / 1e9,
         },
     }
     if not args.no_cpu_baseline:

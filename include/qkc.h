@@ -99,7 +99,18 @@ typedef struct {
     int32_t device;
     int64_t n_prod_flops;      /* real flops of one upward pass (complex ops)  */
     int32_t n_selectors;       /* selector leaves                               */
-    int32_t reserved;
+    /* The sum-of-products plan the streaming sampler and the upward pass run
+       on (every product whose only parent is a sum folded into that sum; see
+       ac_load).  Zero when the graph has no such plan.  The row counts give
+       the plan's bytes per element: upward pass s*(n_super + n_super_node_factors),
+       downward pass s*(n_super + n_super_down_reads), leaf derivatives
+       s*(n_super_leaf_reads + n_indicator_leaves), s = 8 (c64) or 16 (c128). */
+    int32_t n_super;           /* super-nodes (one row each per element)        */
+    int32_t n_super_levels;
+    int64_t n_super_node_factors; /* factors that are super-nodes (rows read upward) */
+    int64_t n_super_down_reads;   /* per occurrence of a super-node as a factor: the
+                                     parent's adjoint row and each super-node sibling */
+    int64_t n_super_leaf_reads;   /* the same for indicator and selector occurrences */
 } ac_info_t;
 
 /*

@@ -34,7 +34,9 @@ class ACInfo(ctypes.Structure):
                 ("max_level_width", ctypes.c_int32), ("n_indicator_leaves", ctypes.c_int32),
                 ("root", ctypes.c_int32), ("device", ctypes.c_int32),
                 ("n_prod_flops", ctypes.c_int64), ("n_selectors", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("n_super", ctypes.c_int32), ("n_super_levels", ctypes.c_int32),
+                ("n_super_node_factors", ctypes.c_int64), ("n_super_down_reads", ctypes.c_int64),
+                ("n_super_leaf_reads", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -48,7 +48,7 @@ hipError_t launch_sample_lds(const DevGraph &g, const LdsPlan &lp, int cpw, int 
 hipError_t launch_zero_f64(double *p, int64_t n, hipStream_t st);
 hipError_t static_scratch_address(void **out);
 template <typename T>
-int resident_blocks(const DevGraph &g, int which, int block);
+int resident_blocks(const DevGraph &g, const SopPlan &sp, int which, int block);
 
 }  // namespace qkc
 
@@ -361,6 +361,7 @@ struct HostSop {
     std::vector<uint32_t> level_ptr, fptr, ostart, occ, osel;
     std::vector<uint64_t> frec;
     uint32_t S = 0, L = 0, root = 0, max_factors = 0;
+    uint64_t node_factors = 0, down_reads = 0, leaf_reads = 0;   // row counts of the streaming model
     bool ok = false;
 };
 
@@ -501,11 +502,17 @@ HostSop build_sop(uint32_t N, const uint8_t *op, const uint32_t *row_ptr, const 
                 } else if (tag == TAG_SEL) {
                     tg = static_cast<int64_t>(M) + n_ind + selpos[r & REF_MASK];
                 }
+                if (tag == TAG_NODE) ++P.node_factors;
                 if (tg < 0) continue;                             // weights need no adjoint here
                 std::array<uint32_t, 4> rec = {j, NO_SIBLING, NO_SIBLING, NO_SIBLING};
                 int k = 1;
+                uint64_t reads = 1;                               // the parent's adjoint row
                 for (size_t g = 0; g < t.size(); ++g)
-                    if (g != f) rec[k++] = pref(t[g]);
+                    if (g != f) {
+                        reads += (t[g] >> 30) == TAG_NODE;
+                        rec[k++] = pref(t[g]);
+                    }
+                (tag == TAG_NODE ? P.down_reads : P.leaf_reads) += reads;
                 occ[tg].push_back(rec);
             }
         }
@@ -841,6 +848,11 @@ extern "C" ac_status ac_load(const void *blob, size_t nbytes, int device, ac_gra
         sp.L = static_cast<int32_t>(hs.L);
         sp.root = static_cast<int32_t>(hs.root);
         sp.max_factors = static_cast<int32_t>(hs.max_factors);
+        // the sampler's decision pass keeps one change bit per variable and
+        // handles variables of at most SEL_DOM values
+        bool small_doms = true;
+        for (uint32_t v = 0; v < n_vars; ++v) small_doms = small_doms && var_dom[v] <= SEL_DOM;
+        sp.mask_words = small_doms && n_vars <= 64u * MAX_MASK_WORDS ? static_cast<int32_t>((n_vars + 63) / 64) : 0;
         g->has_sop = true;
     }
     d.N = static_cast<int32_t>(N);
@@ -868,13 +880,13 @@ extern "C" ac_status ac_load(const void *blob, size_t nbytes, int device, ac_gra
     }
     for (int k = 0; k < 4; ++k) {
         const int blk = k == 3 && g->stream_waves ? g->stream_waves * WAVE : BLOCK;
-        g->resident[AC_C64][k] = resident_blocks<float>(d, k, blk);
-        g->resident[AC_C128][k] = resident_blocks<double>(d, k, blk);
+        g->resident[AC_C64][k] = resident_blocks<float>(d, g->sop, k, blk);
+        g->resident[AC_C128][k] = resident_blocks<double>(d, g->sop, k, blk);
     }
     for (int k : {0, 1, 3})
         for (int j = 0; j < 3; ++j) {
-            g->wide_resident[AC_C64][k][j] = resident_blocks<float>(d, k, BLOCK << j);
-            g->wide_resident[AC_C128][k][j] = resident_blocks<double>(d, k, BLOCK << j);
+            g->wide_resident[AC_C64][k][j] = resident_blocks<float>(d, g->sop, k, BLOCK << j);
+            g->wide_resident[AC_C128][k][j] = resident_blocks<double>(d, g->sop, k, BLOCK << j);
         }
     g->var_dom.assign(var_dom, var_dom + n_vars);
     g->var_offset.assign(var_off, var_off + n_vars);
@@ -895,6 +907,13 @@ extern "C" ac_status ac_load(const void *blob, size_t nbytes, int device, ac_gra
     inf.root = d.root;
     inf.device = device;
     inf.n_prod_flops = flops;
+    if (hs.ok) {
+        inf.n_super = static_cast<int32_t>(hs.S);
+        inf.n_super_levels = static_cast<int32_t>(hs.L);
+        inf.n_super_node_factors = static_cast<int64_t>(hs.node_factors);
+        inf.n_super_down_reads = static_cast<int64_t>(hs.down_reads);
+        inf.n_super_leaf_reads = static_cast<int64_t>(hs.leaf_reads);
+    }
     *out = g;
     return AC_OK;
 }
@@ -1363,6 +1382,9 @@ extern "C" ac_status ac_sample(const ac_graph *g, ac_dtype dtype, const double *
     a.init_states = cfg->init_states;
     a.first_sweep = cfg->first_sweep;
     a.first_var = static_cast<int32_t>(cfg->first_var);
+    // QKC_SEQ_SCAN=1 decides every visit in the scan (comparisons, tests)
+    const char *seq_env = std::getenv("QKC_SEQ_SCAN");
+    a.seq_scan = seq_env && std::atoi(seq_env) == 1 ? 1 : 0;
     hipError_t e;
     int cpw = 0, lgrid = 0;
     const SampleKernel sk = sample_kernel(g, dtype, total);

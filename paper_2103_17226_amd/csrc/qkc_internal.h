@@ -158,7 +158,10 @@ struct SopPlan {
     const uint32_t *osel;       // [selector occurrences]
     int32_t S, L, root;
     int32_t max_factors;        // most factors of one super-node
+    int32_t mask_words;         // words of the per-chain change mask of the streaming
+                                // sampler's decision pass (0: decisions in the scan only)
 };
+constexpr int MAX_MASK_WORDS = 16;   // decision pass for up to 1024 variables
 
 // Arguments of the Gibbs sampler kernel.
 struct SampleArgs {
@@ -175,6 +178,7 @@ struct SampleArgs {
     const uint64_t *init_states;   // [total_chains][W] start states, or null for the seeded start
     uint64_t first_sweep;          // RNG sweep number of this call's first sweep
     int32_t first_var;             // the scan visits variables first_var .. n_vars-1
+    int32_t seq_scan;              // 1: every visit decided in the scan (no decision pass)
 };
 
 }  // namespace qkc

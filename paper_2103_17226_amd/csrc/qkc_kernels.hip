@@ -974,6 +974,37 @@ struct RowBuf {
     }
 };
 
+// One Gibbs visit of a variable with at most SEL_DOM values: weights w_u =
+// |d root / d lambda_{v=u}|^2 in FP64, the smallest u with r * total <
+// w_0 + ... + w_u, or the last value of positive weight when rounding leaves
+// none; zero total keeps the current value.  The scan's own per-visit code
+// performs the same operations in the same order.
+__device__ __forceinline__ uint32_t gibbs_choice(const double (&w)[SEL_DOM], int dom, uint32_t cur, double r) {
+    double total = 0.0;
+#pragma unroll
+    for (int u = 0; u < SEL_DOM; ++u)
+        if (u < dom) total = __dadd_rn(total, w[u]);
+    if (!(total > 0.0)) return cur;
+    const double target = __dmul_rn(r, total);
+    double acc = 0.0;
+    int last_pos = -1, chosen = -1;
+#pragma unroll
+    for (int u = 0; u < SEL_DOM; ++u) {
+        if (u >= dom || chosen >= 0) continue;
+        acc = __dadd_rn(acc, w[u]);
+        if (w[u] > 0.0) last_pos = u;
+        if (target < acc) chosen = u;
+    }
+    if (chosen < 0) chosen = last_pos;
+    return chosen >= 0 ? static_cast<uint32_t>(chosen) : cur;
+}
+
+template <typename T>
+__device__ __forceinline__ double gibbs_weight(const cplx<T> &d) {
+    const double re = static_cast<double>(d.re), im = static_cast<double>(d.im);
+    return __dadd_rn(__dmul_rn(re, re), __dmul_rn(im, im));
+}
+
 // Batch sizes of the streaming passes on the sum-of-products plan
 // (complex64; complex128 halves the factor and occurrence groups):
 // super-nodes per wave batch, factors per group of row loads (upward pass),
@@ -989,6 +1020,10 @@ struct RowBuf {
 #endif
 #ifndef SOP_KE_LEAF
 #define SOP_KE_LEAF 2
+#endif
+// complex64 waves per SIMD the streaming sampler's register budget is bounded for
+#ifndef STREAM_WAVES_PER_EU
+#define STREAM_WAVES_PER_EU 6
 #endif
 
 // Rows of the region: super-node values [0, S), adjoints [S, 2S), indicator
@@ -1168,8 +1203,11 @@ struct StreamTile {
     // indicator leaves into its D rows, then every occurrence of v's selector
     // leaves (contiguous in the plan, in groups of KE whose row loads issue
     // together) adds its term times the occurrence's selector weight for each
-    // value u.  Only D rows are stored; no barrier inside.
-    __device__ void leaf_derivatives(const SopPlan &sp, int wave, int nwaves) {
+    // value u.  Only D rows are stored; no barrier inside.  With `decide`,
+    // each variable's values d[0..dom) (at most SEL_DOM, as stored) are then
+    // handed to dec(v, d, dom) while still in registers.
+    template <typename Decide>
+    __device__ void leaf_derivatives(const SopPlan &sp, int wave, int nwaves, bool decide, Decide &&dec) {
         constexpr int KE = sizeof(T) == 4 ? SOP_KE_LEAF : SOP_KE_LEAF / 2 > 0 ? SOP_KE_LEAF / 2 : 1;
         const uint32_t M = static_cast<uint32_t>(sp.S);
         const uint32_t s0t = M + static_cast<uint32_t>(g.n_ind);   // first selector target
@@ -1181,46 +1219,53 @@ struct StreamTile {
             // all of its values are covered by the selector accumulators
             const bool ind_occ = cld(sp.ostart + M + base) != cld(sp.ostart + M + base + dom);
             const bool walk_ind = dom > 0 && (ind_occ || q0 == q1 || dom > static_cast<uint32_t>(SEL_DOM));
-            if (walk_ind)
-                pull_targets(sp, M + base, M + base + dom, [&](uint32_t i, cplx<T> val) { rb.st(d0 + (i - M), val); });
-            if (q0 == q1) continue;
             cplx<T> acc[SEL_DOM];
 #pragma unroll
-            for (int u = 0; u < SEL_DOM; ++u)       // this wave's own stores, read back in program order
-                acc[u] = walk_ind && static_cast<uint32_t>(u) < dom ? rb.ld(d0 + base + u) : cplx<T>{T(0), T(0)};
-            const uint32_t e1 = cld(sp.ostart + s0t + q1);
-            for (uint32_t e = cld(sp.ostart + s0t + q0); e < e1; e += KE) {
-                uint32_t rr[KE][4];
-                uint32_t qe[KE];
-                cplx<T> ap[KE], sa[KE], sb[KE], sc[KE];
+            for (int u = 0; u < SEL_DOM; ++u) acc[u] = {T(0), T(0)};
+            if (walk_ind)
+                pull_targets(sp, M + base, M + base + dom, [&](uint32_t i, cplx<T> val) {
+                    rb.st(d0 + (i - M), val);
+                    const uint32_t u = i - M - base;
 #pragma unroll
-                for (int j = 0; j < KE; ++j) {
-                    const bool in = e + j < e1;
-                    load_occ(sp, e + j, in, rr[j]);
-                    qe[j] = in ? cld(sp.osel + e + j - sel_e0) : 0u;
-                }
+                    for (int k = 0; k < SEL_DOM; ++k)
+                        if (u == static_cast<uint32_t>(k)) acc[k] = val;
+                });
+            if (q0 != q1) {
+                const uint32_t e1 = cld(sp.ostart + s0t + q1);
+                for (uint32_t e = cld(sp.ostart + s0t + q0); e < e1; e += KE) {
+                    uint32_t rr[KE][4];
+                    uint32_t qe[KE];
+                    cplx<T> ap[KE], sa[KE], sb[KE], sc[KE];
 #pragma unroll
-                for (int j = 0; j < KE; ++j) {
-                    ap[j] = e + j < e1 ? rb.ld(adj0 + rr[j][0]) : cplx<T>{T(0), T(0)};
-                    sa[j] = row(rr[j][1]);
-                    sb[j] = row(rr[j][2]);
-                    sc[j] = row(rr[j][3]);
-                }
+                    for (int j = 0; j < KE; ++j) {
+                        const bool in = e + j < e1;
+                        load_occ(sp, e + j, in, rr[j]);
+                        qe[j] = in ? cld(sp.osel + e + j - sel_e0) : 0u;
+                    }
 #pragma unroll
-                for (int j = 0; j < KE; ++j) {
-                    if (e + j >= e1) break;
-                    const cplx<T> term = occ_term(rr[j], ap[j], sa[j], sb[j], sc[j]);
-                    const uint32_t *rec = g.sel + static_cast<size_t>(qe[j]) * SEL_REC;
+                    for (int j = 0; j < KE; ++j) {
+                        ap[j] = e + j < e1 ? rb.ld(adj0 + rr[j][0]) : cplx<T>{T(0), T(0)};
+                        sa[j] = row(rr[j][1]);
+                        sb[j] = row(rr[j][2]);
+                        sc[j] = row(rr[j][3]);
+                    }
 #pragma unroll
-                    for (int u = 0; u < SEL_DOM; ++u) {
-                        const uint32_t sl = cld(rec + 1 + u);
-                        if (sl != NO_SLOT) acc[u] = cadd(acc[u], cmul(term, wfix[sl]));
+                    for (int j = 0; j < KE; ++j) {
+                        if (e + j >= e1) break;
+                        const cplx<T> term = occ_term(rr[j], ap[j], sa[j], sb[j], sc[j]);
+                        const uint32_t *rec = g.sel + static_cast<size_t>(qe[j]) * SEL_REC;
+#pragma unroll
+                        for (int u = 0; u < SEL_DOM; ++u) {
+                            const uint32_t sl = cld(rec + 1 + u);
+                            if (sl != NO_SLOT) acc[u] = cadd(acc[u], cmul(term, wfix[sl]));
+                        }
                     }
                 }
-            }
 #pragma unroll
-            for (int u = 0; u < SEL_DOM; ++u)
-                if (static_cast<uint32_t>(u) < dom) rb.st(d0 + base + u, acc[u]);
+                for (int u = 0; u < SEL_DOM; ++u)
+                    if (static_cast<uint32_t>(u) < dom) rb.st(d0 + base + u, acc[u]);
+            }
+            if (decide) dec(v, acc, static_cast<int>(dom));
         }
     }
 };
@@ -1230,13 +1275,14 @@ struct StreamTile {
 // (measured: 4 waves 1.49 s, 5 waves 1.44 s, 6-8 waves 1.41 s per 1,024,000
 // 8-qubit samples)
 template <typename T>
-__global__ __launch_bounds__(MAX_BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 1, 8))) void k_sample_stream(DevGraph g, SopPlan sp, const double *theta,
+__global__ __launch_bounds__(MAX_BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? STREAM_WAVES_PER_EU : 1, 8))) void k_sample_stream(DevGraph g, SopPlan sp, const double *theta,
                                                          const Weight<T> *wfix, cplx<T> *vals, size_t per_wg,
                                                          SampleArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     uint64_t *ev_s = reinterpret_cast<uint64_t *>(smem);
     cplx<T> *ang_s = reinterpret_cast<cplx<T> *>(smem + static_cast<size_t>(g.W) * WAVE * 8);
     cplx<T> *fix_s = ang_s + static_cast<size_t>(g.S_ang) * WAVE;
+    uint64_t *mask_s = reinterpret_cast<uint64_t *>(fix_s + g.S);   // [mask_words][64] change bits
     __shared__ int64_t s_chain[WAVE];
     __shared__ int32_t s_pos[WAVE];
     __shared__ uint32_t s_sweep[WAVE];
@@ -1246,6 +1292,7 @@ __global__ __launch_bounds__(MAX_BLOCK) __attribute__((amdgpu_waves_per_eu(sizeo
     const int lane = threadIdx.x & (WAVE - 1);
     const int wave = static_cast<int>(uniform_u32(threadIdx.x / WAVE));
     const int nwaves = blockDim.x / WAVE;
+    const bool decide_all = sp.mask_words > 0 && !a.seq_scan;
     cplx<T> *val = vals + per_wg * blockIdx.x;
     cplx<T> *D = val + 2 * static_cast<size_t>(sp.S) * WAVE;    // [n_ind][64]
     for (int s2 = threadIdx.x; s2 < g.S; s2 += blockDim.x) fix_s[s2] = wval(wfix[s2]);
@@ -1289,10 +1336,33 @@ __global__ __launch_bounds__(MAX_BLOCK) __attribute__((amdgpu_waves_per_eu(sizeo
             slot_value(g.slots[s2], trow, nullptr, re, im);
             ang_s[s2 * WAVE + lane] = {static_cast<T>(re), static_cast<T>(im)};
         }
+        if (decide_all)
+            for (int w2 = wave; w2 < sp.mask_words; w2 += nwaves) mask_s[w2 * WAVE + lane] = 0ull;
         __syncthreads();
         t.forward(sp, wave, nwaves);
         t.backward(sp, wave, nwaves);
-        t.leaf_derivatives(sp, wave, nwaves);
+        // Decisions: the Gibbs choice of every variable at its first visit in
+        // this round (variables before the chain's position come after the
+        // sweep boundary), taken in the leaf step by the wave that has the
+        // variable's derivatives in registers -- they stay valid up to the
+        // first change; a changed value sets the variable's bit in the
+        // chain's change mask, and the scan jumps to the first set bit
+        // instead of visiting the variables one by one.
+        const int32_t pos0 = s_pos[lane];
+        const uint32_t sw0 = s_sweep[lane];
+        t.leaf_derivatives(sp, wave, nwaves, decide_all, [&](int v, const cplx<T> (&d)[SEL_DOM], int dom) {
+            if (ch < 0 || v < a.first_var) return;
+            const uint32_t fld = cld(g.var_field + v);
+            const uint32_t word = fld >> 8, shift = (fld >> 2) & 63u, width = (fld & 3u) + 1u;
+            const uint32_t cur = static_cast<uint32_t>((ev_s[word * WAVE + lane] >> shift) & ((1ull << width) - 1ull));
+            double w[SEL_DOM];
+#pragma unroll
+            for (int u = 0; u < SEL_DOM; ++u) w[u] = u < dom ? gibbs_weight(d[u]) : 0.0;
+            const uint32_t sw = sw0 + (v < pos0 ? 1u : 0u);
+            const double r = rng_uniform(a.seed, static_cast<uint64_t>(ch), a.first_sweep + sw, static_cast<uint64_t>(v));
+            if (gibbs_choice(w, dom, cur, r) != cur)
+                atomicOr(reinterpret_cast<unsigned long long *>(mask_s + (v >> 6) * WAVE + lane), 1ull << (v & 63));
+        });
         __syncthreads();
 
         if (wave == 0 && ch >= 0) {
@@ -1301,12 +1371,92 @@ __global__ __launch_bounds__(MAX_BLOCK) __attribute__((amdgpu_waves_per_eu(sizeo
             uint32_t sweep = s_sweep[lane];
             int32_t emitted = s_emitted[lane];
             bool done = false;
+            // the state after a completed sweep: a sample when past the
+            // burn-in and on the thinning stride
+            auto end_sweep = [&]() -> bool {
+                pos = a.first_var;
+                sweep += 1;
+                if (sweep > static_cast<uint32_t>(a.burn_in) &&
+                    (sweep - static_cast<uint32_t>(a.burn_in)) % static_cast<uint32_t>(a.thin) == 0u) {
+                    const int64_t S = static_cast<int64_t>(a.cpp) * a.spc;
+                    const int64_t idx = static_cast<int64_t>(p) * S + (ch % a.cpp) * a.spc + emitted;
+                    const uint64_t x = ev_s[lane] & xmask;
+                    a.samples[idx * a.nwq] = x;
+                    for (int w2 = 1; w2 < a.nwq; ++w2) a.samples[idx * a.nwq + w2] = 0ull;
+                    if (a.states_out)
+                        for (int w2 = 0; w2 < g.W; ++w2) a.states_out[idx * g.W + w2] = ev_s[w2 * WAVE + lane];
+                    if (a.cost_out) {
+                        int cst = 0;
+                        for (int e = 0; e < a.n_cost_edges; ++e) {
+                            const int i0 = a.cost_edges[2 * e], i1 = a.cost_edges[2 * e + 1];
+                            cst += static_cast<int>(((x >> i0) ^ (x >> i1)) & 1ull);
+                        }
+                        a.cost_out[idx] = static_cast<double>(cst);
+                    }
+                    emitted += 1;
+                }
+                return sweep >= total_sweeps;
+            };
+            bool scan = true;
+            if (decide_all) {
+                // first changed variable in [lo, hi), or -1
+                auto first_set = [&](int lo, int hi) -> int {
+                    for (int v = lo; v < hi;) {
+                        const int off = v & 63;
+                        uint64_t m = mask_s[(v >> 6) * WAVE + lane] >> off;
+                        const int lim = hi - v < 64 - off ? hi - v : 64 - off;
+                        if (lim < 64) m &= (1ull << lim) - 1ull;
+                        if (m) return v + __builtin_ctzll(m);
+                        v += 64 - off;
+                    }
+                    return -1;
+                };
+                // the recorded change at v, decided again from its derivatives
+                auto apply = [&](int v) {
+                    const uint32_t bk = g.ind_base[v];
+                    const int dom = static_cast<int>(g.ind_base[v + 1] - bk);
+                    double w[SEL_DOM];
+#pragma unroll
+                    for (int u = 0; u < SEL_DOM; ++u)
+                        w[u] = u < dom ? gibbs_weight(D[static_cast<size_t>(bk + u) * WAVE + lane]) : 0.0;
+                    const uint32_t fld = g.var_field[v];
+                    const uint32_t word = fld >> 8, shift = (fld >> 2) & 63u, width = (fld & 3u) + 1u;
+                    const uint64_t fmask = (1ull << width) - 1ull;
+                    const uint64_t wv = ev_s[word * WAVE + lane];
+                    const uint32_t cur = static_cast<uint32_t>((wv >> shift) & fmask);
+                    const double r = rng_uniform(a.seed, static_cast<uint64_t>(ch), a.first_sweep + sweep, static_cast<uint64_t>(v));
+                    const uint32_t pick = gibbs_choice(w, dom, cur, r);
+                    ev_s[word * WAVE + lane] = (wv & ~(fmask << shift)) | (static_cast<uint64_t>(pick) << shift);
+                };
+                const int pos0 = pos;
+                const int vs = first_set(pos0, g.n_vars);
+                if (vs >= 0) {                       // a change later in this sweep
+                    apply(vs);
+                    pos = vs + 1;
+                    if (pos == g.n_vars) done = end_sweep();
+                    scan = false;
+                } else {
+                    done = end_sweep();              // the rest of the sweep keeps every value
+                    if (done) {
+                        scan = false;
+                    } else {
+                        const int vb = first_set(a.first_var, pos0);
+                        if (vb >= 0) {               // a change in the next sweep, before pos0
+                            apply(vb);
+                            pos = vb + 1;
+                            scan = false;
+                        } else {
+                            pos = pos0;              // a whole cycle unchanged: scan on from pos0
+                        }
+                    }
+                }
+            }
             // Gibbs weights of the next PF variables, loaded together (the
             // derivatives do not change until the state does)
             constexpr int PF = sizeof(T) == 4 ? 3 : 2;
             double wpf[PF][SEL_DOM];
             int pf_pos = -1;
-            for (;;) {
+            for (; scan && !done;) {
                 const int v = pos;
                 if (pf_pos < 0 || v < pf_pos || v >= pf_pos + PF) {
                     pf_pos = v;
@@ -1374,32 +1524,9 @@ __global__ __launch_bounds__(MAX_BLOCK) __attribute__((amdgpu_waves_per_eu(sizeo
                     ev_s[word * WAVE + lane] = (wv & ~(fmask << shift)) | (static_cast<uint64_t>(pick) << shift);
                 }
                 pos += 1;
-                if (pos == g.n_vars) {
-                    pos = a.first_var;
-                    sweep += 1;
-                    if (sweep > static_cast<uint32_t>(a.burn_in) &&
-                        (sweep - static_cast<uint32_t>(a.burn_in)) % static_cast<uint32_t>(a.thin) == 0u) {
-                        const int64_t S = static_cast<int64_t>(a.cpp) * a.spc;
-                        const int64_t idx = static_cast<int64_t>(p) * S + (ch % a.cpp) * a.spc + emitted;
-                        const uint64_t x = ev_s[lane] & xmask;
-                        a.samples[idx * a.nwq] = x;
-                        for (int w2 = 1; w2 < a.nwq; ++w2) a.samples[idx * a.nwq + w2] = 0ull;
-                        if (a.states_out)
-                            for (int w2 = 0; w2 < g.W; ++w2) a.states_out[idx * g.W + w2] = ev_s[w2 * WAVE + lane];
-                        if (a.cost_out) {
-                            int cst = 0;
-                            for (int e = 0; e < a.n_cost_edges; ++e) {
-                                const int i0 = a.cost_edges[2 * e], i1 = a.cost_edges[2 * e + 1];
-                                cst += static_cast<int>(((x >> i0) ^ (x >> i1)) & 1ull);
-                            }
-                            a.cost_out[idx] = static_cast<double>(cst);
-                        }
-                        emitted += 1;
-                    }
-                    if (sweep >= total_sweeps) {
-                        done = true;
-                        break;
-                    }
+                if (pos == g.n_vars && end_sweep()) {
+                    done = true;
+                    break;
                 }
                 if (changed) break;
             }
@@ -1891,9 +2018,9 @@ size_t lds_bytes(const DevGraph &g) {
 // dynamic LDS of the streaming sampler: evidence words, angle weights and the
 // fixed weights, in the pass dtype
 template <typename T>
-size_t stream_lds_bytes(const DevGraph &g) {
+size_t stream_lds_bytes(const DevGraph &g, const SopPlan &sp) {
     return static_cast<size_t>(g.W) * WAVE * 8 + static_cast<size_t>(g.S_ang) * WAVE * sizeof(cplx<T>) +
-           static_cast<size_t>(g.S) * sizeof(cplx<T>);
+           static_cast<size_t>(g.S) * sizeof(cplx<T>) + static_cast<size_t>(sp.mask_words) * WAVE * 8;
 }
 
 template <typename T>
@@ -1978,7 +2105,7 @@ hipError_t launch_sample_lds(const DevGraph &g, const LdsPlan &lp, int cpw, int 
 // which: 0 = k_eval, 1 = k_grad, 2 = k_sample, 3 = k_sample_stream; block =
 // threads per workgroup.
 template <typename T>
-int resident_blocks(const DevGraph &g, int which, int block) {
+int resident_blocks(const DevGraph &g, const SopPlan &sp, int which, int block) {
     const void *fn = nullptr;
     size_t lds = lds_bytes(g);
     switch (which) {
@@ -1987,7 +2114,7 @@ int resident_blocks(const DevGraph &g, int which, int block) {
         case 2: fn = reinterpret_cast<const void *>(&k_sample<T>); break;
         case 3:
             fn = reinterpret_cast<const void *>(&k_sample_stream<T>);
-            lds = stream_lds_bytes<T>(g);
+            lds = stream_lds_bytes<T>(g, sp);
             break;
         default: return 1;
     }
@@ -1995,8 +2122,8 @@ int resident_blocks(const DevGraph &g, int which, int block) {
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, block, lds) != hipSuccess || n < 1) return 1;
     return n;
 }
-template int resident_blocks<float>(const DevGraph &, int, int);
-template int resident_blocks<double>(const DevGraph &, int, int);
+template int resident_blocks<float>(const DevGraph &, const SopPlan &, int, int);
+template int resident_blocks<double>(const DevGraph &, const SopPlan &, int, int);
 
 template size_t sample_lds_chain_bytes<float>(const DevGraph &, const LdsPlan &);
 template size_t sample_lds_chain_bytes<double>(const DevGraph &, const LdsPlan &);
@@ -2011,7 +2138,7 @@ hipError_t launch_sample_stream(const DevGraph &g, const SopPlan &sp, int grid, 
                                 const void *wfix, void *vals, size_t per_wg_elems, const SampleArgs &a,
                                 hipStream_t st) {
     if (block < WAVE || block > MAX_BLOCK || block % WAVE != 0) return hipErrorInvalidValue;
-    size_t lds = stream_lds_bytes<T>(g);
+    size_t lds = stream_lds_bytes<T>(g, sp);
     hipLaunchKernelGGL(k_sample_stream<T>, dim3(grid), dim3(block), lds, st, g, sp, theta,
                        reinterpret_cast<const Weight<T> *>(wfix), reinterpret_cast<cplx<T> *>(vals), per_wg_elems, a);
     return hipGetLastError();

@@ -238,3 +238,58 @@ def test_error_posterior_and_most_probable_explanation():
     _, _, pval = stats.chi2_pooled(counts, post)
     assert pval > 1e-4
     assert int(np.argmax(counts)) == int(np.argmax(post))
+
+
+def _frozen_circuit():
+    # RX(0) and RZ(0) leave |0..0>: every chain of outputs sits at x = 0 with
+    # probability one after its first visit, so whole sweeps pass unchanged
+    return W.Circuit(n=3, ops=[("RX", 0, 0, 1.0), ("CNOT", 0, 1), ("RX", 2, 0, 1.0), ("DEP", 1, 0),
+                               ("RZ", 2, 1, 2.0)], n_angles=2, noise=[1e-9], edges=[(0, 1), (1, 2)])
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("case", ["qaoa_n8", "random", "conditional", "frozen", "resumed"])
+def test_decision_pass_matches_the_sequential_scan(case, dtype, monkeypatch):
+    # The streaming sampler takes every variable's Gibbs choice for the round
+    # in one pass over all waves and jumps to the first change; deciding each
+    # visit in the scan instead must give the same chains, samples, costs and
+    # round counts bit for bit (thinning, several samples per chain, held
+    # variables, whole sweeps without a change, resumed chains).
+    note(f"decision pass vs sequential scan ({case}, {dtype})")
+    monkeypatch.setenv("QKC_SAMPLE_KERNEL", "stream")
+    kw = dict(dtype=dtype, want_states=True, want_rounds=True)
+    if case == "qaoa_n8":
+        cfg = W.config(2, small=True)
+        circ, theta = cfg["circuit"], cfg["theta"][:5]
+        args = dict(chains_per_param=150, samples_per_chain=3, burn_in=4, thin=2, seed=21)
+    elif case == "random":
+        circ = W.random_circuit(8, n=5, n_ops=40)
+        theta = np.random.default_rng(8).uniform(-3, 3, size=(3, circ.n_angles))
+        args = dict(chains_per_param=100, samples_per_chain=2, burn_in=3, thin=1, seed=5)
+    elif case == "conditional":
+        circ = W.qaoa_maxcut(3, W.ring_graph(3), 1, dep=0.05, ad=0.03)
+        theta = np.array([[0.7, 0.4], [1.9, 2.6]])
+        vals = np.zeros((2 * 70, circ.n_vars), dtype=np.int64)
+        vals[:, :circ.n] = [1, 0, 1]
+        args = dict(chains_per_param=70, samples_per_chain=2, burn_in=2, thin=3, seed=6,
+                    init_states=W.pack_evidence(circ, vals), first_var=circ.n)
+    elif case == "frozen":
+        circ = _frozen_circuit()
+        theta = np.array([[0.0, 0.0], [1e-3, 0.0]])
+        args = dict(chains_per_param=130, samples_per_chain=2, burn_in=3, thin=2, seed=9)
+    else:
+        cfg = W.config(2, small=True)
+        circ, theta = cfg["circuit"], cfg["theta"][5:8]
+        rng = np.random.default_rng(4)
+        vals = np.stack([[rng.integers(0, d) for d in circ.var_domains()] for _ in range(3 * 64)])
+        args = dict(chains_per_param=64, samples_per_chain=2, burn_in=1, thin=1, seed=13,
+                    init_states=W.pack_evidence(circ, vals), first_sweep=17)
+    g = graph(circ)
+    if circ.edges:
+        kw.update(cost_edges=circ.edges, want_cost=True)
+    monkeypatch.setenv("QKC_SEQ_SCAN", "1")
+    a = g.sample(theta, **args, **kw)
+    monkeypatch.setenv("QKC_SEQ_SCAN", "0")
+    b = g.sample(theta, **args, **kw)
+    for key in ("samples", "states", "rounds") + (("cost",) if "cost_edges" in kw else ()):
+        assert torch.equal(a[key], b[key]), key
