@@ -27,10 +27,12 @@ hipError_t launch_eval(const DevGraph &g, const SopPlan &sp, int grid, int block
                        const uint64_t *evidence, int64_t B, const void *wfix, void *vals, size_t per_wg_elems,
                        void *amp_out, double *prob_out, hipStream_t st);
 template <typename T>
-hipError_t launch_grad(const DevGraph &g, int grid, int block, const double *theta, const int32_t *param_of,
+hipError_t launch_grad(const DevGraph &g, const SopPlan &sp, int grid, int block, const double *theta, const int32_t *param_of,
                        const uint64_t *evidence, int64_t B, const void *wfix, void *vals, size_t per_wg_elems,
                        int mode, const void *cotangent, const double *weight, double *contrib, int P,
-                       double *grad, void *amp_out, void *dfdtheta_out, void *dind_out, hipStream_t st);
+                       double *grad, void *amp_out, void *dfdtheta_out, void *dind_out, void *sort_ws,
+                       size_t sort_ws_bytes, hipStream_t st);
+size_t grad_sort_bytes(int64_t B);
 template <typename T>
 hipError_t launch_sample(const DevGraph &g, int grid, const double *theta, const void *wfix, void *vals,
                          size_t per_wg_elems, const SampleArgs &a, hipStream_t st);
@@ -367,7 +369,7 @@ struct HostSop {
 
 HostSop build_sop(uint32_t N, const uint8_t *op, const uint32_t *row_ptr, const uint32_t *col, uint32_t root,
                   const std::vector<uint32_t> &ind_base, const std::vector<uint32_t> &var_field, uint32_t n_ind,
-                  uint32_t n_sel, const std::vector<uint32_t> &vsel) {
+                  uint32_t n_sel, const std::vector<uint32_t> &vsel, uint32_t n_angle_slots) {
     HostSop P;
     // parents of each node: a product with exactly one parent, a sum, is folded into it
     std::vector<uint32_t> npar(N, 0), parent(N, 0);
@@ -481,7 +483,7 @@ HostSop build_sop(uint32_t N, const uint8_t *op, const uint32_t *row_ptr, const 
     // occurrences per target
     std::vector<uint32_t> selpos(n_sel, 0);
     for (uint32_t k = 0; k < n_sel; ++k) selpos[vsel[k]] = k;
-    const size_t T = static_cast<size_t>(M) + n_ind + n_sel;
+    const size_t T = static_cast<size_t>(M) + n_ind + n_sel + n_angle_slots;
     std::vector<std::vector<std::array<uint32_t, 4>>> occ(T);
     for (uint32_t j = 0; j < M; ++j) {
         const SN &x = sn[order[j]];
@@ -501,9 +503,11 @@ HostSop build_sop(uint32_t N, const uint8_t *op, const uint32_t *row_ptr, const 
                     tg = static_cast<int64_t>(M) + ind_base[xx & 0xffffffu] + (xx >> 24);
                 } else if (tag == TAG_SEL) {
                     tg = static_cast<int64_t>(M) + n_ind + selpos[r & REF_MASK];
+                } else if (tag == TAG_SLOT && (r & REF_MASK) < n_angle_slots) {
+                    tg = static_cast<int64_t>(M) + n_ind + n_sel + (r & REF_MASK);   // gradients in theta
                 }
                 if (tag == TAG_NODE) ++P.node_factors;
-                if (tg < 0) continue;                             // weights need no adjoint here
+                if (tg < 0) continue;                             // other weights need no adjoint
                 std::array<uint32_t, 4> rec = {j, NO_SIBLING, NO_SIBLING, NO_SIBLING};
                 int k = 1;
                 uint64_t reads = 1;                               // the parent's adjoint row
@@ -512,7 +516,8 @@ HostSop build_sop(uint32_t N, const uint8_t *op, const uint32_t *row_ptr, const 
                         reads += (t[g] >> 30) == TAG_NODE;
                         rec[k++] = pref(t[g]);
                     }
-                (tag == TAG_NODE ? P.down_reads : P.leaf_reads) += reads;
+                if (tag == TAG_NODE) P.down_reads += reads;
+                else if (tag != TAG_SLOT) P.leaf_reads += reads;
                 occ[tg].push_back(rec);
             }
         }
@@ -705,7 +710,7 @@ extern "C" ac_status ac_load(const void *blob, size_t nbytes, int device, ac_gra
 
     HostPlan hp = build_plan(N, op, row_ptr, col, root, ind_base, var_field, n_ind, n_sel, n_slots, sel_dev,
                              vsel_ptr, vsel);
-    HostSop hs = build_sop(N, op, row_ptr, col, root, ind_base, var_field, n_ind, n_sel, vsel);
+    HostSop hs = build_sop(N, op, row_ptr, col, root, ind_base, var_field, n_ind, n_sel, vsel, n_angle_slots);
 
     // ---- device copy: one allocation, 256-byte aligned sections
     struct Sec { const void *src; size_t bytes; size_t off; };
@@ -1087,7 +1092,7 @@ SopPlan eval_plan(const ac_graph *g) { return g->has_sop ? g->sop : SopPlan{}; }
 size_t eval_rows(const ac_graph *g) { return g->has_sop ? static_cast<size_t>(g->sop.S) : static_cast<size_t>(g->dev.N); }
 
 struct Layout {
-    size_t wfix_off = 0, contrib_off = 0, tiles_off = 0, total = 0;
+    size_t wfix_off = 0, contrib_off = 0, sort_off = 0, sort_bytes = 0, tiles_off = 0, total = 0;
     size_t per_wg_elems = 0;   // complex elements per workgroup buffer
     int grid = 0;
     int block = BLOCK;         // threads per workgroup
@@ -1101,7 +1106,7 @@ bool make_layout(const ac_graph *g, ac_dtype dt, int64_t batch, int op, Layout &
     int kid = 0;
     if (op == AC_OP_EVAL) rows = eval_rows(g);
     else if (op == AC_OP_GRAD) {
-        rows = 2 * static_cast<size_t>(d.N) + d.S_ang + d.n_ind;
+        rows = 2 * eval_rows(g) + d.S_ang + d.n_ind;
         kid = 1;
     } else {
         int cpw = 0, lgrid = 0;
@@ -1140,6 +1145,11 @@ bool make_layout(const ac_graph *g, ac_dtype dt, int64_t batch, int op, Layout &
     off += align256(static_cast<size_t>(std::max(d.S, 1)) * 16);
     L.contrib_off = off;
     if (op == AC_OP_GRAD) off += align256(static_cast<size_t>(std::max<int64_t>(batch, 1)) * std::max(d.K, 1) * 8);
+    L.sort_off = off;
+    if (op == AC_OP_GRAD) {
+        L.sort_bytes = grad_sort_bytes(batch);
+        off += align256(L.sort_bytes);
+    }
     L.tiles_off = off;
     off += align256(static_cast<size_t>(grid) * per_wg * cs);
     L.total = off;
@@ -1298,6 +1308,7 @@ extern "C" ac_status ac_grad_batch(const ac_graph *g, ac_dtype dtype, const doub
     if (g->dev.K > 0 && P > 0 && !grad_theta) return fail(AC_ERR_INVALID_ARG, "ac_grad_batch: grad_theta is null");
     if (B > 0 && (!param_of || !evidence)) return fail(AC_ERR_INVALID_ARG, "ac_grad_batch: null param_of/evidence");
     if (B > 0 && P < 1) return fail(AC_ERR_INVALID_ARG, "ac_grad_batch: P must be >= 1 when B > 0");
+    if (B > 0x7fffffff) return fail(AC_ERR_UNSUPPORTED, "ac_grad_batch: B above 2^31 - 1");
     Layout L;
     make_layout(g, dtype, B, AC_OP_GRAD, L);
     DeviceGuard dg(g->device);
@@ -1317,15 +1328,15 @@ extern "C" ac_status ac_grad_batch(const ac_graph *g, ac_dtype dtype, const doub
     if (dtype == AC_C64) {
         e = launch_fixed_slots<float>(g->dev, noise, w + L.wfix_off, st);
         if (e == hipSuccess)
-            e = launch_grad<float>(g->dev, L.grid, L.block, theta, param_of, evidence, B, w + L.wfix_off, w + L.tiles_off,
+            e = launch_grad<float>(g->dev, eval_plan(g), L.grid, L.block, theta, param_of, evidence, B, w + L.wfix_off, w + L.tiles_off,
                                    L.per_wg_elems, mode, cotangent, weight, contrib, P, grad_theta, amp_out,
-                                   dfdtheta_out, dind_out, st);
+                                   dfdtheta_out, dind_out, w + L.sort_off, L.sort_bytes, st);
     } else {
         e = launch_fixed_slots<double>(g->dev, noise, w + L.wfix_off, st);
         if (e == hipSuccess)
-            e = launch_grad<double>(g->dev, L.grid, L.block, theta, param_of, evidence, B, w + L.wfix_off, w + L.tiles_off,
+            e = launch_grad<double>(g->dev, eval_plan(g), L.grid, L.block, theta, param_of, evidence, B, w + L.wfix_off, w + L.tiles_off,
                                     L.per_wg_elems, mode, cotangent, weight, contrib, P, grad_theta, amp_out,
-                                    dfdtheta_out, dind_out, st);
+                                    dfdtheta_out, dind_out, w + L.sort_off, L.sort_bytes, st);
     }
     if (e != hipSuccess) return fail_hip(e, "ac_grad_batch: launch");
     return AC_OK;

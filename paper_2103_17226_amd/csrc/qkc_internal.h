@@ -139,7 +139,8 @@ struct LdsPlan {
 //                 | SOP_DIRECT if the term is a sum's child that is not a product
 //   ostart[t]     occurrences of target t as a factor: super-node t < S,
 //                 indicator leaf S + i, selector S + n_ind + k with the
-//                 selectors in per-variable order (vsel)
+//                 selectors in per-variable order (vsel), angle-dependent
+//                 weight slot S + n_ind + n_sel + s
 //   occ[4 o ..]   {parent super-node, three sibling references}: the
 //                 occurrence contributes adj[parent] times the product of its
 //                 siblings (the other factors of its term; NO_SIBLING pads)
@@ -153,8 +154,8 @@ struct SopPlan {
     const uint32_t *level_ptr;  // [L+1]
     const uint32_t *fptr;       // [S+1]
     const uint64_t *frec;       // [fptr[S]]
-    const uint32_t *ostart;     // [S + n_ind + n_sel + 1]
-    const uint32_t *occ;        // [4 * ostart[S + n_ind + n_sel]]
+    const uint32_t *ostart;     // [S + n_ind + n_sel + S_ang + 1]
+    const uint32_t *occ;        // [4 * ostart[S + n_ind + n_sel + S_ang]]
     const uint32_t *osel;       // [selector occurrences]
     int32_t S, L, root;
     int32_t max_factors;        // most factors of one super-node

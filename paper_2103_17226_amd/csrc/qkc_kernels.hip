@@ -11,6 +11,7 @@
 // once per call and read through scalar loads.  Grids are persistent: a
 // workgroup walks tiles (or Gibbs chains) until the batch is done.
 #include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
 
 #include "qkc_internal.h"
 
@@ -177,6 +178,12 @@ __device__ __forceinline__ uint32_t batch_nodes(uint32_t width, int nwaves) {
     const uint32_t per_wave = (width + static_cast<uint32_t>(nwaves) - 1) / static_cast<uint32_t>(nwaves);
     return per_wave < 4u ? (per_wave > 0u ? per_wave : 1u) : 4u;
 }
+
+// occurrences per group of row loads in the tile kernels' downward pass on the
+// sum-of-products plan (complex64)
+#ifndef GRAD_SOP_KE
+#define GRAD_SOP_KE 2
+#endif
 
 template <typename T>
 struct Tile {
@@ -420,6 +427,117 @@ struct Tile {
         }
     }
 
+    // Adjoint sums on the sum-of-products plan: out(t, sum over the
+    // occurrences of target t of adj[parent] times its siblings) for the
+    // targets [t0, t1), the occurrences (contiguous per target, in increasing
+    // parent order) walked in groups of KE whose adjoint and sibling rows are
+    // loaded together; terms added in FP64 in that order.  Siblings that are
+    // leaves take their pass-dtype value (weights rounded, as in backward()).
+    template <typename Out>
+    __device__ __forceinline__ void pull_sop(const SopPlan &sp, const cplx<T> *adj, uint32_t t0, uint32_t t1,
+                                             Out out) const {
+        constexpr int KE = sizeof(T) == 4 ? GRAD_SOP_KE : 2;
+        const uint32_t e_end = cld(sp.ostart + t1);
+        uint32_t t = t0, t_next = cld(sp.ostart + t0 + 1);
+        double ar = 0.0, ai = 0.0;
+        for (uint32_t e = cld(sp.ostart + t0); e < e_end; e += KE) {
+            uint32_t rr[KE][4];
+            cplx<T> ap[KE], sv[KE][3];
+#pragma unroll
+            for (int j = 0; j < KE; ++j) {
+                if (e + j < e_end) {
+                    const uint32_t *q = sp.occ + 4 * static_cast<size_t>(e + j);
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) rr[j][k] = cld(q + k);
+                } else {
+                    rr[j][0] = 0u;
+                    rr[j][1] = rr[j][2] = rr[j][3] = NO_SIBLING;
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < KE; ++j) {
+                ap[j] = adj[static_cast<size_t>(rr[j][0]) * WAVE + lane];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) sv[j][k] = eb_guard(rr[j][k + 1]);
+            }
+#pragma unroll
+            for (int j = 0; j < KE; ++j) {
+                const uint32_t ee = e + static_cast<uint32_t>(j);
+                if (ee >= e_end) break;
+                while (ee >= t_next) {
+                    out(t, cplx<T>{static_cast<T>(ar), static_cast<T>(ai)});
+                    ar = 0.0;
+                    ai = 0.0;
+                    ++t;
+                    t_next = cld(sp.ostart + (t + 1));
+                }
+                cplx<T> term = ap[j];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const uint32_t r = rr[j][k + 1];
+                    if (r != NO_SIBLING) term = cmul(term, (r >> 30) == TAG_NODE ? sv[j][k] : child(r));
+                }
+                ar += static_cast<double>(term.re);
+                ai += static_cast<double>(term.im);
+            }
+        }
+        for (; t < t1; ++t) {
+            out(t, cplx<T>{static_cast<T>(ar), static_cast<T>(ai)});
+            ar = 0.0;
+            ai = 0.0;
+        }
+    }
+
+    // downward pass on the sum-of-products plan: adj[s] = d root / d s for
+    // every super-node, level by level from the root
+    __device__ void backward_sop(const SopPlan &sp, cplx<T> *adj, int wave, int nwaves) const {
+        const uint32_t root = static_cast<uint32_t>(sp.root);
+        for (int l = sp.L - 1; l >= 0; --l) {
+            const uint32_t n0 = cld(sp.level_ptr + l), n1 = cld(sp.level_ptr + l + 1);
+            const uint32_t kb = batch_nodes(n1 - n0, nwaves);
+            for (uint32_t b0 = n0 + static_cast<uint32_t>(wave) * kb; b0 < n1;
+                 b0 += static_cast<uint32_t>(nwaves) * kb) {
+                const uint32_t b1 = b0 + kb < n1 ? b0 + kb : n1;
+                pull_sop(sp, adj, b0, b1, [&](uint32_t i, cplx<T> v) {
+                    adj[static_cast<size_t>(i) * WAVE + lane] = i == root ? cplx<T>{T(1), T(0)} : v;
+                });
+            }
+            __syncthreads();
+        }
+    }
+
+    // d root / d (angle slot s) on the sum-of-products plan
+    __device__ __forceinline__ cplx<T> slot_adjoint_sop(const SopPlan &sp, const cplx<T> *adj, uint32_t s) const {
+        const uint32_t t = static_cast<uint32_t>(sp.S + g.n_ind + g.n_sel) + s;
+        cplx<T> res{T(0), T(0)};
+        pull_sop(sp, adj, t, t + 1, [&](uint32_t, cplx<T> v) { res = v; });
+        return res;
+    }
+
+    // d root / d lambda_{v=u} on the sum-of-products plan, written to
+    // out[(base + u) * ostride] (indicator leaves plus selector leaves)
+    __device__ void ind_derivatives_sop(const SopPlan &sp, const cplx<T> *adj, int v, cplx<T> *out,
+                                        size_t ostride) const {
+        const uint32_t M = static_cast<uint32_t>(sp.S);
+        const uint32_t base = cld(g.ind_base + (v)), dom = cld(g.ind_base + (v + 1)) - base;
+        pull_sop(sp, adj, M + base, M + base + dom, [&](uint32_t i, cplx<T> val) { out[(i - M) * ostride] = val; });
+        const uint32_t q1 = cld(g.vsel_ptr + (v + 1));
+        for (uint32_t qq = cld(g.vsel_ptr + (v)); qq < q1; ++qq) {
+            const uint32_t q = cld(g.vsel + (qq));
+            const uint32_t tq = M + static_cast<uint32_t>(g.n_ind) + qq;
+            cplx<T> A{T(0), T(0)};
+            pull_sop(sp, adj, tq, tq + 1, [&](uint32_t, cplx<T> val) { A = val; });
+            const uint32_t *rec = g.sel + static_cast<size_t>(q) * SEL_REC;
+            for (uint32_t u = 0; u < dom && u < static_cast<uint32_t>(SEL_DOM); ++u) {
+                const uint32_t sl = cld(rec + 1 + u);
+                if (sl == NO_SLOT) continue;
+                const cplx<T> t = cmul(A, wval(cld(wfix + sl)));
+                cplx<T> &o = out[(base + u) * ostride];
+                o = cadd(o, t);
+            }
+        }
+    }
+
     // adj[parent] * (product of the other children) summed in FP64 over the
     // parent edges q0..q1 of a node or leaf.  recs holds one record per edge
     // (parent | sibling << 32, see DevGraph), so a group of KQ edges needs one
@@ -603,7 +721,7 @@ __device__ bool stage_tile(const DevGraph &g, uint64_t *ev_s, Weight<T> *ang_s, 
 // complex64: 8 waves per SIMD (64 VGPRs, a few spilled): rows wait on HBM and
 // more resident waves hide it (16-qubit noisy QAOA, 262,144 amplitudes:
 // 6 waves 74 ms, 8 waves 66 ms)
-template <typename T>
+template <typename T, bool SOP>
 __global__ __launch_bounds__(MAX_BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 1, 8))) void k_eval(DevGraph g, SopPlan sp, const double *theta, const int32_t *param_of, int P,
                                                 const uint64_t *evidence, int64_t B, const Weight<T> *wfix,
                                                 cplx<T> *vals, size_t per_wg, cplx<T> *amp_out,
@@ -622,10 +740,10 @@ __global__ __launch_bounds__(MAX_BLOCK) __attribute__((amdgpu_waves_per_eu(sizeo
         const bool valid = b < B;
         const bool in_range = stage_tile(g, ev_s, ang_s, evidence, param_of, P, theta, b, valid, lane, wave, nwaves);
         __syncthreads();
-        if (sp.S > 0) t.forward_sop(sp, wave, nwaves);
+        if constexpr (SOP) t.forward_sop(sp, wave, nwaves);
         else t.forward(wave, nwaves);
         if (wave == 0 && valid) {
-            cplx<T> f = val[static_cast<uint32_t>(sp.S > 0 ? sp.root : g.root) * WAVE + lane];
+            cplx<T> f = val[static_cast<uint32_t>(SOP ? sp.root : g.root) * WAVE + lane];
             if (!in_range) f = {T(NAN), T(NAN)};
             amp_out[b] = f;
             if (prob_out) {
@@ -645,8 +763,8 @@ __global__ __launch_bounds__(MAX_BLOCK) __attribute__((amdgpu_waves_per_eu(sizeo
 // 16-qubit noisy QAOA gradients over 262,144 elements 283 -> 255 ms (4 waves
 // per workgroup as everywhere; the downward pass's edge groups of eight took
 // it to 252 ms)
-template <typename T>
-__global__ __launch_bounds__(MAX_BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 1, 8))) void k_grad(DevGraph g, const double *theta, const int32_t *param_of, int P,
+template <typename T, bool SOP>
+__global__ __launch_bounds__(MAX_BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 1, 8))) void k_grad(DevGraph g, SopPlan sp, const double *theta, const int32_t *param_of, int P,
                                                 const uint64_t *evidence, int64_t B, const Weight<T> *wfix,
                                                 cplx<T> *vals, size_t per_wg, int mode,
                                                 const cplx<T> *cotangent, const double *weight,
@@ -659,8 +777,10 @@ __global__ __launch_bounds__(MAX_BLOCK) __attribute__((amdgpu_waves_per_eu(sizeo
     const int wave = static_cast<int>(uniform_u32(threadIdx.x / WAVE));
     const int nwaves = blockDim.x / WAVE;
     cplx<T> *val = vals + per_wg * blockIdx.x;
-    cplx<T> *adj = val + static_cast<size_t>(g.N) * WAVE;
-    cplx<T> *dsl = adj + static_cast<size_t>(g.N) * WAVE;    // [S_ang][64]
+    constexpr bool sop = SOP;                        // sum-of-products plan, else the DAG itself
+    const size_t rows = sop ? static_cast<size_t>(sp.S) : static_cast<size_t>(g.N);
+    cplx<T> *adj = val + rows * WAVE;
+    cplx<T> *dsl = adj + rows * WAVE;                // [S_ang][64]
     const int64_t n_tiles = (B + WAVE - 1) / WAVE;
     Tile<T> t{g, val, ev_s, ang_s, wfix, lane};
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
@@ -669,12 +789,19 @@ __global__ __launch_bounds__(MAX_BLOCK) __attribute__((amdgpu_waves_per_eu(sizeo
         const bool in_range = stage_tile(g, ev_s, ang_s, evidence, param_of, P, theta, b, in_batch, lane, wave, nwaves);
         const bool valid = in_batch && in_range;
         __syncthreads();
-        t.forward(wave, nwaves);
-        t.backward(adj, wave, nwaves);
+        if constexpr (sop) {
+            t.forward_sop(sp, wave, nwaves);
+            t.backward_sop(sp, adj, wave, nwaves);
+        } else {
+            t.forward(wave, nwaves);
+            t.backward(adj, wave, nwaves);
+        }
         const int p = valid ? param_of[b] : 0;
         const double *trow = theta + static_cast<int64_t>(p) * g.K;
         for (int s = wave; s < g.S_ang; s += nwaves) {
-            cplx<T> a = t.leaf_adjoint(adj, static_cast<uint32_t>(g.n_ind + s));
+            cplx<T> a;
+            if constexpr (sop) a = t.slot_adjoint_sop(sp, adj, static_cast<uint32_t>(s));
+            else a = t.leaf_adjoint(adj, static_cast<uint32_t>(g.n_ind + s));
             double dre, dim;
             slot_dvalue(g.slots[s], trow, dre, dim);
             dsl[s * WAVE + lane] = cmul(a, cplx<T>{static_cast<T>(dre), static_cast<T>(dim)});
@@ -682,14 +809,17 @@ __global__ __launch_bounds__(MAX_BLOCK) __attribute__((amdgpu_waves_per_eu(sizeo
         if (dind_out) {
             // [n_ind][64] rows after the angle-weight rows of this tile's buffer
             cplx<T> *Dt = dsl + static_cast<size_t>(g.S_ang) * WAVE;
-            for (int v = wave; v < g.n_vars; v += nwaves) t.ind_derivatives(adj, v, Dt + lane, WAVE);
+            for (int v = wave; v < g.n_vars; v += nwaves) {
+                if constexpr (sop) t.ind_derivatives_sop(sp, adj, v, Dt + lane, WAVE);
+                else t.ind_derivatives(adj, v, Dt + lane, WAVE);
+            }
             __syncthreads();
             if (valid)
                 for (int li = 0; li < g.n_ind; ++li) dind_out[b * g.n_ind + li] = Dt[static_cast<size_t>(li) * WAVE + lane];
         }
         __syncthreads();
         // cotangent of the root value
-        const cplx<T> f = val[static_cast<uint32_t>(g.root) * WAVE + lane];
+        const cplx<T> f = val[static_cast<uint32_t>(sop ? sp.root : g.root) * WAVE + lane];
         double gre = 0.0, gim = 0.0;
         if (valid) {
             if (mode == 0) {
@@ -727,16 +857,40 @@ __global__ __launch_bounds__(MAX_BLOCK) __attribute__((amdgpu_waves_per_eu(sizeo
     }
 }
 
-// grad[p][j] = sum over b with param_of[b] == p of contrib[b][j], fixed order.
-__global__ __launch_bounds__(BLOCK) void k_grad_reduce(const int32_t *param_of, int64_t B, int K,
-                                                       const double *contrib, double *grad) {
+// grad[p][j] = sum over b with param_of[b] == p of contrib[b][j], in an
+// order fixed by the elements' relative positions: the batch indices are
+// stably sorted by parameter set (a device radix sort on keys param_of, with
+// out-of-range entries in an extra bucket P that is never summed), so each
+// set's elements form one segment in their original order; thread t of the
+// set's workgroup adds segment positions t, t + 256, ... and the 256 partial
+// sums meet in a fixed tree.  O(B K) work, bit for bit the same for any
+// placement of a request's rows in a larger batch.
+__global__ void k_grad_keys(const int32_t *param_of, int64_t B, int P, uint32_t *keys, uint32_t *idx) {
+    const int64_t b = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    const int32_t p = param_of[b];
+    keys[b] = p >= 0 && p < P ? static_cast<uint32_t>(p) : static_cast<uint32_t>(P);
+    idx[b] = static_cast<uint32_t>(b);
+}
+
+__device__ __forceinline__ int64_t lower_bound_u32(const uint32_t *a, int64_t n, uint32_t key) {
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (a[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_grad_segments(const uint32_t *keys, const uint32_t *idx, int64_t B, int K,
+                                                         const double *contrib, double *grad) {
     __shared__ double red[BLOCK];
-    const int p = blockIdx.x;
+    const uint32_t p = blockIdx.x;
+    const int64_t lo = lower_bound_u32(keys, B, p), hi = lower_bound_u32(keys, B, p + 1);
     for (int j = 0; j < K; ++j) {
         double acc = 0.0;
-        for (int64_t b = threadIdx.x; b < B; b += BLOCK) {
-            if (param_of[b] == p) acc += contrib[b * K + j];
-        }
+        for (int64_t q = lo + threadIdx.x; q < hi; q += BLOCK) acc += contrib[static_cast<int64_t>(idx[q]) * K + j];
         red[threadIdx.x] = acc;
         __syncthreads();
         for (int w = BLOCK / 2; w > 0; w >>= 1) {
@@ -2029,20 +2183,23 @@ hipError_t launch_eval(const DevGraph &g, const SopPlan &sp, int grid, int block
                        void *amp_out, double *prob_out, hipStream_t st) {
     size_t lds = lds_bytes(g);
     if (block < WAVE || block > MAX_BLOCK || block % WAVE != 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_eval<T>, dim3(grid), dim3(block), lds, st, g, sp, theta, param_of, P, evidence, B,
+    auto kern = sp.S > 0 ? k_eval<T, true> : k_eval<T, false>;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, st, g, sp, theta, param_of, P, evidence, B,
                        reinterpret_cast<const Weight<T> *>(wfix), reinterpret_cast<cplx<T> *>(vals),
                        per_wg_elems, reinterpret_cast<cplx<T> *>(amp_out), prob_out);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_grad(const DevGraph &g, int grid, int block, const double *theta, const int32_t *param_of,
+hipError_t launch_grad(const DevGraph &g, const SopPlan &sp, int grid, int block, const double *theta, const int32_t *param_of,
                        const uint64_t *evidence, int64_t B, const void *wfix, void *vals, size_t per_wg_elems,
                        int mode, const void *cotangent, const double *weight, double *contrib, int P,
-                       double *grad, void *amp_out, void *dfdtheta_out, void *dind_out, hipStream_t st) {
+                       double *grad, void *amp_out, void *dfdtheta_out, void *dind_out, void *sort_ws,
+                       size_t sort_ws_bytes, hipStream_t st) {
     size_t lds = lds_bytes(g);
     if (block < WAVE || block > MAX_BLOCK || block % WAVE != 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_grad<T>, dim3(grid), dim3(block), lds, st, g, theta, param_of, P, evidence, B,
+    auto kern = sp.S > 0 ? k_grad<T, true> : k_grad<T, false>;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, st, g, sp, theta, param_of, P, evidence, B,
                        reinterpret_cast<const Weight<T> *>(wfix), reinterpret_cast<cplx<T> *>(vals),
                        per_wg_elems, mode, reinterpret_cast<const cplx<T> *>(cotangent), weight, contrib,
                        reinterpret_cast<cplx<T> *>(amp_out), reinterpret_cast<cplx<T> *>(dfdtheta_out),
@@ -2050,10 +2207,42 @@ hipError_t launch_grad(const DevGraph &g, int grid, int block, const double *the
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     if (g.K > 0 && P > 0) {
-        hipLaunchKernelGGL(k_grad_reduce, dim3(P), dim3(BLOCK), 0, st, param_of, B, g.K, contrib, grad);
+        uint32_t *keys = reinterpret_cast<uint32_t *>(sort_ws);
+        uint32_t *idx = keys + B;
+        uint32_t *keys_sorted = idx + B;
+        uint32_t *idx_sorted = keys_sorted + B;
+        void *tmp = idx_sorted + B;
+        const size_t tmp_bytes = sort_ws_bytes - 16 * static_cast<size_t>(B);
+        hipLaunchKernelGGL(k_grad_keys, dim3(static_cast<unsigned>((B + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, st,
+                           param_of, B, P, keys, idx);
+        if ((err = hipGetLastError()) != hipSuccess) return err;
+        int end_bit = 1;
+        while (end_bit < 32 && (static_cast<uint32_t>(P) >> end_bit) != 0u) ++end_bit;   // keys <= P
+        size_t need = 0;
+        err = hipcub::DeviceRadixSort::SortPairs(nullptr, need, keys, keys_sorted, idx, idx_sorted,
+                                                 static_cast<int>(B), 0, end_bit, st);
+        if (err != hipSuccess) return err;
+        if (need > tmp_bytes) return hipErrorInvalidValue;
+        size_t have = tmp_bytes;
+        err = hipcub::DeviceRadixSort::SortPairs(tmp, have, keys, keys_sorted, idx, idx_sorted,
+                                                 static_cast<int>(B), 0, end_bit, st);
+        if (err != hipSuccess) return err;
+        hipLaunchKernelGGL(k_grad_segments, dim3(P), dim3(BLOCK), 0, st, keys_sorted, idx_sorted, B, g.K, contrib, grad);
         err = hipGetLastError();
     }
     return err;
+}
+
+// Workspace bytes of the gradient reduction's sort for a batch of B elements:
+// keys and indices before and after the sort, then the sort's own storage.
+size_t grad_sort_bytes(int64_t B) {
+    if (B <= 0) return 0;
+    size_t tmp = 0;
+    if (hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, static_cast<uint32_t *>(nullptr),
+                                           static_cast<uint32_t *>(nullptr), static_cast<uint32_t *>(nullptr),
+                                           static_cast<uint32_t *>(nullptr), static_cast<int>(B), 0, 32) != hipSuccess)
+        return 0;
+    return 16 * static_cast<size_t>(B) + tmp + 256;
 }
 
 template <typename T>
@@ -2109,8 +2298,10 @@ int resident_blocks(const DevGraph &g, const SopPlan &sp, int which, int block) 
     const void *fn = nullptr;
     size_t lds = lds_bytes(g);
     switch (which) {
-        case 0: fn = reinterpret_cast<const void *>(&k_eval<T>); break;
-        case 1: fn = reinterpret_cast<const void *>(&k_grad<T>); break;
+        case 0: fn = sp.S > 0 ? reinterpret_cast<const void *>(&k_eval<T, true>)
+                              : reinterpret_cast<const void *>(&k_eval<T, false>); break;
+        case 1: fn = sp.S > 0 ? reinterpret_cast<const void *>(&k_grad<T, true>)
+                              : reinterpret_cast<const void *>(&k_grad<T, false>); break;
         case 2: fn = reinterpret_cast<const void *>(&k_sample<T>); break;
         case 3:
             fn = reinterpret_cast<const void *>(&k_sample_stream<T>);
@@ -2154,12 +2345,12 @@ template hipError_t launch_eval<float>(const DevGraph &, const SopPlan &, int, i
                                        int64_t, const void *, void *, size_t, void *, double *, hipStream_t);
 template hipError_t launch_eval<double>(const DevGraph &, const SopPlan &, int, int, const double *, const int32_t *, int, const uint64_t *,
                                         int64_t, const void *, void *, size_t, void *, double *, hipStream_t);
-template hipError_t launch_grad<float>(const DevGraph &, int, int, const double *, const int32_t *, const uint64_t *,
+template hipError_t launch_grad<float>(const DevGraph &, const SopPlan &, int, int, const double *, const int32_t *, const uint64_t *,
                                        int64_t, const void *, void *, size_t, int, const void *, const double *,
-                                       double *, int, double *, void *, void *, void *, hipStream_t);
-template hipError_t launch_grad<double>(const DevGraph &, int, int, const double *, const int32_t *, const uint64_t *,
+                                       double *, int, double *, void *, void *, void *, void *, size_t, hipStream_t);
+template hipError_t launch_grad<double>(const DevGraph &, const SopPlan &, int, int, const double *, const int32_t *, const uint64_t *,
                                         int64_t, const void *, void *, size_t, int, const void *, const double *,
-                                        double *, int, double *, void *, void *, void *, hipStream_t);
+                                        double *, int, double *, void *, void *, void *, void *, size_t, hipStream_t);
 template hipError_t launch_sample<float>(const DevGraph &, int, const double *, const void *, void *, size_t,
                                          const SampleArgs &, hipStream_t);
 template hipError_t launch_sample<double>(const DevGraph &, int, const double *, const void *, void *, size_t,
