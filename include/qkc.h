@@ -107,6 +107,11 @@ typedef struct {
        s*(n_super_leaf_reads + n_indicator_leaves), s = 8 (c64) or 16 (c128). */
     int32_t n_super;           /* super-nodes (one row each per element)        */
     int32_t n_super_levels;
+    int32_t max_live;          /* most super-nodes alive at once in the upward pass
+                                  (from a node's level to its last reader's level):
+                                  the rows per element an amplitude call keeps;
+                                  n_internal when there is no plan             */
+    int32_t reserved;          /* 0 */
     int64_t n_super_node_factors; /* factors that are super-nodes (rows read upward) */
     int64_t n_super_down_reads;   /* per occurrence of a super-node as a factor: the
                                      parent's adjoint row and each super-node sibling */

@@ -361,8 +361,9 @@ HostPlan build_plan(uint32_t N, const uint8_t *op, const uint32_t *row_ptr, cons
 // Sum-of-products plan (see SopPlan in qkc_internal.h), built on the host.
 struct HostSop {
     std::vector<uint32_t> level_ptr, fptr, ostart, occ, osel;
-    std::vector<uint64_t> frec;
-    uint32_t S = 0, L = 0, root = 0, max_factors = 0;
+    std::vector<uint64_t> frec, frec_live;
+    std::vector<uint32_t> srow;
+    uint32_t S = 0, L = 0, root = 0, max_factors = 0, live_rows = 0;
     uint64_t node_factors = 0, down_reads = 0, leaf_reads = 0;   // row counts of the streaming model
     bool ok = false;
 };
@@ -531,6 +532,45 @@ HostSop build_sop(uint32_t N, const uint8_t *op, const uint32_t *row_ptr, const 
     }
     for (uint32_t k = 0; k < n_sel; ++k)
         P.osel.insert(P.osel.end(), occ[static_cast<size_t>(M) + n_ind + k].size(), vsel[k]);
+    // rows of the upward pass alone: super-node j lives from its level to the
+    // level of its last consumer (the root to the end); rows are handed out
+    // in level order and freed after their last reading level
+    {
+        std::vector<uint32_t> lvl(M), death(M, 0);
+        for (uint32_t l = 0; l < Lmax; ++l)
+            for (uint32_t j = P.level_ptr[l]; j < P.level_ptr[l + 1]; ++j) lvl[j] = l;
+        for (uint32_t j = 0; j < M; ++j)
+            for (uint32_t f = P.fptr[j]; f < P.fptr[j + 1]; ++f) {
+                const uint32_t r = static_cast<uint32_t>(P.frec[f]);
+                if ((r >> 30) == TAG_NODE) death[r] = std::max(death[r], lvl[j]);
+            }
+        death[P.root] = Lmax;
+        std::vector<std::vector<uint32_t>> freed_after(Lmax + 1);
+        std::vector<uint32_t> free_rows;
+        P.srow.assign(M, 0);
+        uint32_t next = 0;
+        for (uint32_t l = 0; l < Lmax; ++l) {
+            if (l > 0)                                   // rows whose last reader ran at level l - 1
+                for (uint32_t r : freed_after[l - 1]) free_rows.push_back(r);
+            for (uint32_t j = P.level_ptr[l]; j < P.level_ptr[l + 1]; ++j) {
+                uint32_t r;
+                if (!free_rows.empty()) {
+                    r = free_rows.back();
+                    free_rows.pop_back();
+                } else {
+                    r = next++;
+                }
+                P.srow[j] = r;
+                freed_after[std::max(death[j], l)].push_back(r);
+            }
+        }
+        P.live_rows = next;
+        P.frec_live = P.frec;
+        for (uint64_t &f : P.frec_live) {
+            const uint32_t r = static_cast<uint32_t>(f);
+            if ((r >> 30) == TAG_NODE) f = (f & ~0xffffffffull) | P.srow[r];
+        }
+    }
     P.S = M;
     P.L = Lmax;
     P.root = newid[sroot];
@@ -751,6 +791,8 @@ extern "C" ac_status ac_load(const void *blob, size_t nbytes, int device, ac_gra
         {hs.ostart.data(), hs.ostart.size() * sizeof(uint32_t), 0},
         {hs.occ.data(), hs.occ.size() * sizeof(uint32_t), 0},
         {hs.osel.data(), hs.osel.size() * sizeof(uint32_t), 0},
+        {hs.frec_live.data(), hs.frec_live.size() * sizeof(uint64_t), 0},
+        {hs.srow.data(), hs.srow.size() * sizeof(uint32_t), 0},
     };
     size_t total = 0;
     for (auto &s : secs) {
@@ -853,6 +895,9 @@ extern "C" ac_status ac_load(const void *blob, size_t nbytes, int device, ac_gra
         sp.L = static_cast<int32_t>(hs.L);
         sp.root = static_cast<int32_t>(hs.root);
         sp.max_factors = static_cast<int32_t>(hs.max_factors);
+        sp.frec_live = reinterpret_cast<const uint64_t *>(at(36));
+        sp.srow = reinterpret_cast<const uint32_t *>(at(37));
+        sp.live_rows = static_cast<int32_t>(hs.live_rows);
         // the sampler's decision pass keeps one change bit per variable and
         // handles variables of at most SEL_DOM values
         bool small_doms = true;
@@ -912,12 +957,14 @@ extern "C" ac_status ac_load(const void *blob, size_t nbytes, int device, ac_gra
     inf.root = d.root;
     inf.device = device;
     inf.n_prod_flops = flops;
+    inf.max_live = d.N;
     if (hs.ok) {
         inf.n_super = static_cast<int32_t>(hs.S);
         inf.n_super_levels = static_cast<int32_t>(hs.L);
         inf.n_super_node_factors = static_cast<int64_t>(hs.node_factors);
         inf.n_super_down_reads = static_cast<int64_t>(hs.down_reads);
         inf.n_super_leaf_reads = static_cast<int64_t>(hs.leaf_reads);
+        inf.max_live = static_cast<int32_t>(hs.live_rows);
     }
     *out = g;
     return AC_OK;
@@ -1090,6 +1137,10 @@ int wide_block_for(const ac_graph *g, ac_dtype dt, int64_t batch, int kid, int &
 // only for super-nodes), else on the DAG.
 SopPlan eval_plan(const ac_graph *g) { return g->has_sop ? g->sop : SopPlan{}; }
 size_t eval_rows(const ac_graph *g) { return g->has_sop ? static_cast<size_t>(g->sop.S) : static_cast<size_t>(g->dev.N); }
+// rows of the upward pass alone (super-node rows reused once their readers ran)
+size_t eval_live_rows(const ac_graph *g) {
+    return g->has_sop ? static_cast<size_t>(g->sop.live_rows) : static_cast<size_t>(g->dev.N);
+}
 
 struct Layout {
     size_t wfix_off = 0, contrib_off = 0, sort_off = 0, sort_bytes = 0, tiles_off = 0, total = 0;
@@ -1104,7 +1155,7 @@ bool make_layout(const ac_graph *g, ac_dtype dt, int64_t batch, int op, Layout &
     const size_t cs = dt == AC_C64 ? 8 : 16;
     size_t rows = 0;
     int kid = 0;
-    if (op == AC_OP_EVAL) rows = eval_rows(g);
+    if (op == AC_OP_EVAL) rows = eval_live_rows(g);
     else if (op == AC_OP_GRAD) {
         rows = 2 * eval_rows(g) + d.S_ang + d.n_ind;
         kid = 1;
@@ -1262,12 +1313,12 @@ extern "C" ac_status ac_eval_batch_static(const ac_graph *g, ac_dtype dtype, con
     // workgroups' node rows as fit (the grid is capped to that number)
     const size_t cs = dtype == AC_C64 ? 8 : 16;
     const size_t wfix_bytes = align256(static_cast<size_t>(std::max(g->dev.S, 1)) * 16);
-    const size_t one_tile = align256(eval_rows(g) * WAVE * cs);
+    const size_t one_tile = align256(eval_live_rows(g) * WAVE * cs);
     if (wfix_bytes + one_tile > STATIC_SCRATCH_BYTES)
         return fail(AC_ERR_UNSUPPORTED,
                     "ac_eval_batch_static: one 64-element tile needs %zu bytes of scratch (%zu node rows), above the "
                     "%zu-byte static scratch; use ac_eval_batch with a workspace",
-                    wfix_bytes + one_tile, eval_rows(g), STATIC_SCRATCH_BYTES);
+                    wfix_bytes + one_tile, eval_live_rows(g), STATIC_SCRATCH_BYTES);
     Layout L;
     make_layout(g, dtype, B, AC_OP_EVAL, L, STATIC_SCRATCH_BYTES - wfix_bytes);
     if (L.total > STATIC_SCRATCH_BYTES)

@@ -161,6 +161,13 @@ struct SopPlan {
     int32_t max_factors;        // most factors of one super-node
     int32_t mask_words;         // words of the per-chain change mask of the streaming
                                 // sampler's decision pass (0: decisions in the scan only)
+    // Row reuse for the upward pass alone (no downward pass reads the values
+    // later): a super-node's row is free once its last consumer's level has
+    // run, so rows are handed out again level by level (greedy in level order,
+    // which needs exactly the largest number of super-nodes alive at once).
+    const uint64_t *frec_live;  // frec with super-node references replaced by their rows
+    const uint32_t *srow;       // [S] row of each super-node
+    int32_t live_rows;          // rows the upward pass needs per element
 };
 constexpr int MAX_MASK_WORDS = 16;   // decision pass for up to 1024 variables
 

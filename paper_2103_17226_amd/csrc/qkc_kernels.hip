@@ -361,8 +361,12 @@ struct Tile {
     // FP64) -- so the root comes out bit for bit the same.  A wave takes up to four
     // consecutive super-nodes of a level and walks their factors in groups of
     // KC whose rows are loaded together.
+    // LIVE: the upward pass alone, with rows reused (frec_live, srow).
+    template <bool LIVE = false>
     __device__ void forward_sop(const SopPlan &sp, int wave, int nwaves) {
         constexpr int KC = 8;
+        const uint64_t *frec = LIVE ? sp.frec_live : sp.frec;
+        auto row_of = [&](uint32_t t) -> size_t { return LIVE ? cld(sp.srow + t) : t; };
         for (int l = 0; l < sp.L; ++l) {
             const uint32_t n0 = cld(sp.level_ptr + l), n1 = cld(sp.level_ptr + l + 1);
             const uint32_t kb = batch_nodes(n1 - n0, nwaves);
@@ -377,7 +381,7 @@ struct Tile {
                     uint64_t rec[KC];
                     cplx<T> v[KC];
 #pragma unroll
-                    for (int j = 0; j < KC; ++j) rec[j] = f + j < f_end ? cld(sp.frec + f + j) : static_cast<uint64_t>(IDENT_REF);
+                    for (int j = 0; j < KC; ++j) rec[j] = f + j < f_end ? cld(frec + f + j) : static_cast<uint64_t>(IDENT_REF);
 #pragma unroll
                     for (int j = 0; j < KC; ++j) v[j] = eb_guard(static_cast<uint32_t>(rec[j]));
 #pragma unroll
@@ -385,7 +389,7 @@ struct Tile {
                         const uint32_t ff = f + static_cast<uint32_t>(j);
                         if (ff >= f_end) break;
                         while (ff >= t_next) {          // super-node t has all its terms
-                            val[static_cast<size_t>(t) * WAVE + lane] = cplx<T>{static_cast<T>(sr), static_cast<T>(si)};
+                            val[row_of(t) * WAVE + lane] = cplx<T>{static_cast<T>(sr), static_cast<T>(si)};
                             sr = 0.0;
                             si = 0.0;
                             ++t;
@@ -421,7 +425,7 @@ struct Tile {
                         }
                     }
                 }
-                val[static_cast<size_t>(t) * WAVE + lane] = cplx<T>{static_cast<T>(sr), static_cast<T>(si)};
+                val[row_of(t) * WAVE + lane] = cplx<T>{static_cast<T>(sr), static_cast<T>(si)};
             }
             __syncthreads();
         }
@@ -740,10 +744,12 @@ __global__ __launch_bounds__(MAX_BLOCK) __attribute__((amdgpu_waves_per_eu(sizeo
         const bool valid = b < B;
         const bool in_range = stage_tile(g, ev_s, ang_s, evidence, param_of, P, theta, b, valid, lane, wave, nwaves);
         __syncthreads();
-        if constexpr (SOP) t.forward_sop(sp, wave, nwaves);
+        if constexpr (SOP) t.template forward_sop<true>(sp, wave, nwaves);
         else t.forward(wave, nwaves);
         if (wave == 0 && valid) {
-            cplx<T> f = val[static_cast<uint32_t>(SOP ? sp.root : g.root) * WAVE + lane];
+            uint32_t root_row = static_cast<uint32_t>(g.root);
+            if constexpr (SOP) root_row = cld(sp.srow + sp.root);
+            cplx<T> f = val[static_cast<size_t>(root_row) * WAVE + lane];
             if (!in_range) f = {T(NAN), T(NAN)};
             amp_out[b] = f;
             if (prob_out) {

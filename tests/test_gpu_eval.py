@@ -253,3 +253,27 @@ def test_param_rows_outside_range_give_nan_not_reads():
     good = g.grad(theta, ev[[0, 2]], np.array([0, 1], np.int32), mode="prob", weight=np.ones(2), dtype="c128")
     assert np.array_equal(out["grad"].cpu().numpy(), good["grad"].cpu().numpy())
     assert np.isnan(out["amp"].cpu().numpy()[[1, 3]]).all()
+
+
+def test_liveness_bounds_the_amplitude_workspace():
+    # The upward pass keeps one row per super-node only from its level to its
+    # last reader's level: config 3's amplitude call holds max_live rows per
+    # element, under a fifth of the DAG's node count, and its results equal
+    # the gradient kernel's upward pass (all rows kept) bit for bit.
+    note("liveness-bounded workspace (config 3)")
+    from paper_2103_17226_amd import _lib as L
+    cfg = W.config(3, small=True)
+    g = graph(cfg["circuit"])
+    inf = g.info
+    note(f"  nodes {inf['n_internal']}, super-nodes {inf['n_super']}, max live {inf['max_live']}")
+    assert 0 < inf["max_live"] <= inf["n_super"] <= inf["n_internal"]
+    assert 5 * inf["max_live"] <= inf["n_internal"]
+    B = 262144
+    ws = g.workspace_size("c64", B, L.AC_OP_EVAL)
+    tiles = B // 64
+    assert ws <= min(tiles, 256 * 16) * inf["max_live"] * 64 * 8 + (1 << 20)
+    theta, ev, po = cfg["theta"], cfg["evidence"], cfg["param_of"]
+    for dtype in ("c64", "c128"):
+        amp, _ = g.eval(theta, ev, po, dtype=dtype)
+        out = g.grad(theta, ev, po, mode="prob", weight=np.ones(len(po)), dtype=dtype, want_amp=True)
+        assert torch.equal(amp, out["amp"]), dtype
