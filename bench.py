@@ -22,10 +22,14 @@ serving mix -- a pool of noisy QAOA circuits (p in {1,2}, n in
 U[1e-3,1e-2] per circuit), Poisson arrivals, per request a circuit uniform
 from the pool, P ~ log-uniform{1..256} parameter sets, an amplitude request
 (64 outputs per set) w.p. 0.1 else S ~ log-uniform{1..4096} samples per set,
-a gradient w.p. 0.5 -- through the continuous-batching loop; p50/p99
-latency from arrival to completion, throughput and rejections per offered
-rate.  The default pool leaves out the p=2, n=20 circuits (ACs of 1-2.4M
-nodes that take minutes to compile); --serve-pool full keeps them.
+a gradient w.p. 0.5 -- through the continuous-batching loop at 200, 500,
+1000 and 2000 req/s (10 s warm-up and 60 s measured at 2000 req/s, 5 s and
+15 s at the lower rates);
+requests estimated to hold the device over 0.5 s are split into parts; p50/p99
+latency from arrival to completion, throughput and outcomes per offered rate.
+The pool (all 40 circuits; the p=2, n=20 ones compile to ACs of about a
+million nodes) compiles in worker processes while the other legs run, with
+a blob cache on disk; --serve-pool fast leaves the n=20, p=2 circuits out.
 
 Prints one JSON line.  --gpus > 1 is refused: this build runs on one GPU.
 """
@@ -83,17 +87,25 @@ def parse():
     ap.add_argument("--no-eval", action="store_true")
     ap.add_argument("--eval-steps", type=int, default=5)
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-rates", default="0.5,5,2000",
+    ap.add_argument("--serve-rates", default="200,500,1000,2000",
                     help="offered request rates (req/s), one serving run each")
-    ap.add_argument("--serve-seconds", type=float, default=12.0)
-    ap.add_argument("--serve-warmup", type=float, default=2.0)
-    ap.add_argument("--serve-drain", type=float, default=60.0)
-    ap.add_argument("--serve-pool", choices=["fast", "full"], default="fast")
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
+                    help="measured window at the highest offered rate")
+    ap.add_argument("--serve-seconds-low", type=float, default=15.0,
+                    help="measured window at the lower offered rates")
+    ap.add_argument("--serve-warmup", type=float, default=10.0,
+                    help="warm-up before the measured window at the highest offered rate")
+    ap.add_argument("--serve-warmup-low", type=float, default=5.0)
+    ap.add_argument("--serve-drain", type=float, default=15.0,
+                    help="seconds to let requests in flight finish after the last arrival")
+    ap.add_argument("--serve-pool", choices=["fast", "full"], default="full")
+    ap.add_argument("--blob-cache", default=os.path.join(os.path.expanduser("~"), ".cache", "qkc_blobs"),
+                    help="directory of cached compiled serving-pool blobs ('' for none)")
     ap.add_argument("--serve-streams", type=int, default=8)
     ap.add_argument("--serve-queue", type=int, default=16)
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     ap.add_argument("--serve-max-seconds", type=float, default=0.5,
-                    help="reject requests estimated to hold the device longer than this")
+                    help="split requests estimated to hold the device longer than this into parts")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device-to-device three times (calibrates the HBM "
                          "byte counters of a profiler run) and exit")
@@ -110,22 +122,34 @@ def copy_probe():
     print(json.dumps({"copy_probe_bytes": 3 * (1 << 30)}))
 
 
-def compile_pool(full: bool):
-    """Blobs of the serving pool, compiled in worker processes (started
-    before this process touches the GPU)."""
+def compile_pool_start(full: bool, cache_dir: str):
+    """Start compiling the serving pool in worker processes (spawned before
+    this process touches the GPU), largest circuits first, so that it runs
+    while the GPU legs do; returns (pool, executor, futures, start time).
+    Blobs are cached on disk under cache_dir (keyed by the circuit and the
+    compiler's source), so a second run on the same machine loads them."""
     import multiprocessing as mp
     from concurrent.futures import ProcessPoolExecutor
 
     import workloads as W
-    from paper_2103_17226_amd.blob import compile_blob
+    from paper_2103_17226_amd.blob import compile_blob_cached
     pool = W.serving_pool()
     if not full:
         pool = [c for c in pool if not (c.n >= 20 and c.n_angles == 4)]
     t0 = time.perf_counter()
-    workers = max(1, min(8, (os.cpu_count() or 1)))
-    with ProcessPoolExecutor(workers, mp_context=mp.get_context("spawn")) as ex:
-        blobs = list(ex.map(compile_blob, pool))
-    return pool, blobs, time.perf_counter() - t0
+    workers = max(1, min(16, (os.cpu_count() or 1)))
+    ex = ProcessPoolExecutor(workers, mp_context=mp.get_context("spawn"))
+    order = sorted(range(len(pool)), key=lambda i: -(pool[i].n * pool[i].n_angles))
+    futs = {i: ex.submit(compile_blob_cached, pool[i], cache_dir) for i in order}
+    return pool, ex, [futs[i] for i in range(len(pool))], t0
+
+
+def compile_pool_finish(started):
+    pool, ex, futs, t0 = started
+    out = [f.result() for f in futs]
+    ex.shutdown()
+    blobs = [b for b, _ in out]
+    return pool, blobs, time.perf_counter() - t0, sum(1 for _, hit in out if hit)
 
 
 def serve_run(graphs, pool, rate, args):
@@ -140,7 +164,10 @@ def serve_run(graphs, pool, rate, args):
     ex = GraphExecutor(graphs, edges, n_streams=args.serve_streams)
     srv = Server(ex, mem_budget=int(args.serve_budget_gib * (1 << 30)), max_queue=args.serve_queue,
                  max_seconds=args.serve_max_seconds)
-    total = args.serve_warmup + args.serve_seconds
+    top = rate >= max(float(x) for x in args.serve_rates.split(",") if x)
+    seconds = args.serve_seconds if top else args.serve_seconds_low
+    warmup = args.serve_warmup if top else args.serve_warmup_low
+    total = warmup + seconds
     reqs = W.serving_requests(pool, rate, total, seed=W.sub_seed("arrivals", 5) + int(rate))
     srv.start()
     t0 = time.perf_counter()
@@ -157,7 +184,7 @@ def serve_run(graphs, pool, rate, args):
     t_end = time.perf_counter()
     srv.stop(drain=True, timeout=args.serve_drain)
     torch.cuda.synchronize()
-    since = t0 + args.serve_warmup
+    since = t0 + warmup
     st = srv.latency_stats(since=since)
     window = [q for q in futs if q.t_arrive >= since]
 
@@ -173,12 +200,14 @@ def serve_run(graphs, pool, rate, args):
             return "rejected_queue"
         if "hold the device" in msg:
             return "rejected_cost"
-        if "device memory" in msg:
+        if "device memory" in msg or "resident" in msg:
             return "rejected_memory"
+        if "at least 2 samples" in msg:
+            return "rejected_invalid"
         return "failed"
 
-    counts = {k: 0 for k in ("completed", "rejected_queue", "rejected_cost", "rejected_memory", "failed",
-                             "unfinished")}
+    counts = {k: 0 for k in ("completed", "rejected_queue", "rejected_cost", "rejected_memory", "rejected_invalid",
+                             "failed", "unfinished")}
     for q in window:
         counts[outcome(q)] += 1
     ok = [q for q in window if outcome(q) == "completed"]
@@ -187,7 +216,8 @@ def serve_run(graphs, pool, rate, args):
     ratio = [(q.t_done - q.t_start) / max(ex.cost(q), 1e-6) for q in ok]
     stuck = [{"graph": q.graph, "kind": q.kind, "P": q.n_params, "S": q.samples, "rows": q.n_rows,
               "grad": q.grad, "est_s": ex.cost(q)} for q in window if outcome(q) == "unfinished"]
-    out = {"offered_rps": rate, "arrivals": len(window), **counts,
+    out = {"offered_rps": rate, "warmup_s": warmup, "measured_s": seconds, "arrivals": len(window),
+           **counts, "split_requests": st["split_requests"], "split_parts": st["split_parts"],
            "p50_ms": st.get("p50_ms"), "p99_ms": st.get("p99_ms"), "mean_ms": st.get("mean_ms"),
            "throughput_rps": len(ok) / span,
            "samples_per_s": sum(q.n_params * q.samples for q in ok) / span,
@@ -455,7 +485,65 @@ def cpu_baseline(circ, theta, chains, budget_s):
     return {"value": done * chains / dt, "unit": "samples/s", "cores": cores,
             "kind": "oracle",
             "sample": f"{done} of {theta.shape[0]} parameter sets: density-matrix diagonal, {chains} "
-                      f"exact samples each, parameter-shift gradient of <C> ({dt:.1f} s, numpy complex128)"}
+                      f"exact samples each, parameter-shift gradient of <C> ({dt:.1f} s, numpy complex128)",
+            "host": host_description()}
+
+
+def host_description():
+    """CPU model and logical core count of the host."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "os_cpu_count": os.cpu_count(),
+            "usable_cores": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()}
+
+
+def cpu_evaluator_baseline(circ, theta, chains, eval_cfg, budget_s):
+    """The plain CPU AC evaluator (libqkc_cpu.so, complex128, OpenMP) on
+    the same blobs: Gibbs samples/s on the default sampling job's AC (a
+    bounded slice of its parameter sets, all chains each) and upward-pass
+    node-evals/s on the 16-qubit amplitude job's rows, on all usable cores
+    and on one core."""
+    import numpy as np
+
+    from paper_2103_17226_amd import cpu_eval
+    from paper_2103_17226_amd.blob import to_blob
+    from paper_2103_17226_amd.compiler import compile_circuit
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    out = {"kind": "plain CPU AC evaluator (C++ -O3, OpenMP, complex128; same blobs, same sampler rules)",
+           "host": host_description()}
+    sac = cpu_eval.CpuAC(to_blob(compile_circuit(circ)))
+    eac = cpu_eval.CpuAC(to_blob(compile_circuit(eval_cfg["circuit"])))
+    for label, threads in (("all_cores", cores), ("one_core", 1)):
+        share = budget_s / 4.0
+        # samples: parameter sets one after another, all their chains, until the time share is used
+        done, t0 = 0, time.perf_counter()
+        while done < theta.shape[0] and time.perf_counter() - t0 < share:
+            step = max(1, min(theta.shape[0] - done, threads // 8 or 1))
+            sac.sample(theta[done:done + step], chains, 1, 10, 1, seed=7, threads=threads)
+            done += step
+        ts = time.perf_counter() - t0
+        # amplitudes: blocks of 4096 rows of the 16-qubit job
+        ev, po, th = eval_cfg["evidence"], eval_cfg["param_of"], eval_cfg["theta"]
+        rows, t0 = 0, time.perf_counter()
+        while rows < ev.shape[0] and time.perf_counter() - t0 < share:
+            blk = 4096 if threads > 1 else 256
+            sl = slice(rows, rows + blk)
+            sac_amp = eac.eval(th, ev[sl], po[sl], threads=threads)
+            rows += blk
+        te = time.perf_counter() - t0
+        out[label] = {"threads": threads, "samples_per_s": done * chains / ts,
+                      "sample_job": f"{done} parameter sets x {chains} chains, 10 burn-in sweeps ({ts:.1f} s)",
+                      "node_evals_per_s": rows * eac.n_internal / te, "amplitudes_per_s": rows / te,
+                      "eval_job": f"{rows} rows of the 16-qubit p=2 batch ({te:.1f} s)"}
+        del sac_amp
+    return out
 
 
 def main():
@@ -469,8 +557,9 @@ def main():
         sys.exit(2)
     pool = blobs = None
     t_pool = 0.0
-    if not args.no_serve:
-        pool, blobs, t_pool = compile_pool(args.serve_pool == "full")
+    started = None
+    if not args.no_serve:         # compiles while the GPU legs run
+        started = compile_pool_start(args.serve_pool == "full", args.blob_cache)
     import numpy as np
     import torch
 
@@ -592,8 +681,6 @@ def main():
             "dag_model_GBps": dag_bytes_round * rounds / samp_s / 1e9,
         },
     }
-    if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(circ, theta_np, chains, args.cpu_seconds)
     del s, out, last
     g.close()
     ws_sample = None
@@ -606,7 +693,9 @@ def main():
         print("# 2D Ising VQE", file=sys.stderr, flush=True)
         res["vqe"] = vqe_leg(args.eval_steps)
         torch.cuda.empty_cache()
-    if pool is not None:
+    if started is not None:
+        print("# serving pool (compiled in the background)", file=sys.stderr, flush=True)
+        pool, blobs, t_pool, cache_hits = compile_pool_finish(started)
         graphs = {c.name: ACGraph(b, device=0) for c, b in zip(pool, blobs)}
         runs = []
         for rate in [float(x) for x in args.serve_rates.split(",") if x]:
@@ -616,16 +705,24 @@ def main():
             "workload": "serving mix: noisy QAOA p in {1,2}, n in {6,8,12,16,20}, 4 graphs each, "
                         "Poisson arrivals; P~logU{1..256}, eval(64 x/set) w.p. 0.1 else S~logU{1..4096} "
                         "samples/set, gradient w.p. 0.5; c64",
-            "pool_circuits": len(pool), "pool_compile_s": t_pool,
+            "pool_circuits": len(pool), "pool_compile_s": t_pool, "pool_cache_hits": cache_hits,
             "pool_ac_nodes_max": max(gr.info["n_internal"] for gr in graphs.values()),
             "streams": args.serve_streams, "queue_limit": args.serve_queue,
             "budget_gib": args.serve_budget_gib, "max_request_seconds": args.serve_max_seconds,
             "warmup_s": args.serve_warmup, "measured_s": args.serve_seconds,
+            "measured_s_lower_rates": args.serve_seconds_low,
             "runs": runs,
         }
         main_run = max(runs, key=lambda r: r["offered_rps"]) if runs else {}
         res["serving"]["p50_ms"] = main_run.get("p50_ms")
         res["serving"]["p99_ms"] = main_run.get("p99_ms")
+        for gr in graphs.values():
+            gr.close()
+        torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:    # last: the host cores are idle by now
+        print("# CPU baselines", file=sys.stderr, flush=True)
+        res["cpu_baseline"] = cpu_baseline(circ, theta_np, chains, args.cpu_seconds)
+        res["cpu_evaluator"] = cpu_evaluator_baseline(circ, theta_np, chains, W.config(3), args.cpu_seconds)
     print(json.dumps(res), flush=True)
 
 

@@ -263,8 +263,13 @@ ac_status ac_grad_batch(const ac_graph *g, ac_dtype dtype,
  *
  * Randomness: r = (mix(seed ^ mix(chain ^ mix((sweep << 20) ^ var))) >> 11) * 2^-53
  * with mix(z) the SplitMix64 finaliser of z + 0x9E3779B97F4A7C15 (Steele, Lea
- * and Flood, OOPSLA 2014); chain = p * chains_per_param + c; the sweeps of a
- * call are numbered first_sweep, first_sweep + 1, ...  Initial state:
+ * and Flood, OOPSLA 2014); chain = chain_offset + p * chains_per_param + c;
+ * the sweeps of a call are numbered first_sweep, first_sweep + 1, ...  A
+ * call over parameter sets p0 .. p0 + P - 1 of a larger request (theta from
+ * row p0, chain_offset = p0 * chains_per_param), or over chains c0 ..
+ * c0 + C - 1 of one parameter set p (P = 1, chains_per_param = C,
+ * chain_offset = p * chains_per_param_of_the_request + c0), draws exactly
+ * the chains of the whole request.  Initial state:
  * init_states[chain] (all n_words words: outputs and noise events) if
  * init_states is given, else output bit q = [r(seed, chain, 0xFFFFFFFF, q) < 1/2]
  * and every noise event 0.  Chain c of parameter set p runs burn_in +
@@ -289,11 +294,12 @@ ac_status ac_grad_batch(const ac_graph *g, ac_dtype dtype,
  * c * samples_per_chain + j:
  *   samples    uint64 [P][S][ceil(n_qubits/64)]  output bits (required)
  *   states_out uint64 [P][S][n_words]            full evidence words (optional)
- *   cost_out   float64 [P][S]  MaxCut cost of the sample over cost_edges (optional)
+ *   cost_out   float64 [P][S]  MaxCut cost of the sample over cost_edges (optional;
+ *              NaN if an edge names a qubit outside [0, n_qubits))
  *   rounds_out int64 [P * chains_per_param] downward passes each chain used (optional)
  * cost_edges is a device int32 [n_cost_edges][2] array (NULL if n_cost_edges = 0);
  * init_states is a device uint64 [P * chains_per_param][n_words] array or NULL.
- * Any bit pattern is a valid state (every domain is a power of two).
+ * Any bit pattern is a valid state (ac_load accepts only power-of-two domains).
  * Requires n_qubits <= 64, seed < 2^64, first_sweep + sweeps per chain < 2^32 - 1,
  * n_vars < 2^20, first_var < n_vars, reserved 0.
  */
@@ -309,6 +315,7 @@ typedef struct {
     const uint64_t *init_states;
     uint32_t first_sweep;
     uint32_t first_var;
+    uint64_t chain_offset;   /* RNG chain number of chain 0 (see above); <= 2^62 */
 } ac_sample_cfg;
 
 ac_status ac_sample(const ac_graph *g, ac_dtype dtype,

@@ -49,7 +49,7 @@ class SampleCfg(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("n_cost_edges", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("cost_edges", ctypes.c_void_p),
                 ("init_states", ctypes.c_void_p), ("first_sweep", ctypes.c_uint32),
-                ("first_var", ctypes.c_uint32)]
+                ("first_var", ctypes.c_uint32), ("chain_offset", ctypes.c_uint64)]
 
 
 class ACError(RuntimeError):

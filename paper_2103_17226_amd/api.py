@@ -206,14 +206,17 @@ class ACGraph:
                thin: int = 1, seed: int = 1, cost_edges: Optional[Sequence] = None, noise=None,
                dtype: str = "c64", want_states=False, want_cost=False, want_rounds=False,
                validate: bool = True, ws: Optional[torch.Tensor] = None, init_states=None,
-               first_sweep: int = 0, first_var: int = 0):
+               first_sweep: int = 0, first_var: int = 0, chain_offset: int = 0):
         """Gibbs samples of the output bits (see ac_sample).  ``init_states``
         (uint64/int64 [P * chains_per_param, n_words], e.g. the last sample's
         ``states`` of a previous call) starts every chain from a given state;
         ``first_sweep`` numbers this call's first sweep for the RNG, so a call
         resumed with the previous call's sweep count continues its chains.
         ``first_var`` > 0 keeps variables 0 .. first_var - 1 at their start
-        values (conditional sampling, e.g. noise events given an outcome)."""
+        values (conditional sampling, e.g. noise events given an outcome).
+        ``chain_offset`` numbers this call's first chain for the RNG, so a
+        request split into parts (by parameter sets or by chains of one set)
+        draws exactly the chains of the whole request."""
         code, _ = _CDTYPE[dtype]
         K = self.info["n_angles"]
         theta = self._dev(theta, torch.float64, "theta")
@@ -249,7 +252,8 @@ class ACGraph:
         cfg = L.SampleCfg(int(chains_per_param), int(samples_per_chain), int(burn_in), int(thin),
                           int(seed) & ((1 << 64) - 1), 0 if edges_t is None else int(edges_t.shape[0]), 0,
                           None if edges_t is None else edges_t.data_ptr(),
-                          None if init_t is None else init_t.data_ptr(), int(first_sweep), int(first_var))
+                          None if init_t is None else init_t.data_ptr(), int(first_sweep), int(first_var),
+                          int(chain_offset))
         ws = self.workspace(dtype, P * chains_per_param, L.AC_OP_SAMPLE, ws)
         L.check(L.lib().ac_sample(self._h, code, _ptr(theta), P, _ptr(noise), ctypes.byref(cfg),
                                   _ptr(samples), _ptr(states), _ptr(cost), _ptr(rounds), _ptr(ws),

@@ -76,3 +76,48 @@ def compile_blob(circ, **kw) -> bytes:
     compiling many circuits in worker processes)."""
     from .compiler import compile_circuit
     return to_blob(compile_circuit(circ, **kw))
+
+
+def _compiler_key() -> str:
+    """Hash of the compiler and blob writer sources (a cache entry is stale
+    once either changes)."""
+    import hashlib
+    import os
+    h = hashlib.sha256()
+    here = os.path.dirname(os.path.abspath(__file__))
+    for name in ("compiler.py", "blob.py"):
+        with open(os.path.join(here, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def compile_blob_cached(circ, cache_dir: str, **kw):
+    """compile_blob with an on-disk cache keyed by the circuit (ops, noise
+    strengths, size), the compile options and the compiler's source; returns
+    (blob, cache hit).  An empty cache_dir disables the cache."""
+    import hashlib
+    import os
+    import tempfile
+    if not cache_dir:
+        return compile_blob(circ, **kw), False
+    key = hashlib.sha256(repr((circ.n, [tuple(op) for op in circ.ops], circ.n_angles,
+                               [float(x) for x in circ.noise], sorted(kw.items()),
+                               _compiler_key())).encode()).hexdigest()[:32]
+    path = os.path.join(cache_dir, f"{key}.qkcac")
+    try:
+        with open(path, "rb") as f:
+            blob = f.read()
+        if blob[:8] == MAGIC:
+            return blob, True
+    except OSError:
+        pass
+    blob = compile_blob(circ, **kw)
+    try:
+        os.makedirs(cache_dir, exist_ok=True)
+        fd, tmp = tempfile.mkstemp(dir=cache_dir)
+        with os.fdopen(fd, "wb") as f:
+            f.write(blob)
+        os.replace(tmp, path)
+    except OSError:
+        pass
+    return blob, False

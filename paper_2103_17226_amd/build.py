@@ -25,14 +25,34 @@ FLAGS = [
 ]
 
 
+# the plain CPU evaluator (a host-only baseline library, no HIP)
+CPU_SOURCE = os.path.join(HERE, "cpu", "qkc_cpu.cpp")
+CPU_LIB = os.path.join(HERE, "libqkc_cpu.so")
+CXX = os.environ.get("CXX", "g++")
+CPU_FLAGS = ["-O3", "-std=c++17", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-Wall", "-I", INCLUDE]
+
+
+def build_cpu(verbose: bool = False) -> str:
+    """Compile the CPU evaluator into paper_2103_17226_amd/libqkc_cpu.so."""
+    tmp = CPU_LIB + ".tmp"
+    cmd = [CXX] + CPU_FLAGS + [CPU_SOURCE, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(tmp, CPU_LIB)
+    return CPU_LIB
+
+
 def build(verbose: bool = False) -> str:
-    """Compile every source into paper_2103_17226_amd/libqkc.so (always rebuilds)."""
+    """Compile every source into paper_2103_17226_amd/libqkc.so and the CPU
+    evaluator into libqkc_cpu.so (always rebuilds)."""
     tmp = LIB + ".tmp"
     cmd = [HIPCC] + FLAGS + ["-x", "hip"] + SOURCES + ["-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
+    build_cpu(verbose)
     return LIB
 
 

@@ -505,20 +505,39 @@ def _greedy_order(factors: List[Factor], dom: Dict[int, int], crit: str, rng) ->
     return order, cost
 
 
+# Larger circuits get more order trials: past ORDER_BIG summed clique size
+# (an AC of roughly that many nodes) the search goes on in rounds of `trials`
+# runs while a round still lowers the cost by ORDER_GAIN, up to ORDER_MAX_TRIALS
+# runs -- a trial costs milliseconds, a node of the AC tens of microseconds.
+ORDER_BIG = 2e5
+ORDER_GAIN = 0.02
+ORDER_MAX_TRIALS = 2048
+
+
 def _elimination_order(factors: List[Factor], dom: Dict[int, int], trials: int = 64,
                        seed: int = 0x5EED) -> List[int]:
     """Elimination order (Sec. 3.2.2): the cheapest of several greedy runs.
 
     The three deterministic heuristics run first, then randomised tie-breaks
     of each in turn; the order with the smallest summed clique size wins
-    (earliest on ties), so the result is reproducible."""
+    (earliest on ties).  The number of runs depends only on the costs found,
+    so the result is reproducible."""
     rng = random.Random(seed)
     crits = ("wf", "fw", "deg")
     best = None
-    for t in range(max(1, trials)):
-        order, cost = _greedy_order(factors, dom, crits[t % 3], rng if t >= 3 else None)
-        if best is None or cost < best[1]:
-            best = (order, cost)
+    t = 0
+    n = max(1, trials)
+    while True:
+        round_start = None if best is None else best[1]
+        for _ in range(n):
+            order, cost = _greedy_order(factors, dom, crits[t % 3], rng if t >= 3 else None)
+            if best is None or cost < best[1]:
+                best = (order, cost)
+            t += 1
+        if best[1] <= ORDER_BIG or t >= ORDER_MAX_TRIALS or trials <= 1:
+            break
+        if round_start is not None and best[1] > (1.0 - ORDER_GAIN) * round_start:
+            break
     return best[0]
 
 

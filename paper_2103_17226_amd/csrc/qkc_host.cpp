@@ -622,7 +622,8 @@ extern "C" ac_status ac_load(const void *blob, size_t nbytes, int device, ac_gra
     std::vector<uint32_t> ind_base(n_vars + 1, 0), var_field(n_vars);
     for (uint32_t v = 0; v < n_vars; ++v) {
         const uint32_t d = var_dom[v];
-        if (d < 2 || d > static_cast<uint32_t>(MAX_DOM)) return fail(AC_ERR_FORMAT, "ac_load: variable %u domain %u", v, d);
+        if (d < 2 || d > static_cast<uint32_t>(MAX_DOM) || (d & (d - 1)) != 0)
+            return fail(AC_ERR_FORMAT, "ac_load: variable %u domain %u (a power of two from 2 to %d)", v, d, MAX_DOM);
         if (var_kind[v] > 3) return fail(AC_ERR_FORMAT, "ac_load: variable %u kind %u", v, var_kind[v]);
         if ((v < n_qubits) != (var_kind[v] == 0)) return fail(AC_ERR_FORMAT, "ac_load: outputs must come first");
         uint32_t width = 0;
@@ -1410,6 +1411,8 @@ extern "C" ac_status ac_sample(const ac_graph *g, ac_dtype dtype, const double *
     if (static_cast<uint64_t>(cfg->first_sweep) + sweeps >= 0xFFFFFFFFull)
         return fail(AC_ERR_INVALID_ARG, "ac_sample: first_sweep + sweeps per chain must stay below 2^32 - 1");
     if (cfg->reserved != 0) return fail(AC_ERR_INVALID_ARG, "ac_sample: reserved field must be 0");
+    if (cfg->chain_offset > (1ull << 62))
+        return fail(AC_ERR_INVALID_ARG, "ac_sample: chain_offset above 2^62");
     if (cfg->first_var >= static_cast<uint32_t>(g->dev.n_vars))
         return fail(AC_ERR_INVALID_ARG, "ac_sample: first_var %u leaves no variable to sample", cfg->first_var);
     if (g->dev.n_qubits > 64) return fail(AC_ERR_UNSUPPORTED, "ac_sample: more than 64 output qubits");
@@ -1444,6 +1447,7 @@ extern "C" ac_status ac_sample(const ac_graph *g, ac_dtype dtype, const double *
     a.init_states = cfg->init_states;
     a.first_sweep = cfg->first_sweep;
     a.first_var = static_cast<int32_t>(cfg->first_var);
+    a.chain_offset = cfg->chain_offset;
     // QKC_SEQ_SCAN=1 decides every visit in the scan (comparisons, tests)
     const char *seq_env = std::getenv("QKC_SEQ_SCAN");
     a.seq_scan = seq_env && std::atoi(seq_env) == 1 ? 1 : 0;

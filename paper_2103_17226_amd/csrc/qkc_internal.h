@@ -187,6 +187,7 @@ struct SampleArgs {
     uint64_t first_sweep;          // RNG sweep number of this call's first sweep
     int32_t first_var;             // the scan visits variables first_var .. n_vars-1
     int32_t seq_scan;              // 1: every visit decided in the scan (no decision pass)
+    uint64_t chain_offset;         // RNG chain number of this call's chain 0
 };
 
 }  // namespace qkc

@@ -927,6 +927,22 @@ __device__ __forceinline__ double rng_uniform(uint64_t seed, uint64_t chain, uin
 
 constexpr uint64_t INIT_SWEEP = 0xFFFFFFFFull;
 
+// MaxCut cost of an output word over the caller's edge list: the number of
+// edges whose ends differ; NaN if an edge names a qubit outside [0, n).
+__device__ inline double maxcut_cost(const SampleArgs &a, uint64_t x, int n) {
+    int cst = 0;
+    bool bad = false;
+    for (int e = 0; e < a.n_cost_edges; ++e) {
+        const int i0 = a.cost_edges[2 * e], i1 = a.cost_edges[2 * e + 1];
+        if (i0 < 0 || i0 >= n || i1 < 0 || i1 >= n) {
+            bad = true;
+            continue;
+        }
+        cst += static_cast<int>(((x >> i0) ^ (x >> i1)) & 1ull);
+    }
+    return bad ? static_cast<double>(NAN) : static_cast<double>(cst);
+}
+
 
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_sample(DevGraph g, const double *theta, const Weight<T> *wfix,
@@ -964,7 +980,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(DevGraph g, const double *thet
         if (ch >= 0 && !a.init_states) {
             uint64_t x = 0;
             for (int q = 0; q < g.n_qubits; ++q) {
-                if (rng_uniform(a.seed, static_cast<uint64_t>(ch), INIT_SWEEP, static_cast<uint64_t>(q)) < 0.5)
+                if (rng_uniform(a.seed, a.chain_offset + static_cast<uint64_t>(ch), INIT_SWEEP, static_cast<uint64_t>(q)) < 0.5)
                     x |= (1ull << q);
             }
             ev_s[lane] = x;
@@ -1019,7 +1035,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(DevGraph g, const double *thet
                 }
                 uint32_t pick = cur;
                 if (total > 0.0) {
-                    const double r = rng_uniform(a.seed, static_cast<uint64_t>(ch), a.first_sweep + sweep, static_cast<uint64_t>(v));
+                    const double r = rng_uniform(a.seed, a.chain_offset + static_cast<uint64_t>(ch), a.first_sweep + sweep, static_cast<uint64_t>(v));
                     const double target = __dmul_rn(r, total);
                     double acc = 0.0;
                     int last_pos = -1;
@@ -1053,14 +1069,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(DevGraph g, const double *thet
                         if (a.states_out) {
                             for (int w2 = 0; w2 < g.W; ++w2) a.states_out[idx * g.W + w2] = ev_s[w2 * WAVE + lane];
                         }
-                        if (a.cost_out) {
-                            int c = 0;
-                            for (int e = 0; e < a.n_cost_edges; ++e) {
-                                const int i0 = a.cost_edges[2 * e], i1 = a.cost_edges[2 * e + 1];
-                                c += static_cast<int>(((x >> i0) ^ (x >> i1)) & 1ull);
-                            }
-                            a.cost_out[idx] = static_cast<double>(c);
-                        }
+                        if (a.cost_out) a.cost_out[idx] = maxcut_cost(a, x, g.n_qubits);
                         emitted += 1;
                     }
                     if (sweep >= total_sweeps) { done = true; break; }
@@ -1474,7 +1483,7 @@ __global__ __launch_bounds__(MAX_BLOCK) __attribute__((amdgpu_waves_per_eu(sizeo
         if (ch >= 0 && !a.init_states) {
             uint64_t x = 0;
             for (int q = 0; q < g.n_qubits; ++q)
-                if (rng_uniform(a.seed, static_cast<uint64_t>(ch), INIT_SWEEP, static_cast<uint64_t>(q)) < 0.5)
+                if (rng_uniform(a.seed, a.chain_offset + static_cast<uint64_t>(ch), INIT_SWEEP, static_cast<uint64_t>(q)) < 0.5)
                     x |= (1ull << q);
             ev_s[lane] = x;
         }
@@ -1519,7 +1528,7 @@ __global__ __launch_bounds__(MAX_BLOCK) __attribute__((amdgpu_waves_per_eu(sizeo
 #pragma unroll
             for (int u = 0; u < SEL_DOM; ++u) w[u] = u < dom ? gibbs_weight(d[u]) : 0.0;
             const uint32_t sw = sw0 + (v < pos0 ? 1u : 0u);
-            const double r = rng_uniform(a.seed, static_cast<uint64_t>(ch), a.first_sweep + sw, static_cast<uint64_t>(v));
+            const double r = rng_uniform(a.seed, a.chain_offset + static_cast<uint64_t>(ch), a.first_sweep + sw, static_cast<uint64_t>(v));
             if (gibbs_choice(w, dom, cur, r) != cur)
                 atomicOr(reinterpret_cast<unsigned long long *>(mask_s + (v >> 6) * WAVE + lane), 1ull << (v & 63));
         });
@@ -1546,12 +1555,7 @@ __global__ __launch_bounds__(MAX_BLOCK) __attribute__((amdgpu_waves_per_eu(sizeo
                     if (a.states_out)
                         for (int w2 = 0; w2 < g.W; ++w2) a.states_out[idx * g.W + w2] = ev_s[w2 * WAVE + lane];
                     if (a.cost_out) {
-                        int cst = 0;
-                        for (int e = 0; e < a.n_cost_edges; ++e) {
-                            const int i0 = a.cost_edges[2 * e], i1 = a.cost_edges[2 * e + 1];
-                            cst += static_cast<int>(((x >> i0) ^ (x >> i1)) & 1ull);
-                        }
-                        a.cost_out[idx] = static_cast<double>(cst);
+                        a.cost_out[idx] = maxcut_cost(a, x, g.n_qubits);
                     }
                     emitted += 1;
                 }
@@ -1584,7 +1588,7 @@ __global__ __launch_bounds__(MAX_BLOCK) __attribute__((amdgpu_waves_per_eu(sizeo
                     const uint64_t fmask = (1ull << width) - 1ull;
                     const uint64_t wv = ev_s[word * WAVE + lane];
                     const uint32_t cur = static_cast<uint32_t>((wv >> shift) & fmask);
-                    const double r = rng_uniform(a.seed, static_cast<uint64_t>(ch), a.first_sweep + sweep, static_cast<uint64_t>(v));
+                    const double r = rng_uniform(a.seed, a.chain_offset + static_cast<uint64_t>(ch), a.first_sweep + sweep, static_cast<uint64_t>(v));
                     const uint32_t pick = gibbs_choice(w, dom, cur, r);
                     ev_s[word * WAVE + lane] = (wv & ~(fmask << shift)) | (static_cast<uint64_t>(pick) << shift);
                 };
@@ -1662,7 +1666,7 @@ __global__ __launch_bounds__(MAX_BLOCK) __attribute__((amdgpu_waves_per_eu(sizeo
                 for (int u = 0; u < dom; ++u) total = __dadd_rn(total, weight(u));
                 uint32_t pick = cur;
                 if (total > 0.0) {
-                    const double r = rng_uniform(a.seed, static_cast<uint64_t>(ch), a.first_sweep + sweep, static_cast<uint64_t>(v));
+                    const double r = rng_uniform(a.seed, a.chain_offset + static_cast<uint64_t>(ch), a.first_sweep + sweep, static_cast<uint64_t>(v));
                     const double target = __dmul_rn(r, total);
                     double acc = 0.0;
                     int last_pos = -1, chosen = -1;
@@ -1774,12 +1778,7 @@ __device__ inline void emit_sample(const DevGraph &g, const SampleArgs &a, int64
     if (a.states_out)
         for (int w2 = 0; w2 < g.W; ++w2) a.states_out[idx * g.W + w2] = w2 == cw ? cval : ev[w2];
     if (a.cost_out) {
-        int cst = 0;
-        for (int e = 0; e < a.n_cost_edges; ++e) {
-            const int i0 = a.cost_edges[2 * e], i1 = a.cost_edges[2 * e + 1];
-            cst += static_cast<int>(((x >> i0) ^ (x >> i1)) & 1ull);
-        }
-        a.cost_out[idx] = static_cast<double>(cst);
+        a.cost_out[idx] = maxcut_cost(a, x, g.n_qubits);
     }
 }
 
@@ -1855,7 +1854,7 @@ __global__ __launch_bounds__(WAVE * WPC) void k_sample_lds(DevGraph g, LdsPlan l
         if (ch >= 0 && !a.init_states) {
             uint64_t x = 0;
             for (int q = 0; q < g.n_qubits; ++q)
-                if (rng_uniform(a.seed, static_cast<uint64_t>(ch), INIT_SWEEP, static_cast<uint64_t>(q)) < 0.5)
+                if (rng_uniform(a.seed, a.chain_offset + static_cast<uint64_t>(ch), INIT_SWEEP, static_cast<uint64_t>(q)) < 0.5)
                     x |= (1ull << q);
             c.ev[0] = x;
         }
@@ -2053,7 +2052,7 @@ __global__ __launch_bounds__(WAVE * WPC) void k_sample_lds(DevGraph g, LdsPlan l
                         total = __dadd_rn(total, __dadd_rn(__dmul_rn(re, re), __dmul_rn(im, im)));
                     }
                     if (total > 0.0) {
-                        const double r = rng_uniform(a.seed, static_cast<uint64_t>(ch), a.first_sweep + sw, static_cast<uint64_t>(v));
+                        const double r = rng_uniform(a.seed, a.chain_offset + static_cast<uint64_t>(ch), a.first_sweep + sw, static_cast<uint64_t>(v));
                         const double target = __dmul_rn(r, total);
                         double acc = 0.0;
                         int last_pos = -1, chosen = -1;

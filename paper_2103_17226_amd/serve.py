@@ -13,7 +13,9 @@ resident on the device and a scheduler thread that, on every tick,
   2. admits queued requests in arrival order while their device-memory
      footprint (inputs, outputs, workspace) fits the budget and a stream is
      free; the head of the queue is never overtaken, so a large request
-     cannot starve;
+     cannot starve (parts of a split request beyond ``part_streams`` on the
+     device at once, and requests of a busy session, keep their place while
+     later requests go ahead);
   3. merges an admitted amplitude request with later queued ones of the same
      graph, dtype and kind into one launch.  Parameter sets are stacked and
      every element keeps its own parameter row, so each request gets what it
@@ -29,9 +31,16 @@ resident on the device and a scheduler thread that, on every tick,
 
 Requests that arrive while others are on the device therefore start as soon
 as a stream and memory free up, and their kernels overlap on the device.
-Submissions beyond ``max_queue`` waiting requests, larger than the whole
-budget, or (with ``max_seconds``) estimated to occupy the device longer than
-that, are rejected at once.
+A request estimated (with ``max_seconds``) to occupy the device longer than
+that is split into parts that each fit the limit -- by parameter sets, or by
+chains (sampling) or evidence rows (amplitudes) of one parameter set -- which
+flow through the loop like other requests; its result is assembled when the
+last part completes and equals the unsplit request's (sampling parts number
+their chains from the request's chain offset, so they draw the same chains).
+Submissions beyond ``max_queue`` waiting requests, or larger than the whole
+budget, are rejected at once.  Resident session chains that leave no room
+for the request at the head of the queue, with nothing else on the device,
+are released oldest first; a request that cannot fit even then fails.
 
 The device work is done by an executor (``GraphExecutor`` for libqkc); the
 scheduler only sees its footprint / launch / done / results calls, so tests
@@ -75,6 +84,7 @@ class Request:
     seed: int = 1
     dtype: str = "c64"
     session: Optional[str] = None
+    chain_offset: int = 0                    # RNG number of the first chain (parts of a split request)
     # filled in by the server
     rid: int = -1
     t_arrive: float = 0.0
@@ -83,6 +93,8 @@ class Request:
     t_done: float = 0.0
     footprint: int = 0
     future: Future = field(default_factory=Future, repr=False)
+    parent: Any = field(default=None, repr=False)    # the split request this part belongs to
+    part: Any = field(default=None, repr=False)      # the executor's description of the part
 
     @property
     def kind(self) -> str:
@@ -116,7 +128,7 @@ class Server:
 
     def __init__(self, executor, mem_budget: int, clock: Callable[[], float] = time.perf_counter,
                  max_queue: int = 1 << 30, max_merge: int = 64, max_seconds: Optional[float] = None,
-                 request_timeout: Optional[float] = None, tick: float = 1e-4):
+                 request_timeout: Optional[float] = None, tick: float = 1e-4, part_streams: int = 2):
         if mem_budget <= 0:
             raise ValueError("mem_budget must be positive")
         self.ex = executor
@@ -127,6 +139,7 @@ class Server:
         self.max_seconds = max_seconds
         self.request_timeout = request_timeout
         self.tick = tick
+        self.part_streams = max(1, int(part_streams))   # parts of one split request on the device at once
         self.queue: collections.deque = collections.deque()
         self.inflight: List[tuple] = []            # (handle, [requests], stream, bytes)
         self.free_streams = list(range(executor.n_streams))
@@ -141,6 +154,10 @@ class Server:
         self.rejected_memory = 0
         self.rejected_queue = 0
         self.rejected_cost = 0
+        self.rejected_invalid = 0
+        self.split_requests = 0
+        self.split_parts = 0
+        self.evicted_sessions = 0
         self.timed_out = 0
         self.cancelled = 0
         self.launches = 0
@@ -155,38 +172,63 @@ class Server:
         for callers that replay a schedule of arrivals."""
         req.rid = next(self._ids)
         req.t_arrive = self.clock() if t_arrive is None else float(t_arrive)
-        req.footprint = int(self.ex.footprint(req))
-        if req.footprint > self.budget:
-            self.rejected_memory += 1
+        if req.kind == "sample" and req.grad and req.samples < 2:
+            self.rejected_invalid += 1
             req.future.set_exception(AdmissionError(
-                f"request needs {req.footprint} bytes of device memory, the budget is {self.budget}"))
+                "a sampled gradient needs at least 2 samples per parameter set (leave-one-out baseline)"))
             return req.future
-        if self.max_seconds is not None:
-            est = float(self.ex.cost(req))
-            if est > self.max_seconds:
-                self.rejected_cost += 1
+        parts = None
+        over_time = self.max_seconds is not None and float(self.ex.cost(req)) > self.max_seconds
+        over_memory = int(self.ex.footprint(req)) > self.budget
+        if (over_time or over_memory) and hasattr(self.ex, "split") and req.session is None:
+            limit = self.max_seconds if self.max_seconds is not None else float("inf")
+            parts = self.ex.split(req, limit, max_bytes=self.budget)
+        if over_time and not parts and not over_memory:
+            self.rejected_cost += 1
+            req.future.set_exception(AdmissionError(
+                f"request would hold the device ~{float(self.ex.cost(req)):.3g} s, the limit is "
+                f"{self.max_seconds:.3g} s, and it cannot be split"))
+            return req.future
+        units = parts if parts else [req]
+        for u in units:
+            u.footprint = int(self.ex.footprint(u))
+            if u.footprint > self.budget:
+                self.rejected_memory += 1
                 req.future.set_exception(AdmissionError(
-                    f"request would hold the device ~{est:.3g} s, the limit is {self.max_seconds:.3g} s"))
+                    f"request needs {u.footprint} bytes of device memory, the budget is {self.budget}"))
                 return req.future
         with self.lock:
             if len(self.queue) >= self.max_queue:
                 self.rejected_queue += 1
                 req.future.set_exception(AdmissionError(f"queue full ({self.max_queue} waiting)"))
                 return req.future
-            self.queue.append(req)
+            if parts:
+                req.part = {"n": len(parts), "done": 0, "outs": [None] * len(parts), "failed": False,
+                            "descs": [u.part for u in parts], "inflight": 0}
+                for k, u in enumerate(parts):
+                    u.rid = next(self._ids)
+                    u.t_arrive = req.t_arrive
+                    u.parent = req
+                    u.part = (k, u.part)
+                self.split_requests += 1
+                self.split_parts += len(parts)
+            self.queue.extend(units)
         return req.future
 
     def cancel(self, fut: Future) -> bool:
         """Cancel a request that is still waiting; one already on the device
         runs to completion (returns False)."""
         with self.lock:
-            for r in self.queue:
-                if r.future is fut:
-                    self.queue.remove(r)
-                    self.cancelled += 1
-                    fut.cancel()
-                    return True
-        return False
+            mine = [r for r in self.queue if r.future is fut or (r.parent is not None and r.parent.future is fut)]
+            if not mine:
+                return False
+            if any(r.parent is not None for r in mine) and len(mine) != mine[0].parent.part["n"]:
+                return False                       # some parts already ran
+            for r in mine:
+                self.queue.remove(r)
+            self.cancelled += 1
+            fut.cancel()
+            return True
 
     def start(self):
         if self.thread is not None:
@@ -218,16 +260,52 @@ class Server:
         with self.lock:
             while self.queue:
                 r = self.queue.popleft()
-                self.cancelled += 1
-                r.future.cancel()
+                f = r.parent.future if r.parent is not None else r.future
+                if not f.done():
+                    self.cancelled += 1
+                    f.cancel()
 
     # ------------------------------------------------------------ scheduler
     def _fail(self, reqs, exc):
         for r in reqs:
             r.t_done = self.clock()
+            if r.parent is not None:                 # a part: the split request fails once
+                r.future.set_exception(exc)
+                par = r.parent
+                if not par.part["failed"]:
+                    par.part["failed"] = True
+                    par.t_done = r.t_done
+                    self.failed += 1
+                    if not par.future.done():
+                        par.future.set_exception(exc)
+                continue
             self.failed += 1
             if not r.future.done():
                 r.future.set_exception(exc)
+
+    def _finish(self, r, out, now):
+        """A request or a part completed with the executor's output."""
+        r.t_done = now
+        if r.parent is None:
+            self.completed.append(r)
+            r.future.set_result(self.ex.finalize(r, out) if hasattr(self.ex, "finalize") else out)
+            return 1
+        r.future.set_result(out)
+        par, st = r.parent, r.parent.part
+        st["outs"][r.part[0]] = out
+        st["done"] += 1
+        if st["done"] < st["n"] or st["failed"] or par.future.done():
+            return 0
+        par.t_done = now
+        try:
+            res = self.ex.combine(par, st["outs"])
+        except Exception as exc:
+            self.failed += 1
+            par.future.set_exception(exc)
+            return 0
+        self.completed.append(par)
+        par.future.set_result(res)
+        return 1
 
     def _complete(self) -> int:
         finished = 0
@@ -262,10 +340,7 @@ class Server:
                 for r, o in zip(reqs, outs):
                     if r.future.done():            # timed out earlier
                         continue
-                    r.t_done = now
-                    self.completed.append(r)
-                    r.future.set_result(o)
-                    finished += 1
+                    finished += self._finish(r, o, now)
             with self.lock:
                 self.used -= nbytes
                 self.free_streams.append(stream)
@@ -277,8 +352,12 @@ class Server:
         for r in reqs:
             if r.session is not None:
                 self.busy_sessions.discard((r.graph, r.session))
+            if r.parent is not None:
+                r.parent.part["inflight"] -= 1
 
     def _session_busy(self, r: Request) -> bool:
+        if r.parent is not None and r.parent.part["inflight"] >= self.part_streams:
+            return True                            # its request already has its share of streams
         return r.session is not None and (r.graph, r.session) in self.busy_sessions
 
     def _take_batch(self):
@@ -293,7 +372,25 @@ class Server:
         head = self.queue[idx]
         resident = self.ex.resident_bytes() if hasattr(self.ex, "resident_bytes") else 0
         if self.used + resident + head.footprint > self.budget:
-            return None
+            if self.used or self.inflight or self.launching:
+                return None                        # room comes back as launches complete
+            # nothing else holds memory: only resident session chains can make
+            # room; release idle ones, least recently used first
+            if hasattr(self.ex, "evict_sessions"):
+                self.evicted_sessions += self.ex.evict_sessions(resident + head.footprint - self.budget,
+                                                                self.busy_sessions)
+                resident = self.ex.resident_bytes()
+            if resident + head.footprint > self.budget:
+                del self.queue[idx]
+                self.rejected_memory += 1
+                exc = AdmissionError(f"request needs {head.footprint} bytes next to {resident} bytes of resident "
+                                     f"session chains in use, the budget is {self.budget}")
+                for f in ([head.future] + ([head.parent.future] if head.parent is not None else [])):
+                    if not f.done():
+                        f.set_exception(exc)
+                if head.parent is not None:
+                    head.parent.part["failed"] = True
+                return self._take_batch()
         del self.queue[idx]
         batch, total = [head], head.footprint
         if head.kind == "eval" and self.max_merge > 1:
@@ -309,6 +406,8 @@ class Server:
             self.queue = keep
         if head.session is not None:
             self.busy_sessions.add((head.graph, head.session))
+        if head.parent is not None:
+            head.parent.part["inflight"] += 1
         self.launching += 1
         stream = self.free_streams.pop(0)
         self.used += total
@@ -332,6 +431,8 @@ class Server:
             now = self.clock()
             for r in batch:
                 r.t_start = now
+                if r.parent is not None and not r.parent.t_start:
+                    r.parent.t_start = now
             try:
                 handle = self.ex.launch(batch, stream)
             except Exception as exc:
@@ -345,6 +446,8 @@ class Server:
             now = self.clock()
             for r in batch:
                 r.t_launched = now
+                if r.parent is not None and not r.parent.t_launched:
+                    r.parent.t_launched = now
             self.launches += 1
             self.merged += len(batch) - 1
             with self.lock:
@@ -366,7 +469,10 @@ class Server:
         lat = np.array([r.t_done - r.t_arrive for r in done])
         out: Dict[str, Any] = {"completed": len(done), "failed": self.failed,
                                "rejected_memory": self.rejected_memory,
-                               "rejected_queue": self.rejected_queue, "rejected_cost": self.rejected_cost, "timed_out": self.timed_out,
+                               "rejected_queue": self.rejected_queue, "rejected_cost": self.rejected_cost,
+                               "rejected_invalid": self.rejected_invalid, "timed_out": self.timed_out,
+                               "split_requests": self.split_requests, "split_parts": self.split_parts,
+                               "evicted_sessions": self.evicted_sessions,
                                "cancelled": self.cancelled,
                                "launches": self.launches, "merged": self.merged,
                                "max_inflight": self.max_inflight, "peak_bytes": self.peak_used}
@@ -375,6 +481,20 @@ class Server:
                        p99_ms=float(np.percentile(lat, 99) * 1e3),
                        mean_ms=float(lat.mean() * 1e3))
         return out
+
+
+def loo_score_gradient(A, G, cost_sum, S: int):
+    """Score-function estimate of d<C>/dtheta per parameter set from S
+    samples s_i with the leave-one-out baseline,
+        (1/S) sum_i (C_i - (sum_j C_j - C_i)/(S - 1)) g_i
+      = (A - (sum_j C_j / S) G) / (S - 1),
+    with g_i = d log |f(s_i)|^2 / d theta, A = sum_i C_i g_i (rows [P, K]),
+    G = sum_i g_i and cost_sum = sum_i C_i [P].  Each sample's baseline is
+    independent of it, so the estimate is unbiased (S >= 2)."""
+    A = np.asarray(A, dtype=np.float64)
+    G = np.asarray(G, dtype=np.float64)
+    cbar = np.asarray(cost_sum, dtype=np.float64).reshape(-1, 1) / float(S)
+    return (A - cbar * G) / float(S - 1)
 
 
 def padded_rows(n_rows: int, grad: bool) -> int:
@@ -451,8 +571,9 @@ class GraphExecutor:
         self.n_streams = int(n_streams)
         self.device = torch.device("cuda", device)
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(self.n_streams)]
-        self.sessions = {}        # (graph, session) -> [states [P*S, W] int64 on device, next sweep, P, S]
+        self.sessions = {}        # (graph, session) -> [states [P*S, W] int64 on device, next sweep, P, S, last use]
         self._sess_lock = threading.Lock()
+        self._uses = itertools.count()
         self.edges = {}
         for name, e in (cost_edges or {}).items():
             self.edges[name] = torch.as_tensor(np.asarray(e, dtype=np.int32).reshape(-1, 2)).to(self.device)
@@ -523,6 +644,139 @@ class GraphExecutor:
         with self._sess_lock:
             self.sessions.pop((graph, session), None)
 
+    def evict_sessions(self, need: int, busy) -> int:
+        """Release idle sessions' chains, least recently used first, until
+        ``need`` bytes are free or none is left; returns how many."""
+        n = 0
+        with self._sess_lock:
+            idle = sorted((v[4], k) for k, v in self.sessions.items() if k not in busy)
+            for _, k in idle:
+                if need <= 0:
+                    break
+                need -= int(self.sessions.pop(k)[0].numel()) * 8
+                n += 1
+        return n
+
+    # ---------------------------------------------------------- splitting
+    @staticmethod
+    def _largest(fits, hi: int) -> int:
+        """Largest k in [1, hi] with fits(k) (fits is monotone), else 0."""
+        if hi < 1 or not fits(1):
+            return 0
+        lo = 1
+        while lo < hi:
+            mid = (lo + hi + 1) // 2
+            if fits(mid):
+                lo = mid
+            else:
+                hi = mid - 1
+        return lo
+
+    def split(self, req: Request, limit: float, max_bytes: Optional[int] = None):
+        """Parts of a request whose device time would exceed ``limit``: whole
+        parameter sets per part while they fit, else slices of one set's
+        chains (sampling) or evidence rows (amplitudes).  When one chain or
+        row alone is over the limit (a large circuit), the limit becomes that
+        one unit's time, so a part holds what the device runs in that time
+        anyway (a group of concurrent chains) rather than being refused.
+        With ``max_bytes`` a part's device footprint stays within it too.
+        None if no part fits."""
+        cap = float("inf") if max_bytes is None else max_bytes
+
+        def ok(u, lim):
+            return self.cost(u) <= lim and self.footprint(u) <= cap
+        P = req.n_params
+        th = np.asarray(req.theta, dtype=np.float64).reshape(P, -1)
+        parts = []
+        if req.kind == "sample":
+            S = int(req.samples)
+
+            def part(p0, p1, c0, c1):
+                return Request(graph=req.graph, theta=th[p0:p1], samples=c1 - c0, grad=req.grad,
+                               burn_in=req.burn_in, seed=req.seed, dtype=req.dtype,
+                               chain_offset=req.chain_offset + p0 * S + c0, part=("sample", p0, p1, c0, c1))
+            limit = max(limit, self.cost(part(0, 1, 0, 1)) * (1.0 + 1e-9))
+            pc = self._largest(lambda k: ok(part(0, k, 0, S), limit), P)
+            if pc:
+                return [part(p0, min(P, p0 + pc), 0, S) for p0 in range(0, P, pc)]
+            sc = self._largest(lambda k: ok(part(0, 1, 0, k), limit), S)
+            if not sc:
+                return None
+            return [part(p, p + 1, c0, min(S, c0 + sc)) for p in range(P) for c0 in range(0, S, sc)]
+        po = np.zeros(req.n_rows, dtype=np.int64) if req.param_of is None else np.asarray(req.param_of, np.int64)
+        ev = np.asarray(req.evidence, dtype=np.uint64)
+        wt = None if req.weight is None else np.asarray(req.weight, dtype=np.float64)
+        order = np.argsort(po, kind="stable")
+        starts = np.searchsorted(po[order], np.arange(P + 1))
+
+        def part(p0, p1, rows):
+            return Request(graph=req.graph, theta=th[p0:p1], evidence=ev[rows],
+                           param_of=(po[rows] - p0).astype(np.int32), weight=None if wt is None else wt[rows],
+                           grad=req.grad, dtype=req.dtype, part=("eval", p0, p1, rows))
+
+        def rows_of(p0, p1):
+            return np.sort(order[starts[p0]:starts[p1]])
+        if len(order):
+            one = int(order[0])
+            limit = max(limit, self.cost(part(int(po[one]), int(po[one]) + 1, np.array([one]))) * (1.0 + 1e-9))
+        p0 = 0
+        while p0 < P:
+            k = self._largest(lambda m: ok(part(p0, p0 + m, rows_of(p0, p0 + m)), limit), P - p0)
+            if k:
+                parts.append(part(p0, p0 + k, rows_of(p0, p0 + k)))
+                p0 += k
+                continue
+            rows = rows_of(p0, p0 + 1)              # one parameter set over the limit: slices of its rows
+            m = self._largest(lambda q: ok(part(p0, p0 + 1, rows[:q]), limit), len(rows))
+            if not m:
+                return None
+            parts += [part(p0, p0 + 1, rows[i:i + m]) for i in range(0, len(rows), m)]
+            p0 += 1
+        return parts
+
+    def finalize(self, req: Request, out):
+        """The request's result from one launch's output."""
+        if req.kind == "sample" and req.grad:
+            out = dict(out)
+            A, G = out.pop("A"), out.pop("G")
+            out["grad"] = loo_score_gradient(A, G, out["cost"].sum(axis=1), int(req.samples))
+        return out
+
+    def combine(self, req: Request, outs):
+        """The result of a split request from its parts' outputs, in part order."""
+        P, K = req.n_params, np.asarray(req.theta).reshape(req.n_params, -1).shape[1]
+        if req.kind == "sample":
+            S = int(req.samples)
+            first = outs[0]
+            samples = np.zeros((P, S) + first["samples"].shape[2:], dtype=first["samples"].dtype)
+            cost = np.zeros((P, S)) if "cost" in first else None
+            A = np.zeros((P, K)) if req.grad else None
+            G = np.zeros((P, K)) if req.grad else None
+            for u, o in zip(req.part["descs"], outs):
+                _, p0, p1, c0, c1 = u
+                samples[p0:p1, c0:c1] = o["samples"].reshape((p1 - p0, c1 - c0) + samples.shape[2:])
+                if cost is not None:
+                    cost[p0:p1, c0:c1] = o["cost"].reshape(p1 - p0, c1 - c0)
+                if req.grad:
+                    A[p0:p1] += o["A"]
+                    G[p0:p1] += o["G"]
+            res = {"samples": samples}
+            if cost is not None:
+                res["cost"] = cost
+            if req.grad:
+                res["grad"] = loo_score_gradient(A, G, cost.sum(axis=1), S)
+            return res
+        B = req.n_rows
+        res = {}
+        for u, o in zip(req.part["descs"], outs):
+            _, p0, p1, rows = u
+            for k, v in o.items():
+                if k == "grad":
+                    res.setdefault("grad", np.zeros((P, K)))[p0:p1] += v
+                else:
+                    res.setdefault(k, np.zeros(B, dtype=v.dtype))[rows] = v
+        return res
+
     # ---------------------------------------------------------- launch
     def _to_dev(self, a, dtype):
         t = self.torch.as_tensor(np.ascontiguousarray(a)).to(dtype).pin_memory()
@@ -563,34 +817,40 @@ class GraphExecutor:
                 prev = self.sessions.get(key)
             if prev is not None and prev[2] == P and prev[3] == S:
                 init, first = prev[0], prev[1]
+                prev[4] = next(self._uses)
         res = g.sample(theta, chains_per_param=S, samples_per_chain=1, burn_in=r.burn_in, thin=1,
                        seed=r.seed, cost_edges=edges, dtype=r.dtype, want_cost=edges is not None,
                        want_states=r.grad or r.session is not None, validate=False, ws=ws,
-                       init_states=init, first_sweep=first)
+                       init_states=init, first_sweep=first, chain_offset=r.chain_offset)
         keep += [theta, ws, res]
         if init is not None:
             keep.append(init)      # read on this stream: live until the launch completes
         if r.session is not None:
             # the chains' last states stay on the device for the next request
             with self._sess_lock:
-                self.sessions[key] = [res["states"].reshape(chains, -1), first + r.burn_in + 1, P, S]
+                self.sessions[key] = [res["states"].reshape(chains, -1), first + r.burn_in + 1, P, S,
+                                      next(self._uses)]
         out = {"samples": self._to_host(res["samples"])}
         if res["cost"] is not None:
             out["cost"] = self._to_host(res["cost"])
         if r.grad:
             if res["cost"] is None:
                 raise ValueError(f"graph {r.graph!r} has no cost edges for a sampled gradient")
-            # score-function estimate: d<C>/dtheta = E[(C - mean C) d log P / dtheta]
-            cost = res["cost"]
-            wgt = ((cost - cost.mean(dim=1, keepdim=True)) / S).reshape(-1).contiguous()
+            # the sums the score-function estimate needs per parameter set:
+            # A = sum_i C_i g_i and G = sum_i g_i with g_i = d log|f(s_i)|^2 / d theta
+            # (combined with the leave-one-out baseline once all of a set's samples are in)
             states = res["states"].reshape(chains, -1)
             param_of = torch.arange(P, dtype=torch.int32, device=self.device).repeat_interleave(S)
             gws = torch.empty(max(g.workspace_size(r.dtype, chains, L.AC_OP_GRAD), 256), dtype=torch.uint8,
                               device=self.device)
-            gr = g.grad(theta, states, param_of, mode="logprob", weight=wgt, dtype=r.dtype, validate=False,
+            ones = torch.ones(chains, dtype=torch.float64, device=self.device)
+            ga = g.grad(theta, states, param_of, mode="logprob", weight=res["cost"].reshape(-1), dtype=r.dtype,
+                        validate=False, ws=gws)
+            gg = g.grad(theta, states, param_of, mode="logprob", weight=ones, dtype=r.dtype, validate=False,
                         ws=gws)
-            keep += [wgt, states, param_of, gws, gr]
-            out["grad"] = self._to_host(gr["grad"])
+            keep += [states, param_of, gws, ones, ga, gg]
+            out["A"] = self._to_host(ga["grad"])
+            out["G"] = self._to_host(gg["grad"])
         return ("sample", out)
 
     def _launch_eval(self, g, batch: List[Request], keep):

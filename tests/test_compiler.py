@@ -250,3 +250,15 @@ def test_random_circuits_match_oracle(seed):
     for i in rng.choice(len(states), size=min(120, len(states)), replace=False):
         vals = list(states[i])
         assert abs(H.evaluate_assignment(ac, theta, vals) - oracle_amp(circ, theta, vals)) < 1e-13, vals
+
+
+def test_blob_cache_returns_the_same_blob(tmp_path):
+    from paper_2103_17226_amd.blob import compile_blob, compile_blob_cached
+    circ = W.config(2, small=True)["circuit"]
+    b1, hit1 = compile_blob_cached(circ, str(tmp_path))
+    b2, hit2 = compile_blob_cached(circ, str(tmp_path))
+    assert (hit1, hit2) == (False, True) and b1 == b2 == compile_blob(circ)
+    other = W.qaoa_maxcut(8, W.random_regular_graph(8, 3, 5), 1, dep=0.02)
+    b3, hit3 = compile_blob_cached(other, str(tmp_path))
+    assert not hit3 and b3 != b1
+    assert compile_blob_cached(circ, "")[1] is False

@@ -293,3 +293,48 @@ def test_decision_pass_matches_the_sequential_scan(case, dtype, monkeypatch):
     b = g.sample(theta, **args, **kw)
     for key in ("samples", "states", "rounds") + (("cost",) if "cost_edges" in kw else ()):
         assert torch.equal(a[key], b[key]), key
+
+
+@pytest.mark.parametrize("variant", ["stream", "lds", "global"])
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_chain_offset_splits_a_request_exactly(variant, dtype, monkeypatch):
+    # A request split by parameter sets (theta rows p0.., chain_offset =
+    # p0 * chains_per_param) or by chains of one set (P = 1, chain_offset =
+    # p * chains_per_param + c0) draws exactly the whole request's chains.
+    note(f"chain offset ({variant}, {dtype})")
+    monkeypatch.setenv("QKC_SAMPLE_KERNEL", variant)
+    cfg = W.config(2, small=True)
+    circ = cfg["circuit"]
+    g = graph(circ)
+    theta = cfg["theta"][:6]
+    P, C = theta.shape[0], 50
+    kw = dict(samples_per_chain=2, burn_in=3, thin=2, seed=31, dtype=dtype, cost_edges=circ.edges,
+              want_states=True, want_cost=True, want_rounds=True)
+    whole = g.sample(theta, C, **kw)
+    Wn, S = g.info["n_words"], C * 2
+
+    def part(p0, p1):
+        return {k: whole[k].reshape(P, -1)[p0:p1] for k in ("samples", "states", "cost", "rounds")}
+    for p0, p1 in ((0, 2), (2, 6)):
+        got = g.sample(theta[p0:p1], C, chain_offset=p0 * C, **kw)
+        want = part(p0, p1)
+        for k in want:
+            assert torch.equal(got[k].reshape(p1 - p0, -1), want[k]), (p0, k)
+    p = 3
+    for c0, c1 in ((0, 20), (20, 50)):
+        got = g.sample(theta[p:p + 1], c1 - c0, chain_offset=p * C + c0, **kw)
+        for k, per in (("samples", 2), ("states", 2 * Wn), ("cost", 2), ("rounds", 1)):
+            flat = whole[k].reshape(P, C * per)[p]
+            assert torch.equal(got[k].reshape(-1), flat[c0 * per:c1 * per]), (c0, k)
+
+
+def test_cost_edges_outside_the_register_give_nan():
+    note("cost edge outside the register")
+    cfg = W.config(2, small=True)
+    g = graph(cfg["circuit"])
+    theta = cfg["theta"][:2]
+    good = g.sample(theta, 64, seed=4, cost_edges=cfg["circuit"].edges, want_cost=True)
+    bad = g.sample(theta, 64, seed=4, cost_edges=list(cfg["circuit"].edges) + [(0, 99)], want_cost=True,
+                   validate=False)
+    assert torch.equal(good["samples"], bad["samples"])
+    assert torch.isnan(bad["cost"]).all()

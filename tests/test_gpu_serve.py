@@ -54,11 +54,13 @@ def _plain(g, circ, r, dtype="c64"):
                    cost_edges=circ.edges, dtype=dtype, want_cost=True, want_states=r["grad"])
     out = {"samples": res["samples"].cpu().numpy(), "cost": res["cost"].cpu().numpy()}
     if r["grad"]:
+        from paper_2103_17226_amd.serve import loo_score_gradient
         cost = res["cost"]
-        wgt = ((cost - cost.mean(dim=1, keepdim=True)) / S).reshape(-1).contiguous()
         po = torch.arange(P, dtype=torch.int32, device=cost.device).repeat_interleave(S)
-        gr = g.grad(theta, res["states"].reshape(P * S, -1), po, mode="logprob", weight=wgt, dtype=dtype)
-        out["grad"] = gr["grad"].cpu().numpy()
+        st = res["states"].reshape(P * S, -1)
+        A = g.grad(theta, st, po, mode="logprob", weight=cost.reshape(-1), dtype=dtype)["grad"].cpu().numpy()
+        G = g.grad(theta, st, po, mode="logprob", weight=np.ones(P * S), dtype=dtype)["grad"].cpu().numpy()
+        out["grad"] = loo_score_gradient(A, G, out["cost"].sum(axis=1), S)
     return out
 
 
@@ -80,12 +82,57 @@ def _same(served, plain, what):
             assert np.array_equal(a.view(np.uint8), b.view(np.uint8)), (what, k)
 
 
+def test_split_requests_equal_the_whole_request():
+    # With a small device-time limit, large requests are split into parts
+    # (parameter sets, or chains / rows of one set) that flow through the
+    # loop; each reassembled result equals the whole request through the
+    # plain binding calls: samples and costs bit for bit (the parts' chain
+    # offsets draw the same chains), amplitudes bit for bit, gradients to
+    # 1e-12 of their largest entry.
+    from paper_2103_17226_amd.serve import GraphExecutor, Server
+    circs = _pool()
+    graphs = {k: graph(c) for k, c in circs.items()}
+    names = sorted(circs)
+    raw = W.serving_requests([circs[k] for k in names], rate=200.0, duration=1.0, seed=91, max_params=48,
+                             max_samples=1500, p_eval=0.25)[:24]
+    reqs = [(names[r["circuit"]], r) for r in raw if not (r["samples"] == 1 and r["grad"])]
+    plain = [_plain(graphs[k], circs[k], r) for k, r in reqs]
+    torch.cuda.synchronize()
+    ex = GraphExecutor(graphs, {k: c.edges for k, c in circs.items()}, n_streams=4)
+
+    def smallest_part(k, r):            # one chain, or one evidence row, of one parameter set
+        q = _request(k, r)
+        q.theta = np.asarray(q.theta)[:1]
+        if q.kind == "sample":
+            q.samples = 1
+        else:
+            q.evidence, q.param_of = q.evidence[:1], np.zeros(1, np.int32)
+            q.weight = None if q.weight is None else q.weight[:1]
+        return ex.cost(q)
+    limit = 1.05 * max(smallest_part(k, r) for k, r in reqs)     # every request can be split to fit
+    n_over = sum(ex.cost(_request(k, r)) > limit for k, r in reqs)
+    note(f"serve split: limit {limit:.3g} s, {n_over} of {len(reqs)} requests over it")
+    assert n_over >= 1
+    srv = Server(ex, mem_budget=8 << 30, max_merge=16, max_seconds=limit)
+    futs = [srv.submit(_request(k, r)) for k, r in reqs]
+    srv.start()
+    try:
+        results = [f.result(timeout=300) for f in futs]
+    finally:
+        srv.stop()
+    st = srv.latency_stats()
+    note(f"serve split: {st}")
+    assert st["completed"] == len(reqs) and st["rejected_cost"] == 0 and st["split_requests"] == n_over
+    for i, ((k, r), got, want) in enumerate(zip(reqs, results, plain)):
+        _same(got, want, f"request {i} on {k} (samples={r['samples']}, grad={r['grad']})")
+
+
 def test_served_equals_alone_in_a_mixed_stream():
     from paper_2103_17226_amd.serve import GraphExecutor, Server
     circs = _pool()
     note("serve: compile and load 3 graphs")
     graphs = {k: graph(c) for k, c in circs.items()}
-    reqs = _requests(circs, 60, seed=77)
+    reqs = [(k, r) for k, r in _requests(circs, 64, seed=77) if not (r["samples"] == 1 and r["grad"])][:60]
     kinds = {(r["samples"] > 0, r["grad"]) for _, r in reqs}
     assert len(kinds) == 4, kinds
     note(f"serve: plain calls for {len(reqs)} requests")
@@ -96,8 +143,10 @@ def test_served_equals_alone_in_a_mixed_stream():
     srv = Server(ex, mem_budget=8 << 30, max_merge=16)
     futs = [srv.submit(_request(k, r)) for k, r in reqs]      # queued before the loop starts: merges
     srv.start()
-    results = [f.result(timeout=120) for f in futs]
-    srv.stop()
+    try:
+        results = [f.result(timeout=120) for f in futs]
+    finally:
+        srv.stop()
     st = srv.latency_stats()
     note(f"serve: {st}")
     assert st["completed"] == len(reqs) and st["failed"] == 0
@@ -117,7 +166,19 @@ def test_served_amplitudes_match_the_oracle():
     ex = GraphExecutor({name: g}, n_streams=2)
     srv = Server(ex, mem_budget=1 << 30)
     srv.start()
-    futs, inputs = [], []
+    try:
+        out = _submit_oracle_batch(srv, name, circ, rng, inputs := [])
+    finally:
+        srv.stop()
+    for (theta, vals, po), res in zip(inputs, out):
+        ref = np.array([oracle_amplitudes(circ, theta[po[b]], vals[b:b + 1])[0] for b in range(len(po))])
+        assert np.max(np.abs(res["amp"] - ref)) <= 1e-12
+        np.testing.assert_allclose(res["prob"], np.abs(ref) ** 2, rtol=1e-10, atol=1e-15)
+
+
+def _submit_oracle_batch(srv, name, circ, rng, inputs):
+    from paper_2103_17226_amd.serve import Request
+    futs = []
     for i in range(6):
         P, B = 1 + i, 10 + 7 * i
         theta = rng.uniform(0, 2 * np.pi, size=(P, circ.n_angles))
@@ -130,33 +191,30 @@ def test_served_amplitudes_match_the_oracle():
         inputs.append((theta, vals, po))
         futs.append(srv.submit(Request(graph=name, theta=theta, evidence=W.pack_evidence(circ, vals),
                                        param_of=po, dtype="c128")))
-    out = [f.result(timeout=60) for f in futs]
-    srv.stop()
-    for (theta, vals, po), res in zip(inputs, out):
-        ref = np.array([oracle_amplitudes(circ, theta[po[b]], vals[b:b + 1])[0] for b in range(len(po))])
-        assert np.max(np.abs(res["amp"] - ref)) <= 1e-12
-        np.testing.assert_allclose(res["prob"], np.abs(ref) ** 2, rtol=1e-10, atol=1e-15)
+    return [f.result(timeout=60) for f in futs]
 
 
 def test_loop_admits_while_others_run_and_reports_latency():
     from paper_2103_17226_amd.serve import GraphExecutor, Server
     circs = _pool()
     graphs = {k: graph(c) for k, c in circs.items()}
-    reqs = _requests(circs, 40, seed=91)
+    reqs = [(k, r) for k, r in _requests(circs, 44, seed=91) if not (r["samples"] == 1 and r["grad"])][:40]
     note("serve: timed arrivals")
     ex = GraphExecutor(graphs, {k: c.edges for k, c in circs.items()}, n_streams=4)
     srv = Server(ex, mem_budget=8 << 30)
     srv.start()
-    t0 = time.perf_counter()
-    futs = []
-    for k, r in reqs:
-        delay = t0 + r["t"] - time.perf_counter()
-        if delay > 0:
-            time.sleep(delay)
-        futs.append(srv.submit(_request(k, r)))
-    for f in futs:
-        f.result(timeout=120)
-    srv.stop()
+    try:
+        t0 = time.perf_counter()
+        futs = []
+        for k, r in reqs:
+            delay = t0 + r["t"] - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            futs.append(srv.submit(_request(k, r)))
+        for f in futs:
+            f.result(timeout=120)
+    finally:
+        srv.stop()
     st = srv.latency_stats()
     note(f"serve: {st}")
     assert st["completed"] == len(reqs)
@@ -179,12 +237,14 @@ def test_session_resumes_its_resident_chains():
     ex = GraphExecutor({name: g}, {name: circ.edges}, n_streams=2)
     srv = Server(ex, mem_budget=1 << 30)
     srv.start()
-    f1 = srv.submit(Request(graph=name, theta=th1, samples=50, burn_in=5, seed=9, session="opt"))
-    f2 = srv.submit(Request(graph=name, theta=th2, samples=50, burn_in=0, seed=9, session="opt"))
-    r1, r2 = f1.result(timeout=60), f2.result(timeout=60)
-    assert ex.resident_bytes() == 2 * 50 * g.info["n_words"] * 8
-    srv.close_session(name, "opt")
-    srv.stop()
+    try:
+        f1 = srv.submit(Request(graph=name, theta=th1, samples=50, burn_in=5, seed=9, session="opt"))
+        f2 = srv.submit(Request(graph=name, theta=th2, samples=50, burn_in=0, seed=9, session="opt"))
+        r1, r2 = f1.result(timeout=60), f2.result(timeout=60)
+        assert ex.resident_bytes() == 2 * 50 * g.info["n_words"] * 8
+        srv.close_session(name, "opt")
+    finally:
+        srv.stop()
     assert ex.resident_bytes() == 0
     p1 = g.sample(th1, 50, 1, 5, 1, 9, cost_edges=circ.edges, want_cost=True, want_states=True)
     p2 = g.sample(th2, 50, 1, 0, 1, 9, cost_edges=circ.edges, want_cost=True,

@@ -376,3 +376,226 @@ def test_stacking_rejects_bad_param_rows():
     r.param_of = np.array([0, 1, 2, 0], np.int32)
     with pytest.raises(ValueError):
         stack_eval_batch([r], 2, 3, True)
+
+
+# ---------------------------------------------------------------------------
+# split requests, resident sessions, the sampled-gradient estimator
+# ---------------------------------------------------------------------------
+
+class SplitExecutor(FakeExecutor):
+    """FakeExecutor whose requests carry k units of work in ``samples``
+    (cost = 1 s per unit): split() cuts them into parts of at most
+    floor(limit) units; a part's result is the list of its units' values."""
+
+    def cost(self, req):
+        return float(req.samples)
+
+    def split(self, req, limit, max_bytes=None):
+        k = int(limit)
+        if k < 1:
+            return None
+        out = []
+        for u0 in range(0, req.samples, k):
+            u1 = min(req.samples, u0 + k)
+            out.append(Request(graph=req.graph, theta=req.theta, samples=u1 - u0, part=(u0, u1)))
+        return out
+
+    def launch(self, batch, stream):
+        h = super().launch(batch, stream)
+        h["end"] = self.clock() + max(float(r.samples) for r in batch)
+        return h
+
+    def results(self, h):
+        super().results(h)                       # the failures FakeExecutor injects
+        out = []
+        for r in h["batch"]:
+            u0, u1 = r.part[1] if r.parent is not None else (0, r.samples)
+            out.append([float(r.theta[0, 2]) + u for u in range(u0, u1)])
+        return out
+
+    def combine(self, req, outs):
+        return sum(outs, [])
+
+
+def test_requests_over_the_time_limit_are_split_and_reassembled():
+    clock = Clock()
+    ex = SplitExecutor(clock, n_streams=2)
+    srv = Server(ex, mem_budget=1000, clock=clock, max_seconds=3.0)
+    big = srv.submit(req(10, 0.0, val=100, samples=8))        # 8 units -> parts of 3, 3, 2
+    small = srv.submit(req(10, 0.0, val=7, samples=2))
+    run_until_idle(srv, clock)
+    assert big.result() == [100.0 + u for u in range(8)]
+    assert small.result() == [7.0, 8.0]
+    st = srv.latency_stats()
+    assert st["rejected_cost"] == 0 and st["split_requests"] == 1 and st["split_parts"] == 3
+    assert st["completed"] == 2                                 # parts are not requests of their own
+    done = {r.rid: r for r in srv.completed}
+    assert all(r.t_done >= r.t_arrive for r in done.values())
+
+
+def test_a_split_request_fails_once_when_a_part_fails():
+    clock = Clock()
+    ex = SplitExecutor(clock, n_streams=4, fail_results={5.0})
+    srv = Server(ex, mem_budget=1000, clock=clock, max_seconds=2.0)
+    bad = srv.submit(req(10, 0.0, val=5.0, samples=5))
+    ok = srv.submit(req(10, 0.0, val=1.0, samples=1))
+    run_until_idle(srv, clock)
+    with pytest.raises(RuntimeError):
+        bad.result(timeout=0)
+    assert ok.result() == [1.0] and srv.failed == 1
+
+
+def test_idle_sessions_are_released_when_they_block_the_queue():
+    # resident session bytes never shrink on their own: with nothing in
+    # flight the head of the queue releases idle sessions, least recently
+    # used first, and a request that cannot fit even then fails instead of
+    # blocking every request behind it
+    clock = Clock()
+    ex = FakeExecutor(clock, n_streams=4)
+    ex.sess = {("g", "old"): (30, 0), ("g", "new"): (30, 1), ("g", "busy"): (30, 2)}
+    ex.resident_bytes = lambda: sum(b for b, _ in ex.sess.values())
+
+    def evict(need, busy):
+        n = 0
+        for k, _ in sorted(ex.sess.items(), key=lambda kv: kv[1][1]):
+            if need <= 0:
+                break
+            if k in busy:
+                continue
+            need -= ex.sess.pop(k)[0]
+            n += 1
+        return n
+    ex.evict_sessions = evict
+    srv = Server(ex, mem_budget=100, clock=clock)
+    srv.busy_sessions.add(("g", "busy"))
+    f1 = srv.submit(req(35, 1.0, val=1))          # needs one session released: the oldest
+    f2 = srv.submit(req(80, 1.0, val=2))          # cannot fit next to the busy session: fails
+    f3 = srv.submit(req(10, 1.0, val=3))
+    run_until_idle(srv, clock)
+    assert f1.result() == 2.0 and f3.result() == 6.0
+    with pytest.raises(AdmissionError, match="resident"):
+        f2.result(timeout=0)
+    assert ("g", "old") not in ex.sess and ("g", "busy") in ex.sess
+    assert srv.evicted_sessions >= 1 and srv.rejected_memory == 1
+
+
+def test_sampled_gradient_needs_two_samples():
+    clock = Clock()
+    srv = Server(FakeExecutor(clock), mem_budget=100, clock=clock)
+    f = srv.submit(req(10, 1.0, samples=1, grad=True))
+    with pytest.raises(AdmissionError, match="at least 2"):
+        f.result(timeout=0)
+    assert srv.rejected_invalid == 1
+
+
+@pytest.mark.parametrize("S", [2, 3])
+def test_leave_one_out_score_gradient_is_unbiased(S):
+    # The estimator's mean over every ordered S-tuple of draws from a small
+    # discrete law p(x) with scores g(x) = d log p / d theta (so E[g] = 0)
+    # equals the exact gradient sum_x p(x) C(x) g(x); the mean-over-all-S
+    # baseline misses it by the factor (1 - 1/S).
+    import itertools as it
+
+    from paper_2103_17226_amd.serve import loo_score_gradient
+    rng = np.random.default_rng(S)
+    n, K = 4, 2
+    th = rng.normal(size=(n, K))
+    a = rng.normal(size=K)
+    logits = th @ a
+    p = np.exp(logits) / np.exp(logits).sum()
+    g = th - p @ th                               # d log p(x) / d a for p = softmax(th a)
+    C = rng.uniform(0, 5, size=n)
+    exact = (p * C) @ g
+    mean = np.zeros(K)
+    biased = np.zeros(K)
+    for tup in it.product(range(n), repeat=S):
+        w = np.prod(p[list(tup)])
+        A = sum(C[x] * g[x] for x in tup)
+        G = sum(g[x] for x in tup)
+        mean += w * loo_score_gradient(A[None], G[None], np.array([C[list(tup)].sum()]), S)[0]
+        cb = C[list(tup)].mean()
+        biased += w * sum((C[x] - cb) * g[x] for x in tup) / S
+    assert np.allclose(mean, exact, atol=1e-12)
+    assert np.allclose(biased, (1 - 1 / S) * exact, atol=1e-12)
+
+
+def _fake_graph_executor():
+    from paper_2103_17226_amd.serve import GraphExecutor
+
+    class G:
+        info = {"n_internal": 10000, "n_qubits": 8, "n_angles": 2, "n_words": 3}
+
+        def sample_shape(self, dtype, chains):
+            return "stream", min(chains, 4096)
+
+        def workspace_size(self, dtype, batch, op):
+            return 1024 * batch
+    from paper_2103_17226_amd import _lib
+    ex = object.__new__(GraphExecutor)
+    ex.graphs = {"g": G()}
+    ex.L = _lib
+    return ex
+
+
+def test_graph_executor_splits_cover_the_request_exactly():
+    ex = _fake_graph_executor()
+    limit = 0.5
+    for P, S, by_chains in ((64, 4000, False), (2, 40000, True)):
+        r = Request(graph="g", theta=np.arange(P * 2, dtype=float).reshape(P, 2), samples=S, grad=True,
+                    chain_offset=11)
+        assert ex.cost(r) > limit
+        parts = ex.split(r, limit)
+        assert parts and all(ex.cost(u) <= limit for u in parts)
+        assert any(u.part[4] - u.part[3] < S for u in parts) == by_chains
+        covered = np.zeros((P, S), dtype=int)
+        for u in parts:
+            _, p0, p1, c0, c1 = u.part
+            covered[p0:p1, c0:c1] += 1
+            assert u.chain_offset == 11 + p0 * S + c0 and u.samples == c1 - c0
+            assert np.array_equal(u.theta, r.theta[p0:p1])
+        assert (covered == 1).all()
+    # a memory cap: parts small enough for it
+    big = Request(graph="g", theta=np.zeros((3, 2)), samples=9000, grad=False)
+    parts = ex.split(big, float("inf"), max_bytes=2 * ex.footprint(Request(graph="g", theta=np.zeros((1, 2)),
+                                                                               samples=1000)))
+    assert parts and all(ex.footprint(u) <= 2 * ex.footprint(Request(graph="g", theta=np.zeros((1, 2)),
+                                                                         samples=1000)) for u in parts)
+    assert sum(u.samples * (u.part[2] - u.part[1]) for u in parts) == 27000
+    # a limit below one chain's time: parts of one group of concurrent chains, none refused
+    big = Request(graph="g", theta=np.zeros((3, 2)), samples=9000, grad=False)
+    one = Request(graph="g", theta=np.zeros((1, 2)), samples=1)
+    parts = ex.split(big, ex.cost(one) / 10)
+    assert parts and all(u.samples <= 4096 for u in parts) and sum(u.samples for u in parts) == 27000
+    assert all(ex.cost(u) <= ex.cost(one) * (1 + 1e-6) for u in parts)
+    # amplitudes: rows of each parameter set go to the parts that hold it
+    # (whole sets while they fit, else slices of one set's rows)
+    B = 40000
+    for P in (7, 1):
+        po = np.random.default_rng(P).integers(0, P, size=B).astype(np.int32)
+        e = Request(graph="g", theta=np.arange(P * 2, dtype=float).reshape(P, 2),
+                    evidence=np.arange(B * 3, dtype=np.uint64).reshape(B, 3), param_of=po,
+                    weight=np.arange(B, dtype=float), grad=True)
+        assert ex.cost(e) > 0.004
+        parts = ex.split(e, 0.004)
+        assert len(parts) > 1 and all(ex.cost(u) <= 0.004 for u in parts)
+        seen = np.zeros(B, dtype=int)
+        for u in parts:
+            _, p0, p1, rows = u.part
+            seen[rows] += 1
+            assert np.array_equal(u.param_of + p0, po[rows]) and np.array_equal(u.weight, e.weight[rows])
+            assert np.array_equal(u.evidence, e.evidence[rows])
+        assert (seen == 1).all()
+
+
+def test_parts_of_a_split_request_leave_streams_for_others():
+    clock = Clock()
+    ex = SplitExecutor(clock, n_streams=4)
+    srv = Server(ex, mem_budget=1000, clock=clock, max_seconds=1.0, part_streams=2)
+    big = srv.submit(req(10, 0.0, val=0, samples=6))          # six one-unit parts
+    small = srv.submit(req(10, 0.0, val=50, samples=1))
+    srv.step()
+    first = [x[0] for x in ex.launched]
+    assert first == [[1], [2], [7]]              # two parts (rids 1, 2), then the small request (rid 7)
+    assert [r for r in srv.queue if r.parent is None] == []
+    run_until_idle(srv, clock)
+    assert big.result() == [float(u) for u in range(6)] and small.result() == [50.0]
