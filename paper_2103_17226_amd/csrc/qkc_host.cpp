@@ -676,10 +676,12 @@ extern "C" ac_status ac_load(const void *blob, size_t nbytes, int device, ac_gra
     // ---- DAG
     if (row_ptr[0] != 0 || row_ptr[N] != E) return fail(AC_ERR_FORMAT, "ac_load: row_ptr ends");
     if (level_ptr[0] != 0 || level_ptr[L] != N) return fail(AC_ERR_FORMAT, "ac_load: level_ptr ends");
+    for (uint32_t l = 0; l < L; ++l)                   // whole table first: strictly increasing up to N
+        if (level_ptr[l + 1] <= level_ptr[l] || level_ptr[l + 1] > N)
+            return fail(AC_ERR_FORMAT, "ac_load: empty or out-of-range level %u", l);
     std::vector<uint32_t> level(N);
     uint32_t max_width = 0;
     for (uint32_t l = 0; l < L; ++l) {
-        if (level_ptr[l + 1] <= level_ptr[l]) return fail(AC_ERR_FORMAT, "ac_load: empty level %u", l);
         max_width = std::max(max_width, level_ptr[l + 1] - level_ptr[l]);
         for (uint32_t i = level_ptr[l]; i < level_ptr[l + 1]; ++i) level[i] = l;
     }
