@@ -82,6 +82,9 @@ def parse():
     ap.add_argument("--dtype", default="c64")
     ap.add_argument("--order-trials", type=int, default=64,
                     help="greedy elimination-order runs the compiler picks from")
+    ap.add_argument("--compiler", choices=["ve", "dpll"], default="ve",
+                    help="AC compiler of the sampling and gradient workloads: variable elimination "
+                         "or the search-based (decision-DNNF) compiler")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-eval", action="store_true")
@@ -264,6 +267,15 @@ def plan_byte_model(info, cs: int):
     return up, down, leaf
 
 
+def compile_ac(circ, method: str, order_trials: int = 64):
+    """The AC of a workload circuit from the chosen compiler."""
+    if method == "dpll":
+        from paper_2103_17226_amd.dnnf import compile_circuit_dpll
+        return compile_circuit_dpll(circ)
+    from paper_2103_17226_amd.compiler import compile_circuit
+    return compile_circuit(circ, order_trials=order_trials)
+
+
 def eval_leg(args, circ_cfg):
     """Amplitudes and gradients over the batch of the 16-qubit p=2 workload:
     4096 parameter sets x 64 seeded (x, k) with k from the channel priors."""
@@ -272,9 +284,8 @@ def eval_leg(args, circ_cfg):
 
     from paper_2103_17226_amd import _lib
     from paper_2103_17226_amd.api import ACGraph
-    from paper_2103_17226_amd.compiler import compile_circuit
     t0 = time.perf_counter()
-    comp = compile_circuit(circ_cfg["circuit"])
+    comp = compile_ac(circ_cfg["circuit"], args.compiler)
     t_comp = time.perf_counter() - t0
     g = ACGraph(comp, device=0)
     dev = g.torch_device
@@ -325,7 +336,7 @@ def eval_leg(args, circ_cfg):
                     "p_c~U[1e-3,1e-2] + amplitude damping 5e-3 after every gate; 4096 angle sets x 64 "
                     "seeded (x,k) = 262,144 amplitudes, c64 with FP64 |f|^2",
         "ac_internal_nodes": N, "ac_edges": info["n_edges"], "ac_levels": info["n_levels"],
-        "compile_s": t_comp, "batch": B,
+        "ac_compiler": args.compiler, "ac_super_nodes": info["n_super"], "compile_s": t_comp, "batch": B,
         "eval_ms": t_eval * 1e3, "amplitudes_per_s": B / t_eval, "node_evals_per_s": N * B / t_eval,
         "grad_ms": t_grad * 1e3, "grad_elements_per_s": B / t_grad,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -576,8 +587,7 @@ def main():
     circ = cfg["circuit"]
     P, chains = args.params, args.chains
     theta_np = cfg["theta"][:P]
-    from paper_2103_17226_amd.compiler import compile_circuit
-    g = ACGraph(compile_circuit(circ, order_trials=args.order_trials), device=0)
+    g = ACGraph(compile_ac(circ, args.compiler, order_trials=args.order_trials), device=0)
     info = g.info
     theta = torch.as_tensor(theta_np, dtype=torch.float64, device=dev)
     edges = torch.as_tensor(np.asarray(circ.edges, dtype=np.int32), device=dev)
@@ -658,7 +668,7 @@ def main():
                         "score-function gradient of <C> over the samples",
             "param_sets": P, "samples_per_param": S, "burn_in_sweeps": args.burn_in,
             "ac_internal_nodes": N, "ac_edges": E, "ac_levels": info["n_levels"],
-            "evidence_vars": info["n_vars"],
+            "evidence_vars": info["n_vars"], "ac_compiler": args.compiler,
         },
         "node_evals_per_s": node_evals / dt,
         "amplitude_node_evals_per_s_sampler": 2.0 * N * rounds / samp_s,

@@ -71,11 +71,18 @@ def blob_summary(blob: bytes) -> dict:
     return dict(zip(keys, f))
 
 
-def compile_blob(circ, **kw) -> bytes:
+def compile_blob(circ, method: str = "ve", **kw) -> bytes:
     """Compile a circuit and serialise its AC (picklable entry point for
-    compiling many circuits in worker processes)."""
-    from .compiler import compile_circuit
-    return to_blob(compile_circuit(circ, **kw))
+    compiling many circuits in worker processes).  method "ve" is variable
+    elimination (compiler.compile_circuit), "dpll" the search-based compiler
+    (dnnf.compile_circuit_dpll); both give the same polynomial."""
+    if method == "ve":
+        from .compiler import compile_circuit
+        return to_blob(compile_circuit(circ, **kw))
+    if method == "dpll":
+        from .dnnf import compile_circuit_dpll
+        return to_blob(compile_circuit_dpll(circ, **kw))
+    raise ValueError(f"unknown compile method {method!r}")
 
 
 def _compiler_key() -> str:
@@ -85,7 +92,7 @@ def _compiler_key() -> str:
     import os
     h = hashlib.sha256()
     here = os.path.dirname(os.path.abspath(__file__))
-    for name in ("compiler.py", "blob.py"):
+    for name in ("compiler.py", "dnnf.py", "blob.py"):
         with open(os.path.join(here, name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]

@@ -611,15 +611,26 @@ def _var_layout(doms):
     return offs, max(1, (pos + 63) // 64)
 
 
-def compile_circuit(circ, flatten: bool = True, selectors: bool = True,
-                    order_trials: int = 64) -> CompiledAC:
-    """Compile a circuit (op-list form) into a flat level-ordered AC.
+@dataclass
+class _Factors:
+    """The factor graph of a circuit, ready for a compiler: the BN, the AC
+    store holding its weight leaves, the factors over hidden and evidence
+    variables, constant parts, domains and the evidence variable of each
+    factor-graph variable."""
+    bn: object
+    ac: object
+    live: list
+    const_parts: list
+    dom: dict
+    indicator_of: dict
+    ev_nodes: list
+    n_fg_vars: int
 
-    selectors=True folds each channel's event indicators and Kraus entries
-    into selector leaves (one per matrix entry); False keeps them as sums of
-    indicator x weight products.  Both give the same polynomial.
-    order_trials is the number of greedy elimination-order runs to pick from
-    (1 = plain min-weight/min-fill)."""
+
+def build_factors(circ, selectors: bool = True) -> _Factors:
+    """Circuit -> BN (Sec. 3.1) -> factor graph with symbolic entries (the
+    conditional amplitude tables, simplified as in Sec. 3.2.1): the common
+    first stage of the variable-elimination and the search-based compilers."""
     bn = circuit_to_bn(circ)
     ac = ACBuilder()
 
@@ -720,9 +731,24 @@ def compile_circuit(circ, flatten: bool = True, selectors: bool = True,
             e = ev_index[nd]
             factors.append(Factor((), {(): ac.indicator(e, 0)}))
 
-    # merge factors over identical scopes is implicit in VE
     live = [f for f in factors if f.vars]
     const_parts = [f.table.get(()) for f in factors if not f.vars]
+    return _Factors(bn, ac, live, const_parts, dom, indicator_of, ev_nodes, nvar[0])
+
+
+def compile_circuit(circ, flatten: bool = True, selectors: bool = True,
+                    order_trials: int = 64) -> CompiledAC:
+    """Compile a circuit (op-list form) into a flat level-ordered AC.
+
+    selectors=True folds each channel's event indicators and Kraus entries
+    into selector leaves (one per matrix entry); False keeps them as sums of
+    indicator x weight products.  Both give the same polynomial.
+    order_trials is the number of greedy elimination-order runs to pick from
+    (1 = plain min-weight/min-fill)."""
+    F = build_factors(circ, selectors)
+    bn, ac, live, const_parts, dom, indicator_of, ev_nodes = (F.bn, F.ac, F.live, list(F.const_parts), F.dom,
+                                                               F.indicator_of, F.ev_nodes)
+    # merge factors over identical scopes is implicit in VE
     order = _elimination_order(live, dom, order_trials)
     # variables that appear in no factor but are evidence: they must still carry an indicator
     bucket: Dict[int, List[Factor]] = defaultdict(list)
@@ -749,6 +775,12 @@ def compile_circuit(circ, flatten: bool = True, selectors: bool = True,
     if root is None:
         raise ValueError("the compiled circuit is identically zero")
 
+    return finish_compiled(circ, bn, ac, root, ev_nodes, flatten,
+                           dict(fg_vars=F.n_fg_vars, max_table=max_table))
+
+
+def finish_compiled(circ, bn, ac, root, ev_nodes, flatten: bool, stats: dict) -> "CompiledAC":
+    """Level-ordered flat AC (the blob's form) from an AC store and its root."""
     var_dom = [bn.nodes[nd].dom for nd in ev_nodes]
     var_kind = [0] * bn.n + [{"DEP": 1, "AD": 2, "PD": 3}[op[0]] for op in circ.ops
                              if op[0] in CHANNEL_KINDS]
@@ -759,8 +791,7 @@ def compile_circuit(circ, flatten: bool = True, selectors: bool = True,
                      n_words=W, n_angles=circ.n_angles, n_noise=len(circ.noise),
                      noise_default=list(circ.noise), slots=slot_list, selectors=sel_list,
                      op=op_arr, row_ptr=row_ptr, col=col, level_ptr=level_ptr, root=root_idx)
-    res.stats = dict(bn_nodes=bn_node_count(bn), bn_events=len(bn.events),
-                     fg_vars=nvar[0], max_table=max_table,
+    res.stats = dict(bn_nodes=bn_node_count(bn), bn_events=len(bn.events), **stats,
                      n_internal=res.n_internal, n_edges=res.n_edges, n_levels=res.n_levels,
                      n_slots=len(slot_list), n_selectors=len(sel_list))
     return res
