@@ -50,25 +50,37 @@ KERNELS = os.path.join(ROOT, "paper_2103_17226_amd", "csrc", "qkc_kernels.hip")
 
 # HBM bytes per dispatch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs (scaled by
 # the copy-kernel calibration, FETCH x 2.0, WRITE x 1.0), valid only for the
-# kernel source they were taken on and the default workload of each leg.
+# kernel source and the AC they were taken on, and the default workload of
+# each leg.
 PROFILED_TRAFFIC = {
-    "k_sample_stream": {"kernel_sha256_16": "b5628148f98f97a1", "bytes": 4169501327360,
+    "k_sample_stream": {"kernel_sha256_16": "fb40ac2d41eb0e1c", "ac_sha256_16": "d3190d478a0e63f4",
+                        "bytes": 1656515552256,
                         "profile": "profiles/k_sample_stream_qaoa_n8_p1_dep.md"},
-    "k_eval": {"kernel_sha256_16": "b5628148f98f97a1", "bytes": 363483498496,
+    "k_eval": {"kernel_sha256_16": "fb40ac2d41eb0e1c", "ac_sha256_16": "53555d81365c02e0",
+               "bytes": 93865832448,
                "profile": "profiles/k_eval_qaoa_n16_p2_dep_ad.md"},
 }
 
 
-def profiled_traffic(kernel: str, default_workload: bool):
-    """Profiled bytes per dispatch, or None if the kernel source or the
-    workload differ from the profiled ones."""
+def _sha16(data: bytes) -> str:
     import hashlib
+    return hashlib.sha256(data).hexdigest()[:16]
+
+
+def kernel_sha16() -> str:
+    with open(KERNELS, "rb") as f:
+        return _sha16(f.read())
+
+
+def profiled_traffic(kernel: str, default_workload: bool, blob: bytes):
+    """Profiled bytes per dispatch, or None if the kernel source, the AC or
+    the workload differ from the profiled ones."""
     ent = PROFILED_TRAFFIC.get(kernel)
     if ent is None or not default_workload:
         return None
-    with open(KERNELS, "rb") as f:
-        h = hashlib.sha256(f.read()).hexdigest()[:16]
-    return ent["bytes"] if h == ent["kernel_sha256_16"] else None
+    if kernel_sha16() != ent["kernel_sha256_16"] or _sha16(blob) != ent["ac_sha256_16"]:
+        return None
+    return ent["bytes"]
 
 
 def parse():
@@ -82,7 +94,7 @@ def parse():
     ap.add_argument("--dtype", default="c64")
     ap.add_argument("--order-trials", type=int, default=64,
                     help="greedy elimination-order runs the compiler picks from")
-    ap.add_argument("--compiler", choices=["ve", "dpll"], default="ve",
+    ap.add_argument("--compiler", choices=["ve", "dpll"], default="dpll",
                     help="AC compiler of the sampling and gradient workloads: variable elimination "
                          "or the search-based (decision-DNNF) compiler")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -267,13 +279,21 @@ def plan_byte_model(info, cs: int):
     return up, down, leaf
 
 
+_AC_CACHE = {}
+
+
 def compile_ac(circ, method: str, order_trials: int = 64):
-    """The AC of a workload circuit from the chosen compiler."""
-    if method == "dpll":
-        from paper_2103_17226_amd.dnnf import compile_circuit_dpll
-        return compile_circuit_dpll(circ)
-    from paper_2103_17226_amd.compiler import compile_circuit
-    return compile_circuit(circ, order_trials=order_trials)
+    """The AC of a workload circuit from the chosen compiler (compiled once
+    per run: the GPU legs and the CPU baseline use the same AC)."""
+    key = (circ.name, len(circ.ops), method, order_trials)
+    if key not in _AC_CACHE:
+        if method == "dpll":
+            from paper_2103_17226_amd.dnnf import compile_circuit_dpll
+            _AC_CACHE[key] = compile_circuit_dpll(circ)
+        else:
+            from paper_2103_17226_amd.compiler import compile_circuit
+            _AC_CACHE[key] = compile_circuit(circ, order_trials=order_trials)
+    return _AC_CACHE[key]
 
 
 def eval_leg(args, circ_cfg):
@@ -344,7 +364,8 @@ def eval_leg(args, circ_cfg):
                      "bytes_per_element": up, "ac_super_nodes": info["n_super"],
                      "dag_model_bytes_per_element": dag_up,
                      "dag_model_GBps": dag_up * B / t_eval / 1e9,
-                     "traffic": profiled_traffic("k_eval", circ_cfg["evidence"].shape[0] == 262144),
+                     "traffic": profiled_traffic("k_eval", circ_cfg["evidence"].shape[0] == 262144, g.blob),
+                     "kernel_sha256_16": kernel_sha16(), "ac_sha256_16": _sha16(g.blob),
                      "traffic_unit": "HBM bytes per dispatch (rocprofv3)"},
         "grad_model_GBps": (dag_up + dag_down) * B / t_grad / 1e9,
         "grad_vs_eval_amplitude_max_rel_diff": grad_vs_eval,
@@ -515,7 +536,7 @@ def host_description():
             "usable_cores": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()}
 
 
-def cpu_evaluator_baseline(circ, theta, chains, eval_cfg, budget_s):
+def cpu_evaluator_baseline(circ, theta, chains, eval_cfg, budget_s, method, order_trials):
     """The plain CPU AC evaluator (libqkc_cpu.so, complex128, OpenMP) on
     the same blobs: Gibbs samples/s on the default sampling job's AC (a
     bounded slice of its parameter sets, all chains each) and upward-pass
@@ -525,12 +546,11 @@ def cpu_evaluator_baseline(circ, theta, chains, eval_cfg, budget_s):
 
     from paper_2103_17226_amd import cpu_eval
     from paper_2103_17226_amd.blob import to_blob
-    from paper_2103_17226_amd.compiler import compile_circuit
     cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
     out = {"kind": "plain CPU AC evaluator (C++ -O3, OpenMP, complex128; same blobs, same sampler rules)",
            "host": host_description()}
-    sac = cpu_eval.CpuAC(to_blob(compile_circuit(circ)))
-    eac = cpu_eval.CpuAC(to_blob(compile_circuit(eval_cfg["circuit"])))
+    sac = cpu_eval.CpuAC(to_blob(compile_ac(circ, method, order_trials)))
+    eac = cpu_eval.CpuAC(to_blob(compile_ac(eval_cfg["circuit"], method)))
     for label, threads in (("all_cores", cores), ("one_core", 1)):
         share = budget_s / 4.0
         # samples: parameter sets one after another, all their chains, until the time share is used
@@ -681,7 +701,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": profiled_traffic("k_sample_stream", default_run),
+            "traffic": profiled_traffic("k_sample_stream", default_run, g.blob),
+            "kernel_sha256_16": kernel_sha16(), "ac_sha256_16": _sha16(g.blob),
             "traffic_unit": "HBM bytes per dispatch (rocprofv3)",
             "kernel": "k_sample_stream (Gibbs rounds: upward + downward pass + decisions; "
                       "timed with HIP events around ac_sample on its stream)",
@@ -732,7 +753,8 @@ def main():
     if not args.no_cpu_baseline:    # last: the host cores are idle by now
         print("# CPU baselines", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(circ, theta_np, chains, args.cpu_seconds)
-        res["cpu_evaluator"] = cpu_evaluator_baseline(circ, theta_np, chains, W.config(3), args.cpu_seconds)
+        res["cpu_evaluator"] = cpu_evaluator_baseline(circ, theta_np, chains, W.config(3), args.cpu_seconds,
+                                                      args.compiler, args.order_trials)
     print(json.dumps(res), flush=True)
 
 
