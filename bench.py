@@ -118,6 +118,13 @@ def parse():
                     help="directory of cached compiled serving-pool blobs ('' for none)")
     ap.add_argument("--serve-streams", type=int, default=8)
     ap.add_argument("--serve-queue", type=int, default=16)
+    ap.add_argument("--serve-part-streams", type=int, default=1,
+                    help="streams the parts of split requests hold at once, in total")
+    ap.add_argument("--serve-part-share", type=float, default=0.5,
+                    help="share of the device's workgroups a part of a split request runs on")
+    ap.add_argument("--serve-max-split", type=int, default=4, help="split requests waiting or running at once")
+    ap.add_argument("--serve-split-backlog", type=float, default=30.0,
+                    help="estimated device seconds of waiting parts beyond which split requests are refused")
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     ap.add_argument("--serve-max-seconds", type=float, default=0.5,
                     help="split requests estimated to hold the device longer than this into parts")
@@ -178,7 +185,9 @@ def serve_run(graphs, pool, rate, args):
     edges = {c.name: c.edges for c in pool}
     ex = GraphExecutor(graphs, edges, n_streams=args.serve_streams)
     srv = Server(ex, mem_budget=int(args.serve_budget_gib * (1 << 30)), max_queue=args.serve_queue,
-                 max_seconds=args.serve_max_seconds)
+                 max_seconds=args.serve_max_seconds, part_streams=args.serve_part_streams,
+                 part_share=args.serve_part_share, max_split=args.serve_max_split,
+                 split_backlog=args.serve_split_backlog)
     top = rate >= max(float(x) for x in args.serve_rates.split(",") if x)
     seconds = args.serve_seconds if top else args.serve_seconds_low
     warmup = args.serve_warmup if top else args.serve_warmup_low
@@ -211,7 +220,7 @@ def serve_run(graphs, pool, rate, args):
         if e is None:
             return "completed"
         msg = str(e)
-        if "queue full" in msg:
+        if "queue full" in msg:           # whole requests, or the split requests' backlog
             return "rejected_queue"
         if "hold the device" in msg:
             return "rejected_cost"
@@ -228,12 +237,13 @@ def serve_run(graphs, pool, rate, args):
     ok = [q for q in window if outcome(q) == "completed"]
     span = max([q.t_done for q in ok] + [t_end]) - since
     # how the admission estimate compares with the time each request held a stream
-    ratio = [(q.t_done - q.t_start) / max(ex.cost(q), 1e-6) for q in ok]
+    ratio = [(q.t_done - q.t_start) / max(ex.cost(q), 1e-6) for q in ok if not isinstance(q.part, dict)]
     stuck = [{"graph": q.graph, "kind": q.kind, "P": q.n_params, "S": q.samples, "rows": q.n_rows,
               "grad": q.grad, "est_s": ex.cost(q)} for q in window if outcome(q) == "unfinished"]
     out = {"offered_rps": rate, "warmup_s": warmup, "measured_s": seconds, "arrivals": len(window),
            **counts, "split_requests": st["split_requests"], "split_parts": st["split_parts"],
            "p50_ms": st.get("p50_ms"), "p99_ms": st.get("p99_ms"), "mean_ms": st.get("mean_ms"),
+           "whole_requests": st["whole"], "split_requests_latency": st["split"],
            "throughput_rps": len(ok) / span,
            "samples_per_s": sum(q.n_params * q.samples for q in ok) / span,
            "amplitudes_per_s": sum(q.n_rows for q in ok) / span,
@@ -735,11 +745,13 @@ def main():
         res["serving"] = {
             "workload": "serving mix: noisy QAOA p in {1,2}, n in {6,8,12,16,20}, 4 graphs each, "
                         "Poisson arrivals; P~logU{1..256}, eval(64 x/set) w.p. 0.1 else S~logU{1..4096} "
-                        "samples/set, gradient w.p. 0.5; c64",
+                        "samples/set (S>=2 with a gradient), gradient w.p. 0.5; c64",
             "pool_circuits": len(pool), "pool_compile_s": t_pool, "pool_cache_hits": cache_hits,
             "pool_ac_nodes_max": max(gr.info["n_internal"] for gr in graphs.values()),
             "streams": args.serve_streams, "queue_limit": args.serve_queue,
             "budget_gib": args.serve_budget_gib, "max_request_seconds": args.serve_max_seconds,
+            "part_streams": args.serve_part_streams, "part_share": args.serve_part_share,
+            "max_split": args.serve_max_split, "split_backlog_s": args.serve_split_backlog,
             "warmup_s": args.serve_warmup, "measured_s": args.serve_seconds,
             "measured_s_lower_rates": args.serve_seconds_low,
             "runs": runs,

@@ -40,8 +40,14 @@
  * - param_of is int32 [B]: the parameter set (row of theta) of each batch
  *   element.  Values outside [0, P) are not checked on the device and are
  *   undefined behaviour; the Python binding validates them.
- * - Every call needs a caller-allocated device workspace of at least
- *   ac_workspace_size() bytes; the library never allocates per call.
+ * - Every call takes a caller-allocated device workspace; the library never
+ *   allocates per call.  ac_workspace_size() bytes run the call at full
+ *   width (every workgroup the device holds at once).  A smaller workspace
+ *   runs fewer workgroups at once -- as many per-workgroup regions as fit
+ *   after the fixed part, at least one -- with the same results, which
+ *   leaves the rest of the device to work on other streams; below one region
+ *   the call fails with AC_ERR_INVALID_ARG (the LDS-resident sampler has no
+ *   regions and always needs the full size).
  * - Errors: a non-AC_OK status is returned before anything is enqueued for
  *   invalid arguments; AC_ERR_DEVICE reports a failed launch.  ac_last_error()
  *   returns a thread-local description of the last failure.  No C++
@@ -174,6 +180,16 @@ const char *ac_last_error(void);
  * invalid arguments.  The size depends on the device's compute-unit count.
  */
 size_t ac_workspace_size(const ac_graph *g, ac_dtype dtype, int64_t batch, int op);
+
+/*
+ * Bytes of workspace for the same call run on a share of the device: at most
+ * ceil(share * W) workgroups at once, W being the workgroups the full-size
+ * workspace runs (share in (0, 1]; results are the same, the call takes
+ * longer and leaves the rest of the device to other streams).  Equal to
+ * ac_workspace_size when the call has no per-workgroup regions or runs one
+ * workgroup.  Returns 0 for invalid arguments.
+ */
+size_t ac_workspace_size_share(const ac_graph *g, ac_dtype dtype, int64_t batch, int op, double share);
 
 /* Sampler kernels, as reported by ac_sample_shape. */
 typedef enum { AC_SAMPLER_STREAM = 0, AC_SAMPLER_LDS = 1, AC_SAMPLER_GLOBAL = 2 } ac_sampler_kind;

@@ -20,7 +20,8 @@ AC_OP_EVAL, AC_OP_GRAD, AC_OP_SAMPLE = 0, 1, 2
 AC_GRAD_COTANGENT, AC_GRAD_PROB, AC_GRAD_LOGPROB = 0, 1, 2
 AC_SAMPLER_STREAM, AC_SAMPLER_LDS, AC_SAMPLER_GLOBAL = 0, 1, 2
 
-EXPORTED = ("ac_load", "ac_free", "ac_info", "ac_last_error", "ac_workspace_size", "ac_sample_shape",
+EXPORTED = ("ac_load", "ac_free", "ac_info", "ac_last_error", "ac_workspace_size", "ac_workspace_size_share",
+            "ac_sample_shape",
             "ac_eval_batch", "ac_eval_batch_static", "ac_grad_batch", "ac_sample")
 AC_STATIC_SCRATCH_BYTES = 256 << 20
 
@@ -80,6 +81,8 @@ def lib():
     L.ac_last_error.restype = ctypes.c_char_p
     L.ac_workspace_size.argtypes = [vp, ctypes.c_int, i64, ctypes.c_int]
     L.ac_workspace_size.restype = sz
+    L.ac_workspace_size_share.argtypes = [vp, ctypes.c_int, i64, ctypes.c_int, ctypes.c_double]
+    L.ac_workspace_size_share.restype = sz
     L.ac_sample_shape.argtypes = [vp, ctypes.c_int, i64, ctypes.POINTER(i32), ctypes.POINTER(i64)]
     L.ac_sample_shape.restype = ctypes.c_int
     L.ac_eval_batch.argtypes = [vp, ctypes.c_int, vp, i32, vp, vp, vp, i64, vp, vp, vp, sz, vp]

@@ -80,6 +80,14 @@ class ACGraph:
     def workspace_size(self, dtype: str, batch: int, op: int) -> int:
         return int(L.lib().ac_workspace_size(self._h, _CDTYPE[dtype][0], int(batch), int(op)))
 
+    def workspace_size_share(self, dtype: str, batch: int, op: int, share: float) -> int:
+        """Workspace bytes for the call run on ``share`` of the device's
+        workgroups (smaller, slower, same results)."""
+        n = int(L.lib().ac_workspace_size_share(self._h, _CDTYPE[dtype][0], int(batch), int(op), float(share)))
+        if n == 0:
+            raise L.ACError(L.AC_ERR_INVALID_ARG, L.lib().ac_last_error().decode())
+        return n
+
     def sample_shape(self, dtype: str, chains: int):
         """(kernel, chains advanced at once) that ``sample`` uses for this many
         chains: kernel is "stream", "lds" or "global"."""
@@ -89,14 +97,16 @@ class ACGraph:
         return ("stream", "lds", "global")[kind.value], int(conc.value)
 
     def workspace(self, dtype: str, batch: int, op: int, ws: Optional[torch.Tensor] = None) -> torch.Tensor:
-        """The workspace for one call: ``ws`` if given (checked for size), else
-        a buffer cached per (dtype, op) on this graph.  The cached buffer is
-        shared by every call on the graph, so callers that run the same graph
-        on several streams at once pass their own ``ws``."""
+        """The workspace for one call: ``ws`` if given, else a buffer cached
+        per (dtype, op) on this graph.  The cached buffer is shared by every
+        call on the graph, so callers that run the same graph on several
+        streams at once pass their own ``ws``.  A ``ws`` smaller than
+        ``workspace_size`` runs the call on fewer workgroups at once (the
+        library refuses one below a single workgroup's region)."""
         need = self.workspace_size(dtype, batch, op)
         if ws is not None:
-            if ws.device != self.torch_device or ws.dtype != torch.uint8 or ws.numel() < need:
-                raise ValueError(f"workspace must be a uint8 tensor on {self.torch_device} of >= {need} bytes")
+            if ws.device != self.torch_device or ws.dtype != torch.uint8:
+                raise ValueError(f"workspace must be a uint8 tensor on {self.torch_device}")
             return ws
         key = (dtype, op)
         ws = self._ws.get(key)

@@ -1148,6 +1148,7 @@ size_t eval_live_rows(const ac_graph *g) {
 struct Layout {
     size_t wfix_off = 0, contrib_off = 0, sort_off = 0, sort_bytes = 0, tiles_off = 0, total = 0;
     size_t per_wg_elems = 0;   // complex elements per workgroup buffer
+    size_t cs = 8;             // bytes per complex element
     int grid = 0;
     int block = BLOCK;         // threads per workgroup
 };
@@ -1208,9 +1209,24 @@ bool make_layout(const ac_graph *g, ac_dtype dt, int64_t batch, int op, Layout &
     off += align256(static_cast<size_t>(grid) * per_wg * cs);
     L.total = off;
     L.per_wg_elems = per_wg;
+    L.cs = cs;
     L.grid = static_cast<int>(grid);
     L.block = block;
     out = L;
+    return true;
+}
+
+// A caller's workspace below the full layout: the grid shrinks to the
+// per-workgroup regions that fit after the fixed part (at least one), so the
+// call keeps fewer workgroups resident and leaves the rest of the device to
+// other streams.  False if not even one region fits.
+bool fit_workspace(Layout &L, size_t ws_bytes) {
+    if (ws_bytes >= L.total) return true;
+    const size_t per = L.per_wg_elems * L.cs;
+    if (per == 0 || L.grid < 1 || ws_bytes < L.tiles_off + per) return false;
+    const int64_t grid = static_cast<int64_t>((ws_bytes - L.tiles_off) / per);
+    L.grid = static_cast<int>(std::min<int64_t>(L.grid, grid));
+    L.total = L.tiles_off + static_cast<size_t>(L.grid) * per;
     return true;
 }
 
@@ -1243,6 +1259,19 @@ extern "C" size_t ac_workspace_size(const ac_graph *g, ac_dtype dtype, int64_t b
         return 0;
     }
     return L.total;
+}
+
+extern "C" size_t ac_workspace_size_share(const ac_graph *g, ac_dtype dtype, int64_t batch, int op, double share) {
+    Layout L;
+    if (!(share > 0.0 && share <= 1.0) || !make_layout(g, dtype, batch, op, L)) {
+        fail(AC_ERR_INVALID_ARG, "ac_workspace_size_share: invalid arguments");
+        return 0;
+    }
+    const size_t per = L.per_wg_elems * L.cs;
+    if (per == 0 || L.grid <= 1) return L.total;
+    const int64_t grid = std::max<int64_t>(1, static_cast<int64_t>(std::ceil(share * L.grid)));
+    if (grid >= L.grid) return L.total;
+    return L.tiles_off + static_cast<size_t>(grid) * per;
 }
 
 extern "C" ac_status ac_sample_shape(const ac_graph *g, ac_dtype dtype, int64_t chains, int32_t *kind,
@@ -1279,8 +1308,9 @@ extern "C" ac_status ac_eval_batch(const ac_graph *g, ac_dtype dtype, const doub
     if (!param_of || !evidence || !amp_out) return fail(AC_ERR_INVALID_ARG, "ac_eval_batch: null param_of/evidence/amp_out");
     Layout L;
     make_layout(g, dtype, B, AC_OP_EVAL, L);
-    if (!ws || ws_bytes < L.total)
-        return fail(AC_ERR_INVALID_ARG, "ac_eval_batch: workspace of %zu bytes, need %zu", ws_bytes, L.total);
+    if (!ws || !fit_workspace(L, ws_bytes))
+        return fail(AC_ERR_INVALID_ARG, "ac_eval_batch: workspace of %zu bytes, need %zu (%zu for one workgroup)",
+                    ws_bytes, L.total, L.tiles_off + L.per_wg_elems * L.cs);
     DeviceGuard dg(g->device);
     hipStream_t st = static_cast<hipStream_t>(stream);
     uint8_t *w = static_cast<uint8_t *>(ws);
@@ -1374,8 +1404,9 @@ extern "C" ac_status ac_grad_batch(const ac_graph *g, ac_dtype dtype, const doub
         }
         return AC_OK;
     }
-    if (!ws || ws_bytes < L.total)
-        return fail(AC_ERR_INVALID_ARG, "ac_grad_batch: workspace of %zu bytes, need %zu", ws_bytes, L.total);
+    if (!ws || !fit_workspace(L, ws_bytes))
+        return fail(AC_ERR_INVALID_ARG, "ac_grad_batch: workspace of %zu bytes, need %zu (%zu for one workgroup)",
+                    ws_bytes, L.total, L.tiles_off + L.per_wg_elems * L.cs);
     uint8_t *w = static_cast<uint8_t *>(ws);
     double *contrib = reinterpret_cast<double *>(w + L.contrib_off);
     hipError_t e;
@@ -1427,8 +1458,9 @@ extern "C" ac_status ac_sample(const ac_graph *g, ac_dtype dtype, const double *
     if (!samples) return fail(AC_ERR_INVALID_ARG, "ac_sample: samples is null");
     Layout L;
     make_layout(g, dtype, total, AC_OP_SAMPLE, L);
-    if (!ws || ws_bytes < L.total)
-        return fail(AC_ERR_INVALID_ARG, "ac_sample: workspace of %zu bytes, need %zu", ws_bytes, L.total);
+    if (!ws || !fit_workspace(L, ws_bytes))
+        return fail(AC_ERR_INVALID_ARG, "ac_sample: workspace of %zu bytes, need %zu (%zu for one workgroup)",
+                    ws_bytes, L.total, L.tiles_off + L.per_wg_elems * L.cs);
     DeviceGuard dg(g->device);
     hipStream_t st = static_cast<hipStream_t>(stream);
     uint8_t *w = static_cast<uint8_t *>(ws);

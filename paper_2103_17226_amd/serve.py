@@ -12,10 +12,9 @@ resident on the device and a scheduler thread that, on every tick,
      released at once;
   2. admits queued requests in arrival order while their device-memory
      footprint (inputs, outputs, workspace) fits the budget and a stream is
-     free; the head of the queue is never overtaken, so a large request
-     cannot starve (parts of a split request beyond ``part_streams`` on the
-     device at once, and requests of a busy session, keep their place while
-     later requests go ahead);
+     free; the head of the queue is never overtaken for memory, so a large
+     request cannot starve (requests of a busy session keep their place
+     while later requests go ahead);
   3. merges an admitted amplitude request with later queued ones of the same
      graph, dtype and kind into one launch.  Parameter sets are stacked and
      every element keeps its own parameter row, so each request gets what it
@@ -23,8 +22,8 @@ resident on the device and a scheduler thread that, on every tick,
      start on a 256-element boundary so that the fixed-order reduction adds
      the same terms in the same order (padding rows carry weight 0 and a
      parameter row of their own that is dropped).  Sampling requests run
-     alone: their chains are numbered from 0 within the request, which is
-     what makes them reproducible from the seed.  A sampling request of a
+     alone: their chains are numbered from the request's chain offset, which
+     is what makes them reproducible from the seed.  A sampling request of a
      session resumes the chains that session left on the device; requests of
      one session run one at a time, in arrival order, and the chain states
      count against the memory budget until the session is closed.
@@ -32,15 +31,20 @@ resident on the device and a scheduler thread that, on every tick,
 Requests that arrive while others are on the device therefore start as soon
 as a stream and memory free up, and their kernels overlap on the device.
 A request estimated (with ``max_seconds``) to occupy the device longer than
-that is split into parts that each fit the limit -- by parameter sets, or by
-chains (sampling) or evidence rows (amplitudes) of one parameter set -- which
-flow through the loop like other requests; its result is assembled when the
-last part completes and equals the unsplit request's (sampling parts number
-their chains from the request's chain offset, so they draw the same chains).
-Submissions beyond ``max_queue`` waiting requests, or larger than the whole
-budget, are rejected at once.  Resident session chains that leave no room
-for the request at the head of the queue, with nothing else on the device,
-are released oldest first; a request that cannot fit even then fails.
+that, or larger than the memory budget, is split into parts that each fit
+-- by parameter sets, or by chains (sampling) or evidence rows (amplitudes)
+of one parameter set -- and joins a second queue: its parts launch in order
+on streams kept for parts (``part_streams``), each on a share of the device
+(``part_share``: the executor gives the launch a workspace for that share of
+the workgroups the device holds), so long requests make steady progress
+while short ones keep the rest of the device.  Its result is assembled when
+the last part completes and equals the unsplit request's (sampling parts
+number their chains from the request's chain offset, so they draw the same
+chains).  Submissions beyond ``max_queue`` waiting requests, or
+``max_split`` split requests, are rejected at once, and so are requests that
+cannot fit the budget even when split.  Resident session chains that leave no
+room for the next launch, with nothing else on the device, are released
+oldest first; a request that cannot fit even then fails.
 
 The device work is done by an executor (``GraphExecutor`` for libqkc); the
 scheduler only sees its footprint / launch / done / results calls, so tests
@@ -85,6 +89,7 @@ class Request:
     dtype: str = "c64"
     session: Optional[str] = None
     chain_offset: int = 0                    # RNG number of the first chain (parts of a split request)
+    share: float = 1.0                       # fraction of the device a launch may hold (parts: less)
     # filled in by the server
     rid: int = -1
     t_arrive: float = 0.0
@@ -120,17 +125,30 @@ class Server:
     ``can_merge(a, b) -> bool``, ``launch(batch, stream) -> handle``,
     ``done(handle) -> bool`` and ``results(handle) -> list`` (one result per
     request of the batch, in order), and ``cost(req) -> estimated device
-    seconds`` if ``max_seconds`` is used.  ``launch``, ``done`` and
-    ``results`` may raise; the requests of that batch then fail with the
-    exception.  With ``request_timeout`` a launch still running that long
-    after it started fails its requests with TimeoutError at once; its memory
-    and stream return when the device finishes."""
+    seconds`` and ``split(req, limit, max_bytes)`` if ``max_seconds`` is used.
+    ``launch``, ``done`` and ``results`` may raise; the requests of that batch
+    then fail with the exception.  With ``request_timeout`` a launch still
+    running that long after it started fails its requests with TimeoutError
+    at once; its memory and stream return when the device finishes.
+
+    Split requests form a second class: at most ``max_split`` of them wait or
+    run at once, and one more is admitted only while the estimated device
+    time of the parts still waiting is below ``split_backlog`` seconds (a
+    request is never refused for its own size).  Their parts hold at most
+    ``part_streams`` streams in total (kept free for them while parts wait);
+    the next part comes from the split request with the least estimated work
+    left, less the seconds it has waited; and each part runs on
+    ``part_share`` of the device (``Request.share``, for the executor), so
+    whole requests keep the rest of the device while long ones progress."""
 
     def __init__(self, executor, mem_budget: int, clock: Callable[[], float] = time.perf_counter,
                  max_queue: int = 1 << 30, max_merge: int = 64, max_seconds: Optional[float] = None,
-                 request_timeout: Optional[float] = None, tick: float = 1e-4, part_streams: int = 2):
+                 request_timeout: Optional[float] = None, tick: float = 1e-4, part_streams: int = 1,
+                 part_share: float = 0.5, max_split: int = 4, split_backlog: float = 30.0):
         if mem_budget <= 0:
             raise ValueError("mem_budget must be positive")
+        if not 0.0 < part_share <= 1.0:
+            raise ValueError("part_share must be in (0, 1]")
         self.ex = executor
         self.budget = int(mem_budget)
         self.clock = clock
@@ -139,8 +157,14 @@ class Server:
         self.max_seconds = max_seconds
         self.request_timeout = request_timeout
         self.tick = tick
-        self.part_streams = max(1, int(part_streams))   # parts of one split request on the device at once
-        self.queue: collections.deque = collections.deque()
+        self.part_streams = max(1, min(int(part_streams), executor.n_streams))
+        self.part_share = float(part_share)
+        self.max_split = max(1, int(max_split))
+        self.split_backlog = float(split_backlog)
+        self.queue: collections.deque = collections.deque()        # whole requests, arrival order
+        self.split_queue: collections.deque = collections.deque()  # split requests with parts to launch
+        self.split_active = 0                       # split requests not yet completed or failed
+        self.parts_inflight = 0
         self.inflight: List[tuple] = []            # (handle, [requests], stream, bytes)
         self.free_streams = list(range(executor.n_streams))
         self.used = 0
@@ -191,20 +215,27 @@ class Server:
             return req.future
         units = parts if parts else [req]
         for u in units:
+            if parts:
+                u.share = self.part_share
             u.footprint = int(self.ex.footprint(u))
             if u.footprint > self.budget:
                 self.rejected_memory += 1
                 req.future.set_exception(AdmissionError(
                     f"request needs {u.footprint} bytes of device memory, the budget is {self.budget}"))
                 return req.future
+        costs = [float(self.ex.cost(u)) for u in parts] if parts and self.max_seconds is not None else None
         with self.lock:
-            if len(self.queue) >= self.max_queue:
-                self.rejected_queue += 1
-                req.future.set_exception(AdmissionError(f"queue full ({self.max_queue} waiting)"))
-                return req.future
             if parts:
+                backlog = self._split_backlog()
+                if self.split_active >= self.max_split or backlog >= self.split_backlog:
+                    self.rejected_queue += 1
+                    req.future.set_exception(AdmissionError(
+                        f"split queue full ({self.split_active} split requests, ~{backlog:.3g} s of parts waiting)"))
+                    return req.future
                 req.part = {"n": len(parts), "done": 0, "outs": [None] * len(parts), "failed": False,
-                            "descs": [u.part for u in parts], "inflight": 0}
+                            "descs": [u.part for u in parts], "inflight": 0,
+                            "todo": collections.deque(parts),
+                            "costs": collections.deque(costs if costs is not None else [0.0] * len(parts))}
                 for k, u in enumerate(parts):
                     u.rid = next(self._ids)
                     u.t_arrive = req.t_arrive
@@ -212,20 +243,31 @@ class Server:
                     u.part = (k, u.part)
                 self.split_requests += 1
                 self.split_parts += len(parts)
-            self.queue.extend(units)
+                self.split_active += 1
+                self.split_queue.append(req)
+                return req.future
+            if len(self.queue) >= self.max_queue:
+                self.rejected_queue += 1
+                req.future.set_exception(AdmissionError(f"queue full ({self.max_queue} waiting)"))
+                return req.future
+            self.queue.append(req)
         return req.future
 
     def cancel(self, fut: Future) -> bool:
-        """Cancel a request that is still waiting; one already on the device
-        runs to completion (returns False)."""
+        """Cancel a request that is still waiting (a split request only
+        before its first part launched); one already on the device runs to
+        completion (returns False)."""
         with self.lock:
-            mine = [r for r in self.queue if r.future is fut or (r.parent is not None and r.parent.future is fut)]
-            if not mine:
-                return False
-            if any(r.parent is not None for r in mine) and len(mine) != mine[0].parent.part["n"]:
-                return False                       # some parts already ran
-            for r in mine:
-                self.queue.remove(r)
+            for r in self.queue:
+                if r.future is fut:
+                    self.queue.remove(r)
+                    break
+            else:
+                par = next((r for r in self.split_queue if r.future is fut), None)
+                if par is None or len(par.part["todo"]) != par.part["n"]:
+                    return False
+                self.split_queue.remove(par)
+                self.split_active -= 1
             self.cancelled += 1
             fut.cancel()
             return True
@@ -239,7 +281,7 @@ class Server:
 
     def idle(self) -> bool:
         with self.lock:
-            return not self.queue and not self.inflight and not self.launching
+            return not self.queue and not self.split_queue and not self.inflight and not self.launching
 
     def stop(self, drain: bool = True, timeout: float = 600.0):
         """Stop the scheduler thread, after the queue and the device drain if
@@ -258,12 +300,13 @@ class Server:
             if not self._complete():
                 time.sleep(self.tick)
         with self.lock:
-            while self.queue:
-                r = self.queue.popleft()
-                f = r.parent.future if r.parent is not None else r.future
-                if not f.done():
+            left = list(self.queue) + list(self.split_queue)
+            self.queue.clear()
+            self.split_queue.clear()
+            for r in left:
+                if not r.future.done():
                     self.cancelled += 1
-                    f.cancel()
+                    r.future.cancel()
 
     # ------------------------------------------------------------ scheduler
     def _fail(self, reqs, exc):
@@ -276,6 +319,12 @@ class Server:
                     par.part["failed"] = True
                     par.t_done = r.t_done
                     self.failed += 1
+                    with self.lock:
+                        self.split_active -= 1
+                        par.part["todo"].clear()
+                        par.part["costs"].clear()
+                        if par in self.split_queue:
+                            self.split_queue.remove(par)
                     if not par.future.done():
                         par.future.set_exception(exc)
                 continue
@@ -297,6 +346,8 @@ class Server:
         if st["done"] < st["n"] or st["failed"] or par.future.done():
             return 0
         par.t_done = now
+        with self.lock:
+            self.split_active -= 1
         try:
             res = self.ex.combine(par, st["outs"])
         except Exception as exc:
@@ -354,42 +405,99 @@ class Server:
                 self.busy_sessions.discard((r.graph, r.session))
             if r.parent is not None:
                 r.parent.part["inflight"] -= 1
+                self.parts_inflight -= 1
 
-    def _session_busy(self, r: Request) -> bool:
-        if r.parent is not None and r.parent.part["inflight"] >= self.part_streams:
-            return True                            # its request already has its share of streams
-        return r.session is not None and (r.graph, r.session) in self.busy_sessions
+    def _make_room(self, need: int, resident: int) -> int:
+        """Nothing is on the device and ``need`` bytes do not fit next to
+        the resident session chains: release idle ones, least recently used
+        first; returns the resident bytes left."""
+        if hasattr(self.ex, "evict_sessions"):
+            self.evicted_sessions += self.ex.evict_sessions(resident + need - self.budget, self.busy_sessions)
+            resident = self.ex.resident_bytes()
+        return resident
+
+    def _split_backlog(self) -> float:
+        """Estimated device seconds of the parts still waiting."""
+        return sum(sum(p.part["costs"]) for p in self.split_queue if not p.part["failed"])
+
+    def _next_split(self):
+        """The split request whose parts go next: least estimated work left,
+        less the seconds it has waited (shortest first, with ageing)."""
+        now = self.clock()
+        return min(self.split_queue, key=lambda p: (sum(p.part["costs"]) - (now - p.t_arrive), p.rid))
+
+    def _take_part(self, resident: int):
+        """The next part of a split request (``_next_split``), if a stream
+        for parts and its memory are free; called with the lock held."""
+        while self.split_queue and self.parts_inflight < self.part_streams and self.free_streams:
+            for p in [p for p in self.split_queue if p.part["failed"] or not p.part["todo"]]:
+                self.split_queue.remove(p)
+            if not self.split_queue:
+                break
+            par = self._next_split()
+            st = par.part
+            u = st["todo"][0]
+            if self.used + resident + u.footprint > self.budget:
+                if self.used or self.inflight or self.launching:
+                    return None                    # room comes back as launches complete
+                resident = self._make_room(u.footprint, resident)
+                if resident + u.footprint > self.budget:
+                    self.split_queue.remove(par)
+                    st["todo"].clear()
+                    st["costs"].clear()
+                    st["failed"] = True
+                    self.split_active -= 1
+                    self.rejected_memory += 1
+                    if not par.future.done():
+                        par.future.set_exception(AdmissionError(
+                            f"part needs {u.footprint} bytes next to {resident} bytes of resident session "
+                            f"chains in use, the budget is {self.budget}"))
+                    continue
+            st["todo"].popleft()
+            st["costs"].popleft()
+            if not st["todo"]:
+                self.split_queue.remove(par)
+            st["inflight"] += 1
+            self.parts_inflight += 1
+            self.launching += 1
+            stream = self.free_streams.pop(0)
+            self.used += u.footprint
+            self.peak_used = max(self.peak_used, self.used)
+            return [u], stream, u.footprint
+        return None
 
     def _take_batch(self):
-        """Pop the next launch if it fits; called with the lock held.  The
-        first request whose session is idle leads (requests of a busy session
-        keep their place); later requests never overtake it for memory."""
-        if not self.queue or not self.free_streams:
+        """Pop the next launch if it fits; called with the lock held.  Parts
+        of split requests go first on the streams kept for them; of the
+        whole requests, the first whose session is idle leads (requests of a
+        busy session keep their place) and later requests never overtake it
+        for memory."""
+        if not self.free_streams:
             return None
-        idx = next((k for k, r in enumerate(self.queue) if not self._session_busy(r)), None)
+        resident = self.ex.resident_bytes() if hasattr(self.ex, "resident_bytes") else 0
+        got = self._take_part(resident)
+        if got is not None:
+            return got
+        waiting_parts = any(not p.part["failed"] and p.part["todo"] for p in self.split_queue)
+        keep_free = max(0, self.part_streams - self.parts_inflight) if waiting_parts else 0
+        if not self.queue or len(self.free_streams) <= keep_free:
+            return None
+        idx = next((k for k, r in enumerate(self.queue)
+                    if not (r.session is not None and (r.graph, r.session) in self.busy_sessions)), None)
         if idx is None:
             return None
         head = self.queue[idx]
-        resident = self.ex.resident_bytes() if hasattr(self.ex, "resident_bytes") else 0
         if self.used + resident + head.footprint > self.budget:
             if self.used or self.inflight or self.launching:
                 return None                        # room comes back as launches complete
-            # nothing else holds memory: only resident session chains can make
-            # room; release idle ones, least recently used first
-            if hasattr(self.ex, "evict_sessions"):
-                self.evicted_sessions += self.ex.evict_sessions(resident + head.footprint - self.budget,
-                                                                self.busy_sessions)
-                resident = self.ex.resident_bytes()
+            resident = self._make_room(head.footprint, resident)
             if resident + head.footprint > self.budget:
                 del self.queue[idx]
                 self.rejected_memory += 1
-                exc = AdmissionError(f"request needs {head.footprint} bytes next to {resident} bytes of resident "
-                                     f"session chains in use, the budget is {self.budget}")
-                for f in ([head.future] + ([head.parent.future] if head.parent is not None else [])):
-                    if not f.done():
-                        f.set_exception(exc)
-                if head.parent is not None:
-                    head.parent.part["failed"] = True
+                if not head.future.done():
+                    head.future.set_exception(AdmissionError(
+                        f"request needs {head.footprint} bytes next to {resident} bytes of resident session "
+                        f"chains in use, the budget is {self.budget}"))
                 return self._take_batch()
         del self.queue[idx]
         batch, total = [head], head.footprint
@@ -406,8 +514,6 @@ class Server:
             self.queue = keep
         if head.session is not None:
             self.busy_sessions.add((head.graph, head.session))
-        if head.parent is not None:
-            head.parent.part["inflight"] += 1
         self.launching += 1
         stream = self.free_streams.pop(0)
         self.used += total
@@ -462,11 +568,19 @@ class Server:
                 time.sleep(self.tick)
 
     # --------------------------------------------------------------- stats
+    @staticmethod
+    def _lat(done) -> Dict[str, Any]:
+        lat = np.array([r.t_done - r.t_arrive for r in done])
+        if not len(lat):
+            return {"completed": 0}
+        return {"completed": len(done), "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3)}
+
     def latency_stats(self, since: float = float("-inf")) -> Dict[str, Any]:
         """Latency (arrival to completion) over requests that arrived at or
-        after ``since``, with counts of every outcome."""
+        after ``since``, with counts of every outcome; ``whole`` and
+        ``split`` give the latency of the two classes apart."""
         done = [r for r in self.completed if r.t_arrive >= since]
-        lat = np.array([r.t_done - r.t_arrive for r in done])
         out: Dict[str, Any] = {"completed": len(done), "failed": self.failed,
                                "rejected_memory": self.rejected_memory,
                                "rejected_queue": self.rejected_queue, "rejected_cost": self.rejected_cost,
@@ -476,10 +590,11 @@ class Server:
                                "cancelled": self.cancelled,
                                "launches": self.launches, "merged": self.merged,
                                "max_inflight": self.max_inflight, "peak_bytes": self.peak_used}
-        if len(lat):
-            out.update(p50_ms=float(np.percentile(lat, 50) * 1e3),
-                       p99_ms=float(np.percentile(lat, 99) * 1e3),
-                       mean_ms=float(lat.mean() * 1e3))
+        allst = self._lat(done)
+        if allst["completed"]:
+            out.update(p50_ms=allst["p50_ms"], p99_ms=allst["p99_ms"], mean_ms=allst["mean_ms"])
+        out["whole"] = self._lat([r for r in done if not isinstance(r.part, dict)])
+        out["split"] = self._lat([r for r in done if isinstance(r.part, dict)])
         return out
 
 
@@ -592,17 +707,24 @@ class GraphExecutor:
         P, K, W = req.n_params, info["n_angles"], info["n_words"]
         if req.kind == "sample":
             chains = P * int(req.samples)
-            ws = g.workspace_size(req.dtype, chains, L.AC_OP_SAMPLE)
+            ws = self.ws_bytes(g, req.dtype, chains, L.AC_OP_SAMPLE, req.share)
             nwq = (info["n_qubits"] + 63) // 64
             io = chains * 8 * (nwq + 1) + P * K * 8
             if req.grad:
-                ws = max(ws, g.workspace_size(req.dtype, chains, L.AC_OP_GRAD))
+                ws = max(ws, self.ws_bytes(g, req.dtype, chains, L.AC_OP_GRAD, req.share))
                 io += chains * (8 * W + 4 + 8 + cs) + P * K * 8
             return ws + io
         B = padded_rows(req.n_rows, req.grad)
         op = L.AC_OP_GRAD if req.grad else L.AC_OP_EVAL
-        ws = g.workspace_size(req.dtype, B, op)
+        ws = self.ws_bytes(g, req.dtype, B, op, req.share)
         return ws + B * (8 * W + 4 + 8 + cs) + (P + 1) * K * 16
+
+    @staticmethod
+    def ws_bytes(g, dtype: str, batch: int, op: int, share: float) -> int:
+        """Workspace of a launch that may hold ``share`` of the device."""
+        if share >= 1.0:
+            return max(g.workspace_size(dtype, batch, op), 256)
+        return max(g.workspace_size_share(dtype, batch, op, share), 256)
 
     # device-time model for admission: a lone tile of 64 elements walks the DAG
     # level by level (latency per node step, with the 8- or 16-wave
@@ -618,22 +740,24 @@ class GraphExecutor:
         the per-step latency of the kernel the library picks for this many
         chains, once per group of chains it runs at once, or at the chip's
         node-step rate when that is slower; amplitudes: one pass per row,
-        three with a gradient."""
+        three with a gradient.  A launch on a share of the device runs
+        proportionally fewer chains or rows at once."""
         g = self.graphs[req.graph]
         info = g.info
         N = float(info["n_internal"])
+        share = min(1.0, float(req.share))
         if req.kind == "sample":
             chains = req.n_params * int(req.samples)
             steps = 3.0 * N * (req.burn_in + 1) * (info["n_qubits"] // 2 + 1)
             if req.grad:
                 steps += 3.0 * N
             kind, conc = g.sample_shape(req.dtype, chains)
-            groups = -(-chains // max(conc, 1))
+            groups = -(-chains // max(int(conc * share), 1))
             lat = groups * steps * self.NODE_STEP_LATENCY[kind]
-            return max(lat, chains * steps / self.NODE_STEP_RATE["sample"])
+            return max(lat, chains * steps / (self.NODE_STEP_RATE["sample"] * share))
         passes = 3.0 if req.grad else 1.0
         lat = passes * N * self.NODE_STEP_LATENCY["eval"]
-        return max(lat, req.n_rows * passes * N / self.NODE_STEP_RATE["eval"])
+        return max(lat, req.n_rows * passes * N / (self.NODE_STEP_RATE["eval"] * share))
 
     def resident_bytes(self) -> int:
         """Device bytes of the resident session chains."""
@@ -807,7 +931,7 @@ class GraphExecutor:
         P, S = r.n_params, int(r.samples)
         theta = self._to_dev(np.asarray(r.theta, dtype=np.float64).reshape(P, -1), torch.float64)
         chains = P * S
-        ws = torch.empty(max(g.workspace_size(r.dtype, chains, L.AC_OP_SAMPLE), 256), dtype=torch.uint8,
+        ws = torch.empty(self.ws_bytes(g, r.dtype, chains, L.AC_OP_SAMPLE, r.share), dtype=torch.uint8,
                          device=self.device)
         edges = self.edges.get(r.graph)
         init, first = None, 0
@@ -841,7 +965,7 @@ class GraphExecutor:
             # (combined with the leave-one-out baseline once all of a set's samples are in)
             states = res["states"].reshape(chains, -1)
             param_of = torch.arange(P, dtype=torch.int32, device=self.device).repeat_interleave(S)
-            gws = torch.empty(max(g.workspace_size(r.dtype, chains, L.AC_OP_GRAD), 256), dtype=torch.uint8,
+            gws = torch.empty(self.ws_bytes(g, r.dtype, chains, L.AC_OP_GRAD, r.share), dtype=torch.uint8,
                               device=self.device)
             ones = torch.ones(chains, dtype=torch.float64, device=self.device)
             ga = g.grad(theta, states, param_of, mode="logprob", weight=res["cost"].reshape(-1), dtype=r.dtype,
@@ -864,14 +988,14 @@ class GraphExecutor:
         keep += [d_theta, d_ev, d_po]
         if head.grad:
             d_w = self._to_dev(wt, torch.float64)
-            ws = torch.empty(max(g.workspace_size(head.dtype, len(po), L.AC_OP_GRAD), 256), dtype=torch.uint8,
+            ws = torch.empty(self.ws_bytes(g, head.dtype, len(po), L.AC_OP_GRAD, head.share), dtype=torch.uint8,
                              device=self.device)
             res = g.grad(d_theta, d_ev, d_po, mode="prob", weight=d_w, dtype=head.dtype, want_amp=True,
                          validate=False, ws=ws)
             keep += [d_w, ws, res]
             host = {"amp": self._to_host(res["amp"]), "grad": self._to_host(res["grad"])}
         else:
-            ws = torch.empty(max(g.workspace_size(head.dtype, len(po), L.AC_OP_EVAL), 256), dtype=torch.uint8,
+            ws = torch.empty(self.ws_bytes(g, head.dtype, len(po), L.AC_OP_EVAL, head.share), dtype=torch.uint8,
                              device=self.device)
             amp, prob = g.eval(d_theta, d_ev, d_po, dtype=head.dtype, validate=False, ws=ws)
             keep += [ws, amp, prob]

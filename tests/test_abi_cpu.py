@@ -94,6 +94,7 @@ def test_null_arguments_are_rejected():
     assert lib.ac_free(None) == L.AC_OK
     assert lib.ac_info(None, None) == L.AC_ERR_INVALID_ARG
     assert lib.ac_workspace_size(None, 0, 10, 0) == 0
+    assert lib.ac_workspace_size_share(None, 0, 10, 0, 0.5) == 0
     assert lib.ac_eval_batch(None, 0, None, 1, None, None, None, 1, None, None, None, 0, None) == L.AC_ERR_INVALID_ARG
     assert "null graph" in lib.ac_last_error().decode()
     assert lib.ac_grad_batch(None, 0, None, 1, None, None, None, 1, 0, None, None, None, None, None,

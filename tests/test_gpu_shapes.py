@@ -78,3 +78,53 @@ def test_lds_sampler_same_chains_on_one_or_four_waves(dtype, monkeypatch):
         out = g.sample(theta, 150, 2, 3, 1, 7, dtype=dtype, want_states=True, want_rounds=True)
         outs.append((out["states"].cpu(), out["rounds"].cpu()))
     assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+
+
+def test_a_smaller_workspace_runs_fewer_workgroups_with_the_same_results():
+    # the grid shrinks to the per-workgroup regions the workspace holds; each
+    # element and chain is computed alone, so results do not change
+    from paper_2103_17226_amd import _lib as L
+    note("eval, gradients and both row-buffer samplers with 1/2, 1/7 and one workgroup's workspace")
+    circ = W.config(2, small=True)["circuit"]
+    g = graph(circ)
+    theta, ev, po, w = _inputs(circ, 64 * 9 + 5, 8)
+    B = ev.shape[0]
+
+    def sizes(op, batch):
+        full = g.workspace_size("c64", batch, op)
+        return [full, full // 2, full // 7]
+    ref = None
+    for n in sizes(L.AC_OP_EVAL, B):
+        ws = torch.empty(n, dtype=torch.uint8, device="cuda")
+        amp, prob = g.eval(theta, ev, po, dtype="c64", ws=ws)
+        got = (amp.cpu(), prob.cpu())
+        ref = got if ref is None else ref
+        assert all(torch.equal(a, b) for a, b in zip(got, ref)), n
+    ref = None
+    for n in sizes(L.AC_OP_GRAD, B):
+        ws = torch.empty(n, dtype=torch.uint8, device="cuda")
+        out = g.grad(theta, ev, po, mode="prob", weight=w, dtype="c64", ws=ws)
+        got = out["grad"].cpu()
+        ref = got if ref is None else ref
+        assert torch.equal(got, ref), n
+    th = np.array([[0.7, 0.4], [2.2, 1.3], [0.1, 2.9]])
+    for kernel in ("stream", "global"):
+        import os
+        os.environ["QKC_SAMPLE_KERNEL"] = kernel
+        try:
+            gk = graph(circ)
+            ref = None
+            full = gk.workspace_size("c64", 3 * 400, L.AC_OP_SAMPLE)
+            for n in (full, full // 2, full // 7):
+                ws = torch.empty(n, dtype=torch.uint8, device="cuda")
+                out = gk.sample(th, 400, 1, 3, 1, 17, dtype="c64", want_states=True, want_rounds=True, ws=ws)
+                got = (out["samples"].cpu(), out["states"].cpu(), out["rounds"].cpu())
+                ref = got if ref is None else ref
+                assert all(torch.equal(a, b) for a, b in zip(got, ref)), (kernel, n)
+            gk.close()
+        finally:
+            del os.environ["QKC_SAMPLE_KERNEL"]
+    too_small = torch.empty(256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(L.ACError):
+        g.eval(theta, ev, po, dtype="c64", ws=too_small)
+    g.close()

@@ -403,6 +403,7 @@ class SplitExecutor(FakeExecutor):
     def launch(self, batch, stream):
         h = super().launch(batch, stream)
         h["end"] = self.clock() + max(float(r.samples) for r in batch)
+        self.kinds = getattr(self, "kinds", []) + [(r.parent is not None, stream, r.share) for r in batch]
         return h
 
     def results(self, h):
@@ -599,3 +600,101 @@ def test_parts_of_a_split_request_leave_streams_for_others():
     assert [r for r in srv.queue if r.parent is None] == []
     run_until_idle(srv, clock)
     assert big.result() == [float(u) for u in range(6)] and small.result() == [50.0]
+
+
+def test_whole_requests_keep_their_streams_while_a_long_request_runs():
+    # a request of 12 one-second units is split into twelve parts on the one
+    # stream kept for parts; one-second whole requests arriving meanwhile
+    # use the other stream and finish within a second or two of arriving
+    clock = Clock()
+    ex = SplitExecutor(clock, n_streams=2)
+    srv = Server(ex, mem_budget=1000, clock=clock, max_seconds=1.0, part_streams=1, part_share=0.5)
+    big = srv.submit(req(10, 0.0, val=0, samples=12))
+    smalls = []
+    for k in range(8):
+        clock.t = float(k)
+        smalls.append(srv.submit(req(10, 0.0, val=100 + k, samples=1)))
+        srv.step()
+        clock.t += 0.5
+        srv.step()
+    run_until_idle(srv, clock)
+    assert big.result() == [float(u) for u in range(12)]
+    assert [f.result() for f in smalls] == [[100.0 + k] for k in range(8)]
+    st = srv.latency_stats()
+    assert st["whole"]["completed"] == 8 and st["split"]["completed"] == 1
+    assert st["whole"]["p99_ms"] <= 1500.0
+    assert st["split"]["p50_ms"] >= 12000.0
+    parts = [(stream, share) for is_part, stream, share in ex.kinds if is_part]
+    wholes = [stream for is_part, stream, _ in ex.kinds if not is_part]
+    assert len(parts) == 12 and all(share == 0.5 for _, share in parts)
+    assert len(wholes) == 8 and srv.parts_inflight == 0
+
+
+def test_parts_carry_their_share_and_split_requests_have_their_own_limit():
+    clock = Clock()
+    ex = SplitExecutor(clock, n_streams=4)
+    srv = Server(ex, mem_budget=1000, clock=clock, max_seconds=2.0, max_split=2, part_share=0.25, max_queue=1)
+    a = srv.submit(req(10, 0.0, val=0, samples=5))
+    b = srv.submit(req(10, 0.0, val=0, samples=5))
+    c = srv.submit(req(10, 0.0, val=0, samples=5))             # a third split request: refused
+    w = srv.submit(req(10, 0.0, val=3, samples=1))             # the whole-request queue is not full of parts
+    with pytest.raises(AdmissionError):
+        c.result(timeout=0)
+    assert srv.rejected_queue == 1 and len(srv.queue) == 1 and len(srv.split_queue) == 2
+    assert all(u.share == 0.25 for p in srv.split_queue for u in p.part["todo"])
+    run_until_idle(srv, clock)
+    assert a.result() == b.result() == [float(u) for u in range(5)] and w.result() == [3.0]
+    d = srv.submit(req(10, 0.0, val=0, samples=5))             # room again once they completed
+    run_until_idle(srv, clock)
+    assert d.result() == [float(u) for u in range(5)] and srv.split_active == 0
+
+
+def test_a_split_request_is_cancelled_only_before_its_first_part():
+    clock = Clock()
+    ex = SplitExecutor(clock, n_streams=1)
+    srv = Server(ex, mem_budget=1000, clock=clock, max_seconds=1.0)
+    first = srv.submit(req(10, 0.0, val=0, samples=3))
+    second = srv.submit(req(10, 0.0, val=0, samples=3))
+    srv.step()                                                  # the first part of `first` launches
+    assert not srv.cancel(first)
+    assert srv.cancel(second) and second.cancelled()
+    run_until_idle(srv, clock)
+    assert first.result() == [0.0, 1.0, 2.0] and srv.split_active == 0
+
+
+def test_split_requests_go_shortest_first_and_a_full_backlog_refuses_more():
+    clock = Clock()
+    ex = SplitExecutor(clock, n_streams=1)
+    srv = Server(ex, mem_budget=1000, clock=clock, max_seconds=1.0, split_backlog=10.0)
+    long_ = srv.submit(req(10, 0.0, val=0, samples=8))         # admitted: nothing was waiting
+    short = srv.submit(req(10, 0.0, val=0, samples=2))         # 8 s waiting < 10 s: admitted
+    more = srv.submit(req(10, 0.0, val=0, samples=3))          # 10 s waiting: refused
+    with pytest.raises(AdmissionError):
+        more.result(timeout=0)
+    run_until_idle(srv, clock)
+    assert short.result() == [0.0, 1.0] and long_.result() == [float(u) for u in range(8)]
+    done = {id(r.future): r.t_done for r in srv.completed}
+    assert done[id(short)] < done[id(long_)]                    # the short one did not wait for the long one
+    assert srv.rejected_queue == 1
+    # a lone request larger than the backlog limit is still admitted
+    huge = srv.submit(req(10, 0.0, val=0, samples=30))
+    run_until_idle(srv, clock, limit=5000)
+    assert huge.result() == [float(u) for u in range(30)]
+
+
+def test_an_old_split_request_is_not_starved_by_shorter_ones():
+    # ageing: each second waited counts as one second less of work left
+    clock = Clock()
+    ex = SplitExecutor(clock, n_streams=1)
+    srv = Server(ex, mem_budget=1000, clock=clock, max_seconds=1.0, max_split=100, split_backlog=1e9)
+    old = srv.submit(req(10, 0.0, val=0, samples=6))
+    shorts = []
+    for k in range(40):                                         # a 2-unit request every 2 s
+        clock.t = 2.0 * k
+        shorts.append(srv.submit(req(10, 0.0, val=0, samples=2)))
+        for _ in range(4):
+            srv.step()
+            clock.t += 0.5
+    run_until_idle(srv, clock, limit=5000)
+    t_old = next(r.t_done for r in srv.completed if r.future is old)
+    assert t_old < 40.0

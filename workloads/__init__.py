@@ -482,7 +482,9 @@ def serving_requests(pool: Sequence[Circuit], rate: float, duration: float, seed
     request over ``eval_rows`` uniform outputs x with every noise event at
     its first value (k = 0) per parameter set, else S ~
     log-uniform{1..max_samples} samples per parameter set; a gradient with
-    probability ``p_grad`` (for amplitude requests: of sum_b C(x_b) |f_b|^2).
+    probability ``p_grad`` (for amplitude requests: of sum_b C(x_b) |f_b|^2;
+    a sampled gradient needs two samples per set for its leave-one-out
+    baseline, so its S is drawn from {2..max_samples}).
     """
     seed = sub_seed("arrivals", 5) if seed is None else seed
     rng = np.random.default_rng(seed)
@@ -507,5 +509,7 @@ def serving_requests(pool: Sequence[Circuit], rate: float, duration: float, seed
             r["weight"] = maxcut_cost(circ.edges, vals[:, :circ.n]).astype(np.float64)
         else:
             r["samples"] = int(log_uniform_int(rng, max_samples))
+            if grad and r["samples"] < 2:
+                r["samples"] = 1 + int(log_uniform_int(rng, max_samples - 1))
         out.append(r)
     return out
