@@ -196,10 +196,15 @@ def serve_run(graphs, pool, rate, args):
     srv.start()
     t0 = time.perf_counter()
     futs = []
+    next_note = 10.0
     for r in reqs:
         delay = t0 + r["t"] - time.perf_counter()
         if delay > 0:
             time.sleep(delay)
+        if r["t"] >= next_note:
+            print(f"#   t={r['t']:.0f} s: {len(futs)} submitted, {len(srv.completed)} completed", file=sys.stderr,
+                  flush=True)
+            next_note += 10.0
         q = Request(graph=pool[r["circuit"]].name, theta=r["theta"], evidence=r.get("evidence"),
                     param_of=r.get("param_of"), weight=r.get("weight"), samples=r["samples"], grad=r["grad"],
                     burn_in=10, seed=r["seed"])
@@ -207,6 +212,7 @@ def serve_run(graphs, pool, rate, args):
         futs.append(q)
     t_end = time.perf_counter()
     srv.stop(drain=True, timeout=args.serve_drain)
+    print(f"#   drained: {len(srv.completed)} completed", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     since = t0 + warmup
     st = srv.latency_stats(since=since)

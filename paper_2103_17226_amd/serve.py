@@ -90,6 +90,8 @@ class Request:
     session: Optional[str] = None
     chain_offset: int = 0                    # RNG number of the first chain (parts of a split request)
     share: float = 1.0                       # fraction of the device a launch may hold (parts: less)
+    first_sweep: int = 0                     # sweep number of the first sweep (a part resuming chains)
+    after: int = -1                          # index of the part whose chains this part resumes
     # filled in by the server
     rid: int = -1
     t_arrive: float = 0.0
@@ -325,6 +327,8 @@ class Server:
                         par.part["costs"].clear()
                         if par in self.split_queue:
                             self.split_queue.remove(par)
+                    if hasattr(self.ex, "discard"):
+                        self.ex.discard(par)
                     if not par.future.done():
                         par.future.set_exception(exc)
                 continue
@@ -420,11 +424,22 @@ class Server:
         """Estimated device seconds of the parts still waiting."""
         return sum(sum(p.part["costs"]) for p in self.split_queue if not p.part["failed"])
 
+    @staticmethod
+    def _part_ready(par) -> bool:
+        """The next part of a split request can launch: the part whose
+        chains it resumes, if any, has completed."""
+        u = par.part["todo"][0]
+        return u.after < 0 or par.part["outs"][u.after] is not None
+
     def _next_split(self):
-        """The split request whose parts go next: least estimated work left,
-        less the seconds it has waited (shortest first, with ageing)."""
+        """The split request whose parts go next, among those whose next
+        part is ready: least estimated work left, less the seconds it has
+        waited (shortest first, with ageing); None if none is ready."""
         now = self.clock()
-        return min(self.split_queue, key=lambda p: (sum(p.part["costs"]) - (now - p.t_arrive), p.rid))
+        ready = [p for p in self.split_queue if self._part_ready(p)]
+        if not ready:
+            return None
+        return min(ready, key=lambda p: (sum(p.part["costs"]) - (now - p.t_arrive), p.rid))
 
     def _take_part(self, resident: int):
         """The next part of a split request (``_next_split``), if a stream
@@ -435,6 +450,8 @@ class Server:
             if not self.split_queue:
                 break
             par = self._next_split()
+            if par is None:
+                return None
             st = par.part
             u = st["todo"][0]
             if self.used + resident + u.footprint > self.budget:
@@ -448,6 +465,8 @@ class Server:
                     st["failed"] = True
                     self.split_active -= 1
                     self.rejected_memory += 1
+                    if hasattr(self.ex, "discard"):
+                        self.ex.discard(par)
                     if not par.future.done():
                         par.future.set_exception(AdmissionError(
                             f"part needs {u.footprint} bytes next to {resident} bytes of resident session "
@@ -478,7 +497,7 @@ class Server:
         got = self._take_part(resident)
         if got is not None:
             return got
-        waiting_parts = any(not p.part["failed"] and p.part["todo"] for p in self.split_queue)
+        waiting_parts = any(not p.part["failed"] and p.part["todo"] and self._part_ready(p) for p in self.split_queue)
         keep_free = max(0, self.part_streams - self.parts_inflight) if waiting_parts else 0
         if not self.queue or len(self.free_streams) <= keep_free:
             return None
@@ -687,6 +706,7 @@ class GraphExecutor:
         self.device = torch.device("cuda", device)
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(self.n_streams)]
         self.sessions = {}        # (graph, session) -> [states [P*S, W] int64 on device, next sweep, P, S, last use]
+        self._carry = {}          # (split request id, p0, c0) -> chain states between slices of its sweeps
         self._sess_lock = threading.Lock()
         self._uses = itertools.count()
         self.edges = {}
@@ -799,12 +819,14 @@ class GraphExecutor:
     def split(self, req: Request, limit: float, max_bytes: Optional[int] = None):
         """Parts of a request whose device time would exceed ``limit``: whole
         parameter sets per part while they fit, else slices of one set's
-        chains (sampling) or evidence rows (amplitudes).  When one chain or
-        row alone is over the limit (a large circuit), the limit becomes that
-        one unit's time, so a part holds what the device runs in that time
-        anyway (a group of concurrent chains) rather than being refused.
-        With ``max_bytes`` a part's device footprint stays within it too.
-        None if no part fits."""
+        chains (sampling) or evidence rows (amplitudes), else (sampling)
+        slices of the sweeps of a group of chains, each part resuming the
+        chains of the part before it (``after``).  When one unit alone -- one
+        sweep of one chain, one evidence row -- is over the limit (a large
+        circuit), the limit becomes that unit's time, so a part holds what
+        the device runs in that time anyway rather than being refused.  With
+        ``max_bytes`` a part's device footprint stays within it too.  None if
+        no part fits."""
         cap = float("inf") if max_bytes is None else max_bytes
 
         def ok(u, lim):
@@ -814,19 +836,36 @@ class GraphExecutor:
         parts = []
         if req.kind == "sample":
             S = int(req.samples)
+            sweeps = int(req.burn_in) + 1
 
-            def part(p0, p1, c0, c1):
-                return Request(graph=req.graph, theta=th[p0:p1], samples=c1 - c0, grad=req.grad,
-                               burn_in=req.burn_in, seed=req.seed, dtype=req.dtype,
-                               chain_offset=req.chain_offset + p0 * S + c0, part=("sample", p0, p1, c0, c1))
-            limit = max(limit, self.cost(part(0, 1, 0, 1)) * (1.0 + 1e-9))
+            def part(p0, p1, c0, c1, s0=0, s1=sweeps):
+                return Request(graph=req.graph, theta=th[p0:p1], samples=c1 - c0, grad=req.grad and s1 == sweeps,
+                               burn_in=s1 - s0 - 1, seed=req.seed, dtype=req.dtype, first_sweep=s0,
+                               chain_offset=req.chain_offset + p0 * S + c0,
+                               part=("sample", p0, p1, c0, c1, s0, s1))
+            limit = max(limit, self.cost(part(0, 1, 0, 1, 0, 1)) * (1.0 + 1e-9))
             pc = self._largest(lambda k: ok(part(0, k, 0, S), limit), P)
             if pc:
                 return [part(p0, min(P, p0 + pc), 0, S) for p0 in range(0, P, pc)]
             sc = self._largest(lambda k: ok(part(0, 1, 0, k), limit), S)
-            if not sc:
+            if sc:
+                return [part(p, p + 1, c0, min(S, c0 + sc)) for p in range(P) for c0 in range(0, S, sc)]
+            # one group of chains runs longer than the limit (a large circuit):
+            # its sweeps in slices, each resuming the chains where the slice
+            # before it left them (the same chains as one call)
+            cb = self._largest(lambda k: ok(part(0, 1, 0, k, 0, 1), limit), S)
+            if not cb:
                 return None
-            return [part(p, p + 1, c0, min(S, c0 + sc)) for p in range(P) for c0 in range(0, S, sc)]
+            ns = max(1, self._largest(lambda k: ok(part(0, 1, 0, cb, 0, k), limit), sweeps))
+            for p in range(P):
+                for c0 in range(0, S, cb):
+                    prev = -1
+                    for s0 in range(0, sweeps, ns):
+                        u = part(p, p + 1, c0, min(S, c0 + cb), s0, min(sweeps, s0 + ns))
+                        u.after = prev
+                        prev = len(parts)
+                        parts.append(u)
+            return parts
         po = np.zeros(req.n_rows, dtype=np.int64) if req.param_of is None else np.asarray(req.param_of, np.int64)
         ev = np.asarray(req.evidence, dtype=np.uint64)
         wt = None if req.weight is None else np.asarray(req.weight, dtype=np.float64)
@@ -871,13 +910,15 @@ class GraphExecutor:
         P, K = req.n_params, np.asarray(req.theta).reshape(req.n_params, -1).shape[1]
         if req.kind == "sample":
             S = int(req.samples)
-            first = outs[0]
+            first = next(o for o in outs if "samples" in o)
             samples = np.zeros((P, S) + first["samples"].shape[2:], dtype=first["samples"].dtype)
             cost = np.zeros((P, S)) if "cost" in first else None
             A = np.zeros((P, K)) if req.grad else None
             G = np.zeros((P, K)) if req.grad else None
             for u, o in zip(req.part["descs"], outs):
-                _, p0, p1, c0, c1 = u
+                _, p0, p1, c0, c1, s0, s1 = u
+                if s1 < int(req.burn_in) + 1:
+                    continue                       # an earlier slice of these chains' sweeps
                 samples[p0:p1, c0:c1] = o["samples"].reshape((p1 - p0, c1 - c0) + samples.shape[2:])
                 if cost is not None:
                     cost[p0:p1, c0:c1] = o["cost"].reshape(p1 - p0, c1 - c0)
@@ -936,19 +977,34 @@ class GraphExecutor:
         edges = self.edges.get(r.graph)
         init, first = None, 0
         key = (r.graph, r.session)
+        carry = None
+        if r.parent is not None and r.part[1][0] == "sample":
+            _, p0, _, c0, _, s0, s1 = r.part[1]
+            carry = (r.parent.rid, p0, c0, s1 < int(r.parent.burn_in) + 1)
+            if s0 > 0:
+                with self._sess_lock:
+                    init = self._carry.pop((r.parent.rid, p0, c0))
+                first = s0
         if r.session is not None:
             with self._sess_lock:
                 prev = self.sessions.get(key)
             if prev is not None and prev[2] == P and prev[3] == S:
                 init, first = prev[0], prev[1]
                 prev[4] = next(self._uses)
+        more = carry is not None and carry[3]       # later slices resume these chains
         res = g.sample(theta, chains_per_param=S, samples_per_chain=1, burn_in=r.burn_in, thin=1,
-                       seed=r.seed, cost_edges=edges, dtype=r.dtype, want_cost=edges is not None,
-                       want_states=r.grad or r.session is not None, validate=False, ws=ws,
+                       seed=r.seed, cost_edges=edges, dtype=r.dtype, want_cost=edges is not None and not more,
+                       want_states=r.grad or r.session is not None or more, validate=False, ws=ws,
                        init_states=init, first_sweep=first, chain_offset=r.chain_offset)
         keep += [theta, ws, res]
         if init is not None:
             keep.append(init)      # read on this stream: live until the launch completes
+        if more:
+            # the next slice is launched only after this one completes (the
+            # scheduler orders them), so the states are final by then
+            with self._sess_lock:
+                self._carry[carry[:3]] = res["states"].reshape(chains, -1)
+            return ("sample", {})
         if r.session is not None:
             # the chains' last states stay on the device for the next request
             with self._sess_lock:
@@ -1001,6 +1057,12 @@ class GraphExecutor:
             keep += [ws, amp, prob]
             host = {"amp": self._to_host(amp), "prob": self._to_host(prob)}
         return ("eval", host, spans)
+
+    def discard(self, req: Request):
+        """Drop what a failed split request left on the device."""
+        with self._sess_lock:
+            for k in [k for k in self._carry if k[0] == req.rid]:
+                del self._carry[k]
 
     # ---------------------------------------------------------- completion
     def done(self, handle) -> bool:

@@ -113,7 +113,8 @@ def test_split_requests_equal_the_whole_request():
     n_over = sum(ex.cost(_request(k, r)) > limit for k, r in reqs)
     note(f"serve split: limit {limit:.3g} s, {n_over} of {len(reqs)} requests over it")
     assert n_over >= 1
-    srv = Server(ex, mem_budget=8 << 30, max_merge=16, max_seconds=limit)
+    srv = Server(ex, mem_budget=8 << 30, max_merge=16, max_seconds=limit, max_split=len(reqs),
+                 split_backlog=float("inf"), part_streams=2, part_share=0.5)
     futs = [srv.submit(_request(k, r)) for k, r in reqs]
     srv.start()
     try:
@@ -125,6 +126,44 @@ def test_split_requests_equal_the_whole_request():
     assert st["completed"] == len(reqs) and st["rejected_cost"] == 0 and st["split_requests"] == n_over
     for i, ((k, r), got, want) in enumerate(zip(reqs, results, plain)):
         _same(got, want, f"request {i} on {k} (samples={r['samples']}, grad={r['grad']})")
+
+
+def test_sweep_slices_resume_the_same_chains():
+    # a limit below one chain's full run: sampling requests are cut into
+    # slices of their sweeps, each resuming the chain states the slice before
+    # it left on the device; samples, costs and sampled gradients equal the
+    # whole request's
+    from paper_2103_17226_amd.serve import GraphExecutor, Request, Server
+    circs = _pool()
+    name = sorted(circs)[2]
+    circ = circs[name]
+    g = graph(circ)
+    ex = GraphExecutor({name: g}, {name: circ.edges}, n_streams=3)
+    rng = np.random.default_rng(31)
+    reqs = [dict(theta=rng.uniform(0, 2 * np.pi, size=(P, circ.n_angles)), samples=S, grad=gr, seed=s,
+                 evidence=None, param_of=None, weight=None)
+            for P, S, gr, s in ((2, 300, True, 5), (1, 700, False, 6), (3, 64, True, 7))]
+    plain = [_plain(g, circ, r) for r in reqs]
+    torch.cuda.synchronize()
+    one_sweep = ex.cost(Request(graph=name, theta=reqs[0]["theta"][:1], samples=1, burn_in=0))
+    limit = 2.5 * one_sweep
+    srv = Server(ex, mem_budget=8 << 30, max_seconds=limit, max_split=8, split_backlog=float("inf"),
+                 part_streams=2, part_share=0.5)
+    qs = [_request(name, r) for r in reqs]
+    for q in qs:
+        parts = ex.split(q, limit)
+        assert parts and any(u.part[5] > 0 for u in parts), "no sweep slices"
+    futs = [srv.submit(q) for q in qs]
+    srv.start()
+    try:
+        results = [f.result(timeout=300) for f in futs]
+    finally:
+        srv.stop()
+    st = srv.latency_stats()
+    note(f"serve sweep slices: limit {limit:.3g} s, {st['split_parts']} parts")
+    assert st["completed"] == len(reqs) and not ex._carry
+    for i, (got, want) in enumerate(zip(results, plain)):
+        _same(got, want, f"request {i}")
 
 
 def test_served_equals_alone_in_a_mixed_stream():

@@ -550,7 +550,8 @@ def test_graph_executor_splits_cover_the_request_exactly():
         assert any(u.part[4] - u.part[3] < S for u in parts) == by_chains
         covered = np.zeros((P, S), dtype=int)
         for u in parts:
-            _, p0, p1, c0, c1 = u.part
+            _, p0, p1, c0, c1, s0, s1 = u.part
+            assert (s0, s1) == (0, r.burn_in + 1) and u.after == -1
             covered[p0:p1, c0:c1] += 1
             assert u.chain_offset == 11 + p0 * S + c0 and u.samples == c1 - c0
             assert np.array_equal(u.theta, r.theta[p0:p1])
@@ -562,12 +563,24 @@ def test_graph_executor_splits_cover_the_request_exactly():
     assert parts and all(ex.footprint(u) <= 2 * ex.footprint(Request(graph="g", theta=np.zeros((1, 2)),
                                                                          samples=1000)) for u in parts)
     assert sum(u.samples * (u.part[2] - u.part[1]) for u in parts) == 27000
-    # a limit below one chain's time: parts of one group of concurrent chains, none refused
-    big = Request(graph="g", theta=np.zeros((3, 2)), samples=9000, grad=False)
-    one = Request(graph="g", theta=np.zeros((1, 2)), samples=1)
-    parts = ex.split(big, ex.cost(one) / 10)
-    assert parts and all(u.samples <= 4096 for u in parts) and sum(u.samples for u in parts) == 27000
-    assert all(ex.cost(u) <= ex.cost(one) * (1 + 1e-6) for u in parts)
+    # a limit below one chain's time: slices of the sweeps of one group of
+    # concurrent chains, each resuming the slice before it, none refused
+    big = Request(graph="g", theta=np.zeros((3, 2)), samples=9000, grad=True, burn_in=10)
+    one = Request(graph="g", theta=np.zeros((1, 2)), samples=1, burn_in=10)
+    parts = ex.split(big, ex.cost(one) / 4)
+    assert parts
+    assert all(ex.cost(u) <= ex.cost(one) / 4 for u in parts if not u.grad)
+    sweeps = {}
+    for k, u in enumerate(parts):
+        _, p0, p1, c0, c1, s0, s1 = u.part
+        assert p1 == p0 + 1 and u.first_sweep == s0 and u.burn_in == s1 - s0 - 1
+        assert u.grad == (s1 == 11)
+        chain = sweeps.setdefault((p0, c0, c1), [])
+        assert u.after == (-1 if not chain else chain[-1][2])
+        chain.append((s0, s1, k))
+    for (p0, c0, c1), sl in sweeps.items():
+        assert sl[0][0] == 0 and sl[-1][1] == 11 and all(a[1] == b[0] for a, b in zip(sl, sl[1:]))
+    assert sum(c1 - c0 for p0, c0, c1 in sweeps) == 27000 and len(parts) > len(sweeps)
     # amplitudes: rows of each parameter set go to the parts that hold it
     # (whole sets while they fit, else slices of one set's rows)
     B = 40000
@@ -698,3 +711,26 @@ def test_an_old_split_request_is_not_starved_by_shorter_ones():
     run_until_idle(srv, clock, limit=5000)
     t_old = next(r.t_done for r in srv.completed if r.future is old)
     assert t_old < 40.0
+
+
+def test_resuming_parts_wait_for_the_part_they_resume():
+    # two blocks of chains, each in two sweep slices; a slice launches only
+    # after the slice whose chain states it resumes has completed
+    clock = Clock()
+
+    class SliceExecutor(SplitExecutor):
+        def split(self, req, limit, max_bytes=None):
+            out = []
+            for k in range(4):
+                u = Request(graph=req.graph, theta=req.theta, samples=1, part=(k, k + 1))
+                u.after = k - 1 if k % 2 else -1
+                out.append(u)
+            return out
+    ex = SliceExecutor(clock, n_streams=4)
+    srv = Server(ex, mem_budget=1000, clock=clock, max_seconds=1.0, part_streams=2)
+    f = srv.submit(req(10, 0.0, val=0, samples=4))
+    run_until_idle(srv, clock, dt=0.25)
+    assert f.result() == [0.0, 1.0, 2.0, 3.0]
+    start = {rids[0]: t for rids, _, t in ex.launched}
+    rid = sorted(start)
+    assert start[rid[1]] >= start[rid[0]] + 1.0 and start[rid[3]] >= start[rid[2]] + 1.0
