@@ -17,11 +17,15 @@ def test_more_than_one_gpu_is_refused_with_a_message():
     assert msg["n_gpus_requested"] == 2 and "one GPU" in msg["error"]
 
 
-def test_profiled_traffic_is_reported_only_for_the_profiled_kernel_and_workload():
-    for name in bench.PROFILED_TRAFFIC:
-        assert bench.profiled_traffic(name, default_workload=False) is None
-        got = bench.profiled_traffic(name, default_workload=True)
-        # the table is keyed by the kernel source hash: a stale entry reads None
-        assert got is None or got == bench.PROFILED_TRAFFIC[name]["bytes"]
-        assert os.path.exists(os.path.join(ROOT, bench.PROFILED_TRAFFIC[name]["profile"]))
-    assert bench.profiled_traffic("no_such_kernel", default_workload=True) is None
+def test_profiled_traffic_is_reported_only_for_the_profiled_kernel_ac_and_workload():
+    for name, ent in bench.PROFILED_TRAFFIC.items():
+        blob = b"an AC that was not profiled"
+        assert bench.profiled_traffic(name, False, blob) is None
+        assert bench.profiled_traffic(name, True, blob) is None
+        # keyed by the kernel source hash and the AC's hash: a stale entry reads None
+        assert bench.kernel_sha16() != ent["kernel_sha256_16"] or ent["bytes"] > 0
+        assert os.path.exists(os.path.join(ROOT, ent["profile"]))
+        with open(os.path.join(ROOT, ent["profile"])) as f:
+            text = f.read()
+        assert ent["kernel_sha256_16"] in text and ent["ac_sha256_16"] in text
+    assert bench.profiled_traffic("no_such_kernel", True, b"") is None
