@@ -202,8 +202,8 @@ def serve_run(graphs, pool, rate, args):
         if delay > 0:
             time.sleep(delay)
         if r["t"] >= next_note:
-            print(f"#   t={r['t']:.0f} s: {len(futs)} submitted, {len(srv.completed)} completed", file=sys.stderr,
-                  flush=True)
+            print(f"#   t={r['t']:.0f} s ({time.perf_counter() - t0:.0f} s elapsed): {len(futs)} submitted, "
+                  f"{len(srv.completed)} completed", file=sys.stderr, flush=True)
             next_note += 10.0
         q = Request(graph=pool[r["circuit"]].name, theta=r["theta"], evidence=r.get("evidence"),
                     param_of=r.get("param_of"), weight=r.get("weight"), samples=r["samples"], grad=r["grad"],

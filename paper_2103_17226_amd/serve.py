@@ -90,6 +90,7 @@ class Request:
     session: Optional[str] = None
     chain_offset: int = 0                    # RNG number of the first chain (parts of a split request)
     share: float = 1.0                       # fraction of the device a launch may hold (parts: less)
+    est: float = 0.0                         # estimated device seconds (set by the server)
     first_sweep: int = 0                     # sweep number of the first sweep (a part resuming chains)
     after: int = -1                          # index of the part whose chains this part resumes
     # filled in by the server
@@ -195,64 +196,82 @@ class Server:
     # ------------------------------------------------------------------ API
     def submit(self, req: Request, t_arrive: Optional[float] = None) -> Future:
         """Queue a request; ``t_arrive`` (default: now) is when it arrived,
-        for callers that replay a schedule of arrivals."""
+        for callers that replay a schedule of arrivals.  A request that
+        cannot be admitted is refused at once, before any splitting work."""
         req.rid = next(self._ids)
         req.t_arrive = self.clock() if t_arrive is None else float(t_arrive)
         if req.kind == "sample" and req.grad and req.samples < 2:
-            self.rejected_invalid += 1
-            req.future.set_exception(AdmissionError(
-                "a sampled gradient needs at least 2 samples per parameter set (leave-one-out baseline)"))
+            return self._refuse(req, "invalid", "a sampled gradient needs at least 2 samples per parameter set "
+                                                "(leave-one-out baseline)")
+        req.est = float(self.ex.cost(req)) if self.max_seconds is not None else 0.0
+        over_time = self.max_seconds is not None and req.est > self.max_seconds
+        over_memory = False
+        if not over_time:
+            req.footprint = int(self.ex.footprint(req))
+            over_memory = req.footprint > self.budget
+        if not (over_time or over_memory):
+            with self.lock:
+                if len(self.queue) >= self.max_queue:
+                    return self._refuse(req, "queue", f"queue full ({self.max_queue} waiting)")
+                self.queue.append(req)
             return req.future
-        parts = None
-        over_time = self.max_seconds is not None and float(self.ex.cost(req)) > self.max_seconds
-        over_memory = int(self.ex.footprint(req)) > self.budget
-        if (over_time or over_memory) and hasattr(self.ex, "split") and req.session is None:
-            limit = self.max_seconds if self.max_seconds is not None else float("inf")
-            parts = self.ex.split(req, limit, max_bytes=self.budget)
-        if over_time and not parts and not over_memory:
-            self.rejected_cost += 1
-            req.future.set_exception(AdmissionError(
-                f"request would hold the device ~{float(self.ex.cost(req)):.3g} s, the limit is "
-                f"{self.max_seconds:.3g} s, and it cannot be split"))
-            return req.future
-        units = parts if parts else [req]
-        for u in units:
-            if parts:
-                u.share = self.part_share
+        if not hasattr(self.ex, "split") or req.session is not None:
+            if over_memory:
+                return self._refuse(req, "memory", f"request needs {req.footprint} bytes of device memory, "
+                                                   f"the budget is {self.budget}")
+            return self._refuse(req, "cost", f"request would hold the device ~{float(self.ex.cost(req)):.3g} s, "
+                                             f"the limit is {self.max_seconds:.3g} s, and it cannot be split")
+        with self.lock:
+            full = self._split_full()
+        if full:
+            return self._refuse(req, "queue", f"split queue full: {full}")
+        limit = self.max_seconds if self.max_seconds is not None else float("inf")
+        parts = self.ex.split(req, limit, max_bytes=self.budget)
+        if not parts:
+            if over_memory:
+                return self._refuse(req, "memory", f"request needs {req.footprint} bytes of device memory, "
+                                                   f"the budget is {self.budget}, and it cannot be split")
+            return self._refuse(req, "cost", f"request would hold the device ~{float(self.ex.cost(req)):.3g} s, "
+                                             f"the limit is {self.max_seconds:.3g} s, and it cannot be split")
+        costs = []
+        for u in parts:
+            u.share = self.part_share
             u.footprint = int(self.ex.footprint(u))
             if u.footprint > self.budget:
-                self.rejected_memory += 1
-                req.future.set_exception(AdmissionError(
-                    f"request needs {u.footprint} bytes of device memory, the budget is {self.budget}"))
-                return req.future
-        costs = [float(self.ex.cost(u)) for u in parts] if parts and self.max_seconds is not None else None
+                return self._refuse(req, "memory", f"a part needs {u.footprint} bytes of device memory, "
+                                                   f"the budget is {self.budget}")
+            costs.append(float(self.ex.cost(u)) if self.max_seconds is not None else 0.0)
         with self.lock:
-            if parts:
-                backlog = self._split_backlog()
-                if self.split_active >= self.max_split or backlog >= self.split_backlog:
-                    self.rejected_queue += 1
-                    req.future.set_exception(AdmissionError(
-                        f"split queue full ({self.split_active} split requests, ~{backlog:.3g} s of parts waiting)"))
-                    return req.future
-                req.part = {"n": len(parts), "done": 0, "outs": [None] * len(parts), "failed": False,
-                            "descs": [u.part for u in parts], "inflight": 0,
-                            "todo": collections.deque(parts),
-                            "costs": collections.deque(costs if costs is not None else [0.0] * len(parts))}
-                for k, u in enumerate(parts):
-                    u.rid = next(self._ids)
-                    u.t_arrive = req.t_arrive
-                    u.parent = req
-                    u.part = (k, u.part)
-                self.split_requests += 1
-                self.split_parts += len(parts)
-                self.split_active += 1
-                self.split_queue.append(req)
-                return req.future
-            if len(self.queue) >= self.max_queue:
-                self.rejected_queue += 1
-                req.future.set_exception(AdmissionError(f"queue full ({self.max_queue} waiting)"))
-                return req.future
-            self.queue.append(req)
+            full = self._split_full()
+            if full:
+                return self._refuse(req, "queue", f"split queue full: {full}")
+            req.part = {"n": len(parts), "done": 0, "outs": [None] * len(parts), "failed": False,
+                        "descs": [u.part for u in parts], "inflight": 0,
+                        "todo": collections.deque(parts), "costs": collections.deque(costs)}
+            for k, u in enumerate(parts):
+                u.rid = next(self._ids)
+                u.t_arrive = req.t_arrive
+                u.parent = req
+                u.part = (k, u.part)
+            self.split_requests += 1
+            self.split_parts += len(parts)
+            self.split_active += 1
+            self.split_queue.append(req)
+        return req.future
+
+    def _split_full(self) -> str:
+        """Why no further split request can be admitted now ("" if it can);
+        called with the lock held."""
+        if self.split_active >= self.max_split:
+            return f"{self.split_active} split requests"
+        backlog = self._split_backlog()
+        if backlog >= self.split_backlog:
+            return f"~{backlog:.3g} s of parts waiting"
+        return ""
+
+    def _refuse(self, req: Request, why: str, msg: str) -> Future:
+        setattr(self, "rejected_" + why, getattr(self, "rejected_" + why) + 1)
+        req.future.set_exception(AdmissionError(msg))
         return req.future
 
     def cancel(self, fut: Future) -> bool:
@@ -487,10 +506,12 @@ class Server:
 
     def _take_batch(self):
         """Pop the next launch if it fits; called with the lock held.  Parts
-        of split requests go first on the streams kept for them; of the
-        whole requests, the first whose session is idle leads (requests of a
-        busy session keep their place) and later requests never overtake it
-        for memory."""
+        of split requests go first on the streams kept for them.  Of the
+        whole requests whose session is idle (requests of a busy session
+        keep their place), the one with the least estimated device time less
+        the seconds it has waited leads -- shortest first, with ageing; in
+        arrival order without ``max_seconds`` -- and no other request
+        overtakes it for memory."""
         if not self.free_streams:
             return None
         resident = self.ex.resident_bytes() if hasattr(self.ex, "resident_bytes") else 0
@@ -501,10 +522,12 @@ class Server:
         keep_free = max(0, self.part_streams - self.parts_inflight) if waiting_parts else 0
         if not self.queue or len(self.free_streams) <= keep_free:
             return None
-        idx = next((k for k, r in enumerate(self.queue)
-                    if not (r.session is not None and (r.graph, r.session) in self.busy_sessions)), None)
-        if idx is None:
+        now = self.clock()
+        ready = [(r.est - (now - r.t_arrive), r.rid, k) for k, r in enumerate(self.queue)
+                 if not (r.session is not None and (r.graph, r.session) in self.busy_sessions)]
+        if not ready:
             return None
+        idx = min(ready)[2]
         head = self.queue[idx]
         if self.used + resident + head.footprint > self.budget:
             if self.used or self.inflight or self.launching:

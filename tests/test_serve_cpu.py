@@ -734,3 +734,27 @@ def test_resuming_parts_wait_for_the_part_they_resume():
     start = {rids[0]: t for rids, _, t in ex.launched}
     rid = sorted(start)
     assert start[rid[1]] >= start[rid[0]] + 1.0 and start[rid[3]] >= start[rid[2]] + 1.0
+
+
+def test_whole_requests_go_shortest_first_with_ageing():
+    clock = Clock()
+    ex = FakeExecutor(clock, n_streams=1)
+    srv = Server(ex, mem_budget=100, clock=clock, max_seconds=1.0)
+    a = srv.submit(req(10, 0.5, val=1))
+    srv.step()                                          # a holds the only stream
+    b = srv.submit(req(10, 0.9, val=2))
+    c = srv.submit(req(10, 0.1, val=3))
+    run_until_idle(srv, clock, dt=0.05)
+    order = [rids[0] for rids, _, _ in ex.launched]
+    ids = {id(f): r.rid for r in srv.completed for f in [r.future]}
+    assert order == [ids[id(a)], ids[id(c)], ids[id(b)]]
+    # ageing: a request that has waited longer than the difference goes first
+    clock.t = 100.0
+    d = srv.submit(req(10, 0.5, val=4))
+    srv.step()
+    old = srv.submit(req(10, 0.9, val=5), t_arrive=90.0)
+    new = srv.submit(req(10, 0.1, val=6))
+    run_until_idle(srv, clock, dt=0.05)
+    order = [rids[0] for rids, _, _ in ex.launched][3:]
+    ids = {id(r.future): r.rid for r in srv.completed}
+    assert order == [ids[id(d)], ids[id(old)], ids[id(new)]]
