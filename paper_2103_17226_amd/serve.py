@@ -135,9 +135,10 @@ class Server:
     at once; its memory and stream return when the device finishes.
 
     Split requests form a second class: at most ``max_split`` of them wait or
-    run at once, and one more is admitted only while the estimated device
-    time of the parts still waiting is below ``split_backlog`` seconds (a
-    request is never refused for its own size).  Their parts hold at most
+    run at once, and one more is admitted only if the estimated device time
+    of the parts still waiting, with its own, stays within ``split_backlog``
+    seconds, or if no part is waiting (a request is never refused for its
+    own size alone).  Their parts hold at most
     ``part_streams`` streams in total (kept free for them while parts wait);
     the next part comes from the split request with the least estimated work
     left, less the seconds it has waited; and each part runs on
@@ -222,7 +223,7 @@ class Server:
             return self._refuse(req, "cost", f"request would hold the device ~{float(self.ex.cost(req)):.3g} s, "
                                              f"the limit is {self.max_seconds:.3g} s, and it cannot be split")
         with self.lock:
-            full = self._split_full()
+            full = self._split_full(req.est)
         if full:
             return self._refuse(req, "queue", f"split queue full: {full}")
         limit = self.max_seconds if self.max_seconds is not None else float("inf")
@@ -242,7 +243,7 @@ class Server:
                                                    f"the budget is {self.budget}")
             costs.append(float(self.ex.cost(u)) if self.max_seconds is not None else 0.0)
         with self.lock:
-            full = self._split_full()
+            full = self._split_full(sum(costs))
             if full:
                 return self._refuse(req, "queue", f"split queue full: {full}")
             req.part = {"n": len(parts), "done": 0, "outs": [None] * len(parts), "failed": False,
@@ -259,13 +260,16 @@ class Server:
             self.split_queue.append(req)
         return req.future
 
-    def _split_full(self) -> str:
-        """Why no further split request can be admitted now ("" if it can);
-        called with the lock held."""
+    def _split_full(self, est: float) -> str:
+        """Why a split request of ``est`` estimated seconds cannot be
+        admitted now ("" if it can): the split class holds ``max_split``
+        requests, or its waiting parts and this one would exceed
+        ``split_backlog`` seconds -- unless nothing is waiting, so a request
+        is never refused for its own size alone.  Called with the lock held."""
         if self.split_active >= self.max_split:
             return f"{self.split_active} split requests"
         backlog = self._split_backlog()
-        if backlog >= self.split_backlog:
+        if backlog > 0.0 and backlog + est > self.split_backlog:
             return f"~{backlog:.3g} s of parts waiting"
         return ""
 
