@@ -77,7 +77,7 @@ typedef enum {
 typedef enum { AC_C64 = 0, AC_C128 = 1 } ac_dtype;
 
 /* Workspace kinds for ac_workspace_size. */
-typedef enum { AC_OP_EVAL = 0, AC_OP_GRAD = 1, AC_OP_SAMPLE = 2 } ac_op;
+typedef enum { AC_OP_EVAL = 0, AC_OP_GRAD = 1, AC_OP_SAMPLE = 2, AC_OP_MPE = 3 } ac_op;
 
 /* Loss forms for ac_grad_batch (the cotangent g_b of the root value f_b). */
 typedef enum {
@@ -340,6 +340,32 @@ ac_status ac_sample(const ac_graph *g, ac_dtype dtype,
                     uint64_t *samples, uint64_t *states_out, double *cost_out,
                     int64_t *rounds_out,
                     void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Most probable explanation of observed outcomes (Huang et al., ASPLOS'21,
+ * Sec. 5: which noise events best explain an outcome; the maximum is taken
+ * over real error probabilities, not amplitudes).  For each element b, with
+ * the outputs x_b from evidence[b] (its noise-event fields are ignored) and
+ * angles theta[param_of[b]]:
+ *   prob_out[b] = max_k |f(x_b, k)|^2 = P(x_b, k*)   float64 [B]
+ *   mpe_out[b]  = evidence words of (x_b, k*)        uint64 [B][n_words]
+ * computed by max-product over the noise events: nodes with an event
+ * indicator below them hold the largest |value|^2 over those events
+ * (products multiply, sums keep their largest branch), the rest complex
+ * values; a top-down pass reads k* off the largest branches (the first in
+ * child order on ties, so k* is one of the maximisers).  Exact when every
+ * sum with an event below it decides one evidence variable and a product's
+ * children share no event -- an AC compiled with the events explicit and
+ * decided first (the search-based compiler's MPE mode); ac_load checks the
+ * decisions and this call returns AC_ERR_UNSUPPORTED for other ACs (with
+ * selector leaves, for one).  complex128 only; noise as in ac_eval_batch.
+ * Workspace: ac_workspace_size(g, AC_C128, B, AC_OP_MPE).  Pointers are
+ * device pointers owned by the caller; param_of values outside [0, P) give
+ * NaN.
+ */
+ac_status ac_mpe_batch(const ac_graph *g, const double *theta, int32_t P, const double *noise,
+                       const int32_t *param_of, const uint64_t *evidence, int64_t B, double *prob_out,
+                       uint64_t *mpe_out, void *ws, size_t ws_bytes, void *stream);
 
 #ifdef __cplusplus
 }

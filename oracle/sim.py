@@ -313,3 +313,21 @@ def qaoa_zz_lightcone(edges, theta, i, j):
         ops += [("RX", q, 2 * layer + 1, 2.0) for q in range(m)]
     psi = branch_state(_Ops(m, ops), list(theta))
     return zz_expectation(psi, pos[i], pos[j], m)
+
+
+# ---------------------------------------------------------------------------
+# most probable explanation of an outcome (Sec. 5)
+# ---------------------------------------------------------------------------
+
+def most_probable_events(circ, theta, x_index, noise=None, rtol=1e-12):
+    """The noise events that best explain an observed outcome x: the joint
+    probability of outcome and events is P(x, k) = |f(x, k)|^2 (a real error
+    probability, where the maximum is defined, unlike for amplitudes), so
+    k* = argmax_k |f(x, k)|^2 over every Kraus-index tuple (tiny circuits
+    only).  Returns (max_k P(x, k), every k within rtol of the maximum, in
+    enumeration order)."""
+    ks = all_kraus_assignments(circ)
+    p = np.array([abs(amplitude(circ, theta, x_index, k, noise)) ** 2 for k in ks])
+    best = float(p.max())
+    tie = np.nonzero(p >= best * (1.0 - rtol))[0]
+    return best, [tuple(int(v) for v in ks[i]) for i in tie]

@@ -16,13 +16,13 @@ AC_OK, AC_ERR_INVALID_ARG, AC_ERR_FORMAT, AC_ERR_OOM, AC_ERR_DEVICE, AC_ERR_UNSU
 STATUS_NAMES = {0: "AC_OK", 1: "AC_ERR_INVALID_ARG", 2: "AC_ERR_FORMAT", 3: "AC_ERR_OOM",
                 4: "AC_ERR_DEVICE", 5: "AC_ERR_UNSUPPORTED"}
 AC_C64, AC_C128 = 0, 1
-AC_OP_EVAL, AC_OP_GRAD, AC_OP_SAMPLE = 0, 1, 2
+AC_OP_EVAL, AC_OP_GRAD, AC_OP_SAMPLE, AC_OP_MPE = 0, 1, 2, 3
 AC_GRAD_COTANGENT, AC_GRAD_PROB, AC_GRAD_LOGPROB = 0, 1, 2
 AC_SAMPLER_STREAM, AC_SAMPLER_LDS, AC_SAMPLER_GLOBAL = 0, 1, 2
 
 EXPORTED = ("ac_load", "ac_free", "ac_info", "ac_last_error", "ac_workspace_size", "ac_workspace_size_share",
             "ac_sample_shape",
-            "ac_eval_batch", "ac_eval_batch_static", "ac_grad_batch", "ac_sample")
+            "ac_eval_batch", "ac_eval_batch_static", "ac_grad_batch", "ac_mpe_batch", "ac_sample")
 AC_STATIC_SCRATCH_BYTES = 256 << 20
 
 
@@ -92,6 +92,8 @@ def lib():
     L.ac_grad_batch.argtypes = [vp, ctypes.c_int, vp, i32, vp, vp, vp, i64, ctypes.c_int, vp, vp,
                                 vp, vp, vp, vp, vp, sz, vp]
     L.ac_grad_batch.restype = ctypes.c_int
+    L.ac_mpe_batch.argtypes = [vp, vp, i32, vp, vp, vp, i64, vp, vp, vp, sz, vp]
+    L.ac_mpe_batch.restype = ctypes.c_int
     L.ac_sample.argtypes = [vp, ctypes.c_int, vp, i32, vp, ctypes.POINTER(SampleCfg), vp, vp, vp,
                             vp, vp, sz, vp]
     L.ac_sample.restype = ctypes.c_int

@@ -191,6 +191,20 @@ class ACGraph:
                                              self._stream()))
         return amp, pr
 
+    def mpe(self, theta, evidence, param_of=None, noise=None, validate: bool = True,
+            ws: Optional[torch.Tensor] = None):
+        """Most probable noise events for each element's outcome (see
+        ac_mpe_batch; complex128, an AC compiled with the events decided
+        first): (max_k |f(x, k)|^2 float64 [B], evidence words of (x, k*)
+        uint64-as-int64 [B, n_words])."""
+        theta, evidence, param_of, noise, P, B = self._inputs(theta, evidence, param_of, noise, validate)
+        prob = torch.empty(B, dtype=torch.float64, device=self.torch_device)
+        words = torch.empty((B, self.info["n_words"]), dtype=torch.int64, device=self.torch_device)
+        ws = self.workspace("c128", B, L.AC_OP_MPE, ws)
+        L.check(L.lib().ac_mpe_batch(self._h, _ptr(theta), P, _ptr(noise), _ptr(param_of), _ptr(evidence), B,
+                                     _ptr(prob), _ptr(words), _ptr(ws), ws.numel(), self._stream()))
+        return prob, words
+
     def grad(self, theta, evidence, param_of=None, mode: str = "cotangent", cotangent=None,
              weight=None, noise=None, dtype: str = "c64", want_amp=False, want_dfdtheta=False,
              want_dind=False, validate: bool = True, ws: Optional[torch.Tensor] = None):

@@ -48,6 +48,10 @@ template <typename T>
 hipError_t launch_sample_lds(const DevGraph &g, const LdsPlan &lp, int cpw, int wpc, int grid, const double *theta,
                              const double *noise, const SampleArgs &a, hipStream_t st);
 hipError_t launch_zero_f64(double *p, int64_t n, hipStream_t st);
+size_t mpe_lds_bytes(const DevGraph &g);
+hipError_t launch_mpe(const DevGraph &g, const MpePlan &mp, int grid, const double *theta, const int32_t *param_of,
+                      int P, const uint64_t *evidence, int64_t B, const void *wfix, void *vals,
+                      size_t per_wg_elems, double *prob_out, uint64_t *mpe_out, hipStream_t st);
 hipError_t static_scratch_address(void **out);
 template <typename T>
 int resident_blocks(const DevGraph &g, const SopPlan &sp, int which, int block);
@@ -133,6 +137,8 @@ struct ac_graph {
     ac_info_t info{};
     std::vector<uint8_t> var_dom;
     std::vector<uint32_t> var_offset;
+    MpePlan mpe{};
+    std::string mpe_why;                                  // why ac_mpe_batch refuses this AC ("" if it does not)
 };
 
 namespace {
@@ -751,6 +757,66 @@ extern "C" ac_status ac_load(const void *blob, size_t nbytes, int device, ac_gra
     for (size_t q = 0; q < par_edge.size(); ++q) par_rec[q] = edge_record(par_edge[q]);
     for (size_t q = 0; q < leaf_edge.size(); ++q) leaf_rec[q] = edge_record(leaf_edge[q]);
 
+    // ---- most-probable-explanation plan (MpePlan): the nodes with a noise-event
+    // indicator below, and whether max-product over the events is exact here:
+    // no selector leaves (they fold the events into weights), outputs at bits
+    // 0..n-1, and every such sum node a decision on one evidence variable
+    // (each branch an indicator of it, or a product with one, values distinct).
+    // Decomposability over the events is the compiler's guarantee.
+    std::vector<uint8_t> big(N, 0);
+    std::vector<uint64_t> event_mask(n_words, 0);
+    for (uint32_t v = n_qubits; v < n_vars; ++v) {
+        const uint32_t fld = var_field[v], width = (fld & 3u) + 1u;
+        event_mask[fld >> 8] |= ((1ull << width) - 1ull) << ((fld >> 2) & 63u);
+    }
+    std::string mpe_why;
+    if (n_sel) mpe_why = "selector leaves fold the noise events into weights (compile with the events explicit)";
+    for (uint32_t q = 0; q < n_qubits && mpe_why.empty(); ++q)
+        if (var_off[q] != q) mpe_why = "outputs must occupy bits 0..n-1";
+    auto direct_inds = [&](uint32_t r, std::vector<uint32_t> &out) {   // (var << 8 | value) of r's indicators
+        out.clear();
+        const uint32_t tag = r >> 30, x = r & REF_MASK;
+        if (tag == TAG_IND) out.push_back(((x & 0xffffffu) << 8) | (x >> 24));
+        else if (tag == TAG_NODE && op[x] == 1)
+            for (uint32_t e = row_ptr[x]; e < row_ptr[x + 1]; ++e)
+                if ((col[e] >> 30) == TAG_IND) out.push_back(((col[e] & 0xffffffu) << 8) | ((col[e] & REF_MASK) >> 24));
+    };
+    {
+        std::vector<uint32_t> first, other;
+        for (uint32_t i = 0; i < N; ++i) {
+            for (uint32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+                const uint32_t r = col[e], tag = r >> 30, x = r & REF_MASK;
+                if ((tag == TAG_NODE && big[x]) || (tag == TAG_IND && (x & 0xffffffu) >= n_qubits)) big[i] = 1;
+            }
+            if (!big[i] || op[i] != 0 || !mpe_why.empty()) continue;
+            direct_inds(col[row_ptr[i]], first);
+            bool decided = false;
+            for (uint32_t cand : first) {
+                const uint32_t v = cand >> 8;
+                std::vector<uint32_t> seen;
+                bool ok = true;
+                for (uint32_t e = row_ptr[i]; e < row_ptr[i + 1] && ok; ++e) {
+                    direct_inds(col[e], other);
+                    uint32_t hits = 0, u = 0;
+                    for (uint32_t o : other)
+                        if ((o >> 8) == v) ++hits, u = o & 0xffu;
+                    ok = hits == 1 && std::find(seen.begin(), seen.end(), u) == seen.end();
+                    seen.push_back(u);
+                }
+                if (ok) {
+                    decided = true;
+                    break;
+                }
+            }
+            if (!decided) {
+                char buf[160];
+                std::snprintf(buf, sizeof(buf), "sum node %u has a noise event below it but decides no single "
+                              "variable (compile with the events decided first)", i);
+                mpe_why = buf;
+            }
+        }
+    }
+
     HostPlan hp = build_plan(N, op, row_ptr, col, root, ind_base, var_field, n_ind, n_sel, n_slots, sel_dev,
                              vsel_ptr, vsel);
     HostSop hs = build_sop(N, op, row_ptr, col, root, ind_base, var_field, n_ind, n_sel, vsel, n_angle_slots);
@@ -796,6 +862,8 @@ extern "C" ac_status ac_load(const void *blob, size_t nbytes, int device, ac_gra
         {hs.osel.data(), hs.osel.size() * sizeof(uint32_t), 0},
         {hs.frec_live.data(), hs.frec_live.size() * sizeof(uint64_t), 0},
         {hs.srow.data(), hs.srow.size() * sizeof(uint32_t), 0},
+        {big.data(), big.size() * sizeof(uint8_t), 0},
+        {event_mask.data(), event_mask.size() * sizeof(uint64_t), 0},
     };
     size_t total = 0;
     for (auto &s : secs) {
@@ -864,6 +932,10 @@ extern "C" ac_status ac_load(const void *blob, size_t nbytes, int device, ac_gra
     d.par_rec = reinterpret_cast<const uint64_t *>(at(27));
     d.leaf_rec = reinterpret_cast<const uint64_t *>(at(28));
     d.n_sel = static_cast<int32_t>(n_sel);
+    g->mpe.big = at(38);
+    g->mpe.event_mask = reinterpret_cast<const uint64_t *>(at(39));
+    g->mpe.n_qubits = static_cast<int32_t>(n_qubits);
+    g->mpe_why = mpe_why;
     if (hp.ok) {
         LdsPlan &lp = g->plan;
         lp.fwd = reinterpret_cast<const uint64_t *>(at(16));
@@ -1153,13 +1225,19 @@ struct Layout {
     int block = BLOCK;         // threads per workgroup
 };
 
+// workgroups per CU of the max-product kernel (a query over small ACs; its
+// rows are complex128)
+constexpr int MPE_WG_PER_CU = 4;
+
 bool make_layout(const ac_graph *g, ac_dtype dt, int64_t batch, int op, Layout &out, size_t tile_cap = 0) {
-    if (!g || batch < 0 || (dt != AC_C64 && dt != AC_C128) || op < 0 || op > 2) return false;
+    if (!g || batch < 0 || (dt != AC_C64 && dt != AC_C128) || op < 0 || op > 3) return false;
+    if (op == AC_OP_MPE && dt != AC_C128) return false;
     const DevGraph &d = g->dev;
     const size_t cs = dt == AC_C64 ? 8 : 16;
     size_t rows = 0;
     int kid = 0;
     if (op == AC_OP_EVAL) rows = eval_live_rows(g);
+    else if (op == AC_OP_MPE) rows = static_cast<size_t>(d.N);
     else if (op == AC_OP_GRAD) {
         rows = 2 * eval_rows(g) + d.S_ang + d.n_ind;
         kid = 1;
@@ -1180,7 +1258,8 @@ bool make_layout(const ac_graph *g, ac_dtype dt, int64_t batch, int op, Layout &
     // persistent grids: exactly the workgroups that are resident together
     int wg_per_cu = g->resident[dt][kid];
     int block = BLOCK;
-    if (kid != 2) block = wide_block_for(g, dt, batch, kid, wg_per_cu);
+    if (op == AC_OP_MPE) wg_per_cu = MPE_WG_PER_CU;
+    else if (kid != 2) block = wide_block_for(g, dt, batch, kid, wg_per_cu);
     if (const char *env = std::getenv("QKC_WG_PER_CU")) wg_per_cu = std::max(1, std::min(16, std::atoi(env)));
     int64_t grid = std::min<int64_t>(tiles, static_cast<int64_t>(g->n_cu) * wg_per_cu);
     if (per_wg > 0) {
@@ -1424,6 +1503,35 @@ extern "C" ac_status ac_grad_batch(const ac_graph *g, ac_dtype dtype, const doub
                                     dfdtheta_out, dind_out, w + L.sort_off, L.sort_bytes, st);
     }
     if (e != hipSuccess) return fail_hip(e, "ac_grad_batch: launch");
+    return AC_OK;
+}
+
+extern "C" ac_status ac_mpe_batch(const ac_graph *g, const double *theta, int32_t P, const double *noise,
+                                  const int32_t *param_of, const uint64_t *evidence, int64_t B, double *prob_out,
+                                  uint64_t *mpe_out, void *ws, size_t ws_bytes, void *stream) {
+    ac_status s = check_common(g, AC_C128, theta, P, "ac_mpe_batch");
+    if (s != AC_OK) return s;
+    if (!g->mpe_why.empty()) return fail(AC_ERR_UNSUPPORTED, "ac_mpe_batch: %s", g->mpe_why.c_str());
+    if (mpe_lds_bytes(g->dev) > LDS_LIMIT)
+        return fail(AC_ERR_UNSUPPORTED, "ac_mpe_batch: evidence and angle tables exceed LDS");
+    if (B < 0) return fail(AC_ERR_INVALID_ARG, "ac_mpe_batch: B < 0");
+    if (B == 0) return AC_OK;
+    if (P < 1) return fail(AC_ERR_INVALID_ARG, "ac_mpe_batch: P must be >= 1 when B > 0");
+    if (!param_of || !evidence || !prob_out || !mpe_out)
+        return fail(AC_ERR_INVALID_ARG, "ac_mpe_batch: null param_of/evidence/prob_out/mpe_out");
+    Layout L;
+    make_layout(g, AC_C128, B, AC_OP_MPE, L);
+    if (!ws || !fit_workspace(L, ws_bytes))
+        return fail(AC_ERR_INVALID_ARG, "ac_mpe_batch: workspace of %zu bytes, need %zu (%zu for one workgroup)",
+                    ws_bytes, L.total, L.tiles_off + L.per_wg_elems * L.cs);
+    DeviceGuard dg(g->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    uint8_t *w = static_cast<uint8_t *>(ws);
+    hipError_t e = launch_fixed_slots<double>(g->dev, noise, w + L.wfix_off, st);
+    if (e == hipSuccess)
+        e = launch_mpe(g->dev, g->mpe, L.grid, theta, param_of, P, evidence, B, w + L.wfix_off, w + L.tiles_off,
+                       L.per_wg_elems, prob_out, mpe_out, st);
+    if (e != hipSuccess) return fail_hip(e, "ac_mpe_batch: launch");
     return AC_OK;
 }
 

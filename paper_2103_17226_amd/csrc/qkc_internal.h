@@ -171,6 +171,16 @@ struct SopPlan {
 };
 constexpr int MAX_MASK_WORDS = 16;   // decision pass for up to 1024 variables
 
+// Most-probable-explanation queries: big[i] = 1 for the nodes with a
+// noise-event indicator below them (their rows hold max-products of
+// squared magnitudes), event_mask[w] = bits of word w that hold noise-event
+// fields.
+struct MpePlan {
+    const uint8_t *big;         // [N]
+    const uint64_t *event_mask; // [W]
+    int32_t n_qubits;
+};
+
 // Arguments of the Gibbs sampler kernel.
 struct SampleArgs {
     int64_t total_chains;

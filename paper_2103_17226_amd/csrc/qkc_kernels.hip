@@ -762,6 +762,141 @@ __global__ __launch_bounds__(MAX_BLOCK) __attribute__((amdgpu_waves_per_eu(sizeo
 }
 
 // ---------------------------------------------------------------------------
+// most probable explanation of an outcome: max-product over the noise events
+// ---------------------------------------------------------------------------
+//
+// On an AC whose noise-event decisions all lie above the sums over hidden
+// qubit values (events decided first by the compiler), the nodes split in
+// two domains.  A node with no event indicator below it holds its complex
+// value as in the upward pass.  Every other node holds
+//   M(n) = max over the events below n of |value(n)|^2,
+// a real error probability where the maximum is defined: a product
+// multiplies its children's M (a complex child or leaf contributes |v|^2;
+// the events below a product's children are disjoint), a sum decides one
+// variable and takes its largest branch.  Event indicators are 1 (the
+// events are free); output indicators follow the evidence.  A top-down pass
+// then walks, per element, from the root through the largest branch of
+// every selected sum (the first in child order on ties) and every child of
+// every selected product, and records each event indicator it passes: the
+// events k* with |f(x, k*)|^2 = M(root).  Rows [N][64] complex128: value, or
+// (M, selected flag).
+
+__device__ __forceinline__ bool event_ref(uint32_t r, int n_qubits) {
+    const uint32_t word = (r >> 6) & 0x3ffffu, shift = r & 63u;
+    return word * 64u + shift >= static_cast<uint32_t>(n_qubits);
+}
+
+// max-domain quantity of a child reference: M of a max-domain node, |v|^2 of
+// a complex node or weight, 1 for an event indicator, 0/1 from the evidence
+// for an output indicator
+__device__ __forceinline__ double mpe_child(const Tile<double> &t, const MpePlan &mp, uint32_t r) {
+    const uint32_t tag = r >> 30;
+    if (tag == TAG_NODE) {
+        const uint32_t c = r & REF_MASK;
+        const cplx<double> v = t.val[static_cast<size_t>(c) * WAVE + t.lane];
+        return mp.big[c] ? v.re : __dadd_rn(__dmul_rn(v.re, v.re), __dmul_rn(v.im, v.im));
+    }
+    if (tag == TAG_IND) return event_ref(r, mp.n_qubits) ? 1.0 : (t.ind_hit(r) ? 1.0 : 0.0);
+    const cplx<double> w = wval(t.weight(r));
+    return __dadd_rn(__dmul_rn(w.re, w.re), __dmul_rn(w.im, w.im));
+}
+
+__global__ __launch_bounds__(BLOCK) void k_mpe(DevGraph g, MpePlan mp, const double *theta, const int32_t *param_of,
+                                               int P, const uint64_t *evidence, int64_t B,
+                                               const Weight<double> *wfix, cplx<double> *vals, size_t per_wg,
+                                               double *prob_out, uint64_t *mpe_out) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint64_t *ev_s = reinterpret_cast<uint64_t *>(smem);
+    Weight<double> *ang_s = reinterpret_cast<Weight<double> *>(smem + static_cast<size_t>(g.W) * WAVE * 8);
+    unsigned long long *k_s = reinterpret_cast<unsigned long long *>(
+        smem + static_cast<size_t>(g.W) * WAVE * 8 + static_cast<size_t>(g.S_ang) * WAVE * sizeof(Weight<double>));
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wave = static_cast<int>(uniform_u32(threadIdx.x / WAVE));
+    const int nwaves = blockDim.x / WAVE;
+    cplx<double> *val = vals + per_wg * blockIdx.x;
+    Tile<double> t{g, val, ev_s, ang_s, wfix, lane};
+    const int64_t n_tiles = (B + WAVE - 1) / WAVE;
+    const uint32_t root = static_cast<uint32_t>(g.root);
+    const bool root_big = mp.big[root] != 0;
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const int64_t b = tile * WAVE + lane;
+        const bool valid = b < B;
+        const bool in_range = stage_tile(g, ev_s, ang_s, evidence, param_of, P, theta, b, valid, lane, wave, nwaves);
+        for (int w = wave; w < g.W; w += nwaves)
+            k_s[w * WAVE + lane] = (valid ? evidence[b * g.W + w] : 0ull) & ~mp.event_mask[w];
+        __syncthreads();
+        for (int l = 0; l < g.L; ++l) {
+            const uint32_t n0 = g.level_ptr[l], n1 = g.level_ptr[l + 1];
+            for (uint32_t i = n0 + static_cast<uint32_t>(wave); i < n1; i += static_cast<uint32_t>(nwaves)) {
+                const uint32_t e0 = g.row_ptr[i], e1 = g.row_ptr[i + 1];
+                const bool sum = t.op_at(i) == 0;
+                if (!mp.big[i]) {
+                    cplx<double> acc = sum ? cplx<double>{0.0, 0.0} : cplx<double>{1.0, 0.0};
+                    for (uint32_t e = e0; e < e1; ++e) {
+                        const cplx<double> v = t.child(g.col[e]);
+                        acc = sum ? cadd(acc, v) : cmul(acc, v);
+                    }
+                    val[static_cast<size_t>(i) * WAVE + lane] = acc;
+                } else {
+                    double m = sum ? 0.0 : 1.0;
+                    for (uint32_t e = e0; e < e1; ++e) {
+                        const double c = mpe_child(t, mp, g.col[e]);
+                        m = sum ? (c > m ? c : m) : __dmul_rn(m, c);
+                    }
+                    val[static_cast<size_t>(i) * WAVE + lane] = {m, 0.0};
+                }
+            }
+            __syncthreads();
+        }
+        if (root_big) {
+            if (wave == 0) val[static_cast<size_t>(root) * WAVE + lane].im = 1.0;
+            __syncthreads();
+            for (int l = g.L - 1; l >= 0; --l) {
+                const uint32_t n0 = g.level_ptr[l], n1 = g.level_ptr[l + 1];
+                for (uint32_t i = n0 + static_cast<uint32_t>(wave); i < n1; i += static_cast<uint32_t>(nwaves)) {
+                    if (!mp.big[i]) continue;
+                    const bool chosen = val[static_cast<size_t>(i) * WAVE + lane].im != 0.0;
+                    const uint32_t e0 = g.row_ptr[i], e1 = g.row_ptr[i + 1];
+                    uint32_t lo = e0, hi = e1;
+                    if (t.op_at(i) == 0) {               // the first largest branch
+                        double best = -1.0;
+                        for (uint32_t e = e0; e < e1; ++e) {
+                            const double c = mpe_child(t, mp, g.col[e]);
+                            if (c > best) {
+                                best = c;
+                                lo = e;
+                            }
+                        }
+                        hi = lo + 1;
+                    }
+                    if (!chosen) continue;
+                    for (uint32_t e = lo; e < hi; ++e) {
+                        const uint32_t r = g.col[e], tag = r >> 30;
+                        if (tag == TAG_NODE) {
+                            const uint32_t c = r & REF_MASK;
+                            if (mp.big[c]) val[static_cast<size_t>(c) * WAVE + lane].im = 1.0;
+                        } else if (tag == TAG_IND && event_ref(r, mp.n_qubits)) {
+                            const uint32_t u = (r >> 26) & 15u, word = (r >> 6) & 0x3ffffu, shift = r & 63u;
+                            atomicOr(&k_s[word * WAVE + lane], static_cast<unsigned long long>(u) << shift);
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        if (valid) {
+            for (int w = wave; w < g.W; w += nwaves) mpe_out[b * g.W + w] = k_s[w * WAVE + lane];
+            if (wave == 0) {
+                const cplx<double> v = val[static_cast<size_t>(root) * WAVE + lane];
+                double m = root_big ? v.re : __dadd_rn(__dmul_rn(v.re, v.re), __dmul_rn(v.im, v.im));
+                prob_out[b] = in_range ? m : static_cast<double>(NAN);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // upward + downward pass + chain rule (gradients)
 // ---------------------------------------------------------------------------
 
@@ -2192,6 +2327,17 @@ hipError_t launch_eval(const DevGraph &g, const SopPlan &sp, int grid, int block
     hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, st, g, sp, theta, param_of, P, evidence, B,
                        reinterpret_cast<const Weight<T> *>(wfix), reinterpret_cast<cplx<T> *>(vals),
                        per_wg_elems, reinterpret_cast<cplx<T> *>(amp_out), prob_out);
+    return hipGetLastError();
+}
+
+size_t mpe_lds_bytes(const DevGraph &g) { return lds_bytes(g) + static_cast<size_t>(g.W) * WAVE * 8; }
+
+hipError_t launch_mpe(const DevGraph &g, const MpePlan &mp, int grid, const double *theta, const int32_t *param_of,
+                      int P, const uint64_t *evidence, int64_t B, const void *wfix, void *vals,
+                      size_t per_wg_elems, double *prob_out, uint64_t *mpe_out, hipStream_t st) {
+    hipLaunchKernelGGL(k_mpe, dim3(grid), dim3(BLOCK), mpe_lds_bytes(g), st, g, mp, theta, param_of, P, evidence, B,
+                       reinterpret_cast<const Weight<double> *>(wfix), reinterpret_cast<cplx<double> *>(vals),
+                       per_wg_elems, prob_out, mpe_out);
     return hipGetLastError();
 }
 

@@ -168,8 +168,9 @@ def dtree_from_order(scopes: List[Tuple[int, ...]], order: List[int]) -> Optiona
 # ---------------------------------------------------------------------------
 
 class _Search:
-    def __init__(self, F, dtree: str):
+    def __init__(self, F, dtree: str, first=frozenset()):
         self.F = F
+        self.first = first                  # variables decided before any other in a component
         self.ac = F.ac
         self.factors = F.live
         self.scopes = [f.vars for f in self.factors]
@@ -214,7 +215,16 @@ class _Search:
 
     def choose(self, comp, asg):
         """The next decision: an undecided variable cut by the lowest dtree
-        node that covers the component (most occurrences in it first)."""
+        node that covers the component (most occurrences in it first); with
+        ``first`` variables left in the component, one of them."""
+        if self.first:
+            occ: Dict[int, int] = defaultdict(int)
+            for f in comp:
+                for v in self.scopes[f]:
+                    if v not in asg and v in self.first:
+                        occ[v] += 1
+            if occ:
+                return max(occ, key=lambda v: (occ[v], -v))
         t = self.root
         while t is not None and t.left is not None:
             if comp <= t.left.factors:
@@ -279,13 +289,27 @@ class _Search:
 
 
 def compile_circuit_dpll(circ, flatten: bool = True, selectors: bool = True,
-                         dtree: str = "order") -> CompiledAC:
+                         dtree: str = "order", mpe: bool = False) -> CompiledAC:
     """Compile a circuit (op-list form) with the search-based compiler; the
     same flat AC format and polynomial as ``compiler.compile_circuit``.
     dtree: "order" builds the decomposition tree from the min-fill/min-weight
-    elimination order, "bisect" by recursive hypergraph bisection."""
+    elimination order, "bisect" by recursive hypergraph bisection.
+
+    mpe=True compiles for most-probable-explanation queries over the noise
+    events (Sec. 5): every event is an explicit variable (no selector
+    leaves) and a component decides its events before any other variable,
+    so every sum with an event below it is a decision on one evidence
+    variable and the sums over hidden qubit values sit below all event
+    decisions.  Max-product over the events is then exact on the AC
+    (|a b|^2 = |a|^2 |b|^2 over the disjoint events of a product's
+    children; a decision's branches are disjoint).  The search then
+    enumerates joint event values per component, so the size grows
+    exponentially with the events that share hidden variables."""
+    if mpe:
+        selectors = False
     F = build_factors(circ, selectors)
-    S = _Search(F, dtree)
+    first = frozenset(v for v, e in F.indicator_of.items() if e >= circ.n) if mpe else frozenset()
+    S = _Search(F, dtree, first)
     limit = sys.getrecursionlimit()
     sys.setrecursionlimit(max(limit, 20000))
     try:
@@ -300,5 +324,5 @@ def compile_circuit_dpll(circ, flatten: bool = True, selectors: bool = True,
     if root is None:
         raise ValueError("the compiled circuit is identically zero")
     return finish_compiled(circ, F.bn, F.ac, root, F.ev_nodes, flatten,
-                           dict(fg_vars=F.n_fg_vars, compiler="dpll", dtree=dtree, decisions=S.decisions, cache_hits=S.hits,
+                           dict(fg_vars=F.n_fg_vars, compiler="dpll", dtree=dtree, mpe=mpe, decisions=S.decisions, cache_hits=S.hits,
                                 cache_entries=len(S.cache)))

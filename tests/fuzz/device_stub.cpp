@@ -43,6 +43,11 @@ hipError_t launch_sample_lds(const DevGraph &, const LdsPlan &, int, int, int, c
     return hipErrorNoDevice;
 }
 hipError_t launch_zero_f64(double *, int64_t, hipStream_t) { return hipErrorNoDevice; }
+size_t mpe_lds_bytes(const DevGraph &) { return 0; }
+hipError_t launch_mpe(const DevGraph &, const MpePlan &, int, const double *, const int32_t *, int, const uint64_t *,
+                      int64_t, const void *, void *, size_t, double *, uint64_t *, hipStream_t) {
+    return hipErrorNoDevice;
+}
 hipError_t static_scratch_address(void **) { return hipErrorNoDevice; }
 template <typename T>
 int resident_blocks(const DevGraph &, const SopPlan &, int, int) { return 1; }

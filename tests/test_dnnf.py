@@ -176,3 +176,31 @@ def test_dpll_blob_is_cached_under_its_own_key(tmp_path):
     assert a == c == to_blob(D.compile_circuit_dpll(circ)) and b == compile_blob(circ)
     with pytest.raises(ValueError):
         compile_blob(circ, method="nope")
+
+
+MPE_CIRCUITS = ["bell", "tiny", "ring3_dep", 0, 1, 2, 3, 4, 7, 8, 11]
+
+
+def _mpe_circuit(name):
+    return CIRCUITS[name]() if name in CIRCUITS else W.random_circuit(name)
+
+
+@pytest.mark.parametrize("name", MPE_CIRCUITS)
+def test_mpe_compilation_gives_the_most_probable_events(name):
+    # events decided first: max-product over the AC equals the oracle's
+    # largest |f(x, k)|^2, and the events it reads off achieve it
+    circ = _mpe_circuit(name)
+    ac = D.compile_circuit_dpll(circ, mpe=True)
+    assert not ac.selectors
+    rng = np.random.default_rng(21)
+    theta = rng.uniform(0, 2 * np.pi, size=circ.n_angles)
+    for x in range(1 << circ.n):
+        bits = [(x >> q) & 1 for q in range(circ.n)]
+        best, ks = sim.most_probable_events(circ, theta, x)
+        m, k = H.max_product(ac, theta, bits)
+        assert abs(m - best) <= 1e-12 * max(best, 1e-300), (x, m, best)
+        if best > 0:
+            assert tuple(k) in ks, (x, k, ks)
+    # the same AC still gives every amplitude
+    for vals in all_assignments(circ)[:200]:
+        assert abs(H.evaluate_assignment(ac, theta, vals) - oracle_amp(circ, theta, vals)) < 1e-13

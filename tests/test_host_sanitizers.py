@@ -27,6 +27,8 @@ def _blobs():
              W.random_circuit(11), W.qaoa_maxcut(4, W.ring_graph(4), 2, dep=0.02, ad=0.01)]
     out = [to_blob(compile_circuit(c)) for c in circs]
     out.append(to_blob(_wide_sum_graph(50)))
+    from paper_2103_17226_amd.dnnf import compile_circuit_dpll
+    out.append(to_blob(compile_circuit_dpll(W.random_circuit(1), mpe=True)))   # the MPE plan's checks
     return out
 
 

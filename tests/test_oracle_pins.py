@@ -496,3 +496,34 @@ def test_chi2_detects_bias_and_accepts_truth():
     bad = np.bincount(rng.choice(20, size=20000, p=q), minlength=20)
     assert stats.chi2_pooled(bad, p)[2] < 1e-3
     assert stats.kl_divergence(good, p) < stats.kl_divergence(bad, p)
+
+
+def test_most_probable_events_closed_forms():
+    # Sec. 5: the noise events that best explain an outcome, by the largest
+    # joint probability P(x, k) = |f(x, k)|^2.  One depolarizing channel on
+    # |0>: outcome 1 needs an X or a Y error, P = p/3 each (a tie); outcome 0
+    # is best explained by no error, P = 1 - p.
+    p = 0.12
+    dep = W.Circuit(n=1, ops=[("DEP", 0, 0)], n_angles=0, noise=[p], edges=[])
+    best, ks = sim.most_probable_events(dep, [], 1)
+    assert best == pytest.approx(p / 3, rel=1e-14) and ks == [(1,), (2,)]
+    best, ks = sim.most_probable_events(dep, [], 0)
+    assert best == pytest.approx(1 - p, rel=1e-14) and ks == [(0,)]
+    # |1> then amplitude damping: outcome 0 only through a decay (P = gamma)
+    g = 0.3
+    ad = W.Circuit(n=1, ops=[("RX", 0, 0, 1.0), ("AD", 0, 0)], n_angles=1, noise=[g], edges=[])
+    best, ks = sim.most_probable_events(ad, [np.pi], 0)
+    assert best == pytest.approx(g, rel=1e-12) and ks == [(1,)]
+    best, ks = sim.most_probable_events(ad, [np.pi], 1)
+    assert best == pytest.approx(1 - g, rel=1e-12) and ks == [(0,)]
+    # both in a row: outcome 0 comes from a decay with no Pauli error
+    # (gamma (1 - p)), or no decay and an X or Y error ((1 - gamma) p / 3)
+    both = W.Circuit(n=1, ops=[("RX", 0, 0, 1.0), ("AD", 0, 0), ("DEP", 0, 1)], n_angles=1, noise=[0.3, 0.3],
+                     edges=[])
+    best, ks = sim.most_probable_events(both, [np.pi], 0)
+    assert best == pytest.approx(0.3 * 0.7, rel=1e-12) and ks == [(1, 0)]
+    both.noise = [0.05, 0.6]
+    best, ks = sim.most_probable_events(both, [np.pi], 0)
+    assert best == pytest.approx(0.95 * 0.2, rel=1e-12) and ks == [(0, 1), (0, 2)]
+    # the best branch never exceeds the outcome's probability, the sum over k
+    assert best <= sim.probabilities(both, [np.pi])[0] + 1e-15
