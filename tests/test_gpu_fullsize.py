@@ -10,8 +10,11 @@ of the results one by one, or properties that hold at any size.
   oracle's chain with the same random stream (the same final state wherever
   no decision is a near tie);
 * 16-qubit p=2 noisy QAOA, 262,144 amplitudes: sampled rows against the
-  oracle's branch amplitudes, every row's complex64 probability against
-  complex128 (1e-5 relative), the complex64 gradient against complex128;
+  oracle's branch amplitudes (complex128 amplitudes, complex64
+  probabilities), every row's complex64 probability against complex128
+  (1e-5 relative), the complex64 gradient against complex128;
+
+The 8- and 16-qubit ACs come from the search-based compiler, as in the bench.
 * 32-qubit noise-free QAOA, 256 x 3907 chains: per-edge <Z_i Z_j> of sampled
   parameter sets against the light cone, and every sample's cost.
 """
@@ -23,6 +26,7 @@ import workloads as W
 from oracle import gibbs
 from oracle import grad as ograd
 from oracle import sim, stats
+from paper_2103_17226_amd.dnnf import compile_circuit_dpll
 from tests.gpu_common import graph, note, oracle_amplitudes, prob_ok, require_gpu
 
 pytestmark = pytest.mark.gpu
@@ -44,7 +48,7 @@ def test_config2_full_batch_samples_costs_and_gradient():
     theta = cfg["theta"]
     P, C = theta.shape[0], cfg["chains_per_param"]
     note(f"config 2 full batch: {P} x {C} chains")
-    g = graph(circ)
+    g = graph(compile_circuit_dpll(circ))            # the AC the bench runs
     out = g.sample(theta, C, 1, 10, 1, 2024, cost_edges=circ.edges, dtype="c64", want_states=True,
                    want_cost=True, validate=False)
     x = out["samples"].cpu().numpy().reshape(P, C)
@@ -124,7 +128,7 @@ def test_config2_full_batch_chains_follow_the_oracle_chain():
     P, C = theta.shape[0], cfg["chains_per_param"]
     seed, burn = 777, 10
     note(f"config 2 full batch, complex64 chains against the oracle chain: {P} x {C} chains")
-    g = graph(circ)
+    g = graph(compile_circuit_dpll(circ))            # the AC the bench runs
     out = g.sample(theta, C, 1, burn, 1, seed, dtype="c64", want_states=True, validate=False)
     states = out["states"].reshape(P * C, -1).cpu().numpy().view(np.uint64)
     rng = np.random.default_rng(11)
@@ -147,7 +151,7 @@ def test_config3_full_batch_amplitudes_and_gradient():
     theta, ev, po = cfg["theta"], cfg["evidence"], cfg["param_of"]
     B = ev.shape[0]
     note(f"config 3 full batch: {B} amplitudes")
-    g = graph(circ)
+    g = graph(compile_circuit_dpll(circ))            # the AC the bench runs
 
     def free():
         g.release_workspaces()
@@ -169,6 +173,9 @@ def test_config3_full_batch_amplitudes_and_gradient():
     rows = np.sort(rng.choice(B, size=16, replace=False))
     ref = np.array([oracle_amplitudes(circ, theta[po[b]], vals[b:b + 1])[0] for b in rows])
     assert np.max(np.abs(a128[rows] - ref)) <= 1e-12
+    ok, worst = prob_ok(p64[rows], np.abs(ref) ** 2)            # complex64 rows against the oracle itself
+    note(f"  c64 sampled rows vs oracle worst rel err {worst:.2e}")
+    assert ok
     # gradient of sum_b |f_b|^2 at full size: complex64 against complex128
     w = np.ones(B)
     g64 = g.grad(theta, ev, po, mode="prob", weight=w, dtype="c64", validate=False)["grad"].cpu().numpy()
