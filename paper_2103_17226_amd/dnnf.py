@@ -30,6 +30,7 @@ variable-elimination compiler:
 from __future__ import annotations
 
 import sys
+import threading
 from collections import defaultdict, deque
 from typing import Dict, List, Optional, Tuple
 
@@ -41,12 +42,13 @@ from .compiler import CompiledAC, _elimination_order, build_factors, finish_comp
 # ---------------------------------------------------------------------------
 
 class DNode:
-    __slots__ = ("factors", "left", "right", "cut")
+    __slots__ = ("factors", "left", "right", "cut", "lo", "hi")
 
     def __init__(self, factors, left=None, right=None, cut=()):
         self.factors = factors
         self.left, self.right = left, right
         self.cut = cut                      # variables shared by the two halves
+        self.lo = self.hi = 0               # its leaves' positions [lo, hi) in depth-first order
 
 
 def _bisect(fids: List[int], scopes: List[Tuple[int, ...]], passes: int = 4) -> Tuple[List[int], List[int]]:
@@ -187,6 +189,25 @@ class _Search:
         self.cache: Dict[tuple, object] = {}
         self.decisions = 0
         self.hits = 0
+        # number the dtree's leaves depth-first: a node covers a contiguous
+        # range, so "component inside node" is a test of the component's
+        # smallest and largest leaf position
+        self.pos = [0] * len(self.scopes)
+        stack = [(self.root, False)] if self.root is not None else []
+        k = 0
+        while stack:
+            t, done = stack.pop()
+            if t.left is None:
+                t.lo = k
+                for f in t.factors:
+                    self.pos[f] = k
+                k += 1
+                t.hi = k
+                continue
+            if done:
+                t.lo, t.hi = t.left.lo, t.right.hi
+                continue
+            stack += [(t, True), (t.right, False), (t.left, False)]
 
     def entry(self, fid: int, asg: Dict[int, int]):
         f = self.factors[fid]
@@ -213,10 +234,25 @@ class _Search:
             out.append(frozenset(comp))
         return out
 
-    def choose(self, comp, asg):
-        """The next decision: an undecided variable cut by the lowest dtree
-        node that covers the component (most occurrences in it first); with
-        ``first`` variables left in the component, one of them."""
+    def covering(self, comp, start):
+        """The lowest dtree node that covers the component, searched from
+        ``start`` (a node that covers it: the parent component's)."""
+        lo = min(self.pos[f] for f in comp)
+        hi = max(self.pos[f] for f in comp) + 1
+        t = start
+        while t.left is not None:
+            if t.left.lo <= lo and hi <= t.left.hi:
+                t = t.left
+            elif t.right.lo <= lo and hi <= t.right.hi:
+                t = t.right
+            else:
+                break
+        return t
+
+    def choose(self, comp, asg, t):
+        """The next decision: an undecided variable cut by dtree node t (the
+        lowest that covers the component; most occurrences in it first);
+        with ``first`` variables left in the component, one of them."""
         if self.first:
             occ: Dict[int, int] = defaultdict(int)
             for f in comp:
@@ -225,18 +261,10 @@ class _Search:
                         occ[v] += 1
             if occ:
                 return max(occ, key=lambda v: (occ[v], -v))
-        t = self.root
-        while t is not None and t.left is not None:
-            if comp <= t.left.factors:
-                t = t.left
-                continue
-            if comp <= t.right.factors:
-                t = t.right
-                continue
+        if t is not None and t.left is not None:
             cand = [v for v in t.cut if v not in asg and any(f in comp for f in self.by_var[v])]
             if cand:
                 return max(cand, key=lambda v: (sum(1 for f in self.by_var[v] if f in comp), -v))
-            break
         occ: Dict[int, int] = defaultdict(int)
         for f in comp:
             for v in self.scopes[f]:
@@ -244,15 +272,17 @@ class _Search:
                     occ[v] += 1
         return max(occ, key=lambda v: (occ[v], -v))
 
-    def compile(self, comp, asg):
-        """AC node (or ONE) of a component under the decisions asg; None if zero."""
+    def compile(self, comp, asg, start=None):
+        """AC node (or ONE) of a component under the decisions asg; None if
+        zero.  ``start``: a dtree node covering the component."""
         ctx_vars = sorted({v for f in comp for v in self.scopes[f] if v in asg})
         key = (comp, tuple(asg[v] for v in ctx_vars))
         hit = self.cache.get(key, self)
         if hit is not self:
             self.hits += 1
             return hit
-        x = self.choose(comp, asg)
+        t = self.covering(comp, start if start is not None else self.root) if self.root is not None else None
+        x = self.choose(comp, asg, t)
         self.decisions += 1
         branches = []
         for val in range(self.F.dom[x]):
@@ -261,19 +291,19 @@ class _Search:
             ok = True
             if x in self.F.indicator_of:
                 items.append(self.ac.indicator(self.F.indicator_of[x], val))
-            rest = []
-            for f in comp:
-                if all(v in asg for v in self.scopes[f]):
-                    e = self.entry(f, asg)
-                    if e is None:
-                        ok = False
-                        break
-                    items.append(e)
-                else:
-                    rest.append(f)
+            # only factors that mention x can have become complete (the
+            # component holds no complete factor); the others remain
+            done = [f for f in self.by_var[x] if f in comp and all(v in asg for v in self.scopes[f])]
+            for f in sorted(done):
+                e = self.entry(f, asg)
+                if e is None:
+                    ok = False
+                    break
+                items.append(e)
+            rest = comp.difference(done) if done else comp
             if ok:
                 for c in self.components(rest, asg):
-                    r = self.compile(c, asg)
+                    r = self.compile(c, asg, t)
                     if r is None:
                         ok = False
                         break
@@ -286,6 +316,31 @@ class _Search:
         res = self.ac.total(branches) if branches else None
         self.cache[key] = res
         return res
+
+
+def _deep(fn, depth: int = 100000, stack_bytes: int = 512 << 20):
+    """Run fn in a thread with a large stack and recursion limit (the search
+    recurses once per decision and component along a path)."""
+    out = {}
+
+    def run():
+        limit = sys.getrecursionlimit()
+        sys.setrecursionlimit(max(limit, depth))
+        try:
+            fn()
+        except BaseException as exc:       # re-raised in the caller
+            out["exc"] = exc
+        finally:
+            sys.setrecursionlimit(limit)
+    old = threading.stack_size(stack_bytes)
+    try:
+        t = threading.Thread(target=run, name="dpll")
+        t.start()
+    finally:
+        threading.stack_size(old)
+    t.join()
+    if "exc" in out:
+        raise out["exc"]
 
 
 def compile_circuit_dpll(circ, flatten: bool = True, selectors: bool = True,
@@ -310,14 +365,8 @@ def compile_circuit_dpll(circ, flatten: bool = True, selectors: bool = True,
     F = build_factors(circ, selectors)
     first = frozenset(v for v, e in F.indicator_of.items() if e >= circ.n) if mpe else frozenset()
     S = _Search(F, dtree, first)
-    limit = sys.getrecursionlimit()
-    sys.setrecursionlimit(max(limit, 20000))
-    try:
-        parts = list(F.const_parts)
-        for c in S.components(range(len(S.factors)), {}):
-            parts.append(S.compile(c, {}))
-    finally:
-        sys.setrecursionlimit(limit)
+    parts = list(F.const_parts)
+    _deep(lambda: parts.extend(S.compile(c, {}) for c in S.components(range(len(S.factors)), {})))
     if any(p is None for p in parts):
         raise ValueError("the compiled circuit is identically zero")
     root = F.ac.product(parts)
