@@ -31,7 +31,7 @@ The pool (all 40 circuits; the p=2, n=20 ones compile to ACs of about a
 million nodes) compiles in worker processes while the other legs run, with
 a blob cache on disk; --serve-pool fast leaves the n=20, p=2 circuits out.
 
-Prints one JSON line.  --gpus > 1 is refused: this build runs on one GPU.
+Prints one JSON line.  --gpus > 1 is refused: the library runs on one GPU.
 """
 from __future__ import annotations
 
@@ -599,7 +599,7 @@ def main():
         copy_probe()
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1",
                           "n_gpus_requested": args.gpus}))
         sys.exit(2)
     pool = blobs = None
