@@ -97,3 +97,9 @@ def test_mpe_refuses_acs_not_compiled_for_it():
     g = graph(compile_circuit_dpll(circ, mpe=True))
     prob, words = g.mpe(theta, ev[:0], np.zeros(0, np.int32))          # an empty batch
     assert prob.numel() == 0 and words.shape[0] == 0
+    # a parameter index outside [0, P) reads no parameters and gives NaN
+    prob, _ = g.mpe(theta, ev, np.array([0, 1, -1], np.int32), validate=False)
+    prob = prob.cpu().numpy()
+    assert np.isfinite(prob[0]) and np.isnan(prob[1]) and np.isnan(prob[2])
+    # complex128 only: the workspace query for another dtype is refused
+    assert L.lib().ac_workspace_size(g._h, L.AC_C64, 3, L.AC_OP_MPE) == 0
