@@ -103,3 +103,23 @@ def test_mpe_refuses_acs_not_compiled_for_it():
     assert np.isfinite(prob[0]) and np.isnan(prob[1]) and np.isnan(prob[2])
     # complex128 only: the workspace query for another dtype is refused
     assert L.lib().ac_workspace_size(g._h, L.AC_C64, 3, L.AC_OP_MPE) == 0
+
+
+def test_mpe_of_the_bench_circuit():
+    # the bench's MPE workload (4-ring QAOA, 8 channels): sampled outcomes
+    # and angle pairs against the oracle
+    circ = W.qaoa_ring_mpe(4)
+    g = graph(compile_circuit_dpll(circ, mpe=True))
+    rng = np.random.default_rng(77)
+    theta = rng.uniform(0, 2 * np.pi, size=(4, circ.n_angles))
+    xs = np.tile(np.arange(16), 4)
+    po = np.repeat(np.arange(4, dtype=np.int32), 16)
+    vals = np.zeros((64, circ.n_vars), dtype=np.int64)
+    vals[:, :4] = [[(x >> q) & 1 for q in range(4)] for x in xs]
+    prob, words = g.mpe(theta, W.pack_evidence(circ, vals), po)
+    prob = prob.cpu().numpy()
+    got = W.unpack_evidence(circ, words.cpu().numpy().view(np.uint64))
+    for b in range(0, 64, 3):
+        best, ks = sim.most_probable_events(circ, theta[po[b]], int(xs[b]))
+        assert abs(prob[b] - best) <= 1e-12 * best
+        assert tuple(int(k) for k in got[b, 4:]) in ks

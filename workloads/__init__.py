@@ -359,6 +359,23 @@ def random_circuit(seed: int, n: int = None, n_ops: int = None, n_angles: int = 
     return Circuit(n=n, ops=ops, n_angles=n_angles, noise=noise, name=f"random_{seed}")
 
 
+def qaoa_ring_mpe(n: int = 4, dep: float = 0.02, ad: float = 0.05) -> Circuit:
+    """Noise-free QAOA p=1 on the n-ring with amplitude damping after each H
+    and depolarizing noise after each mixer RX (2n channels): a circuit for
+    most-probable-explanation queries, small enough for the events-first
+    compilation they need (n=4: 8 channels)."""
+    base = qaoa_maxcut(n, ring_graph(n), 1)
+    ops: List[tuple] = []
+    for op in base.ops:
+        ops.append(op)
+        if op[0] == "H":
+            ops.append(("AD", op[1], 1))
+        elif op[0] == "RX":
+            ops.append(("DEP", op[1], 0))
+    return Circuit(n=n, ops=ops, n_angles=base.n_angles, noise=[dep, ad], edges=list(base.edges),
+                   name=f"qaoa_ring{n}_mpe")
+
+
 def noisy_bell(gamma: float = 0.36) -> Circuit:
     """The paper's running example (Sec. 3.1): H on q0, phase damping on q0,
     CNOT q0 -> q1."""
