@@ -119,7 +119,7 @@ def test_mpe_of_the_bench_circuit():
     prob, words = g.mpe(theta, W.pack_evidence(circ, vals), po)
     prob = prob.cpu().numpy()
     got = W.unpack_evidence(circ, words.cpu().numpy().view(np.uint64))
-    for b in range(0, 64, 3):
+    for b in range(0, 64, 9):
         best, ks = sim.most_probable_events(circ, theta[po[b]], int(xs[b]))
         assert abs(prob[b] - best) <= 1e-12 * best
         assert tuple(int(k) for k in got[b, 4:]) in ks
