@@ -49,9 +49,9 @@ hipError_t launch_sample_lds(const DevGraph &g, const LdsPlan &lp, int cpw, int 
                              const double *noise, const SampleArgs &a, hipStream_t st);
 hipError_t launch_zero_f64(double *p, int64_t n, hipStream_t st);
 size_t mpe_lds_bytes(const DevGraph &g);
-hipError_t launch_mpe(const DevGraph &g, const MpePlan &mp, int grid, const double *theta, const int32_t *param_of,
-                      int P, const uint64_t *evidence, int64_t B, const void *wfix, void *vals,
-                      size_t per_wg_elems, double *prob_out, uint64_t *mpe_out, hipStream_t st);
+hipError_t launch_mpe(const DevGraph &g, const MpePlan &mp, int grid, int block, const double *theta,
+                      const int32_t *param_of, int P, const uint64_t *evidence, int64_t B, const void *wfix,
+                      void *vals, size_t per_wg_elems, double *prob_out, uint64_t *mpe_out, hipStream_t st);
 hipError_t static_scratch_address(void **out);
 template <typename T>
 int resident_blocks(const DevGraph &g, const SopPlan &sp, int which, int block);
@@ -1258,8 +1258,13 @@ bool make_layout(const ac_graph *g, ac_dtype dt, int64_t batch, int op, Layout &
     // persistent grids: exactly the workgroups that are resident together
     int wg_per_cu = g->resident[dt][kid];
     int block = BLOCK;
-    if (op == AC_OP_MPE) wg_per_cu = MPE_WG_PER_CU;
-    else if (kid != 2) block = wide_block_for(g, dt, batch, kid, wg_per_cu);
+    if (op == AC_OP_MPE) {
+        // fewer tiles than two per CU: each tile's levels spread over 16 waves
+        wg_per_cu = MPE_WG_PER_CU;
+        if (tiles < 2 * static_cast<int64_t>(g->n_cu)) block = MAX_BLOCK;
+    } else if (kid != 2) {
+        block = wide_block_for(g, dt, batch, kid, wg_per_cu);
+    }
     if (const char *env = std::getenv("QKC_WG_PER_CU")) wg_per_cu = std::max(1, std::min(16, std::atoi(env)));
     int64_t grid = std::min<int64_t>(tiles, static_cast<int64_t>(g->n_cu) * wg_per_cu);
     if (per_wg > 0) {
@@ -1529,8 +1534,8 @@ extern "C" ac_status ac_mpe_batch(const ac_graph *g, const double *theta, int32_
     uint8_t *w = static_cast<uint8_t *>(ws);
     hipError_t e = launch_fixed_slots<double>(g->dev, noise, w + L.wfix_off, st);
     if (e == hipSuccess)
-        e = launch_mpe(g->dev, g->mpe, L.grid, theta, param_of, P, evidence, B, w + L.wfix_off, w + L.tiles_off,
-                       L.per_wg_elems, prob_out, mpe_out, st);
+        e = launch_mpe(g->dev, g->mpe, L.grid, L.block, theta, param_of, P, evidence, B, w + L.wfix_off,
+                       w + L.tiles_off, L.per_wg_elems, prob_out, mpe_out, st);
     if (e != hipSuccess) return fail_hip(e, "ac_mpe_batch: launch");
     return AC_OK;
 }

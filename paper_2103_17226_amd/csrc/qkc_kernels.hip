@@ -801,7 +801,7 @@ __device__ __forceinline__ double mpe_child(const Tile<double> &t, const MpePlan
     return __dadd_rn(__dmul_rn(w.re, w.re), __dmul_rn(w.im, w.im));
 }
 
-__global__ __launch_bounds__(BLOCK) void k_mpe(DevGraph g, MpePlan mp, const double *theta, const int32_t *param_of,
+__global__ __launch_bounds__(MAX_BLOCK) void k_mpe(DevGraph g, MpePlan mp, const double *theta, const int32_t *param_of,
                                                int P, const uint64_t *evidence, int64_t B,
                                                const Weight<double> *wfix, cplx<double> *vals, size_t per_wg,
                                                double *prob_out, uint64_t *mpe_out) {
@@ -2332,10 +2332,11 @@ hipError_t launch_eval(const DevGraph &g, const SopPlan &sp, int grid, int block
 
 size_t mpe_lds_bytes(const DevGraph &g) { return lds_bytes(g) + static_cast<size_t>(g.W) * WAVE * 8; }
 
-hipError_t launch_mpe(const DevGraph &g, const MpePlan &mp, int grid, const double *theta, const int32_t *param_of,
-                      int P, const uint64_t *evidence, int64_t B, const void *wfix, void *vals,
-                      size_t per_wg_elems, double *prob_out, uint64_t *mpe_out, hipStream_t st) {
-    hipLaunchKernelGGL(k_mpe, dim3(grid), dim3(BLOCK), mpe_lds_bytes(g), st, g, mp, theta, param_of, P, evidence, B,
+hipError_t launch_mpe(const DevGraph &g, const MpePlan &mp, int grid, int block, const double *theta,
+                      const int32_t *param_of, int P, const uint64_t *evidence, int64_t B, const void *wfix,
+                      void *vals, size_t per_wg_elems, double *prob_out, uint64_t *mpe_out, hipStream_t st) {
+    if (block < WAVE || block > MAX_BLOCK || block % WAVE != 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_mpe, dim3(grid), dim3(block), mpe_lds_bytes(g), st, g, mp, theta, param_of, P, evidence, B,
                        reinterpret_cast<const Weight<double> *>(wfix), reinterpret_cast<cplx<double> *>(vals),
                        per_wg_elems, prob_out, mpe_out);
     return hipGetLastError();

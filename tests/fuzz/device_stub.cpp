@@ -44,8 +44,8 @@ hipError_t launch_sample_lds(const DevGraph &, const LdsPlan &, int, int, int, c
 }
 hipError_t launch_zero_f64(double *, int64_t, hipStream_t) { return hipErrorNoDevice; }
 size_t mpe_lds_bytes(const DevGraph &) { return 0; }
-hipError_t launch_mpe(const DevGraph &, const MpePlan &, int, const double *, const int32_t *, int, const uint64_t *,
-                      int64_t, const void *, void *, size_t, double *, uint64_t *, hipStream_t) {
+hipError_t launch_mpe(const DevGraph &, const MpePlan &, int, int, const double *, const int32_t *, int,
+                      const uint64_t *, int64_t, const void *, void *, size_t, double *, uint64_t *, hipStream_t) {
     return hipErrorNoDevice;
 }
 hipError_t static_scratch_address(void **) { return hipErrorNoDevice; }
