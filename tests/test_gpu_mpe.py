@@ -123,3 +123,23 @@ def test_mpe_of_the_bench_circuit():
         best, ks = sim.most_probable_events(circ, theta[po[b]], int(xs[b]))
         assert abs(prob[b] - best) <= 1e-12 * best
         assert tuple(int(k) for k in got[b, 4:]) in ks
+
+
+def test_mpe_is_the_same_for_both_launch_shapes():
+    # a small batch runs each tile on 16 waves, a batch of two or more tiles
+    # per CU on 4; every element is computed by its own lane in a fixed order
+    circ = W.qaoa_ring_mpe(4)
+    g = graph(compile_circuit_dpll(circ, mpe=True))
+    rng = np.random.default_rng(5)
+    P = 8
+    theta = rng.uniform(0, 2 * np.pi, size=(P, circ.n_angles))
+    big = 64 * 600
+    xs = rng.integers(0, 16, size=big)
+    po = rng.integers(0, P, size=big).astype(np.int32)
+    vals = np.zeros((big, circ.n_vars), dtype=np.int64)
+    vals[:, :4] = [[(x >> q) & 1 for q in range(4)] for x in xs]
+    ev = W.pack_evidence(circ, vals)
+    pb, wb = g.mpe(theta, ev, po)
+    ps, wsm = g.mpe(theta, ev[:200], po[:200])
+    assert np.array_equal(pb[:200].cpu().numpy(), ps.cpu().numpy())
+    assert np.array_equal(wb[:200].cpu().numpy(), wsm.cpu().numpy())
