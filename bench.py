@@ -53,11 +53,11 @@ KERNELS = os.path.join(ROOT, "paper_2103_17226_amd", "csrc", "qkc_kernels.hip")
 # kernel source and the AC they were taken on, and the default workload of
 # each leg.
 PROFILED_TRAFFIC = {
-    "k_sample_stream": {"kernel_sha256_16": "b2e09e20ccce7b37", "ac_sha256_16": "d3190d478a0e63f4",
-                        "bytes": 1656442792960,
+    "k_sample_stream": {"kernel_sha256_16": "d43077dd393401e9", "ac_sha256_16": "d3190d478a0e63f4",
+                        "bytes": 1656130150400,
                         "profile": "profiles/k_sample_stream_qaoa_n8_p1_dep.md"},
-    "k_eval": {"kernel_sha256_16": "b2e09e20ccce7b37", "ac_sha256_16": "53555d81365c02e0",
-               "bytes": 93998178304,
+    "k_eval": {"kernel_sha256_16": "d43077dd393401e9", "ac_sha256_16": "53555d81365c02e0",
+               "bytes": 93787013120,
                "profile": "profiles/k_eval_qaoa_n16_p2_dep_ad.md"},
 }
 
