@@ -162,7 +162,10 @@ def compile_pool_start(full: bool, cache_dir: str):
     workers = max(1, min(16, (os.cpu_count() or 1)))
     ex = ProcessPoolExecutor(workers, mp_context=mp.get_context("spawn"))
     order = sorted(range(len(pool)), key=lambda i: -(pool[i].n * pool[i].n_angles))
-    futs = {i: ex.submit(compile_blob_cached, pool[i], cache_dir) for i in order}
+    # both compilers for the circuits up to 16 qubits (the smaller AC serves;
+    # the search compiler takes minutes on the 20-qubit p=2 ones)
+    futs = {i: ex.submit(compile_blob_cached, pool[i], cache_dir, method="best" if pool[i].n <= 16 else "ve")
+            for i in order}
     return pool, ex, [futs[i] for i in range(len(pool))], t0
 
 

@@ -75,13 +75,19 @@ def compile_blob(circ, method: str = "ve", **kw) -> bytes:
     """Compile a circuit and serialise its AC (picklable entry point for
     compiling many circuits in worker processes).  method "ve" is variable
     elimination (compiler.compile_circuit), "dpll" the search-based compiler
-    (dnnf.compile_circuit_dpll); both give the same polynomial."""
+    (dnnf.compile_circuit_dpll), "best" the smaller of the two; all give the
+    same polynomial."""
     if method == "ve":
         from .compiler import compile_circuit
         return to_blob(compile_circuit(circ, **kw))
     if method == "dpll":
         from .dnnf import compile_circuit_dpll
         return to_blob(compile_circuit_dpll(circ, **kw))
+    if method == "best":                   # both compilers; the AC with fewer internal nodes
+        from .compiler import compile_circuit
+        from .dnnf import compile_circuit_dpll
+        ve, dp = compile_circuit(circ, **kw), compile_circuit_dpll(circ, **kw)
+        return to_blob(dp if dp.n_internal < ve.n_internal else ve)
     raise ValueError(f"unknown compile method {method!r}")
 
 

@@ -204,3 +204,10 @@ def test_mpe_compilation_gives_the_most_probable_events(name):
     # the same AC still gives every amplitude
     for vals in all_assignments(circ)[:200]:
         assert abs(H.evaluate_assignment(ac, theta, vals) - oracle_amp(circ, theta, vals)) < 1e-13
+
+
+def test_best_of_both_compilers_is_the_smaller_ac():
+    from paper_2103_17226_amd.blob import blob_summary
+    for circ in (W.config(2, small=True)["circuit"], CIRCUITS["vqe2x2_dep_ad"]()):
+        sizes = {m: blob_summary(compile_blob(circ, method=m))["n_int"] for m in ("ve", "dpll", "best")}
+        assert sizes["best"] == min(sizes["ve"], sizes["dpll"])
