@@ -77,7 +77,17 @@ def test_chains_follow_the_oracle_chain():
                                      n_samples=S)
             i = p * C * S + c * S
             assert np.array_equal(got[i:i + S], ref), (p, c)
-    assert (out["rounds"] > 0).all()
+            # one pass per change of state, plus one after the last change
+            bc = gibbs.BranchCache(circ, theta[p])
+            s = gibbs.init_state(circ, 17, p * C + c)
+            changes, last = 0, False
+            for sw in range(burn + S * thin):
+                for v in range(circ.n_vars):
+                    u = gibbs.choose(gibbs.conditional_weights(bc, s, v), gibbs.uniform(17, p * C + c, sw, v))
+                    last = u is not None and u != s[v]
+                    if last:
+                        s[v], changes = u, changes + 1
+            assert out["rounds"].reshape(-1)[p * C + c] == changes + (0 if last else 1)
 
 
 def test_results_do_not_depend_on_the_thread_count():

@@ -25,6 +25,22 @@ def _gpu():
     require_gpu()
 
 
+def oracle_changes(circ, theta, seed, chain, sweeps):
+    """(visits of the oracle's chain that change its state, whether the last
+    visit is one of them), from the oracle's own per-visit steps."""
+    bc = gibbs.BranchCache(circ, theta)
+    s = gibbs.init_state(circ, seed, chain)
+    n, last = 0, False
+    for sw in range(sweeps):
+        for v in range(circ.n_vars):
+            u = gibbs.choose(gibbs.conditional_weights(bc, s, v), gibbs.uniform(seed, chain, sw, v))
+            last = u is not None and u != s[v]
+            if last:
+                s[v] = u
+                n += 1
+    return n, last
+
+
 @pytest.mark.parametrize("variant", ["auto", "stream", "lds-cpw1", "lds-cpw2", "lds-cpw4", "lds-wpc4", "global"])
 def test_same_chain_bitwise_c128(variant, monkeypatch):
     note(f"same-chain bitwise ({variant})")
@@ -53,7 +69,17 @@ def test_same_chain_bitwise_c128(variant, monkeypatch):
                 got = W.unpack_evidence(circ, states[p, c * spc + j])[0]
                 assert np.array_equal(got, ref[j]), (p, c, j)
                 assert int(samples[p, c * spc + j, 0]) == W.x_index(ref[j][:circ.n])
-    assert int(out["rounds"].min()) >= 1
+    # derivatives are reused while the state is unchanged: one upward and
+    # downward pass per change, plus one for the visits after the last change
+    rounds = out["rounds"].cpu().numpy()
+    visits = 0
+    for p in range(2):
+        for c in range(cpp):
+            ch = p * cpp + c
+            n, last = oracle_changes(circ, theta[p], seed, ch, burn + spc * thin)
+            assert int(rounds[ch]) == n + (0 if last else 1), (ch, int(rounds[ch]), n, last)
+            visits += (burn + spc * thin) * circ.n_vars
+    assert rounds.sum() < visits
 
 
 @pytest.mark.parametrize("name,sweeps", [("ring3", 1), ("ring3", 2), ("bell", 1), ("bell", 3)])
