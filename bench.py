@@ -25,8 +25,11 @@ from the pool, P ~ log-uniform{1..256} parameter sets, an amplitude request
 a gradient w.p. 0.5 -- through the continuous-batching loop at 200, 500,
 1000 and 2000 req/s (10 s warm-up and 60 s measured at 2000 req/s, 5 s and
 15 s at the lower rates);
-requests estimated to hold the device over 0.5 s are split into parts; p50/p99
-latency from arrival to completion, throughput and outcomes per offered rate.
+requests estimated to hold the device over 0.5 s are split into parts; 12
+streams, each on a hardware queue of its own (the process asks for 16); p50/p99
+latency from arrival to completion, throughput (requests completed inside the
+measured window per second) and outcomes per offered rate, and the admission
+estimate against requests run alone.
 The pool (all 40 circuits; the p=2, n=20 ones compile to ACs of about a
 million nodes) compiles in worker processes while the other legs run, with
 a blob cache on disk; --serve-pool fast leaves the n=20, p=2 circuits out.
@@ -116,7 +119,11 @@ def parse():
     ap.add_argument("--serve-pool", choices=["fast", "full"], default="full")
     ap.add_argument("--blob-cache", default=os.path.join(os.path.expanduser("~"), ".cache", "qkc_blobs"),
                     help="directory of cached compiled serving-pool blobs ('' for none)")
-    ap.add_argument("--serve-streams", type=int, default=8)
+    ap.add_argument("--serve-streams", type=int, default=12)
+    ap.add_argument("--serve-hw-queues", type=int, default=16,
+                    help="hardware queues of this process (GPU_MAX_HW_QUEUES, read when HIP starts; at most 32): "
+                         "at least one per serving stream, so a short launch never waits behind a long kernel "
+                         "on a shared queue")
     ap.add_argument("--serve-queue", type=int, default=16)
     ap.add_argument("--serve-part-streams", type=int, default=1,
                     help="streams the parts of split requests hold at once, in total")
@@ -175,6 +182,53 @@ def compile_pool_finish(started):
     ex.shutdown()
     blobs = [b for b, _ in out]
     return pool, blobs, time.perf_counter() - t0, sum(1 for _, hit in out if hit)
+
+
+def estimate_check(graphs, pool, args, n=40, budget_s=20.0):
+    """The admission estimate against each request's service time when it
+    runs alone (one stream, nothing else on the device): requests of the
+    serving mix that the server would launch whole, each launched twice and
+    the second launch timed from launch to completion (inputs staged from
+    the host, results copied back).  Under load the same ratio also holds
+    the time a launch waits for compute units behind the other streams."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2103_17226_amd.serve import GraphExecutor, Request
+    edges = {c.name: c.edges for c in pool}
+    ex = GraphExecutor(graphs, edges, n_streams=1)
+    reqs = W.serving_requests(pool, 50.0, 10.0, seed=W.sub_seed("arrivals", 5) + 7919)
+    rows, t_all = [], time.perf_counter()
+    for r in reqs:
+        if len(rows) >= n or time.perf_counter() - t_all > budget_s:
+            break
+        q = Request(graph=pool[r["circuit"]].name, theta=r["theta"], evidence=r.get("evidence"),
+                    param_of=r.get("param_of"), weight=r.get("weight"), samples=r["samples"], grad=r["grad"],
+                    burn_in=10, seed=r["seed"])
+        q.rid = len(rows)
+        est = ex.cost(q)
+        if est > args.serve_max_seconds:
+            continue
+        for rep in range(2):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            h = ex.launch([q], 0)
+            h[0].synchronize()
+            ex.results(h)
+            dt = time.perf_counter() - t
+        rows.append((dt / est, dt, est, q.kind, graphs[q.graph].info["n_internal"]))
+    del ex
+    torch.cuda.synchronize()
+    if not rows:
+        return None
+    ratio = np.array([x[0] for x in rows])
+    return {"requests": len(rows), "ratio_p50": float(np.median(ratio)), "ratio_min": float(ratio.min()),
+            "ratio_max": float(ratio.max()),
+            "ratio_p50_above_10ms": (float(np.median([x[0] for x in rows if x[1] > 0.01]))
+                                     if any(x[1] > 0.01 for x in rows) else None),
+            "service_ms_p50": float(np.median([x[1] for x in rows]) * 1e3),
+            "est_ms_p50": float(np.median([x[2] for x in rows]) * 1e3)}
 
 
 def serve_run(graphs, pool, rate, args):
@@ -244,7 +298,11 @@ def serve_run(graphs, pool, rate, args):
     for q in window:
         counts[outcome(q)] += 1
     ok = [q for q in window if outcome(q) == "completed"]
-    span = max([q.t_done for q in ok] + [t_end]) - since
+    # steady-state rate: requests of any arrival time completed inside the
+    # measured window (a split request finishing in the drain does not
+    # stretch the window)
+    span = t_end - since
+    done_in = [q for q in futs if outcome(q) == "completed" and since <= q.t_done <= t_end]
     # how the admission estimate compares with the time each request held a stream
     ratio = [(q.t_done - q.t_start) / max(ex.cost(q), 1e-6) for q in ok if not isinstance(q.part, dict)]
     stuck = [{"graph": q.graph, "kind": q.kind, "P": q.n_params, "S": q.samples, "rows": q.n_rows,
@@ -253,9 +311,10 @@ def serve_run(graphs, pool, rate, args):
            **counts, "split_requests": st["split_requests"], "split_parts": st["split_parts"],
            "p50_ms": st.get("p50_ms"), "p99_ms": st.get("p99_ms"), "mean_ms": st.get("mean_ms"),
            "whole_requests": st["whole"], "split_requests_latency": st["split"],
-           "throughput_rps": len(ok) / span,
-           "samples_per_s": sum(q.n_params * q.samples for q in ok) / span,
-           "amplitudes_per_s": sum(q.n_rows for q in ok) / span,
+           "completed_in_window": len(done_in),
+           "throughput_rps": len(done_in) / span,
+           "samples_per_s": sum(q.n_params * q.samples for q in done_in) / span,
+           "amplitudes_per_s": sum(q.n_rows for q in done_in) / span,
            "launches": st["launches"], "merged": st["merged"], "max_inflight": st["max_inflight"],
            "peak_gib": st["peak_bytes"] / (1 << 30),
            "launch_host_ms_p50": float(np.median([(q.t_launched - q.t_start) * 1e3 for q in ok])) if ok else None,
@@ -659,6 +718,9 @@ def main():
     started = None
     if not args.no_serve:         # compiles while the GPU legs run
         started = compile_pool_start(args.serve_pool == "full", args.blob_cache)
+        if not 1 <= args.serve_hw_queues <= 32:
+            sys.exit("--serve-hw-queues must be in [1, 32]")
+        os.environ["GPU_MAX_HW_QUEUES"] = str(args.serve_hw_queues)     # before HIP starts
     import numpy as np
     import torch
 
@@ -798,6 +860,8 @@ def main():
         print("# serving pool (compiled in the background)", file=sys.stderr, flush=True)
         pool, blobs, t_pool, cache_hits = compile_pool_finish(started)
         graphs = {c.name: ACGraph(b, device=0) for c, b in zip(pool, blobs)}
+        print("# admission estimate, requests alone", file=sys.stderr, flush=True)
+        est_alone = estimate_check(graphs, pool, args)
         runs = []
         for rate in [float(x) for x in args.serve_rates.split(",") if x]:
             print(f"# serving at {rate:g} req/s", file=sys.stderr, flush=True)
@@ -808,12 +872,14 @@ def main():
                         "samples/set (S>=2 with a gradient), gradient w.p. 0.5; c64",
             "pool_circuits": len(pool), "pool_compile_s": t_pool, "pool_cache_hits": cache_hits,
             "pool_ac_nodes_max": max(gr.info["n_internal"] for gr in graphs.values()),
-            "streams": args.serve_streams, "queue_limit": args.serve_queue,
+            "streams": args.serve_streams, "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES"),
+            "queue_limit": args.serve_queue,
             "budget_gib": args.serve_budget_gib, "max_request_seconds": args.serve_max_seconds,
             "part_streams": args.serve_part_streams, "part_share": args.serve_part_share,
             "max_split": args.serve_max_split, "split_backlog_s": args.serve_split_backlog,
             "warmup_s": args.serve_warmup, "measured_s": args.serve_seconds,
             "measured_s_lower_rates": args.serve_seconds_low,
+            "estimate_alone": est_alone,
             "runs": runs,
         }
         main_run = max(runs, key=lambda r: r["offered_rps"]) if runs else {}

@@ -720,7 +720,13 @@ class GraphExecutor:
     stream; results are copied back on the same stream into pinned host
     buffers before the completion event, so the scheduler never blocks on the
     device.  Every launch brings its own workspace (the graph's cached one is
-    shared, and launches of one graph overlap)."""
+    shared, and launches of one graph overlap).
+
+    HIP maps streams onto the process's hardware queues (GPU_MAX_HW_QUEUES,
+    read when HIP starts; 4 unless set), and launches on streams that share a
+    queue run one after the other: with fewer queues than streams a short
+    request can wait behind a long kernel of another stream.  Give the
+    process at least one queue per stream."""
 
     def __init__(self, graphs: Dict[str, Any], cost_edges: Optional[Dict[str, Any]] = None,
                  n_streams: int = 8, device: int = 0):
