@@ -117,7 +117,10 @@ typedef struct {
                                   (from a node's level to its last reader's level):
                                   the rows per element an amplitude call keeps;
                                   n_internal when there is no plan             */
-    int32_t reserved;          /* 0 */
+    int32_t max_siblings;      /* most siblings (other factors of the term) of one
+                                  occurrence of a super-node, indicator or selector
+                                  in the plan, 0..3; at most 2 lets the streaming
+                                  sampler take larger occurrence groups          */
     int64_t n_super_node_factors; /* factors that are super-nodes (rows read upward) */
     int64_t n_super_down_reads;   /* per occurrence of a super-node as a factor: the
                                      parent's adjoint row and each super-node sibling */

@@ -36,7 +36,7 @@ class ACInfo(ctypes.Structure):
                 ("root", ctypes.c_int32), ("device", ctypes.c_int32),
                 ("n_prod_flops", ctypes.c_int64), ("n_selectors", ctypes.c_int32),
                 ("n_super", ctypes.c_int32), ("n_super_levels", ctypes.c_int32),
-                ("max_live", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("max_live", ctypes.c_int32), ("max_siblings", ctypes.c_int32),
                 ("n_super_node_factors", ctypes.c_int64), ("n_super_down_reads", ctypes.c_int64),
                 ("n_super_leaf_reads", ctypes.c_int64)]
 

@@ -371,6 +371,7 @@ struct HostSop {
     std::vector<uint32_t> srow;
     uint32_t S = 0, L = 0, root = 0, max_factors = 0, live_rows = 0;
     uint64_t node_factors = 0, down_reads = 0, leaf_reads = 0;   // row counts of the streaming model
+    uint32_t max_sib = 0;      // most siblings of an occurrence of a super-node or leaf target
     bool ok = false;
 };
 
@@ -538,6 +539,10 @@ HostSop build_sop(uint32_t N, const uint8_t *op, const uint32_t *row_ptr, const 
     }
     for (uint32_t k = 0; k < n_sel; ++k)
         P.osel.insert(P.osel.end(), occ[static_cast<size_t>(M) + n_ind + k].size(), vsel[k]);
+    for (size_t t = 0; t < static_cast<size_t>(M) + n_ind + n_sel; ++t)
+        for (const auto &rec : occ[t])
+            for (uint32_t k = 1; k < 4; ++k)
+                if (rec[k] != NO_SIBLING) P.max_sib = std::max(P.max_sib, k);
     // rows of the upward pass alone: super-node j lives from its level to the
     // level of its last consumer (the root to the end); rows are handed out
     // in level order and freed after their last reading level
@@ -973,6 +978,9 @@ extern "C" ac_status ac_load(const void *blob, size_t nbytes, int device, ac_gra
         sp.frec_live = reinterpret_cast<const uint64_t *>(at(36));
         sp.srow = reinterpret_cast<const uint32_t *>(at(37));
         sp.live_rows = static_cast<int32_t>(hs.live_rows);
+        // QKC_SAMPLE_SIB3=1 keeps the three-sibling groups on any plan (tests)
+        const char *sib_env = std::getenv("QKC_SAMPLE_SIB3");
+        sp.occ_sib3 = hs.max_sib > 2 || (sib_env && std::atoi(sib_env) == 1) ? 1 : 0;
         // the sampler's decision pass keeps one change bit per variable and
         // handles variables of at most SEL_DOM values
         bool small_doms = true;
@@ -1040,6 +1048,7 @@ extern "C" ac_status ac_load(const void *blob, size_t nbytes, int device, ac_gra
         inf.n_super_down_reads = static_cast<int64_t>(hs.down_reads);
         inf.n_super_leaf_reads = static_cast<int64_t>(hs.leaf_reads);
         inf.max_live = static_cast<int32_t>(hs.live_rows);
+        inf.max_siblings = static_cast<int32_t>(hs.max_sib);
     }
     *out = g;
     return AC_OK;

@@ -161,6 +161,9 @@ struct SopPlan {
     int32_t max_factors;        // most factors of one super-node
     int32_t mask_words;         // words of the per-chain change mask of the streaming
                                 // sampler's decision pass (0: decisions in the scan only)
+    int32_t occ_sib3;           // 1 if an occurrence of a super-node or an indicator or
+                                // selector leaf has three siblings (the streaming
+                                // passes then walk occurrences in smaller groups)
     // Row reuse for the upward pass alone (no downward pass reads the values
     // later): a super-node's row is free once its last consumer's level has
     // run, so rows are handed out again level by level (greedy in level order,

@@ -723,8 +723,8 @@ __device__ bool stage_tile(const DevGraph &g, uint64_t *ev_s, Weight<T> *ang_s, 
 // ---------------------------------------------------------------------------
 
 // complex64: 8 waves per SIMD (64 VGPRs, a few spilled): rows wait on HBM and
-// more resident waves hide it (16-qubit noisy QAOA, 262,144 amplitudes:
-// 6 waves 74 ms, 8 waves 66 ms)
+// more resident waves hide it (16-qubit noisy QAOA, 262,144 amplitudes, on
+// the binary-node plan: 6 waves 74 ms, 8 waves 66 ms)
 template <typename T, bool SOP>
 __global__ __launch_bounds__(MAX_BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 1, 8))) void k_eval(DevGraph g, SopPlan sp, const double *theta, const int32_t *param_of, int P,
                                                 const uint64_t *evidence, int64_t B, const Weight<T> *wfix,
@@ -901,9 +901,8 @@ __global__ __launch_bounds__(MAX_BLOCK) void k_mpe(DevGraph g, MpePlan mp, const
 // ---------------------------------------------------------------------------
 
 // complex64: 6 waves per SIMD (80 VGPRs, a few spilled; 5 waves unbounded):
-// 16-qubit noisy QAOA gradients over 262,144 elements 283 -> 255 ms (4 waves
-// per workgroup as everywhere; the downward pass's edge groups of eight took
-// it to 252 ms)
+// 16-qubit noisy QAOA gradients over 262,144 elements, on the binary-node
+// plan, 283 -> 255 ms
 template <typename T, bool SOP>
 __global__ __launch_bounds__(MAX_BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 1, 8))) void k_grad(DevGraph g, SopPlan sp, const double *theta, const int32_t *param_of, int P,
                                                 const uint64_t *evidence, int64_t B, const Weight<T> *wfix,
@@ -1325,14 +1324,24 @@ __device__ __forceinline__ double gibbs_weight(const cplx<T> &d) {
 #ifndef SOP_KE_LEAF
 #define SOP_KE_LEAF 2
 #endif
+// the same groups when no occurrence of the plan has a third sibling (two
+// sibling rows per occurrence instead of three, so more fit in registers)
+#ifndef SOP_KE2
+#define SOP_KE2 4
+#endif
+#ifndef SOP_KE_LEAF2
+#define SOP_KE_LEAF2 3
+#endif
 // complex64 waves per SIMD the streaming sampler's register budget is bounded for
 #ifndef STREAM_WAVES_PER_EU
 #define STREAM_WAVES_PER_EU 6
 #endif
 
 // Rows of the region: super-node values [0, S), adjoints [S, 2S), indicator
-// derivatives d root / d lambda_{v=u} [2S, 2S + n_ind).
-template <typename T>
+// derivatives d root / d lambda_{v=u} [2S, 2S + n_ind).  SIB3 = false: no
+// occurrence of the plan has a third sibling, so the occurrence walks hold
+// two sibling rows each and take larger groups.
+template <typename T, bool SIB3>
 struct StreamTile {
     DevGraph g;
     RowBuf<T> rb;
@@ -1428,13 +1437,15 @@ struct StreamTile {
         return term;
     }
 
+    // occurrence record o (parent, siblings); without SIB3 the third sibling
+    // is known to be absent and is not read
     __device__ __forceinline__ void load_occ(const SopPlan &sp, uint32_t o, bool in, uint32_t (&r)[4]) const {
         if (in) {
             const uint32_t *q = sp.occ + 4 * static_cast<size_t>(o);
             r[0] = cld(q);
             r[1] = cld(q + 1);
             r[2] = cld(q + 2);
-            r[3] = cld(q + 3);
+            r[3] = SIB3 ? cld(q + 3) : NO_SIBLING;
         } else {
             r[0] = 0u;
             r[1] = r[2] = r[3] = NO_SIBLING;
@@ -1445,10 +1456,10 @@ struct StreamTile {
     // selector leaves): out(t, sum over the occurrences of t of adj[parent] *
     // siblings), the occurrences in increasing parent order.  The occurrences
     // of the whole range are walked in groups of KE whose row loads (adjoint
-    // and sibling rows) are all issued before any term is added.
-    template <typename Out>
-    __device__ __forceinline__ void pull_targets(const SopPlan &sp, uint32_t t0, uint32_t t1, Out out) const {
-        constexpr int KE = sizeof(T) == 4 ? SOP_KE : SOP_KE / 2;
+    // and sibling rows) are all issued before any term is added.  Without
+    // SIB3 no occurrence has a third sibling.
+    template <int KE, typename Out>
+    __device__ __forceinline__ void pull_group(const SopPlan &sp, uint32_t t0, uint32_t t1, Out out) const {
         const uint32_t e_end = cld(sp.ostart + t1);
         uint32_t t = t0;
         uint32_t t_next = cld(sp.ostart + t0 + 1);      // first occurrence past target t
@@ -1463,7 +1474,7 @@ struct StreamTile {
                 ap[j] = rb.ld(adj0 + rr[j][0]);
                 s0[j] = row(rr[j][1]);
                 s1[j] = row(rr[j][2]);
-                s2[j] = row(rr[j][3]);
+                s2[j] = SIB3 ? row(rr[j][3]) : cplx<T>{T(0), T(0)};
             }
 #pragma unroll
             for (int j = 0; j < KE; ++j) {
@@ -1487,6 +1498,11 @@ struct StreamTile {
             ai = 0.0;
         }
     }
+    template <typename Out>
+    __device__ __forceinline__ void pull_targets(const SopPlan &sp, uint32_t t0, uint32_t t1, Out out) const {
+        constexpr int KE = SIB3 ? SOP_KE : SOP_KE2;
+        pull_group<sizeof(T) == 4 ? KE : KE / 2>(sp, t0, t1, out);
+    }
 
     __device__ void backward(const SopPlan &sp, int wave, int nwaves) {
         constexpr int KB = SOP_KB;
@@ -1503,6 +1519,44 @@ struct StreamTile {
         }
     }
 
+    // acc[u] += sum over the selector occurrences [e, e1) of adj[parent] *
+    // siblings * W[slot of value u], in occurrence order; groups of KE
+    // occurrences issue their row loads together.  Without SIB3 no occurrence
+    // has a third sibling.
+    template <int KE>
+    __device__ __forceinline__ void sel_occurrences(const SopPlan &sp, uint32_t e, uint32_t e1, uint32_t sel_e0,
+                                                    cplx<T> (&acc)[SEL_DOM]) const {
+        for (; e < e1; e += KE) {
+            uint32_t rr[KE][4];
+            uint32_t qe[KE];
+            cplx<T> ap[KE], sa[KE], sb[KE], sc[KE];
+#pragma unroll
+            for (int j = 0; j < KE; ++j) {
+                const bool in = e + j < e1;
+                load_occ(sp, e + j, in, rr[j]);
+                qe[j] = in ? cld(sp.osel + e + j - sel_e0) : 0u;
+            }
+#pragma unroll
+            for (int j = 0; j < KE; ++j) {
+                ap[j] = e + j < e1 ? rb.ld(adj0 + rr[j][0]) : cplx<T>{T(0), T(0)};
+                sa[j] = row(rr[j][1]);
+                sb[j] = row(rr[j][2]);
+                sc[j] = SIB3 ? row(rr[j][3]) : cplx<T>{T(0), T(0)};
+            }
+#pragma unroll
+            for (int j = 0; j < KE; ++j) {
+                if (e + j >= e1) break;
+                const cplx<T> term = occ_term(rr[j], ap[j], sa[j], sb[j], sc[j]);
+                const uint32_t *rec = g.sel + static_cast<size_t>(qe[j]) * SEL_REC;
+#pragma unroll
+                for (int u = 0; u < SEL_DOM; ++u) {
+                    const uint32_t sl = cld(rec + 1 + u);
+                    if (sl != NO_SLOT) acc[u] = cadd(acc[u], cmul(term, wfix[sl]));
+                }
+            }
+        }
+    }
+
     // d root / d lambda_{v=u}, one wave per variable: the adjoint sums of v's
     // indicator leaves into its D rows, then every occurrence of v's selector
     // leaves (contiguous in the plan, in groups of KE whose row loads issue
@@ -1512,7 +1566,8 @@ struct StreamTile {
     // handed to dec(v, d, dom) while still in registers.
     template <typename Decide>
     __device__ void leaf_derivatives(const SopPlan &sp, int wave, int nwaves, bool decide, Decide &&dec) {
-        constexpr int KE = sizeof(T) == 4 ? SOP_KE_LEAF : SOP_KE_LEAF / 2 > 0 ? SOP_KE_LEAF / 2 : 1;
+        constexpr int KL = SIB3 ? SOP_KE_LEAF : SOP_KE_LEAF2;
+        constexpr int KE = sizeof(T) == 4 ? KL : KL / 2 > 0 ? KL / 2 : 1;
         const uint32_t M = static_cast<uint32_t>(sp.S);
         const uint32_t s0t = M + static_cast<uint32_t>(g.n_ind);   // first selector target
         const uint32_t sel_e0 = cld(sp.ostart + s0t);               // first selector occurrence
@@ -1535,36 +1590,8 @@ struct StreamTile {
                         if (u == static_cast<uint32_t>(k)) acc[k] = val;
                 });
             if (q0 != q1) {
-                const uint32_t e1 = cld(sp.ostart + s0t + q1);
-                for (uint32_t e = cld(sp.ostart + s0t + q0); e < e1; e += KE) {
-                    uint32_t rr[KE][4];
-                    uint32_t qe[KE];
-                    cplx<T> ap[KE], sa[KE], sb[KE], sc[KE];
-#pragma unroll
-                    for (int j = 0; j < KE; ++j) {
-                        const bool in = e + j < e1;
-                        load_occ(sp, e + j, in, rr[j]);
-                        qe[j] = in ? cld(sp.osel + e + j - sel_e0) : 0u;
-                    }
-#pragma unroll
-                    for (int j = 0; j < KE; ++j) {
-                        ap[j] = e + j < e1 ? rb.ld(adj0 + rr[j][0]) : cplx<T>{T(0), T(0)};
-                        sa[j] = row(rr[j][1]);
-                        sb[j] = row(rr[j][2]);
-                        sc[j] = row(rr[j][3]);
-                    }
-#pragma unroll
-                    for (int j = 0; j < KE; ++j) {
-                        if (e + j >= e1) break;
-                        const cplx<T> term = occ_term(rr[j], ap[j], sa[j], sb[j], sc[j]);
-                        const uint32_t *rec = g.sel + static_cast<size_t>(qe[j]) * SEL_REC;
-#pragma unroll
-                        for (int u = 0; u < SEL_DOM; ++u) {
-                            const uint32_t sl = cld(rec + 1 + u);
-                            if (sl != NO_SLOT) acc[u] = cadd(acc[u], cmul(term, wfix[sl]));
-                        }
-                    }
-                }
+                const uint32_t e0 = cld(sp.ostart + s0t + q0), e1 = cld(sp.ostart + s0t + q1);
+                sel_occurrences<KE>(sp, e0, e1, sel_e0, acc);
 #pragma unroll
                 for (int u = 0; u < SEL_DOM; ++u)
                     if (static_cast<uint32_t>(u) < dom) rb.st(d0 + base + u, acc[u]);
@@ -1576,9 +1603,13 @@ struct StreamTile {
 
 // complex64: 6 waves per SIMD (80 VGPRs, a few spilled to scratch) -- the
 // kernel waits on dependent row loads and more resident waves hide more of it
-// (measured: 4 waves 1.49 s, 5 waves 1.44 s, 6-8 waves 1.41 s per 1,024,000
-// 8-qubit samples)
-template <typename T>
+// (1,024,000 8-qubit samples on the sum-of-products plan with three sibling
+// rows per occurrence: 4 waves 546 ms, 5 waves 509 ms, 6 waves 484 ms; with
+// two, 6 and 7 waves both 461 ms).  SIB3 = false when the plan has no
+// occurrence with a third sibling: the downward pass then holds two sibling
+// rows per occurrence in its groups of 4 and the leaf step takes groups of 3
+// instead of 2 (larger groups spill); the chains are the same.
+template <typename T, bool SIB3>
 __global__ __launch_bounds__(MAX_BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? STREAM_WAVES_PER_EU : 1, 8))) void k_sample_stream(DevGraph g, SopPlan sp, const double *theta,
                                                          const Weight<T> *wfix, cplx<T> *vals, size_t per_wg,
                                                          SampleArgs a) {
@@ -1601,7 +1632,7 @@ __global__ __launch_bounds__(MAX_BLOCK) __attribute__((amdgpu_waves_per_eu(sizeo
     cplx<T> *D = val + 2 * static_cast<size_t>(sp.S) * WAVE;    // [n_ind][64]
     for (int s2 = threadIdx.x; s2 < g.S; s2 += blockDim.x) fix_s[s2] = wval(wfix[s2]);
     const uint32_t N = static_cast<uint32_t>(sp.S);
-    StreamTile<T> t{g, RowBuf<T>(val, per_wg / WAVE, lane), N, 2 * N, ev_s, ang_s, fix_s, lane};
+    StreamTile<T, SIB3> t{g, RowBuf<T>(val, per_wg / WAVE, lane), N, 2 * N, ev_s, ang_s, fix_s, lane};
     const int64_t stride = static_cast<int64_t>(gridDim.x) * WAVE;
     const uint32_t total_sweeps = static_cast<uint32_t>(a.burn_in) +
                                   static_cast<uint32_t>(a.spc) * static_cast<uint32_t>(a.thin);
@@ -2456,7 +2487,8 @@ int resident_blocks(const DevGraph &g, const SopPlan &sp, int which, int block) 
                               : reinterpret_cast<const void *>(&k_grad<T, false>); break;
         case 2: fn = reinterpret_cast<const void *>(&k_sample<T>); break;
         case 3:
-            fn = reinterpret_cast<const void *>(&k_sample_stream<T>);
+            fn = sp.occ_sib3 ? reinterpret_cast<const void *>(&k_sample_stream<T, true>)
+                             : reinterpret_cast<const void *>(&k_sample_stream<T, false>);
             lds = stream_lds_bytes<T>(g, sp);
             break;
         default: return 1;
@@ -2482,8 +2514,12 @@ hipError_t launch_sample_stream(const DevGraph &g, const SopPlan &sp, int grid, 
                                 hipStream_t st) {
     if (block < WAVE || block > MAX_BLOCK || block % WAVE != 0) return hipErrorInvalidValue;
     size_t lds = stream_lds_bytes<T>(g, sp);
-    hipLaunchKernelGGL(k_sample_stream<T>, dim3(grid), dim3(block), lds, st, g, sp, theta,
-                       reinterpret_cast<const Weight<T> *>(wfix), reinterpret_cast<cplx<T> *>(vals), per_wg_elems, a);
+    if (sp.occ_sib3)
+        hipLaunchKernelGGL((k_sample_stream<T, true>), dim3(grid), dim3(block), lds, st, g, sp, theta,
+                           reinterpret_cast<const Weight<T> *>(wfix), reinterpret_cast<cplx<T> *>(vals), per_wg_elems, a);
+    else
+        hipLaunchKernelGGL((k_sample_stream<T, false>), dim3(grid), dim3(block), lds, st, g, sp, theta,
+                           reinterpret_cast<const Weight<T> *>(wfix), reinterpret_cast<cplx<T> *>(vals), per_wg_elems, a);
     return hipGetLastError();
 }
 template hipError_t launch_fixed_slots<float>(const DevGraph &, const double *, void *, hipStream_t);

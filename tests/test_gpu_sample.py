@@ -15,6 +15,7 @@ import torch
 
 import workloads as W
 from oracle import gibbs, sim, stats
+from paper_2103_17226_amd.dnnf import compile_circuit_dpll
 from tests.gpu_common import graph, note, require_gpu
 
 pytestmark = pytest.mark.gpu
@@ -41,11 +42,15 @@ def oracle_changes(circ, theta, seed, chain, sweeps):
     return n, last
 
 
-@pytest.mark.parametrize("variant", ["auto", "stream", "lds-cpw1", "lds-cpw2", "lds-cpw4", "lds-wpc4", "global"])
+@pytest.mark.parametrize("variant", ["auto", "stream", "stream-sib3", "lds-cpw1", "lds-cpw2", "lds-cpw4", "lds-wpc4",
+                                     "global"])
 def test_same_chain_bitwise_c128(variant, monkeypatch):
     note(f"same-chain bitwise ({variant})")
     if variant in ("global", "stream"):
         monkeypatch.setenv("QKC_SAMPLE_KERNEL", variant)
+    elif variant == "stream-sib3":                   # three-sibling occurrence groups
+        monkeypatch.setenv("QKC_SAMPLE_KERNEL", "stream")
+        monkeypatch.setenv("QKC_SAMPLE_SIB3", "1")
     elif variant == "lds-wpc4":                      # four waves on each chain
         monkeypatch.setenv("QKC_SAMPLE_KERNEL", "lds")
         monkeypatch.setenv("QKC_SAMPLE_CPW", "1")
@@ -80,6 +85,33 @@ def test_same_chain_bitwise_c128(variant, monkeypatch):
             assert int(rounds[ch]) == n + (0 if last else 1), (ch, int(rounds[ch]), n, last)
             visits += (burn + spc * thin) * circ.n_vars
     assert rounds.sum() < visits
+
+
+def test_two_sibling_groups_give_the_same_chains(monkeypatch):
+    # the streaming sampler takes larger occurrence groups when no occurrence
+    # of the plan has a third sibling; the terms are added in the same order,
+    # so the chains equal those of the three-sibling groups bit for bit
+    monkeypatch.setenv("QKC_SAMPLE_KERNEL", "stream")
+    cfg = W.config(2)
+    circ = cfg["circuit"]
+    outs = []
+    for forced in ("0", "1"):
+        monkeypatch.setenv("QKC_SAMPLE_SIB3", forced)
+        g = graph(compile_circuit_dpll(circ))
+        if forced == "0":
+            assert g.info["max_siblings"] == 2
+        for dtype in ("c64", "c128"):
+            out = g.sample(cfg["theta"][:8], 300, 1, 4, 1, 5, dtype=dtype, want_states=True, want_rounds=True)
+            outs.append((out["states"].cpu(), out["rounds"].cpu()))
+    for a, b in zip(outs[:2], outs[2:]):
+        assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    # plans with a third sibling exist among the test circuits (they run the
+    # three-sibling groups: test_gpu_random_circuits, and the stream-sib3
+    # variant of test_same_chain_bitwise_c128 forces them)
+    monkeypatch.delenv("QKC_SAMPLE_SIB3")
+    sibs = [graph(W.random_circuit(k)).info["max_siblings"] for k in range(6)]
+    note(f"  most siblings of random circuits 0-5: {sibs}")
+    assert 3 in sibs and all(0 <= x <= 3 for x in sibs)
 
 
 @pytest.mark.parametrize("name,sweeps", [("ring3", 1), ("ring3", 2), ("bell", 1), ("bell", 3)])
