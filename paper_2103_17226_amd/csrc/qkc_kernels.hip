@@ -1332,9 +1332,18 @@ __device__ __forceinline__ double gibbs_weight(const cplx<T> &d) {
 #ifndef SOP_KE_LEAF2
 #define SOP_KE_LEAF2 3
 #endif
-// complex64 waves per SIMD the streaming sampler's register budget is bounded for
+// variables whose Gibbs weights the scan loads together (complex64; 1 holds
+// fewer registers and measured faster than 2 or 3)
+#ifndef SCAN_PF
+#define SCAN_PF 1
+#endif
+// complex64 waves per SIMD the streaming sampler's register budget is bounded
+// for (three-sibling instance, two-sibling instance)
 #ifndef STREAM_WAVES_PER_EU
 #define STREAM_WAVES_PER_EU 6
+#endif
+#ifndef STREAM_WAVES_PER_EU2
+#define STREAM_WAVES_PER_EU2 8
 #endif
 
 // Rows of the region: super-node values [0, S), adjoints [S, 2S), indicator
@@ -1605,12 +1614,14 @@ struct StreamTile {
 // kernel waits on dependent row loads and more resident waves hide more of it
 // (1,024,000 8-qubit samples on the sum-of-products plan with three sibling
 // rows per occurrence: 4 waves 546 ms, 5 waves 509 ms, 6 waves 484 ms; with
-// two, 6 and 7 waves both 461 ms).  SIB3 = false when the plan has no
-// occurrence with a third sibling: the downward pass then holds two sibling
-// rows per occurrence in its groups of 4 and the leaf step takes groups of 3
-// instead of 2 (larger groups spill); the chains are the same.
+// two, 6 and 7 waves both 461 ms, and with the scan loading one variable's
+// weights at a time, 8 waves (64 VGPRs) 453 ms against 456 ms at 6).
+// SIB3 = false when the plan has no occurrence with a third sibling: the
+// downward pass then holds two sibling rows per occurrence in its groups of
+// 4 and the leaf step takes groups of 3 instead of 2 (larger groups spill);
+// the chains are the same.
 template <typename T, bool SIB3>
-__global__ __launch_bounds__(MAX_BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? STREAM_WAVES_PER_EU : 1, 8))) void k_sample_stream(DevGraph g, SopPlan sp, const double *theta,
+__global__ __launch_bounds__(MAX_BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? (SIB3 ? STREAM_WAVES_PER_EU : STREAM_WAVES_PER_EU2) : 1, 8))) void k_sample_stream(DevGraph g, SopPlan sp, const double *theta,
                                                          const Weight<T> *wfix, cplx<T> *vals, size_t per_wg,
                                                          SampleArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1783,7 +1794,7 @@ __global__ __launch_bounds__(MAX_BLOCK) __attribute__((amdgpu_waves_per_eu(sizeo
             }
             // Gibbs weights of the next PF variables, loaded together (the
             // derivatives do not change until the state does)
-            constexpr int PF = sizeof(T) == 4 ? 3 : 2;
+            constexpr int PF = sizeof(T) == 4 ? SCAN_PF : 2;
             double wpf[PF][SEL_DOM];
             int pf_pos = -1;
             for (; scan && !done;) {
