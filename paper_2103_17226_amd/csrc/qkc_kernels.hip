@@ -1340,7 +1340,7 @@ __device__ __forceinline__ double gibbs_weight(const cplx<T> &d) {
 // complex64 waves per SIMD the streaming sampler's register budget is bounded
 // for (three-sibling instance, two-sibling instance)
 #ifndef STREAM_WAVES_PER_EU
-#define STREAM_WAVES_PER_EU 6
+#define STREAM_WAVES_PER_EU 7
 #endif
 #ifndef STREAM_WAVES_PER_EU2
 #define STREAM_WAVES_PER_EU2 8
@@ -1610,12 +1610,14 @@ struct StreamTile {
     }
 };
 
-// complex64: 6 waves per SIMD (80 VGPRs, a few spilled to scratch) -- the
-// kernel waits on dependent row loads and more resident waves hide more of it
-// (1,024,000 8-qubit samples on the sum-of-products plan with three sibling
-// rows per occurrence: 4 waves 546 ms, 5 waves 509 ms, 6 waves 484 ms; with
-// two, 6 and 7 waves both 461 ms, and with the scan loading one variable's
-// weights at a time, 8 waves (64 VGPRs) 453 ms against 456 ms at 6).
+// complex64: the kernel waits on dependent row loads and more resident waves
+// hide more of it, against more spills (1,024,000 8-qubit samples on the
+// sum-of-products plan with three sibling rows per occurrence: 4 waves 546
+// ms, 5 waves 509 ms, 6 waves 484 ms; with two, 6 and 7 waves both 461 ms,
+// and with the scan loading one variable's weights at a time, 8 waves (64
+// VGPRs) 453 ms against 456 ms at 6).  The three-sibling instance runs 7
+// waves (72 VGPRs): 1,000,192 32-qubit samples 1980 / 1872 / 1870 ms at
+// 6 / 7 / 8 waves, but 8 slows the 32-qubit p=2 batch (2715 / 2758 / 2866 ms).
 // SIB3 = false when the plan has no occurrence with a third sibling: the
 // downward pass then holds two sibling rows per occurrence in its groups of
 // 4 and the leaf step takes groups of 3 instead of 2 (larger groups spill);
