@@ -56,11 +56,11 @@ KERNELS = os.path.join(ROOT, "paper_2103_17226_amd", "csrc", "qkc_kernels.hip")
 # kernel source and the AC they were taken on, and the default workload of
 # each leg.
 PROFILED_TRAFFIC = {
-    "k_sample_stream": {"kernel_sha256_16": "90e9e0e980219ba0", "ac_sha256_16": "d3190d478a0e63f4",
-                        "bytes": 1779045814272,
+    "k_sample_stream": {"kernel_sha256_16": "4febe89df2813f23", "ac_sha256_16": "d3190d478a0e63f4",
+                        "bytes": 1777480143872,
                         "profile": "profiles/k_sample_stream_qaoa_n8_p1_dep.md"},
-    "k_eval": {"kernel_sha256_16": "90e9e0e980219ba0", "ac_sha256_16": "53555d81365c02e0",
-               "bytes": 93890745344,
+    "k_eval": {"kernel_sha256_16": "4febe89df2813f23", "ac_sha256_16": "53555d81365c02e0",
+               "bytes": 93710172160,
                "profile": "profiles/k_eval_qaoa_n16_p2_dep_ad.md"},
 }
 
@@ -105,6 +105,7 @@ def parse():
     ap.add_argument("--no-eval", action="store_true")
     ap.add_argument("--eval-steps", type=int, default=5)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--mpe-params", type=int, default=4096, help="angle pairs of the MPE leg (16 outcomes each)")
     ap.add_argument("--serve-rates", default="200,500,1000,2000",
                     help="offered request rates (req/s), one serving run each")
     ap.add_argument("--serve-seconds", type=float, default=60.0,
@@ -456,10 +457,10 @@ def eval_leg(args, circ_cfg):
     return out
 
 
-def mpe_leg(steps: int):
+def mpe_leg(steps: int, P: int = 4096):
     """Most probable noise events (max-product pass, complex128) for every
-    outcome of a 4-qubit ring QAOA with 8 channels, 1024 angle pairs x 16
-    outcomes = 16,384 queries per call."""
+    outcome of a 4-qubit ring QAOA with 8 channels, P angle pairs x 16
+    outcomes per call."""
     import numpy as np
     import torch
 
@@ -472,7 +473,7 @@ def mpe_leg(steps: int):
     t_comp = time.perf_counter() - t0
     g = ACGraph(ac, device=0)
     dev = g.torch_device
-    P, n = 1024, circ.n
+    n = circ.n
     theta = torch.as_tensor(W.uniform_angles(P, circ.n_angles, W.sub_seed("angles", 7)), device=dev)
     vals = np.zeros((P << n, circ.n_vars), dtype=np.int64)
     vals[:, :n] = np.tile([[(x >> q) & 1 for q in range(n)] for x in range(1 << n)], (P, 1))
@@ -495,7 +496,7 @@ def mpe_leg(steps: int):
     e_ii = int((tags == 0).sum())
     up = 16 * (e_ii + N) + 8 * g.info["n_words"]          # upward pass, complex128 rows
     out = {"workload": "most probable noise events of every outcome: QAOA p=1, 4-ring, amplitude damping "
-                       "0.05 after each H, depolarizing 0.02 after each RX (8 channels); 1024 angle pairs x "
+                       f"0.05 after each H, depolarizing 0.02 after each RX (8 channels); {P} angle pairs x "
                        "16 outcomes, complex128",
            "ac_internal_nodes": N, "ac_edges": E, "ac_levels": g.info["n_levels"], "compile_s": t_comp,
            "queries": B, "ms_per_call": t * 1e3, "queries_per_s": B / t, "node_evals_per_s": N * B / t,
@@ -854,7 +855,7 @@ def main():
         print("# 2D Ising VQE", file=sys.stderr, flush=True)
         res["vqe"] = vqe_leg(args.eval_steps)
         print("# most probable explanations", file=sys.stderr, flush=True)
-        res["mpe"] = mpe_leg(args.eval_steps)
+        res["mpe"] = mpe_leg(args.eval_steps, args.mpe_params)
         torch.cuda.empty_cache()
     if started is not None:
         print("# serving pool (compiled in the background)", file=sys.stderr, flush=True)

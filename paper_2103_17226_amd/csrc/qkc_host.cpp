@@ -132,7 +132,7 @@ struct ac_graph {
     int n_cu = 0;
     int resident[2][4] = {{1, 1, 1, 1}, {1, 1, 1, 1}};   // [dtype][eval, grad, sample, stream] per CU
     int stream_waves = 0;                                 // forced waves per streaming workgroup (0: per call)
-    int tile_waves = 0;                                   // forced waves per upward/gradient workgroup (0: per call)
+    int tile_waves = 0;                                   // forced waves per upward/gradient/max-product workgroup (0: per call)
     int wide_resident[2][4][3] = {};                      // [dtype][eval, grad, -, stream][4, 8, 16 waves] per CU
     ac_info_t info{};
     std::vector<uint8_t> var_dom;
@@ -1191,7 +1191,7 @@ bool sample_lds_shape(const ac_graph *g, ac_dtype dt, int64_t chains, int &cpw, 
 // (measured on noisy QAOA ACs of 3.6k and 138k nodes, batches of 1306 to
 // 262,144: the rule picked the fastest size at every point).
 // QKC_STREAM_WAVES forces the sampler's size, QKC_TILE_WAVES (4, 8, 16) the
-// others' (measurements).
+// others' and the max-product kernel's (measurements, tests).
 int wide_block_for(const ac_graph *g, ac_dtype dt, int64_t batch, int kid, int &wg_per_cu) {
     if (kid == 3 && g->stream_waves) {
         wg_per_cu = g->resident[dt][3];
@@ -1234,9 +1234,12 @@ struct Layout {
     int block = BLOCK;         // threads per workgroup
 };
 
-// workgroups per CU of the max-product kernel (a query over small ACs; its
-// rows are complex128)
-constexpr int MPE_WG_PER_CU = 4;
+// The max-product kernel (a query over small ACs; complex128 rows) spreads
+// each tile's levels over 16 waves, two such workgroups per CU (its register
+// budget is bounded for 8 waves per SIMD).  Measured on 16-outcome queries
+// of a 17k-node AC: 512 tiles 5.1 ms against 10.1 ms as four workgroups of
+// 4 waves per CU and 6.3 ms as one of 16.
+constexpr int MPE_WG_PER_CU = 2;
 
 bool make_layout(const ac_graph *g, ac_dtype dt, int64_t batch, int op, Layout &out, size_t tile_cap = 0) {
     if (!g || batch < 0 || (dt != AC_C64 && dt != AC_C128) || op < 0 || op > 3) return false;
@@ -1270,7 +1273,7 @@ bool make_layout(const ac_graph *g, ac_dtype dt, int64_t batch, int op, Layout &
     if (op == AC_OP_MPE) {
         // fewer tiles than two per CU: each tile's levels spread over 16 waves
         wg_per_cu = MPE_WG_PER_CU;
-        if (tiles < 2 * static_cast<int64_t>(g->n_cu)) block = MAX_BLOCK;
+        block = g->tile_waves ? g->tile_waves * WAVE : MAX_BLOCK;
     } else if (kid != 2) {
         block = wide_block_for(g, dt, batch, kid, wg_per_cu);
     }

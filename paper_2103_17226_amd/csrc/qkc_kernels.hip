@@ -801,7 +801,8 @@ __device__ __forceinline__ double mpe_child(const Tile<double> &t, const MpePlan
     return __dadd_rn(__dmul_rn(w.re, w.re), __dmul_rn(w.im, w.im));
 }
 
-__global__ __launch_bounds__(MAX_BLOCK) void k_mpe(DevGraph g, MpePlan mp, const double *theta, const int32_t *param_of,
+// 8 waves per SIMD (64 VGPRs, a few spilled): two 16-wave workgroups per CU
+__global__ __launch_bounds__(MAX_BLOCK) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_mpe(DevGraph g, MpePlan mp, const double *theta, const int32_t *param_of,
                                                int P, const uint64_t *evidence, int64_t B,
                                                const Weight<double> *wfix, cplx<double> *vals, size_t per_wg,
                                                double *prob_out, uint64_t *mpe_out) {

@@ -125,11 +125,16 @@ def test_mpe_of_the_bench_circuit():
         assert tuple(int(k) for k in got[b, 4:]) in ks
 
 
-def test_mpe_is_the_same_for_both_launch_shapes():
-    # a small batch runs each tile on 16 waves, a batch of two or more tiles
-    # per CU on 4; every element is computed by its own lane in a fixed order
+def test_mpe_is_the_same_for_every_launch_shape(monkeypatch):
+    # tiles of 16 waves (two workgroups per CU, grid-stride rounds for large
+    # batches) and of 4 waves give the same bits: every element is computed
+    # by its own lane in a fixed order
     circ = W.qaoa_ring_mpe(4)
-    g = graph(compile_circuit_dpll(circ, mpe=True))
+    ac = compile_circuit_dpll(circ, mpe=True)
+    g = graph(ac)
+    monkeypatch.setenv("QKC_TILE_WAVES", "4")
+    g4 = graph(ac)
+    monkeypatch.delenv("QKC_TILE_WAVES")
     rng = np.random.default_rng(5)
     P = 8
     theta = rng.uniform(0, 2 * np.pi, size=(P, circ.n_angles))
@@ -143,3 +148,6 @@ def test_mpe_is_the_same_for_both_launch_shapes():
     ps, wsm = g.mpe(theta, ev[:200], po[:200])
     assert np.array_equal(pb[:200].cpu().numpy(), ps.cpu().numpy())
     assert np.array_equal(wb[:200].cpu().numpy(), wsm.cpu().numpy())
+    p4, w4 = g4.mpe(theta, ev, po)
+    assert np.array_equal(pb.cpu().numpy(), p4.cpu().numpy())
+    assert np.array_equal(wb.cpu().numpy(), w4.cpu().numpy())
