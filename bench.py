@@ -56,11 +56,11 @@ KERNELS = os.path.join(ROOT, "paper_2103_17226_amd", "csrc", "qkc_kernels.hip")
 # kernel source and the AC they were taken on, and the default workload of
 # each leg.
 PROFILED_TRAFFIC = {
-    "k_sample_stream": {"kernel_sha256_16": "4febe89df2813f23", "ac_sha256_16": "d3190d478a0e63f4",
-                        "bytes": 1777480143872,
+    "k_sample_stream": {"kernel_sha256_16": "22605b8be4dbf50d", "ac_sha256_16": "d3190d478a0e63f4",
+                        "bytes": 1777647754240,
                         "profile": "profiles/k_sample_stream_qaoa_n8_p1_dep.md"},
-    "k_eval": {"kernel_sha256_16": "4febe89df2813f23", "ac_sha256_16": "53555d81365c02e0",
-               "bytes": 93710172160,
+    "k_eval": {"kernel_sha256_16": "22605b8be4dbf50d", "ac_sha256_16": "53555d81365c02e0",
+               "bytes": 93752513536,
                "profile": "profiles/k_eval_qaoa_n16_p2_dep_ad.md"},
 }
 

@@ -1621,8 +1621,8 @@ struct StreamTile {
 // 6 / 7 / 8 waves, but 8 slows the 32-qubit p=2 batch (2715 / 2758 / 2866 ms).
 // SIB3 = false when the plan has no occurrence with a third sibling: the
 // downward pass then holds two sibling rows per occurrence in its groups of
-// 4 and the leaf step takes groups of 3 instead of 2 (larger groups spill);
-// the chains are the same.
+// 4 and the leaf step takes groups of 3 instead of 2 (groups of 5 and 4
+// measured slower); the chains are the same.
 template <typename T, bool SIB3>
 __global__ __launch_bounds__(MAX_BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? (SIB3 ? STREAM_WAVES_PER_EU : STREAM_WAVES_PER_EU2) : 1, 8))) void k_sample_stream(DevGraph g, SopPlan sp, const double *theta,
                                                          const Weight<T> *wfix, cplx<T> *vals, size_t per_wg,
